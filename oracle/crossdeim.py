@@ -1,0 +1,398 @@
+"""Cross-DEIM low-rank Poisson solve, written out in plain FP64 NumPy.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, the smoke entry point and the
+benchmark's CPU-baseline leg, never by the GPU library.
+
+The solver (Section 3.2): the right-hand side F = U_F diag(sigma) V_F^T is moved to
+the sine basis with the orthonormal DST-I, the spectrally divided solution
+W^(i,j) = h^2 F^(i,j) / (lambda_i + lambda_j) (Section 3.1, eq. g_for_p) is
+approximated by Cross-DEIM (Algorithm 4) without ever forming it, and the factors
+are moved back with the same DST.
+
+Readings of passages that are silent, ambiguous or garbled (each is also listed in
+the design notes of the repository):
+  * eigenvalues: 2(1 - cos(pi k/(n+1))) is evaluated as 4 sin^2(pi k/(2(n+1))),
+    equal in exact arithmetic, without the cancellation at small k.
+  * index selection: Algorithm 3 samples at random; here the leverage scores of the
+    leading r_sig columns choose the top r_sig indices from the complement of the
+    current set (ties and scores below a rounding floor go to the smaller index);
+    the new indices are appended in ascending index order after the old ones (the
+    paper notes that leverage-score sets are unordered); the set size is capped at
+    r_max. This replaces the union and the random safeguard of
+    Algorithm 4 (the paper allows dropping the safeguard for leverage scores).
+  * r_sig = #{sigma_l > eps * sigma_1} of the previous iterate.
+  * the warm start U_{-1}, V_{-1} is the truncated SVD of F^ itself (the paper only
+    asks for an initial guess of the singular vector matrices).
+  * Algorithm 1 roles: k = |J| and l = |I|; the first branch (|J| <= |I|) solves
+    Q(I,:) W = G(I,:); the second solves with Z(J,:) (written Z(:,J) in the
+    listing). Both solves use the pseudo-inverse with the default relative cutoff
+    max(rows, cols) * eps of torch.linalg.pinv, the routine the paper names; the
+    "truncated SVD" of the core uses the same cutoff with max(|I|, |J|).
+  * the pruning thresholds of Algorithm 4 are relative to max |diag R|; all flags
+    are computed before anything is removed; the second loop runs over J.
+  * eta_1, eta_2 are the norms of the pseudo-inverses of U_k(I_k,:), V_k(J_k,:)
+    (the DEIM error constants), on the pruned sets.
+  * eps is relative to ||S_k||_F in rho, in the indicator and in the final
+    truncation; the loop makes exactly maxiter passes; no stop at k = 0; when the
+    pre-prune index sets repeat, the iteration has reached a fixed point and the
+    previous iterate is returned.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+EPS = float(np.finfo(np.float64).eps)
+
+STATUS_OK = 0
+STATUS_NOT_CONVERGED = 1
+STATUS_STAGNATED = 2
+
+#: Leverage scores at or below FLOOR_REL * max(pi) are rounding noise; they count as 0.
+FLOOR_REL = (64.0 * EPS) ** 2
+
+
+# ----------------------------------------------------------------------------------------
+# Section 3: eigenpairs of T = tridiag(-1, 2, -1), and the orthonormal DST-I
+# ----------------------------------------------------------------------------------------
+def eigenvalues(n: int) -> np.ndarray:
+    """lambda_k = 2(1 - cos(pi k/(n+1))) = 4 sin^2(pi k/(2(n+1))), k = 1..n (Section 3)."""
+    k = np.arange(1, n + 1, dtype=np.float64)
+    return 4.0 * np.sin(k * np.pi / (2.0 * (n + 1))) ** 2
+
+
+def dst1(X: np.ndarray) -> np.ndarray:
+    """Orthonormal DST-I along axis 0: (Z x)_i = sqrt(2/(n+1)) sum_k x_k sin(i k pi/(n+1)).
+
+    Z holds the eigenvectors z_k of T (Section 3); it is symmetric and orthogonal, so
+    DST(DST(x)) = x as Section 3.2 requires. Computed through the DFT of the odd
+    extension [0, x, 0, -reverse(x)] of length 2(n+1), whose imaginary part is
+    -2 sum_k x_k sin(pi i k/(n+1)).
+    """
+    X = np.asarray(X, dtype=np.float64)
+    vec = X.ndim == 1
+    if vec:
+        X = X[:, None]
+    n = X.shape[0]
+    N = n + 1
+    ext = np.zeros((2 * N, X.shape[1]))
+    ext[1:N] = X
+    ext[N + 1 :] = -X[::-1]
+    Y = np.fft.fft(ext, axis=0)
+    out = -Y[1:N].imag / math.sqrt(2.0 * N)
+    return out[:, 0] if vec else out
+
+
+def spectral_factors(n: int, U_F: np.ndarray, sigma: np.ndarray, V_F: np.ndarray):
+    """U^ = DST(U_F) diag(h^2 sigma), V^ = DST(V_F) (Section 3.2).
+
+    With these, W^(i,j) = sum_t U^(i,t) V^(j,t) / (lambda_i + lambda_j), i.e. eq. g_for_p
+    with F^ = DST(U_F) S_F DST(V_F)^T; the h^2 and sigma factors are folded into U^.
+    """
+    h = 1.0 / (n + 1)
+    Uh = dst1(U_F) * (h * h * np.asarray(sigma, dtype=np.float64))[None, :]
+    Vh = dst1(V_F)
+    return Uh, Vh
+
+
+# ----------------------------------------------------------------------------------------
+# Section 3.1, eq. g_for_p: entries, columns and rows of W^
+# ----------------------------------------------------------------------------------------
+def columns(Uh: np.ndarray, Vh: np.ndarray, lam: np.ndarray, J: Sequence[int]) -> np.ndarray:
+    """C = W^(:, J), an n x |J| array."""
+    J = np.asarray(J, dtype=np.int64)
+    return (Uh @ Vh[J].T) / (lam[:, None] + lam[J][None, :])
+
+
+def rows(Uh: np.ndarray, Vh: np.ndarray, lam: np.ndarray, I: Sequence[int]) -> np.ndarray:
+    """R = W^(I, :), an |I| x n array."""
+    I = np.asarray(I, dtype=np.int64)
+    return (Uh[I] @ Vh.T) / (lam[I][:, None] + lam[None, :])
+
+
+# ----------------------------------------------------------------------------------------
+# Linear-algebra steps used by Algorithm 1
+# ----------------------------------------------------------------------------------------
+def thin_qr(X: np.ndarray):
+    """Householder QR, X = Q R with Q n x k orthonormal and R k x k upper triangular."""
+    Q, R = np.linalg.qr(X, mode="reduced")
+    return Q, R
+
+
+def pinv(A: np.ndarray) -> np.ndarray:
+    """Pseudo-inverse by SVD; singular values <= max(m, n) * eps * sigma_1 are dropped."""
+    m, k = A.shape
+    if m == 0 or k == 0:
+        return np.zeros((k, m))
+    Ua, s, Vt = np.linalg.svd(A, full_matrices=False)
+    if s[0] == 0.0:
+        return np.zeros((k, m))
+    keep = s > max(m, k) * EPS * s[0]
+    return (Vt[keep].T / s[keep][None, :]) @ Ua[:, keep].T
+
+
+def sigma_min(A: np.ndarray) -> float:
+    """Smallest of the min(rows, cols) singular values of A."""
+    if A.size == 0:
+        return 0.0
+    return float(np.linalg.svd(A, compute_uv=False)[-1])
+
+
+@dataclasses.dataclass
+class Cross:
+    U: np.ndarray  # n x r, orthonormal columns
+    S: np.ndarray  # r, descending
+    V: np.ndarray  # n x r
+    rC: np.ndarray  # diag(R_C), one per index of J
+    rR: np.ndarray  # diag(R_R), one per index of I
+
+
+def scross(Uh, Vh, lam, I: Sequence[int], J: Sequence[int]) -> Cross:
+    """Algorithm 1: stabilized cross approximation from the fibers W^(:,J), W^(I,:).
+
+    C = W^(:,J) = Q R_C and R^T = W^(I,:)^T = Z R_R (thin QRs). With k = |J|, l = |I|:
+      k <= l: W = Q(I,:)^+ R = [Q(I,:)^+ R_R^T] Z^T;
+      k >  l: W^T = Z(J,:)^+ C^T, i.e. W = Q [R_C (Z(J,:)^+)^T] Z^T.
+    Either way the approximation is Q M Z^T with a |J| x |I| core M, so the truncated
+    SVD of M = U^ S V~^T gives U = Q U^, V = Z V~ (the SVD of the |J| x n matrix in the
+    listing has the same singular values and left factor).
+    """
+    I = list(I)
+    J = list(J)
+    C = columns(Uh, Vh, lam, J)
+    Rt = rows(Uh, Vh, lam, I).T
+    Q, RC = thin_qr(C)
+    Zq, RR = thin_qr(Rt)
+    if len(J) <= len(I):
+        M = pinv(Q[I, :]) @ RR.T
+    else:
+        M = RC @ pinv(Zq[J, :]).T
+    A, s, Bt = np.linalg.svd(M, full_matrices=False)
+    if s.size == 0 or s[0] == 0.0:
+        r = 0
+    else:
+        r = int(np.count_nonzero(s > max(len(I), len(J)) * EPS * s[0]))
+    return Cross(Q @ A[:, :r], s[:r].copy(), Zq @ Bt[:r].T, np.diag(RC).copy(), np.diag(RR).copy())
+
+
+# ----------------------------------------------------------------------------------------
+# Algorithm 3 (leverage scores) and the index-set update of Algorithm 4
+# ----------------------------------------------------------------------------------------
+def leverage_scores(U: np.ndarray, r_sig: int) -> np.ndarray:
+    """pi_i = sum over the leading r_sig columns of U(i, eta)^2 (Algorithm 3; the 1/k factor
+    does not change the ranking and is left out)."""
+    return np.sum(U[:, :r_sig] ** 2, axis=1)
+
+
+@dataclasses.dataclass
+class Selection:
+    indices: List[int]  # old indices, then the new ones in selection order
+    new: List[int]
+    gap: float  # (score of last taken - score of first left) / max score; inf if none left
+
+
+def select(U: np.ndarray, r_sig: int, I_prev: Sequence[int], p_max: int) -> Selection:
+    """Append the r_sig highest leverage scores outside I_prev to I_prev (capped at p_max)."""
+    n = U.shape[0]
+    pi = leverage_scores(U, r_sig)
+    top = float(pi.max()) if n else 0.0
+    score = np.where(pi <= FLOOR_REL * top, 0.0, pi)
+    free = np.ones(n, dtype=bool)
+    free[np.asarray(list(I_prev), dtype=np.int64)] = False
+    cand = np.nonzero(free)[0]
+    order = cand[np.lexsort((cand, -score[cand]))]
+    s = max(0, min(r_sig, p_max - len(I_prev), order.size))
+    # Leverage-score sets carry no order (Algorithm 4 notes this); the new indices are
+    # appended in ascending index order so that rounding in equal scores cannot reorder them.
+    new = sorted(int(i) for i in order[:s])
+    if s < order.size and s > 0 and top > 0.0:
+        gap = float(score[order[s - 1]] - score[order[s]]) / top
+    else:
+        gap = math.inf
+    return Selection(list(I_prev) + new, new, gap)
+
+
+def prune(idx: Sequence[int], diag: np.ndarray, tau: float) -> List[int]:
+    """Drop idx[l] where |diag[l]| < tau * max|diag| (Algorithm 4, redundant rows/columns)."""
+    a = np.abs(np.asarray(diag))
+    if a.size == 0:
+        return []
+    keep = a >= tau * a.max()
+    return [int(i) for i, kp in zip(idx, keep) if kp]
+
+
+# ----------------------------------------------------------------------------------------
+# Frobenius norms of factored matrices (the rho of Algorithm 4, and error metrics)
+# ----------------------------------------------------------------------------------------
+def lr_norm(terms) -> float:
+    """|| sum_i U_i diag(s_i) V_i^T ||_F for a list of (U_i, s_i, V_i), without forming it.
+
+    [U_1 .. U_m] = Q_a R_a and [V_1 .. V_m] = Q_b R_b (Householder), so the sum equals
+    Q_a R_a diag(s) R_b^T Q_b^T and its norm is || R_a diag(s) R_b^T ||_F.
+    """
+    A = np.hstack([np.asarray(t[0], dtype=np.float64) for t in terms])
+    B = np.hstack([np.asarray(t[2], dtype=np.float64) for t in terms])
+    d = np.concatenate([np.asarray(t[1], dtype=np.float64).ravel() for t in terms])
+    if d.size == 0:
+        return 0.0
+    _, Ra = np.linalg.qr(A, mode="reduced")
+    _, Rb = np.linalg.qr(B, mode="reduced")
+    return float(np.linalg.norm((Ra * d[None, :]) @ Rb.T))
+
+
+def lr_diff_norm(Ua, Sa, Va, Ub, Sb, Vb) -> float:
+    """|| Ua diag(Sa) Va^T - Ub diag(Sb) Vb^T ||_F."""
+    return lr_norm([(Ua, Sa, Va), (Ub, -np.asarray(Sb), Vb)])
+
+
+def rel_err(a, b) -> float:
+    """|| A - B ||_F / || B ||_F for factored A = (U, S, V), B = (U, S, V)."""
+    den = lr_norm([b])
+    return lr_diff_norm(*a, *b) / den if den > 0 else lr_norm([a])
+
+
+# ----------------------------------------------------------------------------------------
+# Algorithm 4: Cross-DEIM, warm started, applied to W^ (Section 3.2)
+# ----------------------------------------------------------------------------------------
+@dataclasses.dataclass
+class IterRecord:
+    k: int
+    I_pre: List[int]
+    J_pre: List[int]
+    I: List[int]
+    J: List[int]
+    r_sig_in: int
+    rank: int
+    S: np.ndarray
+    rho: float
+    indicator: float
+    eta1: float
+    eta2: float
+    gapI: float
+    gapJ: float
+
+
+@dataclasses.dataclass
+class Result:
+    U: np.ndarray  # n x r, physical-space factors
+    S: np.ndarray  # r
+    V: np.ndarray  # n x r
+    rank: int
+    status: int
+    iters: int  # number of scross calls made
+    I: List[int]  # pruned index sets of the returned iterate
+    J: List[int]
+    rho: float
+    indicator: float
+    trace: List[IterRecord]
+    Uk: Optional[np.ndarray] = None  # spectral factors of the returned iterate (untruncated)
+    Sk: Optional[np.ndarray] = None
+    Vk: Optional[np.ndarray] = None
+
+
+def warm_start(Uh: np.ndarray, Vh: np.ndarray):
+    """U_{-1}, S_{-1}, V_{-1}: truncated SVD of F^ = U^ V^^T from the two thin QRs."""
+    Qu, Ru = thin_qr(Uh)
+    Qv, Rv = thin_qr(Vh)
+    A, s, Bt = np.linalg.svd(Ru @ Rv.T)
+    if s.size == 0 or s[0] == 0.0:
+        return None
+    r = int(np.count_nonzero(s > Uh.shape[1] * EPS * s[0]))
+    return Qu @ A[:, :r], s[:r].copy(), Qv @ Bt[:r].T
+
+
+def indicator(U, S, V, I, J):
+    """min(eta1 (1 + eta2), eta2 (1 + eta1)) * S_min / ||S||_F (Algorithm 4 stopping test)."""
+    s1 = sigma_min(U[np.asarray(I, dtype=np.int64), :])
+    s2 = sigma_min(V[np.asarray(J, dtype=np.int64), :])
+    eta1 = math.inf if s1 == 0.0 else 1.0 / s1
+    eta2 = math.inf if s2 == 0.0 else 1.0 / s2
+    nrm = float(np.linalg.norm(S))
+    val = min(eta1 * (1.0 + eta2), eta2 * (1.0 + eta1)) * float(S[-1]) / nrm
+    return val, eta1, eta2
+
+
+def final_rank(S: np.ndarray, tol: float, r_max: int) -> int:
+    """Smallest r with sum_{l > r} S_l^2 < (tol ||S||_F)^2, clamped to [1, r_max]."""
+    nrm2 = float(np.sum(S * S))
+    thr = (tol * math.sqrt(nrm2)) ** 2
+    tail = 0.0
+    r_star = S.size
+    # walk from the end: tail(r) = sum_{l >= r} S_l^2 (0-based), r* = smallest r with tail < thr
+    for r in range(S.size, -1, -1):
+        if r < S.size:
+            tail += float(S[r]) ** 2
+        if tail < thr:
+            r_star = r
+        else:
+            break
+    return max(min(r_star, r_max), 1)
+
+
+def solve(
+    n: int,
+    U_F: np.ndarray,
+    sigma: np.ndarray,
+    V_F: np.ndarray,
+    r_max: int,
+    tol: float,
+    maxiter: int,
+    prune_tau: float = 1e-12,
+    stop_at_fixed_point: bool = True,
+) -> Result:
+    """Low-rank Poisson solve: -Lap u = f, u = 0 on the boundary of the unit square.
+
+    Returns W ~= U diag(S) V^T on the n x n interior grid (Sections 3.2 and Algorithm 4).
+    """
+    U_F = np.asarray(U_F, dtype=np.float64)
+    V_F = np.asarray(V_F, dtype=np.float64)
+    lam = eigenvalues(n)
+    Uh, Vh = spectral_factors(n, U_F, sigma, V_F)
+    ws = warm_start(Uh, Vh)
+    if ws is None:  # F = 0: the solution is 0
+        z = np.zeros((n, 1))
+        return Result(z, np.zeros(1), z.copy(), 1, STATUS_OK, 0, [], [], 0.0, 0.0, [])
+    U_prev, S_prev, V_prev = ws
+    I: List[int] = []
+    J: List[int] = []
+    pre_prev = None
+    trace: List[IterRecord] = []
+    status = STATUS_NOT_CONVERGED
+    rho = math.inf
+    ind = math.inf
+    iters = 0
+    for k in range(maxiter):
+        r_sig = int(np.count_nonzero(S_prev > tol * S_prev[0]))
+        selI = select(U_prev, r_sig, I, r_max)
+        selJ = select(V_prev, r_sig, J, r_max)
+        pre = (selI.indices, selJ.indices)
+        if stop_at_fixed_point and pre_prev is not None and pre == pre_prev:
+            status = STATUS_STAGNATED
+            break
+        cr = scross(Uh, Vh, lam, selI.indices, selJ.indices)
+        iters += 1
+        I = prune(selI.indices, cr.rR, prune_tau)
+        J = prune(selJ.indices, cr.rC, prune_tau)
+        ind, eta1, eta2 = indicator(cr.U, cr.S, cr.V, I, J)
+        nrm = float(np.linalg.norm(cr.S))
+        if k == 0:
+            rho = math.inf
+        else:
+            rho = lr_diff_norm(cr.U, cr.S, cr.V, U_prev, S_prev, V_prev) / nrm
+        trace.append(
+            IterRecord(k, selI.indices, selJ.indices, I, J, r_sig, cr.S.size, cr.S, rho, ind,
+                       eta1, eta2, selI.gap, selJ.gap)
+        )
+        U_prev, S_prev, V_prev = cr.U, cr.S, cr.V
+        pre_prev = pre
+        if max(rho, ind) < tol:
+            status = STATUS_OK
+            break
+    r = final_rank(S_prev, tol, r_max)
+    U_out = dst1(U_prev[:, :r])
+    V_out = dst1(V_prev[:, :r])
+    return Result(U_out, S_prev[:r].copy(), V_out, r, status, iters, I, J, rho, ind, trace,
+                  U_prev, S_prev, V_prev)
