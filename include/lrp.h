@@ -1,0 +1,164 @@
+/*
+ * lrp.h -- low-rank Poisson solver (Cross-DEIM with leverage scores) on one MI355X.
+ *
+ * Problem (paper, Section 3, eq. poisson / matrix_poisson): -Lap u = f on the unit square,
+ * u = 0 on the boundary, 5-point stencil on n x n interior points with h = 1/(n+1), i.e.
+ * T W + W T^T = h^2 F with T = tridiag(-1, 2, -1). The right-hand side is given in low-rank
+ * form F = U_F diag(sigma_F) V_F^T (Section 3.2). The solver moves the factors to the sine
+ * basis with the orthonormal DST-I, runs the warm-started Cross-DEIM iteration (Algorithm 4,
+ * with the stabilized cross approximation of Algorithm 1 and leverage-score index selection
+ * of Algorithm 3) on W^(i,j) = h^2 F^(i,j)/(lambda_i + lambda_j) (Section 3.1, eq. g_for_p)
+ * and moves the factors of the result back: W ~= U_W diag(S) V_W^T.
+ *
+ * Conventions for every entry point below:
+ *   - Matrices are column-major; "ld" is the leading dimension (distance in elements between
+ *     columns, ld >= n). Row and column indices are 0-based; frequency index i (0-based)
+ *     stands for the paper's 1-based mode i+1.
+ *   - Pointers documented as "device" are HIP device pointers (hipMalloc or torch CUDA
+ *     tensors); "host" pointers are ordinary CPU memory. The caller owns every buffer it
+ *     passes; the library never frees them and keeps no pointer to them after a call returns.
+ *   - Input buffers are read-only. Output buffers must not overlap inputs (LRP_EINVAL).
+ *   - A context owns all of its device workspace; it is allocated in lrp_create and reused
+ *     by every lrp_solve, which allocates nothing.
+ *   - Negative return codes mean no valid result; positive codes are warnings with a valid
+ *     result; LRP_OK is 0. Argument checks happen before any device work.
+ *   - One context is used by one host thread at a time (calls on a context are not
+ *     thread-safe); work is ordered on the context's stream.
+ */
+#ifndef LRP_H
+#define LRP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lrp_ctx lrp_ctx;
+
+enum lrp_status {
+  LRP_OK = 0,
+  LRP_NOT_CONVERGED = 1, /* maxiter passes made without meeting the tolerance (Algorithm 4 returns its last iterate) */
+  LRP_STAGNATED = 2,     /* the index sets repeated: a fixed point; the last distinct iterate is returned */
+  LRP_EINVAL = -1,       /* bad argument: sizes, null or overlapping pointers, n+1 not a power of two */
+  LRP_ENOMEM = -2,       /* device allocation failed in lrp_create */
+  LRP_EDEVICE = -3,      /* a HIP call failed */
+  LRP_ENUMERIC = -4      /* NaN or Inf in the right-hand side factors */
+};
+
+enum lrp_precision {
+  LRP_FP64 = 0,  /* every step in FP64 */
+  LRP_MIXED = 1  /* DSTs and fiber evaluation in FP32 with FP32 accumulation; QR, leverage
+                    scores, core pseudo-inverse and the stopping test in FP64; the effective
+                    tolerance is max(tol, 1e-7) and the prune threshold 1e-7 */
+};
+
+/* Options of lrp_create (host struct). All-zero selects the defaults. */
+typedef struct lrp_opts {
+  int32_t maxiter;   /* passes of the Cross-DEIM loop; 0 -> 20 */
+  int32_t precision; /* enum lrp_precision */
+  double prune_tau;  /* relative threshold on |diag R| for dropping redundant indices
+                        (Algorithm 4); 0 -> 1e-12 (FP64) or 1e-7 (mixed) */
+  void* stream;      /* hipStream_t to order all work on; NULL -> a stream owned by the context */
+} lrp_opts;
+
+/* Per-solve report (host struct), filled by lrp_solve when non-NULL. */
+typedef struct lrp_info {
+  int32_t status;    /* same as the return code */
+  int32_t iters;     /* cross approximations computed (calls of Algorithm 1) */
+  int32_t rank;      /* rank of the returned solution */
+  int32_t nI, nJ;    /* sizes of the final (pruned) index sets */
+  double rho;        /* ||X_k - X_{k-1}||_F / ||S_k||_F of the last pass (inf if not computed) */
+  double indicator;  /* min(eta1 (1+eta2), eta2 (1+eta1)) S_min / ||S_k||_F of the last pass */
+  float ms;          /* device time of the whole solve, milliseconds (HIP events) */
+} lrp_info;
+
+/*
+ * lrp_create -- context for grids of n interior points per dimension and rank cap r_max.
+ *   ctx    out (host): receives the context.
+ *   n      grid size; n+1 must be a power of two, 3 <= n <= 2^24 - 1.
+ *   r_max  rank cap of the result and cap of each index set, 1 <= r_max <= 64, r_max <= n.
+ *   tol    tolerance eps of Algorithm 4, relative to ||S_k||_F; tol >= 0.
+ *   opts   host, may be NULL (defaults).
+ * Allocates all device workspace (about 12 n r_max doubles) and the eigenvalue and DST
+ * twiddle tables (Section 3: lambda_k = 4 sin^2(pi k/(2(n+1)))).
+ * Returns LRP_OK, LRP_EINVAL, LRP_ENOMEM or LRP_EDEVICE.
+ */
+int lrp_create(lrp_ctx** ctx, int64_t n, int32_t r_max, double tol, const lrp_opts* opts);
+
+/*
+ * lrp_solve -- one low-rank Poisson solve (Section 3.2 with Algorithm 4).
+ *   r_F      rank of the right-hand side, 1 <= r_F <= r_max.
+ *   U_F      device, n x r_F, leading dimension ldu >= n; need not be orthonormal.
+ *   sigma_F  device, r_F values (signed allowed); F = U_F diag(sigma_F) V_F^T.
+ *   V_F      device, n x r_F, leading dimension ldv >= n.
+ *   U_out    device, n x r_max, leading dimension ldou >= n: left factors of W in columns
+ *            0..rank-1; columns rank..r_max-1 are set to 0.
+ *   S_out    device, r_max values: the rank singular values in descending order, then 0.
+ *   V_out    device, n x r_max, leading dimension ldov >= n, as U_out.
+ *   r_out    host, receives the rank (1 <= rank <= r_max).
+ *   info     host, may be NULL.
+ * Blocks until the result is complete. Returns LRP_OK, LRP_NOT_CONVERGED or LRP_STAGNATED
+ * with a valid result, or LRP_EINVAL / LRP_ENUMERIC / LRP_EDEVICE without one. A zero
+ * right-hand side gives the zero solution with rank 1 and LRP_OK.
+ */
+int lrp_solve(lrp_ctx* ctx, int32_t r_F, const double* U_F, int64_t ldu, const double* sigma_F,
+              const double* V_F, int64_t ldv, double* U_out, int64_t ldou, double* S_out,
+              double* V_out, int64_t ldov, int32_t* r_out, lrp_info* info);
+
+/*
+ * lrp_get_index_sets -- the pruned row set I and column set J of the iterate returned by the
+ * last lrp_solve, in their stored order (old indices first, then new ones ascending).
+ *   I, J   host, capacity r_max each; nI, nJ host, receive the sizes.
+ * Returns LRP_OK or LRP_EINVAL (no solve yet).
+ */
+int lrp_get_index_sets(const lrp_ctx* ctx, int64_t* I, int32_t* nI, int64_t* J, int32_t* nJ);
+
+/*
+ * lrp_get_trace -- per-pass record of the last lrp_solve (Algorithm 4), pass k = 0..count-1:
+ *   Ipre, Jpre  host, count x r_max: the index sets handed to the cross approximation;
+ *   nIpre, nJpre, nI, nJ  host, count: their sizes before and after pruning;
+ *   rank        host, count: rank of the pass's cross approximation;
+ *   indicator, rho  host, count (rho is +inf where it was not needed).
+ *   count       host in/out: capacity in passes on input, passes recorded on output.
+ * Any array pointer may be NULL. Returns LRP_OK or LRP_EINVAL.
+ */
+int lrp_get_trace(const lrp_ctx* ctx, int32_t* count, int32_t* Ipre, int32_t* nIpre, int32_t* Jpre,
+                  int32_t* nJpre, int32_t* nI, int32_t* nJ, int32_t* rank, double* indicator,
+                  double* rho);
+
+/* lrp_destroy -- frees the context and its workspace (NULL is a no-op). */
+int lrp_destroy(lrp_ctx* ctx);
+
+/* lrp_strerror -- static description of a return code. */
+const char* lrp_strerror(int code);
+
+/*
+ * lrp_dst1 -- orthonormal DST-I along the columns of a device matrix (Section 3:
+ * (Z x)_i = sqrt(2/(n+1)) sum_k x_k sin(i k pi/(n+1)), Z = Z^T = Z^{-1}, Section 3.2).
+ *   X  device, n x ncols, ld ldx >= n (read);  Y  device, n x ncols, ld ldy >= n (written).
+ *   scale  device or NULL: if given, column c of Y is multiplied by scale[c] (ncols values).
+ *   mul    host scalar multiplying every output (1.0 for the plain transform).
+ *   precision  LRP_FP64 or LRP_MIXED (FP32 arithmetic, FP64 in and out).
+ * Uses the context's stream and tables, so n must equal the context's n; X and Y must not
+ * overlap; ncols <= 2 r_max. Returns LRP_OK, LRP_EINVAL or LRP_EDEVICE; does not block.
+ */
+int lrp_dst1(lrp_ctx* ctx, int32_t ncols, const double* X, int64_t ldx, double* Y, int64_t ldy,
+             const double* scale, double mul, int32_t precision);
+
+/*
+ * lrp_tsqr -- thin Householder QR of a tall device matrix, A = Q R (the QR of Algorithm 1,
+ * computed as a tree of block QRs). The rows of the context's grid are the rows of A.
+ *   A  device, n x ncols, ld lda >= n (read); 1 <= ncols <= r_max.
+ *   Q  device, n x ncols, ld ldq >= n (written; orthonormal columns).
+ *   R  device, ncols x ncols, ld ldr >= ncols (written; upper triangular, zeros below).
+ * Blocks until done. Returns LRP_OK, LRP_EINVAL or LRP_EDEVICE.
+ */
+int lrp_tsqr(lrp_ctx* ctx, int32_t ncols, const double* A, int64_t lda, double* Q, int64_t ldq,
+             double* R, int64_t ldr);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LRP_H */

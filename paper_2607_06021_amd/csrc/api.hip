@@ -1,0 +1,613 @@
+// C-ABI of the low-rank Poisson library: context, workspace and the solve pipeline.
+//
+// One solve (paper, Section 3.2 with Algorithm 4):
+//   DST-I of the factors (U side scaled by h^2 sigma)          -> U^, V^
+//   warm start: thin QRs of U^, V^ and the SVD of R_u R_v^T      -> U_{-1}, S_{-1}, V_{-1}
+//   pass k = 0 .. maxiter-1:
+//     leverage-score selection from U_{k-1}, V_{k-1}             -> I_k, J_k (fixed-point test)
+//     fibers C = W^(:, J_k), R^T = W^(I_k, :)^T
+//     thin QRs C = Q R_C, R^T = Z R_R (Householder TSQR)
+//     core: pseudo-inverse, |J| x |I| core, its SVD, pruning, indicator
+//     U_k = Q U^, V_k = Z V~
+//     rho (only if the indicator passes) and the stopping decision
+//   final truncation of the returned iterate and DST-I back to physical space.
+// Every size, index set and flag stays in device memory; each kernel of a pass reads them
+// there and returns at once after the solve has stopped, so a pass is enqueued without any
+// read-back. The host polls the stop flag one pass behind the device.
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "lrp_kernels.h"
+
+using namespace lrp;
+
+struct lrp_ctx {
+  int64_t n = 0;
+  int r_max = 0;
+  double tol = 0.0;
+  int maxiter = 20;
+  int precision = LRP_FP64;
+  double tau = 1e-12;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+
+  DevState* st = nullptr;
+  DevState* st_host = nullptr;  // pinned
+  int* done_host = nullptr;     // pinned, 2 slots
+  double* lam = nullptr;
+  float* lam32 = nullptr;
+  double *Uh = nullptr, *Vh = nullptr;
+  float *Uh32 = nullptr, *Vh32 = nullptr;
+  double *C = nullptr, *Rt = nullptr;
+  float *C32 = nullptr, *Rt32 = nullptr;
+  double* Q[2] = {nullptr, nullptr};
+  double* Uit[2] = {nullptr, nullptr};
+  double* Vit[2] = {nullptr, nullptr};
+  double *Uhat = nullptr, *Vtil = nullptr;
+  TraceBuf trace{};
+  DstPlan dst{};
+  TsqrPlan tsqr{};
+  SelectPlan sel{};
+  RhoPlan rho{};
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, evit[2] = {nullptr, nullptr};
+  bool solved = false;
+  int last_passes = 0;
+};
+
+namespace {
+
+template <typename T>
+int dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void**)p, sizeof(T) * count) == hipSuccess ? LRP_OK : LRP_ENOMEM;
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+bool pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// [p, p + bytes) of a column-major n x cols matrix with leading dimension ld
+struct Range {
+  uintptr_t lo, hi;
+};
+Range span(const void* p, int64_t n, int64_t ld, int64_t cols, size_t w) {
+  uintptr_t lo = (uintptr_t)p;
+  uintptr_t hi = lo + (uintptr_t)(((cols - 1) * ld + n) * (int64_t)w);
+  return {lo, hi};
+}
+bool overlap(Range a, Range b) { return a.lo < b.hi && b.lo < a.hi; }
+
+void free_ctx(lrp_ctx* c) {
+  if (!c) return;
+  dfree(c->st);
+  if (c->st_host) (void)hipHostFree(c->st_host);
+  if (c->done_host) (void)hipHostFree(c->done_host);
+  dfree(c->lam);
+  dfree(c->lam32);
+  dfree(c->Uh);
+  dfree(c->Vh);
+  dfree(c->Uh32);
+  dfree(c->Vh32);
+  dfree(c->C);
+  dfree(c->Rt);
+  dfree(c->C32);
+  dfree(c->Rt32);
+  for (int s = 0; s < 2; ++s) {
+    dfree(c->Q[s]);
+    dfree(c->Uit[s]);
+    dfree(c->Vit[s]);
+  }
+  dfree(c->Uhat);
+  dfree(c->Vtil);
+  dfree(c->trace.Ipre);
+  dfree(c->trace.Jpre);
+  dfree(c->trace.nIpre);
+  dfree(c->trace.nJpre);
+  dfree(c->trace.nI);
+  dfree(c->trace.nJ);
+  dfree(c->trace.rank);
+  dfree(c->trace.ind);
+  dfree(c->trace.rho);
+  dfree(c->dst.t1_64);
+  dfree(c->dst.t2_64);
+  dfree(c->dst.tl_64);
+  dfree(c->dst.t1_32);
+  dfree(c->dst.t2_32);
+  dfree(c->dst.tl_32);
+  dfree(c->dst.work);
+  for (int L = 0; L < c->tsqr.nlevels; ++L)
+    for (int s = 0; s < 2; ++s) {
+      dfree(c->tsqr.lev[L].V[s]);
+      dfree(c->tsqr.lev[L].tau[s]);
+      dfree(c->tsqr.lev[L].Rout[s]);
+      dfree(c->tsqr.lev[L].Y[s]);
+    }
+  for (int s = 0; s < 2; ++s) {
+    dfree(c->sel.pi[s]);
+    dfree(c->sel.bmax[s]);
+    for (int b = 0; b < 2; ++b) {
+      dfree(c->sel.cand_s[b][s]);
+      dfree(c->sel.cand_i[b][s]);
+    }
+  }
+  dfree(c->sel.gmax);
+  dfree(c->rho.part);
+  dfree(c->rho.M);
+  dfree(c->rho.G);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  for (int s = 0; s < 2; ++s)
+    if (c->evit[s]) (void)hipEventDestroy(c->evit[s]);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+#define TRY(expr)                 \
+  do {                            \
+    int rc_ = (expr);             \
+    if (rc_ != LRP_OK) return rc_; \
+  } while (0)
+
+int create_impl(lrp_ctx* c) {
+  const int64_t n = c->n;
+  const int pm = c->r_max;
+  const bool mixed = c->precision == LRP_MIXED;
+  const size_t np = (size_t)n * pm;
+  if (hipGetDevice(&c->device) != hipSuccess) return LRP_EDEVICE;
+  TRY(dalloc(&c->st, 1));
+  if (hipHostMalloc((void**)&c->st_host, sizeof(DevState)) != hipSuccess) return LRP_ENOMEM;
+  if (hipHostMalloc((void**)&c->done_host, 2 * sizeof(int)) != hipSuccess) return LRP_ENOMEM;
+  TRY(dalloc(&c->lam, n));
+  TRY(dalloc(&c->lam32, n));
+  if (mixed) {
+    TRY(dalloc(&c->Uh32, np));
+    TRY(dalloc(&c->Vh32, np));
+    TRY(dalloc(&c->C32, np));
+    TRY(dalloc(&c->Rt32, np));
+  } else {
+    TRY(dalloc(&c->Uh, np));
+    TRY(dalloc(&c->Vh, np));
+    TRY(dalloc(&c->C, np));
+    TRY(dalloc(&c->Rt, np));
+  }
+  for (int s = 0; s < 2; ++s) {
+    TRY(dalloc(&c->Q[s], np));
+    TRY(dalloc(&c->Uit[s], np));
+    TRY(dalloc(&c->Vit[s], np));
+  }
+  TRY(dalloc(&c->Uhat, (size_t)pm * pm));
+  TRY(dalloc(&c->Vtil, (size_t)pm * pm));
+  const size_t mi = (size_t)std::max(c->maxiter, 1);
+  TRY(dalloc(&c->trace.Ipre, mi * kPMax));
+  TRY(dalloc(&c->trace.Jpre, mi * kPMax));
+  TRY(dalloc(&c->trace.nIpre, mi));
+  TRY(dalloc(&c->trace.nJpre, mi));
+  TRY(dalloc(&c->trace.nI, mi));
+  TRY(dalloc(&c->trace.nJ, mi));
+  TRY(dalloc(&c->trace.rank, mi));
+  TRY(dalloc(&c->trace.ind, mi));
+  TRY(dalloc(&c->trace.rho, mi));
+  // DST tables and work
+  TRY(dst_plan(&c->dst, n, 2 * pm));
+  {
+    const int c1 = c->dst.t1_count, c2 = std::max(c->dst.t2_count, 1);
+    TRY(dalloc(&c->dst.t1_64, c1));
+    TRY(dalloc(&c->dst.t1_32, c1));
+    TRY(dalloc(&c->dst.t2_64, c2));
+    TRY(dalloc(&c->dst.t2_32, c2));
+    TRY(dalloc(&c->dst.tl_64, c2));
+    TRY(dalloc(&c->dst.tl_32, c2));
+    if (c->dst.four_step) {
+      if (hipMalloc(&c->dst.work, (size_t)c->dst.max_pairs * 2 * (n + 1) * 16) != hipSuccess) return LRP_ENOMEM;
+    }
+  }
+  TRY(tsqr_plan(&c->tsqr, n, pm));
+  TRY(select_plan(&c->sel, n));
+  TRY(rho_plan(&c->rho, n));
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+      hipEventCreateWithFlags(&c->evit[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->evit[1], hipEventDisableTiming) != hipSuccess)
+    return LRP_EDEVICE;
+  TRY(lambda_launch(c->lam, c->lam32, n, c->stream));
+  TRY(dst_tables(&c->dst, c->stream));
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return LRP_EDEVICE;
+  return LRP_OK;
+}
+
+int enqueue_pass(lrp_ctx* c, int k) {
+  const bool mixed = c->precision == LRP_MIXED;
+  const int nb_new = (k + 1) & 1, nb_old = k & 1;
+  const int64_t n = c->n;
+  const int pm = c->r_max;
+  hipStream_t s = c->stream;
+  // selection from the previous iterate (candidates were computed right after it)
+  SelectArgs sa{};
+  sa.st = c->st;
+  sa.pmax = pm;
+  sa.kpass = k;
+  sa.trace = c->trace;
+  // the candidate slot depends only on the merge depth, which is fixed per context
+  const int slot = c->sel.nlevels & 1;
+  sa.cs[0] = c->sel.cand_s[slot][0];
+  sa.cs[1] = c->sel.cand_s[slot][1];
+  sa.ci[0] = c->sel.cand_i[slot][0];
+  sa.ci[1] = c->sel.cand_i[slot][1];
+  TRY(select_update(sa, s));
+  FiberArgs fa{};
+  fa.st = c->st;
+  fa.Uh = mixed ? (const void*)c->Uh32 : (const void*)c->Uh;
+  fa.Vh = mixed ? (const void*)c->Vh32 : (const void*)c->Vh;
+  fa.ldh = n;
+  fa.lam = mixed ? (const void*)c->lam32 : (const void*)c->lam;
+  fa.C = mixed ? (void*)c->C32 : (void*)c->C;
+  fa.Rt = mixed ? (void*)c->Rt32 : (void*)c->Rt;
+  fa.ldc = n;
+  fa.n = n;
+  TRY(fiber_launch(fa, mixed, s));
+  TsqrIO io{};
+  io.st = c->st;
+  io.nsides = 2;
+  io.X[0] = fa.C;
+  io.X[1] = fa.Rt;
+  io.x_f32 = mixed;
+  io.ldx = n;
+  io.Q[0] = c->Q[0];
+  io.Q[1] = c->Q[1];
+  io.ldq = n;
+  TRY(tsqr_run(c->tsqr, io, s));
+  CoreArgs ca{};
+  ca.st = c->st;
+  ca.Q0 = c->Q[0];
+  ca.Q1 = c->Q[1];
+  ca.ldq = n;
+  ca.R0 = tsqr_R(c->tsqr, 0);
+  ca.R1 = tsqr_R(c->tsqr, 1);
+  ca.pmax = pm;
+  ca.Uhat = c->Uhat;
+  ca.Vtil = c->Vtil;
+  ca.nb = nb_new;
+  ca.kpass = k;
+  ca.trace = c->trace;
+  ca.maxiter = c->maxiter;
+  TRY(core_launch(ca, false, s));
+  ProdArgs pa{};
+  pa.st = c->st;
+  pa.Q[0] = c->Q[0];
+  pa.Q[1] = c->Q[1];
+  pa.ldq = n;
+  pa.B[0] = c->Uhat;
+  pa.B[1] = c->Vtil;
+  pa.pmax = pm;
+  pa.out[0] = c->Uit[nb_new];
+  pa.out[1] = c->Vit[nb_new];
+  pa.ldo = n;
+  pa.n = n;
+  pa.nb = nb_new;
+  TRY(prod_launch(pa, s));
+  RhoArgs ra{};
+  ra.st = c->st;
+  ra.Unew[0] = c->Uit[nb_new];
+  ra.Unew[1] = c->Vit[nb_new];
+  ra.Uold[0] = c->Uit[nb_old];
+  ra.Uold[1] = c->Vit[nb_old];
+  ra.ldu = n;
+  ra.nb_new = nb_new;
+  ra.nb_old = nb_old;
+  ra.kpass = k;
+  ra.maxiter = c->maxiter;
+  ra.trace = c->trace;
+  TRY(rho_launch(c->rho, ra, s));
+  const double* U[2] = {c->Uit[nb_new], c->Vit[nb_new]};
+  int fslot = 0;
+  TRY(select_candidates(c->sel, c->st, U, n, s, &fslot));
+  return LRP_OK;
+}
+
+int solve_impl(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const double* sigma_F,
+               const double* V_F, int64_t ldv, double* U_out, int64_t ldou, double* S_out,
+               double* V_out, int64_t ldov, int32_t* r_out, lrp_info* info) {
+  const bool mixed = c->precision == LRP_MIXED;
+  const int64_t n = c->n;
+  const int pm = c->r_max;
+  hipStream_t s = c->stream;
+  const double eps = mixed ? std::max(c->tol, 1e-7) : c->tol;
+  const double h = 1.0 / (double)(n + 1);
+  if (hipEventRecord(c->ev0, s) != hipSuccess) return LRP_EDEVICE;
+  TRY(init_state_launch(c->st, rF, eps, c->tau, s));
+  TRY(scan_inputs_launch(c->st, U_F, ldu, V_F, ldv, sigma_F, n, rF, s));
+  // spectral factors U^ = DST(U_F) diag(h^2 sigma), V^ = DST(V_F)
+  DstArgs da{};
+  da.X = U_F;
+  da.ldx = ldu;
+  da.ncols = rF;
+  da.ncols_out = rF;
+  da.ldy = n;
+  da.st = c->st;
+  da.scale = sigma_F;
+  da.outscale = h * h;
+  if (mixed)
+    da.Yf = c->Uh32;
+  else
+    da.Y = c->Uh;
+  TRY(dst_launch(c->dst, da, mixed, s));
+  da.X = V_F;
+  da.ldx = ldv;
+  da.scale = nullptr;
+  da.outscale = 1.0;
+  da.Y = nullptr;
+  da.Yf = nullptr;
+  if (mixed)
+    da.Yf = c->Vh32;
+  else
+    da.Y = c->Vh;
+  TRY(dst_launch(c->dst, da, mixed, s));
+  // warm start
+  TsqrIO io{};
+  io.st = c->st;
+  io.nsides = 2;
+  io.X[0] = mixed ? (const void*)c->Uh32 : (const void*)c->Uh;
+  io.X[1] = mixed ? (const void*)c->Vh32 : (const void*)c->Vh;
+  io.x_f32 = mixed;
+  io.ldx = n;
+  io.Q[0] = c->Q[0];
+  io.Q[1] = c->Q[1];
+  io.ldq = n;
+  TRY(tsqr_run(c->tsqr, io, s));
+  CoreArgs ca{};
+  ca.st = c->st;
+  ca.R0 = tsqr_R(c->tsqr, 0);
+  ca.R1 = tsqr_R(c->tsqr, 1);
+  ca.pmax = pm;
+  ca.Uhat = c->Uhat;
+  ca.Vtil = c->Vtil;
+  ca.nb = 0;
+  ca.kpass = -1;
+  ca.trace = c->trace;
+  ca.maxiter = c->maxiter;
+  TRY(core_launch(ca, true, s));
+  ProdArgs pa{};
+  pa.st = c->st;
+  pa.Q[0] = c->Q[0];
+  pa.Q[1] = c->Q[1];
+  pa.ldq = n;
+  pa.B[0] = c->Uhat;
+  pa.B[1] = c->Vtil;
+  pa.pmax = pm;
+  pa.out[0] = c->Uit[0];
+  pa.out[1] = c->Vit[0];
+  pa.ldo = n;
+  pa.n = n;
+  pa.nb = 0;
+  TRY(prod_launch(pa, s));
+  {
+    const double* U[2] = {c->Uit[0], c->Vit[0]};
+    int fslot = 0;
+    TRY(select_candidates(c->sel, c->st, U, n, s, &fslot));
+  }
+  // passes; the stop flag is read one pass behind
+  int passes = 0;
+  for (int k = 0; k < c->maxiter; ++k) {
+    TRY(enqueue_pass(c, k));
+    ++passes;
+    const int slot = k & 1;
+    if (hipMemcpyAsync(&c->done_host[slot], &c->st->done, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
+      return LRP_EDEVICE;
+    if (hipEventRecord(c->evit[slot], s) != hipSuccess) return LRP_EDEVICE;
+    if (k >= 1) {
+      if (hipEventSynchronize(c->evit[slot ^ 1]) != hipSuccess) return LRP_EDEVICE;
+      if (c->done_host[slot ^ 1]) break;
+    }
+  }
+  c->last_passes = passes;
+  TRY(finalize_launch(c->st, S_out, pm, s));
+  DstArgs db{};
+  db.st = c->st;
+  db.pick_ret = 1;
+  db.X = c->Uit[0];
+  db.X1 = c->Uit[1];
+  db.ldx = n;
+  db.Y = U_out;
+  db.ldy = ldou;
+  db.ncols = 0;
+  db.ncols_out = pm;
+  db.outscale = 1.0;
+  TRY(dst_launch(c->dst, db, mixed, s));
+  db.X = c->Vit[0];
+  db.X1 = c->Vit[1];
+  db.Y = V_out;
+  db.ldy = ldov;
+  TRY(dst_launch(c->dst, db, mixed, s));
+  if (hipEventRecord(c->ev1, s) != hipSuccess) return LRP_EDEVICE;
+  if (hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return LRP_EDEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return LRP_EDEVICE;
+  const DevState& h_st = *c->st_host;
+  c->solved = true;
+  const int status = h_st.status;
+  if (status < 0) return status;
+  if (r_out) *r_out = h_st.r_final;
+  if (info) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    info->status = status;
+    info->iters = h_st.k;
+    info->rank = h_st.r_final;
+    info->nI = h_st.nIb[h_st.ret];
+    info->nJ = h_st.nJb[h_st.ret];
+    info->rho = h_st.rhob[h_st.ret];
+    info->indicator = h_st.indb[h_st.ret];
+    info->ms = ms;
+  }
+  return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lrp_strerror(int code) {
+  switch (code) {
+    case LRP_OK: return "converged";
+    case LRP_NOT_CONVERGED: return "maxiter passes made without meeting the tolerance";
+    case LRP_STAGNATED: return "index sets repeated (fixed point); last distinct iterate returned";
+    case LRP_EINVAL: return "invalid argument";
+    case LRP_ENOMEM: return "device allocation failed";
+    case LRP_EDEVICE: return "HIP runtime error";
+    case LRP_ENUMERIC: return "non-finite input or degenerate fibers";
+    default: return "unknown status";
+  }
+}
+
+int lrp_create(lrp_ctx** ctx, int64_t n, int32_t r_max, double tol, const lrp_opts* opts) {
+  if (!ctx) return LRP_EINVAL;
+  *ctx = nullptr;
+  if (n < 3 || !pow2(n + 1) || n + 1 > (int64_t(1) << 23)) return LRP_EINVAL;
+  if (r_max < 1 || r_max > kPMax || r_max > n) return LRP_EINVAL;
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return LRP_EINVAL;
+  lrp_opts o{};
+  if (opts) o = *opts;
+  if (o.maxiter < 0 || o.maxiter > 1000) return LRP_EINVAL;
+  if (o.precision != LRP_FP64 && o.precision != LRP_MIXED) return LRP_EINVAL;
+  if (!(o.prune_tau >= 0.0) || o.prune_tau >= 1.0) return LRP_EINVAL;
+  lrp_ctx* c = new (std::nothrow) lrp_ctx();
+  if (!c) return LRP_ENOMEM;
+  c->n = n;
+  c->r_max = r_max;
+  c->tol = tol;
+  c->maxiter = o.maxiter == 0 ? 20 : o.maxiter;
+  c->precision = o.precision;
+  c->tau = o.prune_tau > 0.0 ? o.prune_tau : (o.precision == LRP_MIXED ? 1e-7 : 1e-12);
+  if (o.stream) {
+    c->stream = (hipStream_t)o.stream;
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) {
+      delete c;
+      return LRP_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  const int rc = create_impl(c);
+  if (rc != LRP_OK) {
+    free_ctx(c);
+    return rc;
+  }
+  *ctx = c;
+  return LRP_OK;
+}
+
+int lrp_solve(lrp_ctx* c, int32_t r_F, const double* U_F, int64_t ldu, const double* sigma_F,
+              const double* V_F, int64_t ldv, double* U_out, int64_t ldou, double* S_out,
+              double* V_out, int64_t ldov, int32_t* r_out, lrp_info* info) {
+  if (!c || !U_F || !sigma_F || !V_F || !U_out || !S_out || !V_out || !r_out) return LRP_EINVAL;
+  const int64_t n = c->n;
+  if (r_F < 1 || r_F > c->r_max) return LRP_EINVAL;
+  if (ldu < n || ldv < n || ldou < n || ldov < n) return LRP_EINVAL;
+  const Range in[3] = {span(U_F, n, ldu, r_F, 8), span(V_F, n, ldv, r_F, 8), span(sigma_F, r_F, r_F, 1, 8)};
+  const Range out[3] = {span(U_out, n, ldou, c->r_max, 8), span(V_out, n, ldov, c->r_max, 8),
+                        span(S_out, c->r_max, c->r_max, 1, 8)};
+  for (int a = 0; a < 3; ++a) {
+    for (int b = 0; b < 3; ++b)
+      if (overlap(out[a], in[b])) return LRP_EINVAL;
+    for (int b = a + 1; b < 3; ++b)
+      if (overlap(out[a], out[b])) return LRP_EINVAL;
+  }
+  c->solved = false;
+  return solve_impl(c, r_F, U_F, ldu, sigma_F, V_F, ldv, U_out, ldou, S_out, V_out, ldov, r_out, info);
+}
+
+int lrp_get_index_sets(const lrp_ctx* c, int64_t* I, int32_t* nI, int64_t* J, int32_t* nJ) {
+  if (!c || !c->solved || !I || !nI || !J || !nJ) return LRP_EINVAL;
+  const DevState& s = *c->st_host;
+  const int b = s.ret;
+  *nI = s.nIb[b];
+  *nJ = s.nJb[b];
+  for (int q = 0; q < s.nIb[b]; ++q) I[q] = s.Ib[b][q];
+  for (int q = 0; q < s.nJb[b]; ++q) J[q] = s.Jb[b][q];
+  return LRP_OK;
+}
+
+int lrp_get_trace(const lrp_ctx* c, int32_t* count, int32_t* Ipre, int32_t* nIpre, int32_t* Jpre,
+                  int32_t* nJpre, int32_t* nI, int32_t* nJ, int32_t* rank, double* indicator,
+                  double* rho) {
+  if (!c || !c->solved || !count || *count < 0) return LRP_EINVAL;
+  const int avail = std::min(c->st_host->k, c->maxiter);
+  const int m = std::min(*count, avail);
+  *count = m;
+  if (m == 0) return LRP_OK;
+  const TraceBuf& t = c->trace;
+  auto cp = [&](void* dst, const void* src, size_t bytes) {
+    return dst ? hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost) : hipSuccess;
+  };
+  if (Ipre && c->r_max > 0) {
+    for (int k = 0; k < m; ++k)
+      if (hipMemcpy(Ipre + (size_t)k * c->r_max, t.Ipre + (size_t)k * kPMax, sizeof(int) * c->r_max,
+                    hipMemcpyDeviceToHost) != hipSuccess)
+        return LRP_EDEVICE;
+  }
+  if (Jpre && c->r_max > 0) {
+    for (int k = 0; k < m; ++k)
+      if (hipMemcpy(Jpre + (size_t)k * c->r_max, t.Jpre + (size_t)k * kPMax, sizeof(int) * c->r_max,
+                    hipMemcpyDeviceToHost) != hipSuccess)
+        return LRP_EDEVICE;
+  }
+  if (cp(nIpre, t.nIpre, sizeof(int) * m) != hipSuccess || cp(nJpre, t.nJpre, sizeof(int) * m) != hipSuccess ||
+      cp(nI, t.nI, sizeof(int) * m) != hipSuccess || cp(nJ, t.nJ, sizeof(int) * m) != hipSuccess ||
+      cp(rank, t.rank, sizeof(int) * m) != hipSuccess || cp(indicator, t.ind, sizeof(double) * m) != hipSuccess ||
+      cp(rho, t.rho, sizeof(double) * m) != hipSuccess)
+    return LRP_EDEVICE;
+  return LRP_OK;
+}
+
+int lrp_destroy(lrp_ctx* c) {
+  if (!c) return LRP_OK;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  free_ctx(c);
+  return LRP_OK;
+}
+
+int lrp_dst1(lrp_ctx* c, int32_t ncols, const double* X, int64_t ldx, double* Y, int64_t ldy,
+             const double* scale, double mul, int32_t precision) {
+  if (!c || !X || !Y || ncols < 1 || ncols > 2 * c->r_max) return LRP_EINVAL;
+  if (ldx < c->n || ldy < c->n) return LRP_EINVAL;
+  if (precision != LRP_FP64 && precision != LRP_MIXED) return LRP_EINVAL;
+  if (overlap(span(X, c->n, ldx, ncols, 8), span(Y, c->n, ldy, ncols, 8))) return LRP_EINVAL;
+  DstArgs a{};
+  a.X = X;
+  a.ldx = ldx;
+  a.Y = Y;
+  a.ldy = ldy;
+  a.ncols = ncols;
+  a.ncols_out = ncols;
+  a.scale = scale;
+  a.outscale = mul;
+  return dst_launch(c->dst, a, precision == LRP_MIXED, c->stream);
+}
+
+int lrp_tsqr(lrp_ctx* c, int32_t ncols, const double* A, int64_t lda, double* Q, int64_t ldq,
+             double* R, int64_t ldr) {
+  if (!c || !A || !Q || !R || ncols < 1 || ncols > c->r_max) return LRP_EINVAL;
+  if (lda < c->n || ldq < c->n || ldr < ncols) return LRP_EINVAL;
+  if (overlap(span(A, c->n, lda, ncols, 8), span(Q, c->n, ldq, ncols, 8))) return LRP_EINVAL;
+  TsqrIO io{};
+  io.st = nullptr;
+  io.ncols[0] = ncols;
+  io.ncols[1] = 0;
+  io.nsides = 1;
+  io.X[0] = A;
+  io.x_f32 = 0;
+  io.ldx = lda;
+  io.Q[0] = Q;
+  io.ldq = ldq;
+  TRY(tsqr_run(c->tsqr, io, c->stream));
+  if (hipMemcpy2DAsync(R, sizeof(double) * ldr, tsqr_R(c->tsqr, 0), sizeof(double) * c->r_max,
+                       sizeof(double) * ncols, ncols, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return LRP_EDEVICE;
+  return hipStreamSynchronize(c->stream) == hipSuccess ? LRP_OK : LRP_EDEVICE;
+}
+
+}  // extern "C"

@@ -1,0 +1,151 @@
+// Internal definitions shared by the HIP sources of the low-rank Poisson library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lrp.h"
+
+namespace lrp {
+
+constexpr int kPMax = 64;          // largest index set / rank the kernels are built for
+constexpr int kTsqrRows = 256;     // rows of one block QR
+constexpr int kTsqrThreads = 256;  // 4 threads per column, 64 rows per thread
+constexpr int kSelRows = 256;      // rows per leverage-score block
+constexpr int kMergeFan = 16;      // candidate lists merged per block
+constexpr int kMaxLevels = 12;     // TSQR tree levels (n <= 2^23 needs 7 at p_max = 64)
+constexpr double kEps = 2.220446049250313e-16;
+// leverage scores at or below (64 eps)^2 * max(pi) are rounding noise and count as 0
+constexpr double kFloorRel = (64.0 * kEps) * (64.0 * kEps);
+
+// Device-resident control state of one solve. Sizes and index sets live here so that the
+// whole pass can be enqueued without reading anything back to the host.
+struct DevState {
+  int done;     // 1: stop -- every later kernel of the solve returns at once
+  int status;   // lrp_status of the solve so far
+  int k;        // cross approximations computed
+  int ret;      // iterate buffer (0/1) holding the result
+  int zero;     // right-hand side is exactly zero
+  int rF;       // rank of the right-hand side
+  int ncols[2]; // columns of the QR inputs: side 0 = C = W^(:,J) (|J|), side 1 = R^T (|I|)
+  int nI, nJ;   // pruned sets of the newest iterate
+  int nIpre, nJpre;
+  int nIprev, nJprev;  // pre-prune sets of the previous pass (fixed-point test)
+  int r_sig;    // leading singular vectors used by the next selection
+  int r_final;  // rank of the returned solution
+  int pad0;
+  double nrm, ind, rho, eta1, eta2;
+  double eps;   // effective tolerance
+  double tau;   // prune threshold
+  int I[kPMax], J[kPMax];
+  int Ipre[kPMax], Jpre[kPMax];
+  int Iprev[kPMax], Jprev[kPMax];
+  // per iterate buffer
+  double S[2][kPMax];
+  int r[2];
+  int nIb[2], nJb[2];
+  int Ib[2][kPMax], Jb[2][kPMax];
+  double indb[2], rhob[2];
+};
+
+struct TraceBuf {
+  int* Ipre;   // maxiter x kPMax
+  int* Jpre;
+  int* nIpre;  // maxiter
+  int* nJpre;
+  int* nI;
+  int* nJ;
+  int* rank;
+  double* ind;
+  double* rho;
+};
+
+// One level of the TSQR tree, two independent sides per launch.
+struct TsqrLevel {
+  int64_t rows;      // rows of this level's input
+  int block_rows;    // rows per block (<= kTsqrRows)
+  int nblocks;
+  double* V[2];      // Householder vectors, rows x p_max (ld = rows), 1 on the diagonal
+  double* tau[2];    // nblocks x p_max
+  double* Rout[2];   // R factors stacked for the next level: (nblocks p_max) x p_max
+  double* Y[2];      // top-down output of this level: rows x p_max (ld = rows)
+};
+
+// ----------------------------------------------------------------------------------------
+// Wavefront helpers (64 lanes)
+// ----------------------------------------------------------------------------------------
+__device__ inline double shfl_xor_d(double x, int mask) {
+  int lo = __double2loint(x);
+  int hi = __double2hiint(x);
+  lo = __shfl_xor(lo, mask, 64);
+  hi = __shfl_xor(hi, mask, 64);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 4 lanes of a quad (lanes 4q .. 4q+3) using DPP quad permutes.
+__device__ inline double quad_sum(double x) {
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  int lo1 = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
+  int hi1 = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false);
+  x += __hiloint2double(hi1, lo1);
+  lo = __double2loint(x);
+  hi = __double2hiint(x);
+  int lo2 = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
+  int hi2 = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false);
+  return x + __hiloint2double(hi2, lo2);
+}
+
+__device__ inline float quad_sum_f(float x) {
+  int v = __float_as_int(x);
+  x += __int_as_float(__builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));
+  v = __float_as_int(x);
+  return x + __int_as_float(__builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));
+}
+
+__device__ inline double wave_sum(double x) {
+  for (int m = 32; m >= 1; m >>= 1) x += shfl_xor_d(x, m);
+  return x;
+}
+
+__device__ inline double wave_max(double x) {
+  for (int m = 32; m >= 1; m >>= 1) x = fmax(x, shfl_xor_d(x, m));
+  return x;
+}
+
+// Sum over groups of 8 consecutive lanes.
+__device__ inline double oct_sum(double x) {
+  x += shfl_xor_d(x, 1);
+  x += shfl_xor_d(x, 2);
+  x += shfl_xor_d(x, 4);
+  return x;
+}
+
+// Block-wide sum for blockDim.x == 256; `scratch` holds >= 4 doubles of LDS. Ends with every
+// thread holding the total; contains two barriers.
+__device__ inline double block_sum256(double x, double* scratch) {
+  x = wave_sum(x);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) scratch[w] = x;
+  __syncthreads();
+  double t = scratch[0] + scratch[1] + scratch[2] + scratch[3];
+  __syncthreads();
+  return t;
+}
+
+__device__ inline double block_max256(double x, double* scratch) {
+  x = wave_max(x);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) scratch[w] = x;
+  __syncthreads();
+  double t = fmax(fmax(scratch[0], scratch[1]), fmax(scratch[2], scratch[3]));
+  __syncthreads();
+  return t;
+}
+
+}  // namespace lrp
+
+#define LRP_HIP_CHECK(expr)                          \
+  do {                                               \
+    hipError_t e_ = (expr);                          \
+    if (e_ != hipSuccess) return LRP_EDEVICE;        \
+  } while (0)

@@ -1,0 +1,172 @@
+// Kernel argument blocks and host-side launchers of the low-rank Poisson library.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+
+#include "lrp_internal.h"
+
+namespace lrp {
+
+// ---------------------------------------------------------------- DST-I (dst.hip)
+struct DstPlan {
+  int64_t n;
+  int logL, logL1, logL2;
+  int four_step;
+  int tile1, tile2;
+  int max_pairs;
+  int t1_count, t2_count;
+  double2 *t1_64, *t2_64, *tl_64;
+  float2 *t1_32, *t2_32, *tl_32;
+  void* work;  // four-step intermediate: max_pairs x 2(n+1) complex doubles
+};
+
+struct DstArgs {
+  const double* X;   // source columns (ld ldx)
+  const double* X1;  // second candidate source (pick_ret)
+  int64_t ldx;
+  double* Y;         // FP64 destination (ld ldy), or
+  float* Yf;         // FP32 destination
+  int64_t ldy;
+  int ncols;         // columns to transform
+  int ncols_out;     // columns written (extra ones are zero-filled)
+  const double* scale;  // per-column factor or null
+  double outscale;      // global factor (the launcher folds in 1/sqrt(2N))
+  const DevState* st;   // optional: skip after an error; pick_ret selects source/rank
+  int pick_ret;
+  // filled by the launcher
+  int logL, logL1, logL2, tile1, tile2;
+  const void *t1, *t2, *tl;
+  void* work;
+};
+
+int dst_plan(DstPlan* p, int64_t n, int max_cols);
+int dst_tables(DstPlan* p, hipStream_t s);
+int dst_launch(const DstPlan& p, DstArgs a, bool fp32, hipStream_t s);
+
+// ---------------------------------------------------------------- TSQR (tsqr.hip)
+struct TsqrPlan {
+  int64_t n;
+  int pmax;
+  int nlevels;
+  TsqrLevel lev[kMaxLevels];
+};
+
+// Level-0 input and output of one two-sided TSQR.
+struct TsqrIO {
+  const DevState* st;  // if set: ncols per side from st->ncols[side]; skip when st->done
+  int ncols[2];        // used when st is null
+  int nsides;
+  const void* X[2];    // level-0 inputs (n rows), FP64 or FP32
+  int x_f32;
+  int64_t ldx;
+  double* Q[2];        // level-0 apply output (n rows), ld ldq; null -> internal Y
+  int64_t ldq;
+};
+
+int tsqr_plan(TsqrPlan* p, int64_t n, int pmax);
+int tsqr_run(const TsqrPlan& p, const TsqrIO& io, hipStream_t s);
+// Final R of side `side` (pmax x pmax, ld pmax, upper triangular).
+inline const double* tsqr_R(const TsqrPlan& p, int side) { return p.lev[p.nlevels - 1].Rout[side]; }
+
+// ---------------------------------------------------------------- fibers (fiber.hip)
+struct FiberArgs {
+  const DevState* st;
+  const void* Uh;  // n x rF spectral factors (U side carries h^2 sigma), FP64 or FP32
+  const void* Vh;
+  int64_t ldh;
+  const void* lam;  // eigenvalues, same type
+  void* C;          // n x pmax: C = W^(:, Jpre)
+  void* Rt;         // n x pmax: R^T = W^(Ipre, :)^T
+  int64_t ldc;
+  int64_t n;
+};
+int fiber_launch(const FiberArgs& a, bool fp32, hipStream_t s);
+
+// ---------------------------------------------------------------- core (core.hip)
+struct CoreArgs {
+  DevState* st;
+  const double* Q0;  // explicit Q of side 0 (C), n x ncols[0]
+  const double* Q1;  // explicit Q of side 1 (R^T), n x ncols[1]
+  int64_t ldq;
+  const double* R0;  // pmax x pmax
+  const double* R1;
+  int pmax;
+  double* Uhat;      // out: pmax x pmax (ld pmax): coefficients of U_k in Q
+  double* Vtil;      // out: coefficients of V_k in Z
+  int nb;            // iterate buffer written by this pass
+  int kpass;         // pass index (trace row); -1 for the warm start
+  TraceBuf trace;
+  int maxiter;
+};
+int core_launch(const CoreArgs& a, bool warm, hipStream_t s);
+
+// ---------------------------------------------------------------- products (prod.hip)
+struct ProdArgs {
+  const DevState* st;
+  const double* Q[2];
+  int64_t ldq;
+  const double* B[2];  // pmax x pmax coefficient matrices (Uhat / Vtil)
+  int pmax;
+  double* out[2];      // n x pmax (ld ldo)
+  int64_t ldo;
+  int64_t n;
+  int nb;              // buffer index whose rank st->r[nb] gives the columns
+};
+int prod_launch(const ProdArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------- selection (select.hip)
+struct SelectPlan {
+  int64_t n;
+  int nblocks;            // ceil(n / kSelRows)
+  int nlevels;            // merge levels after the block level
+  int lists[8];           // lists at each merge level input
+  double* pi[2];          // n
+  double* bmax[2];        // nblocks
+  double* gmax;           // 2
+  double* cand_s[2][2];   // ping-pong candidate scores
+  int* cand_i[2][2];
+};
+int select_plan(SelectPlan* p, int64_t n);
+// Leverage scores of the iterate in buffers U0/U1 and top candidates outside the pruned sets.
+int select_candidates(const SelectPlan& p, const DevState* st, const double* U[2], int64_t ldu,
+                      hipStream_t s, int* final_list_slot);
+struct SelectArgs {
+  DevState* st;
+  const double* cs[2];  // final candidate list per side (kPMax entries, best first)
+  const int* ci[2];
+  int pmax;
+  int kpass;
+  TraceBuf trace;
+};
+int select_update(const SelectArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------- rho / stop (rho.hip)
+struct RhoPlan {
+  int64_t n;
+  int nblocks;
+  double* part;  // nblocks x 2 x kPMax x kPMax
+  double* M;     // 2 x kPMax x kPMax : M_u, N_v
+  double* G;     // 2 x kPMax x kPMax : Y^T Y, Y'^T Y'
+};
+int rho_plan(RhoPlan* p, int64_t n);
+struct RhoArgs {
+  DevState* st;
+  const double* Unew[2];  // U_k, V_k
+  const double* Uold[2];  // U_{k-1}, V_{k-1}
+  int64_t ldu;
+  int nb_new, nb_old;
+  int kpass;
+  int maxiter;
+  TraceBuf trace;
+};
+int rho_launch(const RhoPlan& p, const RhoArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------- misc (core.hip)
+int scan_inputs_launch(DevState* st, const double* U, int64_t ldu, const double* V, int64_t ldv,
+                       const double* sig, int64_t n, int rF, hipStream_t s);
+int finalize_launch(DevState* st, double* S_out, int r_max, hipStream_t s);
+int init_state_launch(DevState* st, int rF, double eps, double tau, hipStream_t s);
+int lambda_launch(double* lam, float* lam32, int64_t n, hipStream_t s);
+
+}  // namespace lrp

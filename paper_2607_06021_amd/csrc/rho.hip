@@ -1,0 +1,257 @@
+// Stopping test of Algorithm 4 (paper): rho = ||U_k S_k V_k^T - U' S' V'^T||_F / ||S_k||_F,
+// with (U', S', V') the previous iterate, and the decision max(rho, indicator) < eps.
+//
+// rho is formed without cancellation (never as ||A||^2 + ||B||^2 - 2 <A, B>): with
+// M_u = U_k^T U', Y = U' - U_k M_u, N_v = V_k^T V', Y' = V' - V_k N_v formed explicitly,
+//   X_k - X_{k-1} = U_k (S_k - M_u S' N_v^T) V_k^T - U_k M_u S' Y'^T - Y S' N_v^T V_k^T - Y S' Y'^T,
+// four mutually orthogonal terms, so rho^2 ||S_k||^2 is the sum of
+//   ||S_k - M_u S' N_v^T||^2, tr(M_u S' G' S' M_u^T), tr(N_v S' G S' N_v^T), tr(S' G S' G'),
+// with G = Y^T Y and G' = Y'^T Y' Gram matrices of explicitly formed small numbers.
+// rho is only needed when the indicator already passes (the decision needs both), so the
+// n-length kernels return at once otherwise. All reductions have a fixed order.
+#include "lrp_kernels.h"
+
+namespace lrp {
+
+constexpr int kRhoChunk = 64;
+
+struct RhoKArgs {
+  DevState* st;
+  const double* A[2];  // U_k / V_k
+  const double* B[2];  // U' / V'
+  int64_t ldu;
+  int64_t n;
+  int rows_per_block;
+  int nb_new, nb_old;
+  int kpass;
+  const double* M;     // M_u, N_v (for the second pass)
+  double* part;
+};
+
+__device__ inline bool rho_needed(const DevState* st, int kpass) {
+  return !st->done && kpass >= 1 && st->ind < st->eps;
+}
+
+// Stage rows [r0, r0 + 64) of the first `cols` columns of X into S (row-major, ld 65).
+__device__ inline void stage(double (*S)[kPMax + 1], const double* X, int64_t ldu, int64_t n,
+                             int64_t r0, int cols) {
+  for (int e = threadIdx.x; e < kRhoChunk * kPMax; e += blockDim.x) {
+    const int row = e % kRhoChunk, c = e / kRhoChunk;
+    const int64_t i = r0 + row;
+    S[row][c] = (c < cols && i < n) ? X[i + (int64_t)c * ldu] : 0.0;
+  }
+}
+
+// Pass A: partial M = A^T B over the block's rows, 4x4 output tile per thread.
+__global__ __launch_bounds__(256) void k_rho_a(RhoKArgs a) {
+  DevState* st = a.st;
+  if (!rho_needed(st, a.kpass)) return;
+  const int side = blockIdx.y;
+  const int r = st->r[a.nb_new], ro = st->r[a.nb_old];
+  __shared__ double As[kRhoChunk][kPMax + 1], Bs[kRhoChunk][kPMax + 1];
+  const int t = threadIdx.x, ta = t >> 4, tb = t & 15;
+  double acc[4][4] = {};
+  const int64_t row0 = (int64_t)blockIdx.x * a.rows_per_block;
+  const int64_t rend = min(a.n, row0 + a.rows_per_block);
+  for (int64_t r0 = row0; r0 < rend; r0 += kRhoChunk) {
+    stage(As, a.A[side], a.ldu, rend, r0, r);
+    stage(Bs, a.B[side], a.ldu, rend, r0, ro);
+    __syncthreads();
+    for (int row = 0; row < kRhoChunk; ++row) {
+      double x[4], y[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        x[q] = As[row][4 * ta + q];
+        y[q] = Bs[row][4 * tb + q];
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = fma(x[p], y[q], acc[p][q]);
+    }
+    __syncthreads();
+  }
+  double* out = a.part + ((int64_t)blockIdx.x * 2 + side) * kPMax * kPMax;
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[(4 * ta + p) * kPMax + 4 * tb + q] = acc[p][q];
+}
+
+// Pass B: Y = B - A M (rows of the chunk), partial G = Y^T Y.
+__global__ __launch_bounds__(256) void k_rho_b(RhoKArgs a) {
+  DevState* st = a.st;
+  if (!rho_needed(st, a.kpass)) return;
+  const int side = blockIdx.y;
+  const int r = st->r[a.nb_new], ro = st->r[a.nb_old];
+  __shared__ double As[kRhoChunk][kPMax + 1], Bs[kRhoChunk][kPMax + 1];
+  __shared__ double Ms[kPMax][kPMax + 1];
+  const double* Mg = a.M + (int64_t)side * kPMax * kPMax;
+  for (int e = threadIdx.x; e < kPMax * kPMax; e += blockDim.x) Ms[e / kPMax][e % kPMax] = Mg[e];
+  const int t = threadIdx.x, ta = t >> 4, tb = t & 15;
+  double acc[4][4] = {};
+  const int64_t row0 = (int64_t)blockIdx.x * a.rows_per_block;
+  const int64_t rend = min(a.n, row0 + a.rows_per_block);
+  for (int64_t r0 = row0; r0 < rend; r0 += kRhoChunk) {
+    stage(As, a.A[side], a.ldu, rend, r0, r);
+    stage(Bs, a.B[side], a.ldu, rend, r0, ro);
+    __syncthreads();
+    for (int e = t; e < kRhoChunk * kPMax; e += blockDim.x) {
+      const int row = e / kPMax, b = e % kPMax;
+      double s = Bs[row][b];
+      for (int q = 0; q < r; ++q) s = fma(-As[row][q], Ms[q][b], s);
+      Bs[row][b] = b < ro ? s : 0.0;
+    }
+    __syncthreads();
+    for (int row = 0; row < kRhoChunk; ++row) {
+      double x[4], y[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        x[q] = Bs[row][4 * ta + q];
+        y[q] = Bs[row][4 * tb + q];
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = fma(x[p], y[q], acc[p][q]);
+    }
+    __syncthreads();
+  }
+  double* out = a.part + ((int64_t)blockIdx.x * 2 + side) * kPMax * kPMax;
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[(4 * ta + p) * kPMax + 4 * tb + q] = acc[p][q];
+}
+
+// Sum the per-block partials in block order: out[side][e] = sum_b part[b][side][e].
+__global__ __launch_bounds__(256) void k_rho_reduce(const DevState* st, int kpass, const double* part,
+                                                    int nblocks, double* out) {
+  if (!rho_needed(st, kpass)) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;  // 0 .. 2*4096
+  if (e >= 2 * kPMax * kPMax) return;
+  const int side = e / (kPMax * kPMax), q = e % (kPMax * kPMax);
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += part[((int64_t)b * 2 + side) * kPMax * kPMax + q];
+  out[e] = s;
+}
+
+struct RhoFinalArgs {
+  DevState* st;
+  const double* M;  // M_u, N_v   (row a: new column, col m: old column)
+  const double* G;  // G_u = Y^T Y, G_v = Y'^T Y'
+  int nb_new, nb_old;
+  int kpass, maxiter;
+  TraceBuf trace;
+};
+
+__global__ __launch_bounds__(256) void k_rho_final(RhoFinalArgs a) {
+  DevState* st = a.st;
+  if (st->done) return;
+  const bool need = rho_needed(st, a.kpass);
+  __shared__ double red[4];
+  __shared__ double Am[kPMax][kPMax + 1], Bm[kPMax][kPMax + 1];
+  double rho = INFINITY;
+  if (need) {
+    const int r = st->r[a.nb_new], ro = st->r[a.nb_old];
+    const double* S = st->S[a.nb_new];
+    const double* So = st->S[a.nb_old];
+    const double* Mu = a.M;
+    const double* Nv = a.M + kPMax * kPMax;
+    const double* Gu = a.G;
+    const double* Gv = a.G + kPMax * kPMax;
+    for (int e = threadIdx.x; e < kPMax * kPMax; e += blockDim.x) {
+      const int aa = e / kPMax, m = e % kPMax;
+      Am[aa][m] = (aa < r && m < ro) ? Mu[aa * kPMax + m] * So[m] : 0.0;  // M_u S'
+      Bm[aa][m] = (aa < r && m < ro) ? Nv[aa * kPMax + m] * So[m] : 0.0;  // N_v S'
+    }
+    __syncthreads();
+    double part = 0.0;
+    for (int e = threadIdx.x; e < r * r; e += blockDim.x) {  // T1
+      const int aa = e / r, b = e % r;
+      double s = (aa == b) ? S[aa] : 0.0;
+      for (int m = 0; m < ro; ++m) s = fma(-Am[aa][m], Nv[b * kPMax + m], s);
+      part = fma(s, s, part);
+    }
+    for (int e = threadIdx.x; e < r * ro; e += blockDim.x) {  // T2 and T3
+      const int aa = e / ro, m2 = e % ro;
+      double p2 = 0.0, p3 = 0.0;
+      for (int m = 0; m < ro; ++m) {
+        p2 = fma(Am[aa][m], Gv[m * kPMax + m2], p2);
+        p3 = fma(Bm[aa][m], Gu[m * kPMax + m2], p3);
+      }
+      part = fma(p2, Am[aa][m2], part);
+      part = fma(p3, Bm[aa][m2], part);
+    }
+    for (int e = threadIdx.x; e < ro * ro; e += blockDim.x) {  // T4
+      const int m = e / ro, m2 = e % ro;
+      part += So[m] * Gu[m * kPMax + m2] * So[m2] * Gv[m2 * kPMax + m];
+    }
+    const double tot = block_sum256(part, red);
+    rho = sqrt(fmax(tot, 0.0)) / st->nrm;
+  }
+  if (threadIdx.x == 0) {
+    const int kp = a.kpass;
+    st->rho = rho;
+    st->rhob[a.nb_new] = rho;
+    st->ret = a.nb_new;
+    st->k = kp + 1;
+    if (kp < a.maxiter) a.trace.rho[kp] = rho;
+    if (kp >= 1 && fmax(rho, st->ind) < st->eps) {
+      st->done = 1;
+      st->status = LRP_OK;
+    } else if (kp == a.maxiter - 1) {
+      st->done = 1;
+      st->status = LRP_NOT_CONVERGED;
+    }
+  }
+}
+
+int rho_plan(RhoPlan* p, int64_t n) {
+  p->n = n;
+  const int64_t chunks = (n + 255) / 256;
+  const int64_t per = (chunks + 511) / 512;  // 256-row chunks per block, <= 512 blocks
+  p->nblocks = (int)((chunks + per - 1) / per);
+  if (hipMalloc(&p->part, sizeof(double) * (size_t)p->nblocks * 2 * kPMax * kPMax) != hipSuccess)
+    return LRP_ENOMEM;
+  if (hipMalloc(&p->M, sizeof(double) * 2 * kPMax * kPMax) != hipSuccess) return LRP_ENOMEM;
+  if (hipMalloc(&p->G, sizeof(double) * 2 * kPMax * kPMax) != hipSuccess) return LRP_ENOMEM;
+  return LRP_OK;
+}
+
+int rho_launch(const RhoPlan& p, const RhoArgs& ra, hipStream_t s) {
+  const int64_t chunks = (p.n + 255) / 256;
+  const int64_t per = (chunks + 511) / 512;
+  RhoKArgs a{};
+  a.st = ra.st;
+  for (int q = 0; q < 2; ++q) {
+    a.A[q] = ra.Unew[q];
+    a.B[q] = ra.Uold[q];
+  }
+  a.ldu = ra.ldu;
+  a.n = p.n;
+  a.rows_per_block = (int)(per * 256);
+  a.nb_new = ra.nb_new;
+  a.nb_old = ra.nb_old;
+  a.kpass = ra.kpass;
+  a.part = p.part;
+  const int red_blocks = (2 * kPMax * kPMax + 255) / 256;
+  hipLaunchKernelGGL(k_rho_a, dim3(p.nblocks, 2), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_rho_reduce, dim3(red_blocks), dim3(256), 0, s, ra.st, ra.kpass, p.part, p.nblocks, p.M);
+  a.M = p.M;
+  hipLaunchKernelGGL(k_rho_b, dim3(p.nblocks, 2), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_rho_reduce, dim3(red_blocks), dim3(256), 0, s, ra.st, ra.kpass, p.part, p.nblocks, p.G);
+  RhoFinalArgs f{};
+  f.st = ra.st;
+  f.M = p.M;
+  f.G = p.G;
+  f.nb_new = ra.nb_new;
+  f.nb_old = ra.nb_old;
+  f.kpass = ra.kpass;
+  f.maxiter = ra.maxiter;
+  f.trace = ra.trace;
+  hipLaunchKernelGGL(k_rho_final, dim3(1), dim3(256), 0, s, f);
+  return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
+}
+
+}  // namespace lrp

@@ -1,0 +1,298 @@
+// Leverage-score index selection (paper, Algorithm 3) in the deterministic form used here:
+//   pi_i = sum_{eta < r_sig} U(i, eta)^2 over the leading r_sig singular vectors;
+//   scores <= (64 eps)^2 max_i pi_i are rounding noise and count as 0;
+//   the r_sig best indices outside the current (pruned) set are taken, best score first,
+//   equal scores to the smaller index; they are appended to the set in ascending order
+//   (leverage-score sets carry no order), the set capped at p_max (Algorithm 4's update).
+// A pass stops at a fixed point: when both new sets equal the previous pass's sets, the
+// cross approximation would repeat, and the previous iterate is the result.
+//
+// Kernels: k_pi (scores and per-block maxima), k_gmax (global maximum), k_topk_block
+// (bitonic sort of each 256-row block, its best 64 kept), k_topk_merge (16 lists of 64 per
+// block until one list is left), k_select (set update, fixed-point test, trace).
+#include "lrp_kernels.h"
+
+namespace lrp {
+
+struct Cand {
+  double s;
+  int i;
+};
+
+// a comes before b: higher score, then smaller index
+__device__ inline bool before(const Cand& a, const Cand& b) {
+  return a.s > b.s || (a.s == b.s && a.i < b.i);
+}
+
+template <int N>
+__device__ void bitonic(Cand* e) {
+  for (int k = 2; k <= N; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const bool up = (i & k) == 0;
+          const Cand a = e[i], b = e[ixj];
+          const bool sw = up ? before(b, a) : before(a, b);
+          if (sw) {
+            e[i] = b;
+            e[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+struct PiArgs {
+  const DevState* st;
+  const double* U[2];
+  int64_t ldu;
+  int64_t n;
+  double* pi[2];
+  double* bmax[2];
+};
+
+__global__ __launch_bounds__(256) void k_pi(PiArgs a) {
+  const DevState* st = a.st;
+  if (st->done) return;
+  const int side = blockIdx.y;
+  const int rs = st->r_sig;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double p = 0.0;
+  if (i < a.n) {
+    const double* U = a.U[side] + i;
+    for (int e = 0; e < rs; ++e) {
+      const double u = U[(int64_t)e * a.ldu];
+      p = fma(u, u, p);
+    }
+    a.pi[side][i] = p;
+  }
+  __shared__ double red[4];
+  const double m = block_max256(p, red);
+  if (threadIdx.x == 0) a.bmax[side][blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(256) void k_gmax(const DevState* st, double* const* bmax_unused,
+                                              const double* b0, const double* b1, int nb,
+                                              double* gmax) {
+  if (st->done) return;
+  const double* b = blockIdx.x == 0 ? b0 : b1;
+  double m = 0.0;
+  for (int e = threadIdx.x; e < nb; e += blockDim.x) m = fmax(m, b[e]);
+  __shared__ double red[4];
+  m = block_max256(m, red);
+  if (threadIdx.x == 0) gmax[blockIdx.x] = m;
+}
+
+struct TopkArgs {
+  const DevState* st;
+  const double* pi[2];
+  const double* gmax;
+  int64_t n;
+  double* cs[2];  // out: nblocks x kPMax scores
+  int* ci[2];
+};
+
+__global__ __launch_bounds__(256) void k_topk_block(TopkArgs a) {
+  const DevState* st = a.st;
+  if (st->done) return;
+  const int side = blockIdx.y;
+  __shared__ Cand e[kSelRows];
+  __shared__ int excl[kPMax];
+  const int ne = side == 0 ? st->nI : st->nJ;
+  const int* set = side == 0 ? st->I : st->J;
+  if (threadIdx.x < ne) excl[threadIdx.x] = set[threadIdx.x];
+  __syncthreads();
+  const double floor_v = kFloorRel * a.gmax[side];
+  const int64_t i = (int64_t)blockIdx.x * kSelRows + threadIdx.x;
+  Cand c;
+  if (i < a.n) {
+    const double p = a.pi[side][i];
+    bool ex = false;
+    for (int q = 0; q < ne; ++q) ex |= (excl[q] == (int)i);
+    c.s = ex ? -1.0 : (p <= floor_v ? 0.0 : p);
+    c.i = (int)i;
+  } else {
+    c.s = -2.0;
+    c.i = 0x7fffffff;
+  }
+  e[threadIdx.x] = c;
+  __syncthreads();
+  bitonic<kSelRows>(e);
+  if (threadIdx.x < kPMax) {
+    a.cs[side][(int64_t)blockIdx.x * kPMax + threadIdx.x] = e[threadIdx.x].s;
+    a.ci[side][(int64_t)blockIdx.x * kPMax + threadIdx.x] = e[threadIdx.x].i;
+  }
+}
+
+struct MergeArgs {
+  const DevState* st;
+  const double* in_s[2];
+  const int* in_i[2];
+  int nlists;
+  double* out_s[2];
+  int* out_i[2];
+};
+
+__global__ __launch_bounds__(256) void k_topk_merge(MergeArgs a) {
+  if (a.st->done) return;
+  const int side = blockIdx.y;
+  constexpr int NE = kMergeFan * kPMax;
+  __shared__ Cand e[NE];
+  const int first = blockIdx.x * kMergeFan;
+  for (int q = threadIdx.x; q < NE; q += blockDim.x) {
+    const int l = first + q / kPMax;
+    Cand c;
+    if (l < a.nlists) {
+      c.s = a.in_s[side][(int64_t)first * kPMax + q];
+      c.i = a.in_i[side][(int64_t)first * kPMax + q];
+    } else {
+      c.s = -2.0;
+      c.i = 0x7fffffff;
+    }
+    e[q] = c;
+  }
+  __syncthreads();
+  bitonic<NE>(e);
+  if (threadIdx.x < kPMax) {
+    a.out_s[side][(int64_t)blockIdx.x * kPMax + threadIdx.x] = e[threadIdx.x].s;
+    a.out_i[side][(int64_t)blockIdx.x * kPMax + threadIdx.x] = e[threadIdx.x].i;
+  }
+}
+
+__global__ void k_select(SelectArgs a) {
+  DevState* st = a.st;
+  if (st->done) return;
+  if (threadIdx.x != 0) return;
+  const int pm = a.pmax;
+  for (int side = 0; side < 2; ++side) {
+    const double* cs = a.cs[side];
+    const int* ci = a.ci[side];
+    const int nold = side == 0 ? st->nI : st->nJ;
+    const int* old = side == 0 ? st->I : st->J;
+    int* pre = side == 0 ? st->Ipre : st->Jpre;
+    int take = min(st->r_sig, pm - nold);
+    int nv = 0;
+    while (nv < kPMax && cs[nv] >= 0.0) ++nv;
+    take = max(0, min(take, nv));
+    for (int q = 0; q < nold; ++q) pre[q] = old[q];
+    // the new indices in ascending order (insertion sort of at most 64 values)
+    for (int q = 0; q < take; ++q) {
+      const int v = ci[q];
+      int pos = nold + q;
+      while (pos > nold && pre[pos - 1] > v) {
+        pre[pos] = pre[pos - 1];
+        --pos;
+      }
+      pre[pos] = v;
+    }
+    if (side == 0)
+      st->nIpre = nold + take;
+    else
+      st->nJpre = nold + take;
+  }
+  // fixed point: the pass would repeat the previous cross approximation exactly
+  bool same = st->nIprev == st->nIpre && st->nJprev == st->nJpre;
+  for (int q = 0; same && q < st->nIpre; ++q) same = st->Iprev[q] == st->Ipre[q];
+  for (int q = 0; same && q < st->nJpre; ++q) same = st->Jprev[q] == st->Jpre[q];
+  if (same) {
+    st->done = 1;
+    st->status = LRP_STAGNATED;
+    return;
+  }
+  for (int q = 0; q < st->nIpre; ++q) st->Iprev[q] = st->Ipre[q];
+  for (int q = 0; q < st->nJpre; ++q) st->Jprev[q] = st->Jpre[q];
+  st->nIprev = st->nIpre;
+  st->nJprev = st->nJpre;
+  st->ncols[0] = st->nJpre;
+  st->ncols[1] = st->nIpre;
+  const int kp = a.kpass;
+  for (int q = 0; q < kPMax; ++q) {
+    a.trace.Ipre[kp * kPMax + q] = q < st->nIpre ? st->Ipre[q] : -1;
+    a.trace.Jpre[kp * kPMax + q] = q < st->nJpre ? st->Jpre[q] : -1;
+  }
+  a.trace.nIpre[kp] = st->nIpre;
+  a.trace.nJpre[kp] = st->nJpre;
+}
+
+// ----------------------------------------------------------------------------------------
+int select_plan(SelectPlan* p, int64_t n) {
+  p->n = n;
+  p->nblocks = (int)((n + kSelRows - 1) / kSelRows);
+  int lists = p->nblocks;
+  int L = 0;
+  while (lists > 1) {
+    if (L >= 8) return LRP_EINVAL;
+    p->lists[L] = lists;
+    lists = (lists + kMergeFan - 1) / kMergeFan;
+    ++L;
+  }
+  p->nlevels = L;
+  for (int s = 0; s < 2; ++s) {
+    if (hipMalloc(&p->pi[s], sizeof(double) * n) != hipSuccess) return LRP_ENOMEM;
+    if (hipMalloc(&p->bmax[s], sizeof(double) * p->nblocks) != hipSuccess) return LRP_ENOMEM;
+    for (int b = 0; b < 2; ++b) {
+      if (hipMalloc(&p->cand_s[b][s], sizeof(double) * p->nblocks * kPMax) != hipSuccess) return LRP_ENOMEM;
+      if (hipMalloc(&p->cand_i[b][s], sizeof(int) * p->nblocks * kPMax) != hipSuccess) return LRP_ENOMEM;
+    }
+  }
+  if (hipMalloc(&p->gmax, sizeof(double) * 2) != hipSuccess) return LRP_ENOMEM;
+  return LRP_OK;
+}
+
+// Writes the final candidate lists (side 0 then 1) into cand_s/cand_i[*final_list_slot].
+// The final list of side s starts at element 0 of cand_*[slot][s].
+int select_candidates(const SelectPlan& p, const DevState* st, const double* U[2], int64_t ldu,
+                      hipStream_t s, int* final_list_slot) {
+  PiArgs pa{};
+  pa.st = st;
+  pa.U[0] = U[0];
+  pa.U[1] = U[1];
+  pa.ldu = ldu;
+  pa.n = p.n;
+  for (int q = 0; q < 2; ++q) {
+    pa.pi[q] = p.pi[q];
+    pa.bmax[q] = p.bmax[q];
+  }
+  hipLaunchKernelGGL(k_pi, dim3(p.nblocks, 2), dim3(256), 0, s, pa);
+  hipLaunchKernelGGL(k_gmax, dim3(2), dim3(256), 0, s, st, nullptr, p.bmax[0], p.bmax[1], p.nblocks,
+                     p.gmax);
+  TopkArgs ta{};
+  ta.st = st;
+  ta.pi[0] = p.pi[0];
+  ta.pi[1] = p.pi[1];
+  ta.gmax = p.gmax;
+  ta.n = p.n;
+  for (int q = 0; q < 2; ++q) {
+    ta.cs[q] = p.cand_s[0][q];
+    ta.ci[q] = p.cand_i[0][q];
+  }
+  hipLaunchKernelGGL(k_topk_block, dim3(p.nblocks, 2), dim3(256), 0, s, ta);
+  int slot = 0;
+  for (int L = 0; L < p.nlevels; ++L) {
+    const int lists = p.lists[L];
+    const int outl = (lists + kMergeFan - 1) / kMergeFan;
+    MergeArgs ma{};
+    ma.st = st;
+    ma.nlists = lists;
+    for (int q = 0; q < 2; ++q) {
+      ma.in_s[q] = p.cand_s[slot][q];
+      ma.in_i[q] = p.cand_i[slot][q];
+      ma.out_s[q] = p.cand_s[slot ^ 1][q];
+      ma.out_i[q] = p.cand_i[slot ^ 1][q];
+    }
+    hipLaunchKernelGGL(k_topk_merge, dim3(outl, 2), dim3(256), 0, s, ma);
+    slot ^= 1;
+  }
+  *final_list_slot = slot;
+  return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
+}
+
+int select_update(const SelectArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, s, a);
+  return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
+}
+
+}  // namespace lrp

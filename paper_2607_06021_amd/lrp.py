@@ -1,0 +1,249 @@
+"""ctypes binding of liblrp.so (include/lrp.h), the HIP low-rank Poisson solver.
+
+Argument marshalling only: every step of a solve runs in the library's HIP kernels.
+PyTorch provides device memory and the stream. Matrices cross the boundary column-major:
+an n x r factor is passed as a torch tensor of shape (n, r) whose transpose is contiguous
+(``t.t().is_contiguous()``), i.e. the storage of an (r, n) row-major tensor.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import re
+from typing import Dict, List, Optional, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblrp.so")
+HEADER = os.path.join(HERE, "..", "include", "lrp.h")
+
+LRP_OK, LRP_NOT_CONVERGED, LRP_STAGNATED = 0, 1, 2
+LRP_EINVAL, LRP_ENOMEM, LRP_EDEVICE, LRP_ENUMERIC = -1, -2, -3, -4
+LRP_FP64, LRP_MIXED = 0, 1
+
+_c_i32 = ctypes.c_int32
+_c_i64 = ctypes.c_int64
+_c_dbl = ctypes.c_double
+_c_vp = ctypes.c_void_p
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("maxiter", _c_i32), ("precision", _c_i32), ("prune_tau", _c_dbl), ("stream", _c_vp)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("status", _c_i32),
+        ("iters", _c_i32),
+        ("rank", _c_i32),
+        ("nI", _c_i32),
+        ("nJ", _c_i32),
+        ("rho", _c_dbl),
+        ("indicator", _c_dbl),
+        ("ms", ctypes.c_float),
+    ]
+
+    def as_dict(self) -> Dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class LrpError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {strerror(code)} (code {code})")
+        self.code = code
+
+
+_LIB: Optional[ctypes.CDLL] = None
+
+
+def header_functions() -> List[str]:
+    """Names of the functions declared in include/lrp.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    return re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(lrp_\w+)\s*\(", text, flags=re.M)
+
+
+def lib() -> ctypes.CDLL:
+    """Load liblrp.so; raises if the library has not been built (there is no fallback)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2607_06021_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    L.lrp_create.argtypes = [P(_c_vp), _c_i64, _c_i32, _c_dbl, P(Opts)]
+    L.lrp_create.restype = ctypes.c_int
+    L.lrp_solve.argtypes = [_c_vp, _c_i32, _c_vp, _c_i64, _c_vp, _c_vp, _c_i64, _c_vp, _c_i64, _c_vp,
+                            _c_vp, _c_i64, P(_c_i32), P(Info)]
+    L.lrp_solve.restype = ctypes.c_int
+    L.lrp_get_index_sets.argtypes = [_c_vp, P(_c_i64), P(_c_i32), P(_c_i64), P(_c_i32)]
+    L.lrp_get_index_sets.restype = ctypes.c_int
+    L.lrp_get_trace.argtypes = [_c_vp, P(_c_i32), P(_c_i32), P(_c_i32), P(_c_i32), P(_c_i32), P(_c_i32),
+                                P(_c_i32), P(_c_i32), P(_c_dbl), P(_c_dbl)]
+    L.lrp_get_trace.restype = ctypes.c_int
+    L.lrp_destroy.argtypes = [_c_vp]
+    L.lrp_destroy.restype = ctypes.c_int
+    L.lrp_strerror.argtypes = [ctypes.c_int]
+    L.lrp_strerror.restype = ctypes.c_char_p
+    L.lrp_dst1.argtypes = [_c_vp, _c_i32, _c_vp, _c_i64, _c_vp, _c_i64, _c_vp, _c_dbl, _c_i32]
+    L.lrp_dst1.restype = ctypes.c_int
+    L.lrp_tsqr.argtypes = [_c_vp, _c_i32, _c_vp, _c_i64, _c_vp, _c_i64, _c_vp, _c_i64]
+    L.lrp_tsqr.restype = ctypes.c_int
+    _LIB = L
+    return L
+
+
+def strerror(code: int) -> str:
+    return lib().lrp_strerror(code).decode()
+
+
+def _check(code: int, where: str, warn_ok: bool = False) -> int:
+    if code < 0 or (code > 0 and not warn_ok):
+        raise LrpError(code, where)
+    return code
+
+
+def _colmajor(t, n: int):
+    """Pointer and leading dimension of a column-major (n, c) torch tensor."""
+    if t.dim() != 2 or t.shape[0] != n:
+        raise ValueError(f"expected an ({n}, c) matrix, got {tuple(t.shape)}")
+    if t.stride(0) != 1:
+        raise ValueError("matrix must be column-major (t.t().is_contiguous())")
+    return t.data_ptr(), max(t.stride(1), n)
+
+
+def fortran(t):
+    """Column-major copy of a 2-D tensor (same shape)."""
+    return t.t().contiguous().t()
+
+
+def empty_fortran(n: int, c: int, dtype, device):
+    import torch
+
+    return torch.empty((c, n), dtype=dtype, device=device).t()
+
+
+class Solver:
+    """A library context: grid size n (n+1 a power of two), rank cap r_max, tolerance tol."""
+
+    def __init__(self, n: int, r_max: int, tol: float, maxiter: int = 20, precision: str = "fp64",
+                 prune_tau: float = 0.0, stream=None):
+        import torch
+
+        self.n, self.r_max, self.tol = int(n), int(r_max), float(tol)
+        self.maxiter = int(maxiter)
+        self.precision = precision
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        o = Opts(self.maxiter, LRP_MIXED if precision == "mixed" else LRP_FP64, float(prune_tau),
+                 _c_vp(stream.cuda_stream))
+        h = _c_vp()
+        _check(lib().lrp_create(ctypes.byref(h), self.n, self.r_max, self.tol, ctypes.byref(o)), "lrp_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().lrp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------------------------------
+    def solve(self, U_F, sigma, V_F, out=None):
+        """Solve with F = U_F diag(sigma) V_F^T (FP64 CUDA tensors, factors column-major).
+
+        Returns (U, S, V, rank, info): U, V are (n, r_max) column-major with zero columns
+        beyond `rank`, S has r_max entries.
+        """
+        import torch
+
+        n, rm = self.n, self.r_max
+        rF = U_F.shape[1]
+        pu, ldu = _colmajor(U_F, n)
+        pv, ldv = _colmajor(V_F, n)
+        if sigma.dim() != 1 or sigma.shape[0] != rF or not sigma.is_contiguous():
+            raise ValueError("sigma must be a contiguous vector of length r_F")
+        for t in (U_F, V_F, sigma):
+            if t.dtype != torch.float64 or not t.is_cuda:
+                raise ValueError("inputs must be float64 CUDA tensors")
+        if out is None:
+            Uo = empty_fortran(n, rm, torch.float64, U_F.device)
+            Vo = empty_fortran(n, rm, torch.float64, U_F.device)
+            So = torch.empty(rm, dtype=torch.float64, device=U_F.device)
+        else:
+            Uo, So, Vo = out
+        puo, lduo = _colmajor(Uo, n)
+        pvo, ldvo = _colmajor(Vo, n)
+        r = _c_i32(0)
+        info = Info()
+        code = lib().lrp_solve(self._h, rF, pu, ldu, sigma.data_ptr(), pv, ldv, puo, lduo, So.data_ptr(),
+                               pvo, ldvo, ctypes.byref(r), ctypes.byref(info))
+        _check(code, "lrp_solve", warn_ok=True)
+        return Uo, So, Vo, int(r.value), info
+
+    def index_sets(self) -> Tuple[List[int], List[int]]:
+        I = (_c_i64 * self.r_max)()
+        J = (_c_i64 * self.r_max)()
+        nI, nJ = _c_i32(), _c_i32()
+        _check(lib().lrp_get_index_sets(self._h, I, ctypes.byref(nI), J, ctypes.byref(nJ)), "lrp_get_index_sets")
+        return list(I[: nI.value]), list(J[: nJ.value])
+
+    def trace(self) -> List[Dict]:
+        m = self.maxiter
+        rm = self.r_max
+        cnt = _c_i32(m)
+        Ip = (_c_i32 * (m * rm))()
+        Jp = (_c_i32 * (m * rm))()
+        nIp, nJp, nI, nJ, rk = [(_c_i32 * m)() for _ in range(5)]
+        ind, rho = (_c_dbl * m)(), (_c_dbl * m)()
+        _check(lib().lrp_get_trace(self._h, ctypes.byref(cnt), Ip, nIp, Jp, nJp, nI, nJ, rk, ind, rho),
+               "lrp_get_trace")
+        out = []
+        for k in range(cnt.value):
+            out.append({
+                "k": k,
+                "I_pre": list(Ip[k * rm: k * rm + nIp[k]]),
+                "J_pre": list(Jp[k * rm: k * rm + nJp[k]]),
+                "nI": nI[k],
+                "nJ": nJ[k],
+                "rank": rk[k],
+                "indicator": ind[k],
+                "rho": rho[k],
+            })
+        return out
+
+    def dst1(self, X, scale=None, mul: float = 1.0, precision: str = "fp64"):
+        """Orthonormal DST-I of the columns of X (n x c, column-major FP64 CUDA tensor)."""
+        import torch
+
+        px, ldx = _colmajor(X, self.n)
+        Y = empty_fortran(self.n, X.shape[1], torch.float64, X.device)
+        py, ldy = _colmajor(Y, self.n)
+        ps = scale.data_ptr() if scale is not None else None
+        _check(lib().lrp_dst1(self._h, X.shape[1], px, ldx, py, ldy, ps, float(mul),
+                              LRP_MIXED if precision == "mixed" else LRP_FP64), "lrp_dst1")
+        return Y
+
+    def tsqr(self, A):
+        """Thin Householder QR of A (n x c, column-major FP64 CUDA tensor): returns Q, R."""
+        import torch
+
+        pa, lda = _colmajor(A, self.n)
+        c = A.shape[1]
+        Q = empty_fortran(self.n, c, torch.float64, A.device)
+        R = empty_fortran(c, c, torch.float64, A.device)
+        pq, ldq = _colmajor(Q, self.n)
+        _check(lib().lrp_tsqr(self._h, c, pa, lda, pq, ldq, R.data_ptr(), c), "lrp_tsqr")
+        return Q, R

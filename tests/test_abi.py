@@ -1,0 +1,60 @@
+"""The C-ABI library loads, exports every function include/lrp.h declares, and rejects bad
+arguments before touching a device. No compute call is made here (no GPU needed)."""
+import ctypes
+import os
+
+import pytest
+
+from paper_2607_06021_amd import lrp as L
+
+pytestmark = pytest.mark.skipif(not os.path.exists(L.LIB_PATH), reason="liblrp.so not built")
+
+
+def test_header_symbols_exported():
+    names = L.header_functions()
+    assert {"lrp_create", "lrp_solve", "lrp_destroy", "lrp_get_index_sets", "lrp_get_trace",
+            "lrp_strerror", "lrp_dst1", "lrp_tsqr"} <= set(names)
+    lib = L.lib()
+    for nm in names:
+        assert hasattr(lib, nm), nm
+
+
+def test_strerror_codes():
+    for code in (L.LRP_OK, L.LRP_NOT_CONVERGED, L.LRP_STAGNATED, L.LRP_EINVAL, L.LRP_ENOMEM,
+                 L.LRP_EDEVICE, L.LRP_ENUMERIC):
+        assert isinstance(L.strerror(code), str) and L.strerror(code)
+    assert L.strerror(99) == "unknown status"
+
+
+@pytest.mark.parametrize("n,rmax,tol", [(256, 8, 1e-10), (254, 8, 1e-10), (2, 1, 1e-10), (255, 0, 1e-10),
+                                        (255, 65, 1e-10), (255, 8, -1.0), (255, 8, float("nan")),
+                                        ((1 << 24) - 1, 8, 1e-10), (7, 8, 1e-10)])
+def test_create_rejects_bad_sizes(n, rmax, tol):
+    h = ctypes.c_void_p()
+    assert L.lib().lrp_create(ctypes.byref(h), n, rmax, tol, None) == L.LRP_EINVAL
+    assert not h.value
+
+
+def test_create_rejects_bad_options():
+    h = ctypes.c_void_p()
+    for o in (L.Opts(-1, 0, 0.0, None), L.Opts(5, 7, 0.0, None), L.Opts(5, 0, 2.0, None)):
+        assert L.lib().lrp_create(ctypes.byref(h), 255, 8, 1e-10, ctypes.byref(o)) == L.LRP_EINVAL
+
+
+def test_null_context_and_arguments():
+    lib = L.lib()
+    r = ctypes.c_int32()
+    assert lib.lrp_solve(None, 2, None, 0, None, None, 0, None, 0, None, None, 0, ctypes.byref(r), None) == L.LRP_EINVAL
+    assert lib.lrp_destroy(None) == L.LRP_OK
+    cnt = ctypes.c_int32(4)
+    assert lib.lrp_get_trace(None, ctypes.byref(cnt), None, None, None, None, None, None, None, None, None) == L.LRP_EINVAL
+    assert lib.lrp_get_index_sets(None, None, None, None, None) == L.LRP_EINVAL
+    assert lib.lrp_dst1(None, 1, None, 0, None, 0, None, 1.0, 0) == L.LRP_EINVAL
+    assert lib.lrp_tsqr(None, 1, None, 0, None, 0, None, 0) == L.LRP_EINVAL
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(L.Opts) == 24
+    assert L.Opts.prune_tau.offset == 8 and L.Opts.stream.offset == 16
+    assert ctypes.sizeof(L.Info) == 48
+    assert L.Info.rho.offset == 24 and L.Info.indicator.offset == 32 and L.Info.ms.offset == 40

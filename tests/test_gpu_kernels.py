@@ -1,0 +1,115 @@
+"""GPU parity of the stage kernels exposed through the C-ABI: DST-I and the TSQR.
+
+Compared element by element with the CPU oracle (FP64 NumPy) on seeded inputs."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import crossdeim as cd
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def to_dev(a):
+    torch = _torch()
+    from paper_2607_06021_amd import fortran
+
+    return fortran(torch.from_numpy(np.ascontiguousarray(a)).cuda())
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("n,ncols", [(7, 1), (255, 5), (1023, 8), (4095, 7), (65535, 6), (262143, 3)])
+def test_dst_fp64_matches_oracle(n, ncols):
+    from paper_2607_06021_amd import Solver
+
+    print(f"dst fp64 n={n} ncols={ncols}", flush=True)
+    rng = np.random.default_rng(n + ncols)
+    X = rng.standard_normal((n, ncols))
+    scale = rng.standard_normal(ncols)
+    torch = _torch()
+    with Solver(n, min(8, n), 1e-10) as s:
+        Y = to_np(s.dst1(to_dev(X), scale=torch.from_numpy(scale).cuda(), mul=0.5))
+        torch.cuda.synchronize()
+    ref = cd.dst1(X) * scale[None, :] * 0.5
+    err = np.max(np.abs(Y - ref)) / np.max(np.abs(ref))
+    print(f"  max rel err {err:.2e}")
+    assert err <= 1e-14 * math.log2(n + 1)
+
+
+@pytest.mark.parametrize("n", [255, 65535])
+def test_dst_fp32_and_involution(n):
+    from paper_2607_06021_amd import Solver
+
+    print(f"dst mixed/involution n={n}", flush=True)
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((n, 4))
+    _torch()
+    with Solver(n, 8, 1e-10) as s:
+        Xd = to_dev(X)
+        Y32 = to_np(s.dst1(Xd, precision="mixed"))
+        Y = s.dst1(Xd)
+        back = to_np(s.dst1(Y))
+    ref = cd.dst1(X)
+    e32 = np.max(np.abs(Y32 - ref)) / np.max(np.abs(ref))
+    print(f"  fp32 rel err {e32:.2e}")
+    assert e32 <= 2e-6
+    assert np.max(np.abs(back - X)) <= 1e-13 * math.log2(n + 1)
+
+
+def _ill_conditioned(n, p, rng, kappa=1e12):
+    Q, _ = np.linalg.qr(rng.standard_normal((n, p)))
+    W, _ = np.linalg.qr(rng.standard_normal((p, p)))
+    s = np.logspace(0, -np.log10(kappa), p)
+    return (Q * s[None, :]) @ W
+
+
+@pytest.mark.parametrize("n,p,kind", [(255, 5, "rand"), (4095, 32, "rand"), (4095, 64, "ill"), (65535, 64, "ill"),
+                                      (65535, 20, "deficient"), (131071, 1, "rand"),
+                                      (1023, 64, "fibers")])
+def test_tsqr_matches_householder(n, p, kind):
+    from paper_2607_06021_amd import Solver
+
+    print(f"tsqr n={n} p={p} kind={kind}", flush=True)
+    rng = np.random.default_rng(p)
+    if kind == "rand":
+        A = rng.standard_normal((n, p))
+    elif kind == "ill":
+        A = _ill_conditioned(n, p, rng)
+    elif kind == "deficient":
+        A = rng.standard_normal((n, p))
+        A[:, 5] = A[:, 2] * 3.0  # exactly dependent column
+        A[:, 9] = 0.0            # zero column
+    else:  # columns of W^ at random J: the matrices the solver factors
+        U, s, V = workloads.make("n255_r5_fp64", 1, n=n)
+        Uh, Vh = cd.spectral_factors(n, U, s, V)
+        A = cd.columns(Uh, Vh, cd.eigenvalues(n), rng.choice(n, p, replace=False))
+    _torch()
+    with Solver(n, p, 1e-10) as s:
+        Qd, Rd = s.tsqr(to_dev(A))
+        Q, R = to_np(Qd), to_np(Rd)
+    nrm = np.linalg.norm(A)
+    assert np.array_equal(np.tril(R, -1), np.zeros_like(R))
+    orth = np.linalg.norm(Q.T @ Q - np.eye(p))
+    recon = np.linalg.norm(Q @ R - A) / nrm
+    Rref = np.linalg.qr(A, mode="r")
+    ddiff = np.max(np.abs(np.abs(np.diag(R)) - np.abs(np.diag(Rref)))) / nrm
+    print(f"  |QtQ-I| {orth:.2e}  |QR-A|/|A| {recon:.2e}  diag diff {ddiff:.2e}")
+    assert recon <= 1e-14 * math.sqrt(p) * 10
+    assert ddiff <= 1e-14 * math.sqrt(p) * 10
+    assert orth <= 1e-13 * math.sqrt(p)
+    if kind != "deficient":
+        # R agrees with LAPACK's up to the sign of each row
+        sg = np.sign(np.diag(R)) * np.sign(np.diag(Rref))
+        assert np.linalg.norm(R - sg[:, None] * Rref) <= 1e-12 * math.sqrt(p) * nrm * (1e4 if kind == "ill" else 1)

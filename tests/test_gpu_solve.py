@@ -1,0 +1,214 @@
+"""Whole-solve parity of the HIP path (through the C-ABI) against the CPU oracle.
+
+FP64: the ordered index sets handed to every cross approximation, the pruned sizes, the
+ranks, the status and the pass count must be identical; the relative Frobenius error of the
+solution against the oracle's must be <= 1e-10. Mixed precision: error <= 1e-5 against the
+oracle (printed for every case)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import crossdeim as cd
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _torch():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def dev(a):
+    torch = _torch()
+    from paper_2607_06021_amd import fortran
+
+    a = np.asarray(a, dtype=np.float64)
+    t = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    return fortran(t) if a.ndim == 2 else t
+
+
+def gpu_solve(n, U, s, V, r_max, tol, maxiter, precision="fp64", prune_tau=0.0):
+    from paper_2607_06021_amd import Solver
+
+    with Solver(n, r_max, tol, maxiter=maxiter, precision=precision, prune_tau=prune_tau) as sol:
+        Uo, So, Vo, r, info = sol.solve(dev(U), dev(s), dev(V))
+        res = {
+            "U": Uo[:, :r].cpu().numpy(),
+            "S": So.cpu().numpy(),
+            "V": Vo[:, :r].cpu().numpy(),
+            "rank": r,
+            "info": info.as_dict(),
+            "sets": sol.index_sets(),
+            "trace": sol.trace(),
+            "Ufull": Uo.cpu().numpy(),
+            "Vfull": Vo.cpu().numpy(),
+        }
+    return res
+
+
+def compare_fp64(g, o, label):
+    info = g["info"]
+    print(f"{label}: status {info['status']}/{o.status} iters {info['iters']}/{o.iters} rank {g['rank']}/{o.rank}",
+          flush=True)
+    for tg, to in zip(g["trace"], o.trace):
+        same = tg["I_pre"] == to.I_pre and tg["J_pre"] == to.J_pre
+        if not same:
+            print(f"  pass {to.k}: sets differ; oracle cut margins gapI {to.gapI:.2e} gapJ {to.gapJ:.2e}")
+            print("   gpu I", tg["I_pre"], "\n   orc I", to.I_pre, "\n   gpu J", tg["J_pre"], "\n   orc J", to.J_pre)
+    assert len(g["trace"]) == len(o.trace)
+    for tg, to in zip(g["trace"], o.trace):
+        assert tg["I_pre"] == to.I_pre and tg["J_pre"] == to.J_pre, f"pass {to.k}"
+        assert tg["nI"] == len(to.I) and tg["nJ"] == len(to.J), f"pass {to.k} pruning"
+        assert tg["rank"] == to.rank, f"pass {to.k} rank"
+    assert info["status"] == o.status
+    assert info["iters"] == o.iters
+    assert g["rank"] == o.rank
+    assert g["sets"] == (o.I, o.J)
+    e = cd.rel_err((g["U"], g["S"][: g["rank"]], g["V"]), (o.U, o.S, o.V))
+    print(f"  rel err vs oracle {e:.3e}  gpu ms {info['ms']:.3f}")
+    assert e <= 1e-10
+    # output padding: zero columns and singular values beyond the rank
+    assert np.all(g["S"][g["rank"]:] == 0.0)
+    assert np.all(g["Ufull"][:, g["rank"]:] == 0.0) and np.all(g["Vfull"][:, g["rank"]:] == 0.0)
+    return e
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_n255_fp64_parity(seed):
+    w = workloads.CONFIGS["n255_r5_fp64"]
+    U, s, V = workloads.make(w, seed)
+    print(f"solve {w.name} seed {seed}", flush=True)
+    o = cd.solve(w.n, U, s, V, w.r_max, w.tol, w.maxiter)
+    g = gpu_solve(w.n, U, s, V, w.r_max, w.tol, w.maxiter)
+    compare_fp64(g, o, f"{w.name} seed {seed}")
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_n4095_fp64_parity(seed):
+    w = workloads.CONFIGS["n4095_r10_fp64"]
+    U, s, V = workloads.make(w, seed)
+    print(f"solve {w.name} seed {seed}", flush=True)
+    o = cd.solve(w.n, U, s, V, w.r_max, w.tol, w.maxiter)
+    g = gpu_solve(w.n, U, s, V, w.r_max, w.tol, w.maxiter)
+    compare_fp64(g, o, f"{w.name} seed {seed}")
+
+
+def test_n65535_fp64_parity():
+    w = workloads.CONFIGS["n65535_r20_fp64"]
+    U, s, V = workloads.make(w, 0)
+    print(f"solve {w.name} seed 0", flush=True)
+    o = cd.solve(w.n, U, s, V, w.r_max, w.tol, w.maxiter)
+    g = gpu_solve(w.n, U, s, V, w.r_max, w.tol, w.maxiter)
+    compare_fp64(g, o, w.name)
+
+
+def test_n65535_mixed_error():
+    w = workloads.CONFIGS["n65535_r20_mixed"]
+    U, s, V = workloads.make(w, 0)
+    print(f"solve {w.name} seed 0", flush=True)
+    o = cd.solve(w.n, U, s, V, w.r_max, w.tol, w.maxiter)
+    g = gpu_solve(w.n, U, s, V, w.r_max, w.tol, w.maxiter, precision="mixed")
+    e = cd.rel_err((g["U"], g["S"][: g["rank"]], g["V"]), (o.U, o.S, o.V))
+    print(f"  mixed: status {g['info']['status']} iters {g['info']['iters']} rank {g['rank']} "
+          f"rel err vs FP64 oracle {e:.3e}")
+    assert e <= 1e-5
+
+
+@pytest.mark.parametrize("n", [255, 65535])
+def test_manufactured_sine_rank_one(n):
+    k, l, a = 5, 9, 2.0
+    U, s, V = workloads.sine_rhs(n, [(k, l, a)])
+    print(f"sine n={n}", flush=True)
+    g = gpu_solve(n, U, s, V, 8, 1e-10, 10)
+    assert g["rank"] == 1
+    h = 1.0 / (n + 1)
+    den = (4.0 / h ** 2) * (math.sin(k * math.pi * h / 2) ** 2 + math.sin(l * math.pi * h / 2) ** 2)
+    x = workloads.grid(n)
+    e = cd.rel_err((g["U"], g["S"][:1], g["V"]), (np.sin(k * math.pi * x)[:, None], np.array([a / den]),
+                                                  np.sin(l * math.pi * x)[:, None]))
+    print(f"  rel err vs closed form {e:.2e}")
+    assert e <= 1e-13
+    assert g["sets"] == ([k - 1], [l - 1])
+
+
+def test_edge_cases_status_and_zero_rhs():
+    n = 255
+    U, s, V = workloads.make("n255_r5_fp64", 0, n=n)
+    print("edge: zero rhs", flush=True)
+    z = gpu_solve(n, U, np.zeros_like(s), V, 16, 1e-10, 10)
+    assert z["rank"] == 1 and z["info"]["status"] == 0 and np.all(z["S"] == 0.0) and np.all(z["U"] == 0.0)
+    print("edge: maxiter 1", flush=True)
+    o1 = cd.solve(n, U, s, V, 16, 1e-10, 1)
+    g1 = gpu_solve(n, U, s, V, 16, 1e-10, 1)
+    compare_fp64(g1, o1, "maxiter=1")
+    print("edge: tiny cap", flush=True)
+    o2 = cd.solve(n, U, s, V, 3, 1e-14, 20)
+    g2 = gpu_solve(n, U, s, V, 3, 1e-14, 20)
+    compare_fp64(g2, o2, "r_max=3")
+    print("edge: rank-1 rhs of width 1 column", flush=True)
+    o3 = cd.solve(n, U[:, :1], s[:1], V[:, :1], 16, 1e-10, 10)
+    g3 = gpu_solve(n, U[:, :1], s[:1], V[:, :1], 16, 1e-10, 10)
+    compare_fp64(g3, o3, "r_F=1")
+
+
+def test_nonfinite_input_rejected():
+    from paper_2607_06021_amd import LrpError
+
+    n = 255
+    U, s, V = workloads.make("n255_r5_fp64", 0, n=n)
+    U[17, 2] = np.nan
+    print("edge: NaN input", flush=True)
+    with pytest.raises(LrpError) as ei:
+        gpu_solve(n, U, s, V, 16, 1e-10, 10)
+    assert ei.value.code == -4
+
+
+def test_repeat_solves_are_bitwise_identical():
+    w = workloads.CONFIGS["n4095_r10_fp64"]
+    U, s, V = workloads.make(w, 3)
+    from paper_2607_06021_amd import Solver
+
+    print("determinism", flush=True)
+    with Solver(w.n, w.r_max, w.tol, maxiter=w.maxiter) as sol:
+        a = sol.solve(dev(U), dev(s), dev(V))
+        A = [t.cpu().numpy().copy() for t in a[:3]]
+        b = sol.solve(dev(U), dev(s), dev(V))
+        B = [t.cpu().numpy() for t in b[:3]]
+    for x, y in zip(A, B):
+        assert np.array_equal(x, y)
+
+
+def test_n1048575_fp64_against_golden():
+    """Full-size n = 2^20 - 1: the oracle takes minutes, so its index sets, ranks, singular
+    values and sampled rows were stored by tests/golden/make_golden.py (oracle only)."""
+    path = os.path.join(GOLDEN, "n1048575_r30_fp64_seed0.json")
+    if not os.path.exists(path):
+        pytest.skip("golden file not generated")
+    with open(path) as f:
+        gold = json.load(f)
+    w = workloads.CONFIGS["n1048575_r30_fp64"]
+    U, s, V = workloads.make(w, 0)
+    print(f"solve {w.name} seed 0 (golden)", flush=True)
+    g = gpu_solve(w.n, U, s, V, w.r_max, w.tol, w.maxiter)
+    info = g["info"]
+    print(f"  status {info['status']}/{gold['status']} iters {info['iters']}/{gold['iters']} rank {g['rank']}/{gold['rank']} ms {info['ms']:.2f}")
+    assert [t["I_pre"] for t in g["trace"]] == gold["I_pre"]
+    assert [t["J_pre"] for t in g["trace"]] == gold["J_pre"]
+    assert info["status"] == gold["status"] and info["iters"] == gold["iters"] and g["rank"] == gold["rank"]
+    S = g["S"][: g["rank"]]
+    assert np.max(np.abs(S - np.array(gold["S"]))) <= 1e-10 * gold["S"][0]
+    rows = np.array(gold["rows"])
+    # W(i, j) at sampled grid points, computed from the stored oracle rows
+    Wg = (g["U"][rows] * S[None, :]) @ g["V"][rows].T
+    Wo = (np.array(gold["U_rows"]) * np.array(gold["S"])[None, :]) @ np.array(gold["V_rows"]).T
+    err = np.max(np.abs(Wg - Wo)) / np.max(np.abs(Wo))
+    print(f"  sampled entries max rel err {err:.2e}")
+    assert err <= 1e-9
