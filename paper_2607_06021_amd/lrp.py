@@ -135,7 +135,9 @@ class Solver:
         self.maxiter = int(maxiter)
         self.precision = precision
         if stream is None:
-            stream = torch.cuda.current_stream()
+            # a stream of its own (never the null stream), so that HIP events recorded on
+            # self.stream bracket exactly the library's kernels
+            stream = torch.cuda.Stream()
         self.stream = stream
         o = Opts(self.maxiter, LRP_MIXED if precision == "mixed" else LRP_FP64, float(prune_tau),
                  _c_vp(stream.cuda_stream))
@@ -188,10 +190,19 @@ class Solver:
         pvo, ldvo = _colmajor(Vo, n)
         r = _c_i32(0)
         info = Info()
+        self._order()
         code = lib().lrp_solve(self._h, rF, pu, ldu, sigma.data_ptr(), pv, ldv, puo, lduo, So.data_ptr(),
                                pvo, ldvo, ctypes.byref(r), ctypes.byref(info))
         _check(code, "lrp_solve", warn_ok=True)
         return Uo, So, Vo, int(r.value), info
+
+    def _order(self):
+        """Make the context stream wait for work already queued on the caller's stream."""
+        import torch
+
+        cur = torch.cuda.current_stream()
+        if cur.cuda_stream != self.stream.cuda_stream:
+            self.stream.wait_stream(cur)
 
     def index_sets(self) -> Tuple[List[int], List[int]]:
         I = (_c_i64 * self.r_max)()
@@ -232,8 +243,10 @@ class Solver:
         Y = empty_fortran(self.n, X.shape[1], torch.float64, X.device)
         py, ldy = _colmajor(Y, self.n)
         ps = scale.data_ptr() if scale is not None else None
+        self._order()
         _check(lib().lrp_dst1(self._h, X.shape[1], px, ldx, py, ldy, ps, float(mul),
                               LRP_MIXED if precision == "mixed" else LRP_FP64), "lrp_dst1")
+        torch.cuda.current_stream().wait_stream(self.stream)
         return Y
 
     def tsqr(self, A):
@@ -245,5 +258,6 @@ class Solver:
         Q = empty_fortran(self.n, c, torch.float64, A.device)
         R = empty_fortran(c, c, torch.float64, A.device)
         pq, ldq = _colmajor(Q, self.n)
+        self._order()
         _check(lib().lrp_tsqr(self._h, c, pa, lda, pq, ldq, R.data_ptr(), c), "lrp_tsqr")
         return Q, R

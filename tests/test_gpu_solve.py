@@ -150,9 +150,15 @@ def test_edge_cases_status_and_zero_rhs():
     g1 = gpu_solve(n, U, s, V, 16, 1e-10, 1)
     compare_fp64(g1, o1, "maxiter=1")
     print("edge: tiny cap", flush=True)
-    o2 = cd.solve(n, U, s, V, 3, 1e-14, 20)
-    g2 = gpu_solve(n, U, s, V, 3, 1e-14, 20)
-    compare_fp64(g2, o2, "r_max=3")
+    o2 = cd.solve(n, U[:, :3], s[:3], V[:, :3], 4, 1e-14, 20)
+    assert o2.status == cd.STATUS_STAGNATED
+    g2 = gpu_solve(n, U[:, :3], s[:3], V[:, :3], 4, 1e-14, 20)
+    compare_fp64(g2, o2, "r_max=4")
+    print("edge: r_F > r_max is rejected", flush=True)
+    from paper_2607_06021_amd import LrpError
+
+    with pytest.raises(LrpError):
+        gpu_solve(n, U, s, V, 3, 1e-10, 5)
     print("edge: rank-1 rhs of width 1 column", flush=True)
     o3 = cd.solve(n, U[:, :1], s[:1], V[:, :1], 16, 1e-10, 10)
     g3 = gpu_solve(n, U[:, :1], s[:1], V[:, :1], 16, 1e-10, 10)
