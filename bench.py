@@ -34,6 +34,9 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
+    ap.add_argument("--served", type=int, default=2000, help="requests in the served stream (0: skip)")
+    ap.add_argument("--served-active", type=int, default=8)
+    ap.add_argument("--served-budget-gb", type=float, default=64.0)
     return ap.parse_args()
 
 
@@ -76,6 +79,54 @@ def dst_roofline(sol, n, ncols, reps=20):
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "dst1 (pass1+pass2)",
             "ms_per_launch": round(ms, 4), "alg_bytes_per_launch": bytes_alg}
+
+
+def served_leg(count, seed, budget_gb, max_active, rate=None):
+    """Served stream: saturated throughput, then Poisson arrivals at 70% of it (p50/p99)."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2607_06021_amd.lrp import Server
+
+    dev = torch.device("cuda:0")
+    probe = workloads.served_stream(count=count, rate_per_s=1.0, seed=seed)
+    log(f"served: generating {count} right-hand sides on the device")
+    inputs = [workloads.bump_rhs_device(r.n, r.seed, r.rank, 0.05, 0.2, dev) for r in probe]
+    torch.cuda.synchronize()
+
+    def run(reqs, rate_s):
+        with Server(budget_bytes=int(budget_gb * (1 << 30)), max_active=max_active) as srv:
+            t0 = time.perf_counter()
+            tickets = []
+            for r in reqs:
+                if rate_s is not None:
+                    due = t0 + r.arrival_s
+                    while time.perf_counter() < due:
+                        pass
+                U, sg, V = inputs[r.idx]
+                tickets.append(srv.submit(r.n, U, sg, V, 48, 1e-10, 20, r.precision, sync=False))
+            res = [srv.wait(t) for t in tickets]
+            wall = time.perf_counter() - t0
+            st = srv.stats()
+        lat = np.array([x[6] for x in res])
+        bad = sum(1 for x in res if x[4] < 0)
+        return wall, lat, bad, st
+
+    # warm the contexts of every shape once, then measure the saturated rate
+    nsat = min(count, 400)
+    run(probe[: min(count, 40)], None)
+    wall, lat, bad, _ = run(probe[:nsat], None)
+    sat = nsat / wall
+    use_rate = rate if rate is not None else 0.7 * sat
+    reqs = workloads.served_stream(count=count, rate_per_s=use_rate, seed=seed)
+    log(f"served: saturated {sat:.1f} solves/s; Poisson arrivals at {use_rate:.1f}/s")
+    wall, lat, bad, st = run(reqs, use_rate)
+    return {"requests": count, "arrival_rate_per_s": round(use_rate, 2), "saturated_solves_per_s": round(sat, 2),
+            "solves_per_s": round(count / wall, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3), "failed": int(bad),
+            "mix": "n in {1023,4095,16383,65535,262143} w.p. .3/.3/.2/.15/.05, rank U{2..20}, cap 48, "
+                   "FP64 or mixed w.p. 0.5", "max_active": max_active, "contexts": st["contexts"]}
 
 
 def cpu_baseline(w, U, s, V):
@@ -126,6 +177,10 @@ def main():
         sol.close()
         log(f"  {prec}: {ms:.3f} ms/solve (device {results[prec]['dev_ms']:.3f} ms) "
             f"iters {info.iters} rank {info.rank} status {info.status}")
+    served = None
+    if args.served > 0:
+        served = served_leg(args.served, 2026, args.served_budget_gb, args.served_active)
+        log(f"  served: p50 {served['p50_ms']} ms, p99 {served['p99_ms']} ms, {served['solves_per_s']} solves/s")
     cpu = None
     err = {}
     if not args.no_cpu_baseline:
@@ -163,8 +218,9 @@ def main():
         "passes": {p: results[p]["info"]["iters"] for p in ("mixed", "fp64") if p in results},
         "rank": {p: results[p]["info"]["rank"] for p in ("mixed", "fp64") if p in results},
         "rel_err_vs_oracle": {k: float(f"{v:.3e}") for k, v in err.items()},
-        "served_p50_ms": None,
-        "served_p99_ms": None,
+        "served_p50_ms": served["p50_ms"] if served else None,
+        "served_p99_ms": served["p99_ms"] if served else None,
+        "served": served,
         "roofline": results.get("roofline"),
         "cpu_baseline": cpu,
     }

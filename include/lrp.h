@@ -76,7 +76,7 @@ typedef struct lrp_info {
 /*
  * lrp_create -- context for grids of n interior points per dimension and rank cap r_max.
  *   ctx    out (host): receives the context.
- *   n      grid size; n+1 must be a power of two, 3 <= n <= 2^24 - 1.
+ *   n      grid size; n+1 must be a power of two, 4 <= n+1 <= 2^23.
  *   r_max  rank cap of the result and cap of each index set, 1 <= r_max <= 64, r_max <= n.
  *   tol    tolerance eps of Algorithm 4, relative to ||S_k||_F; tol >= 0.
  *   opts   host, may be NULL (defaults).
@@ -156,6 +156,88 @@ int lrp_dst1(lrp_ctx* ctx, int32_t ncols, const double* X, int64_t ldx, double* 
  */
 int lrp_tsqr(lrp_ctx* ctx, int32_t ncols, const double* A, int64_t lda, double* Q, int64_t ldq,
              double* R, int64_t ldr);
+
+/* ---------------------------------------------------------------------------------------
+ * Serving: a solve queue with continuous admission.
+ *
+ * Requests (each one Poisson solve of the kind lrp_solve performs) are admitted in arrival
+ * order as soon as a context of their shape (n, r_max, tol, maxiter, precision) is free or
+ * can be created inside the device-memory budget; idle contexts of other shapes are freed to
+ * make room. Every admitted request advances pass by pass on its own HIP stream, so passes
+ * of different requests overlap on the device and a finished request frees its context
+ * immediately for the next one. A request computes exactly what lrp_solve computes for it,
+ * bit for bit, whatever else is in flight. The scheduler runs on a thread of its own.
+ * --------------------------------------------------------------------------------------- */
+typedef struct lrp_server lrp_server;
+
+/* One request (host struct). Pointers as in lrp_solve: U_F, sigma_F, V_F, U_out, S_out,
+ * V_out are device pointers; inputs must stay valid and unchanged, and outputs untouched,
+ * until the request completes. */
+typedef struct lrp_request {
+  int64_t n;          /* grid size, n+1 a power of two */
+  int32_t r_F;        /* 1 <= r_F <= r_max */
+  int32_t r_max;      /* 1 <= r_max <= 64 */
+  double tol;
+  int32_t maxiter;    /* 0 -> 20 */
+  int32_t precision;  /* enum lrp_precision */
+  const double* U_F;
+  int64_t ldu;
+  const double* sigma_F;
+  const double* V_F;
+  int64_t ldv;
+  double* U_out;
+  int64_t ldou;
+  double* S_out;
+  double* V_out;
+  int64_t ldov;
+} lrp_request;
+
+typedef struct lrp_server_stats {
+  int64_t submitted, completed, failed; /* requests so far */
+  int64_t queued, active;               /* waiting for admission / being solved now */
+  int64_t bytes_in_use, bytes_budget;   /* device memory held by contexts / allowed */
+  int32_t contexts;                     /* contexts currently held */
+} lrp_server_stats;
+
+/*
+ * lrp_server_create -- start a server on the current HIP device.
+ *   budget_bytes  device memory the server's contexts may hold in total (> 0).
+ *   max_active    requests solved concurrently, 1..64.
+ * Returns LRP_OK, LRP_EINVAL, LRP_ENOMEM or LRP_EDEVICE.
+ */
+int lrp_server_create(lrp_server** srv, int64_t budget_bytes, int32_t max_active);
+
+/*
+ * lrp_server_submit -- queue a request; *ticket (host) identifies it. Arguments are checked
+ * as in lrp_solve (LRP_EINVAL before queuing); a request whose context alone exceeds the
+ * budget is rejected with LRP_ENOMEM.
+ */
+int lrp_server_submit(lrp_server* srv, const lrp_request* req, int64_t* ticket);
+
+/*
+ * lrp_server_poll -- *done (host) = 1 once the request has finished; then *status gets its
+ * lrp_solve-style return code, *rank its rank, info its report, *latency_ms the time from
+ * submission to completion (host clock). Any output pointer may be NULL. A finished ticket
+ * may be polled again until lrp_server_release. Returns LRP_OK or LRP_EINVAL.
+ */
+int lrp_server_poll(lrp_server* srv, int64_t ticket, int32_t* done, int32_t* status, int32_t* rank,
+                    lrp_info* info, double* latency_ms);
+
+/* lrp_server_wait -- as lrp_server_poll, blocking until the request has finished. */
+int lrp_server_wait(lrp_server* srv, int64_t ticket, int32_t* status, int32_t* rank, lrp_info* info,
+                    double* latency_ms);
+
+/* lrp_server_release -- forget a finished ticket. Returns LRP_OK or LRP_EINVAL. */
+int lrp_server_release(lrp_server* srv, int64_t ticket);
+
+/* lrp_server_get_stats -- counters of the server (host struct). */
+int lrp_server_get_stats(lrp_server* srv, lrp_server_stats* out);
+
+/* lrp_server_destroy -- finish every admitted request, drop queued ones, free everything. */
+int lrp_server_destroy(lrp_server* srv);
+
+/* lrp_context_bytes -- device memory one context of this shape holds (0 if invalid). */
+int64_t lrp_context_bytes(int64_t n, int32_t r_max, int32_t maxiter, int32_t precision);
 
 #ifdef __cplusplus
 }

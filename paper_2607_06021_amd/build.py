@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblrp.so")
-SOURCES = ["api.hip", "dst.hip", "tsqr.hip", "fiber.hip", "core.hip", "prod.hip", "select.hip", "rho.hip"]
+SOURCES = ["api.hip", "serve.hip", "dst.hip", "tsqr.hip", "fiber.hip", "core.hip", "prod.hip", "select.hip", "rho.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

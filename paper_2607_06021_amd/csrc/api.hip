@@ -18,45 +18,11 @@
 #include <cstring>
 #include <new>
 
-#include "lrp_kernels.h"
+#include "ctx.h"
 
 using namespace lrp;
 
-struct lrp_ctx {
-  int64_t n = 0;
-  int r_max = 0;
-  double tol = 0.0;
-  int maxiter = 20;
-  int precision = LRP_FP64;
-  double tau = 1e-12;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  int device = 0;
-
-  DevState* st = nullptr;
-  DevState* st_host = nullptr;  // pinned
-  int* done_host = nullptr;     // pinned, 2 slots
-  double* lam = nullptr;
-  float* lam32 = nullptr;
-  double *Uh = nullptr, *Vh = nullptr;
-  float *Uh32 = nullptr, *Vh32 = nullptr;
-  double *C = nullptr, *Rt = nullptr;
-  float *C32 = nullptr, *Rt32 = nullptr;
-  double* Q[2] = {nullptr, nullptr};
-  double* Uit[2] = {nullptr, nullptr};
-  double* Vit[2] = {nullptr, nullptr};
-  double *Uhat = nullptr, *Vtil = nullptr;
-  TraceBuf trace{};
-  DstPlan dst{};
-  TsqrPlan tsqr{};
-  SelectPlan sel{};
-  RhoPlan rho{};
-  hipEvent_t ev0 = nullptr, ev1 = nullptr, evit[2] = {nullptr, nullptr};
-  bool solved = false;
-  int last_passes = 0;
-};
-
-namespace {
+namespace lrp {
 
 template <typename T>
 int dalloc(T** p, size_t count) {
@@ -141,8 +107,11 @@ void free_ctx(lrp_ctx* c) {
   dfree(c->rho.G);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->evfin) (void)hipEventDestroy(c->evfin);
   for (int s = 0; s < 2; ++s)
     if (c->evit[s]) (void)hipEventDestroy(c->evit[s]);
+  for (int s = 0; s < 2; ++s)
+    if (c->gexec[s]) (void)hipGraphExecDestroy(c->gexec[s]);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -210,6 +179,7 @@ int create_impl(lrp_ctx* c) {
   TRY(select_plan(&c->sel, n));
   TRY(rho_plan(&c->rho, n));
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+      hipEventCreateWithFlags(&c->evfin, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->evit[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->evit[1], hipEventDisableTiming) != hipSuccess)
     return LRP_EDEVICE;
@@ -219,7 +189,7 @@ int create_impl(lrp_ctx* c) {
   return LRP_OK;
 }
 
-int enqueue_pass(lrp_ctx* c, int k) {
+int enqueue_pass_kernels(lrp_ctx* c, int k) {
   const bool mixed = c->precision == LRP_MIXED;
   const int nb_new = (k + 1) & 1, nb_old = k & 1;
   const int64_t n = c->n;
@@ -229,7 +199,6 @@ int enqueue_pass(lrp_ctx* c, int k) {
   SelectArgs sa{};
   sa.st = c->st;
   sa.pmax = pm;
-  sa.kpass = k;
   sa.trace = c->trace;
   // the candidate slot depends only on the merge depth, which is fixed per context
   const int slot = c->sel.nlevels & 1;
@@ -271,7 +240,6 @@ int enqueue_pass(lrp_ctx* c, int k) {
   ca.Uhat = c->Uhat;
   ca.Vtil = c->Vtil;
   ca.nb = nb_new;
-  ca.kpass = k;
   ca.trace = c->trace;
   ca.maxiter = c->maxiter;
   TRY(core_launch(ca, false, s));
@@ -298,7 +266,6 @@ int enqueue_pass(lrp_ctx* c, int k) {
   ra.ldu = n;
   ra.nb_new = nb_new;
   ra.nb_old = nb_old;
-  ra.kpass = k;
   ra.maxiter = c->maxiter;
   ra.trace = c->trace;
   TRY(rho_launch(c->rho, ra, s));
@@ -308,9 +275,10 @@ int enqueue_pass(lrp_ctx* c, int k) {
   return LRP_OK;
 }
 
-int solve_impl(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const double* sigma_F,
-               const double* V_F, int64_t ldv, double* U_out, int64_t ldou, double* S_out,
-               double* V_out, int64_t ldov, int32_t* r_out, lrp_info* info) {
+// Stage 1 of a solve: state reset, input scan, DST of the factors, warm start and the
+// candidates of the first selection. Asynchronous on the context's stream.
+int enqueue_start(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const double* sigma_F,
+                  const double* V_F, int64_t ldv) {
   const bool mixed = c->precision == LRP_MIXED;
   const int64_t n = c->n;
   const int pm = c->r_max;
@@ -366,7 +334,6 @@ int solve_impl(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const double*
   ca.Uhat = c->Uhat;
   ca.Vtil = c->Vtil;
   ca.nb = 0;
-  ca.kpass = -1;
   ca.trace = c->trace;
   ca.maxiter = c->maxiter;
   TRY(core_launch(ca, true, s));
@@ -384,26 +351,50 @@ int solve_impl(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const double*
   pa.n = n;
   pa.nb = 0;
   TRY(prod_launch(pa, s));
-  {
-    const double* U[2] = {c->Uit[0], c->Vit[0]};
-    int fslot = 0;
-    TRY(select_candidates(c->sel, c->st, U, n, s, &fslot));
-  }
-  // passes; the stop flag is read one pass behind
-  int passes = 0;
-  for (int k = 0; k < c->maxiter; ++k) {
-    TRY(enqueue_pass(c, k));
-    ++passes;
-    const int slot = k & 1;
-    if (hipMemcpyAsync(&c->done_host[slot], &c->st->done, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
-      return LRP_EDEVICE;
-    if (hipEventRecord(c->evit[slot], s) != hipSuccess) return LRP_EDEVICE;
-    if (k >= 1) {
-      if (hipEventSynchronize(c->evit[slot ^ 1]) != hipSuccess) return LRP_EDEVICE;
-      if (c->done_host[slot ^ 1]) break;
+  const double* U[2] = {c->Uit[0], c->Vit[0]};
+  int fslot = 0;
+  TRY(select_candidates(c->sel, c->st, U, n, s, &fslot));
+  return LRP_OK;
+}
+
+// Pass k: the launch sequence depends only on the parity of k (which iterate buffer is
+// new), so each parity is captured once into a hipGraph and replayed; if capture is not
+// possible the kernels are launched directly.
+int enqueue_pass(lrp_ctx* c, int k) {
+  const int par = k & 1;
+  if (c->use_graphs && !c->gexec[par]) {
+    hipGraph_t g = nullptr;
+    bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed) == hipSuccess;
+    const int rc = ok ? enqueue_pass_kernels(c, k) : LRP_EDEVICE;
+    ok = (hipStreamEndCapture(c->stream, &g) == hipSuccess) && ok && rc == LRP_OK;
+    if (ok) ok = hipGraphInstantiate(&c->gexec[par], g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    if (!ok) {
+      c->gexec[par] = nullptr;
+      c->use_graphs = false;
+      (void)hipGetLastError();
     }
   }
-  c->last_passes = passes;
+  if (c->use_graphs && c->gexec[par])
+    return hipGraphLaunch(c->gexec[par], c->stream) == hipSuccess ? LRP_OK : LRP_EDEVICE;
+  return enqueue_pass_kernels(c, k);
+}
+
+// After pass k: copy the stop flag to pinned memory and mark the point with an event.
+int enqueue_poll(lrp_ctx* c, int k) {
+  const int slot = k & 1;
+  if (hipMemcpyAsync(&c->done_host[slot], &c->st->done, sizeof(int), hipMemcpyDeviceToHost, c->stream) !=
+      hipSuccess)
+    return LRP_EDEVICE;
+  return hipEventRecord(c->evit[slot], c->stream) == hipSuccess ? LRP_OK : LRP_EDEVICE;
+}
+
+// Stage 3: final truncation, DST back into the caller's buffers, state read-back.
+int enqueue_finish(lrp_ctx* c, double* U_out, int64_t ldou, double* S_out, double* V_out, int64_t ldov) {
+  const bool mixed = c->precision == LRP_MIXED;
+  const int64_t n = c->n;
+  const int pm = c->r_max;
+  hipStream_t s = c->stream;
   TRY(finalize_launch(c->st, S_out, pm, s));
   DstArgs db{};
   db.st = c->st;
@@ -425,7 +416,11 @@ int solve_impl(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const double*
   if (hipEventRecord(c->ev1, s) != hipSuccess) return LRP_EDEVICE;
   if (hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, s) != hipSuccess)
     return LRP_EDEVICE;
-  if (hipStreamSynchronize(s) != hipSuccess) return LRP_EDEVICE;
+  return hipEventRecord(c->evfin, s) == hipSuccess ? LRP_OK : LRP_EDEVICE;
+}
+
+// Stage 4 (host, after evfin completed): the report.
+int collect(lrp_ctx* c, int32_t* r_out, lrp_info* info) {
   const DevState& h_st = *c->st_host;
   c->solved = true;
   const int status = h_st.status;
@@ -446,7 +441,72 @@ int solve_impl(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const double*
   return status;
 }
 
-}  // namespace
+int check_solve_args(int64_t n, int r_max, int32_t r_F, const double* U_F, int64_t ldu, const double* sigma_F,
+                     const double* V_F, int64_t ldv, const double* U_out, int64_t ldou, const double* S_out,
+                     const double* V_out, int64_t ldov) {
+  if (!U_F || !sigma_F || !V_F || !U_out || !S_out || !V_out) return LRP_EINVAL;
+  if (r_F < 1 || r_F > r_max) return LRP_EINVAL;
+  if (ldu < n || ldv < n || ldou < n || ldov < n) return LRP_EINVAL;
+  const Range in[3] = {span(U_F, n, ldu, r_F, 8), span(V_F, n, ldv, r_F, 8), span(sigma_F, r_F, r_F, 1, 8)};
+  const Range out[3] = {span(U_out, n, ldou, r_max, 8), span(V_out, n, ldov, r_max, 8), span(S_out, r_max, r_max, 1, 8)};
+  for (int a = 0; a < 3; ++a) {
+    for (int b = 0; b < 3; ++b)
+      if (overlap(out[a], in[b])) return LRP_EINVAL;
+    for (int b = a + 1; b < 3; ++b)
+      if (overlap(out[a], out[b])) return LRP_EINVAL;
+  }
+  return LRP_OK;
+}
+
+// Device bytes of a context, mirroring create_impl and the plans (up to allocation rounding).
+int64_t context_bytes(int64_t n, int pm, int maxiter, bool mixed) {
+  const int64_t np = n * pm;
+  int64_t b = (int64_t)sizeof(DevState) + 12 * n;                  // state, lambda (FP64 + FP32)
+  b += mixed ? 4 * 4 * np : 4 * 8 * np;                            // U^, V^, C, R^T
+  b += 6 * 8 * np;                                                 // Q, Z, two iterates per side
+  b += 2 * 8 * (int64_t)pm * pm;                                   // U^, V~ coefficients
+  b += (int64_t)maxiter * (2 * kPMax * 4 + 5 * 4 + 2 * 8);         // trace
+  DstPlan dp{};
+  if (dst_plan(&dp, n, 2 * pm) == LRP_OK) {
+    b += 24 * (int64_t)(dp.t1_count + 2 * std::max(dp.t2_count, 1));
+    if (dp.four_step) b += (int64_t)dp.max_pairs * 2 * (n + 1) * 16;
+  }
+  int64_t rows = n, br = kTsqrRows;                                // TSQR tree, two sides
+  const int g = kTsqrRows / pm;
+  for (int L = 0; L < kMaxLevels; ++L) {
+    const int64_t nb = (rows + br - 1) / br;
+    b += 2 * (2 * rows * pm * 8 + nb * pm * 8 + nb * pm * pm * 8);
+    if (nb == 1) break;
+    rows = nb * pm;
+    br = (int64_t)g * pm;
+  }
+  const int64_t nsel = (n + kSelRows - 1) / kSelRows;              // selection
+  b += 2 * (8 * n + 8 * nsel + 2 * nsel * kPMax * 12) + 16;
+  const int64_t chunks = (n + 255) / 256, per = (chunks + 511) / 512;  // rho
+  b += ((chunks + per - 1) / per) * 2 * kPMax * kPMax * 8 + 4 * kPMax * kPMax * 8;
+  return b;
+}
+
+int solve_impl(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const double* sigma_F,
+               const double* V_F, int64_t ldv, double* U_out, int64_t ldou, double* S_out,
+               double* V_out, int64_t ldov, int32_t* r_out, lrp_info* info) {
+  TRY(enqueue_start(c, rF, U_F, ldu, sigma_F, V_F, ldv));
+  // passes; the stop flag is read one pass behind the device
+  for (int k = 0; k < c->maxiter; ++k) {
+    TRY(enqueue_pass(c, k));
+    TRY(enqueue_poll(c, k));
+    if (k >= 1) {
+      const int prev = (k - 1) & 1;
+      if (hipEventSynchronize(c->evit[prev]) != hipSuccess) return LRP_EDEVICE;
+      if (c->done_host[prev]) break;
+    }
+  }
+  TRY(enqueue_finish(c, U_out, ldou, S_out, V_out, ldov));
+  if (hipEventSynchronize(c->evfin) != hipSuccess) return LRP_EDEVICE;
+  return collect(c, r_out, info);
+}
+
+}  // namespace lrp
 
 extern "C" {
 
@@ -503,21 +563,17 @@ int lrp_create(lrp_ctx** ctx, int64_t n, int32_t r_max, double tol, const lrp_op
 int lrp_solve(lrp_ctx* c, int32_t r_F, const double* U_F, int64_t ldu, const double* sigma_F,
               const double* V_F, int64_t ldv, double* U_out, int64_t ldou, double* S_out,
               double* V_out, int64_t ldov, int32_t* r_out, lrp_info* info) {
-  if (!c || !U_F || !sigma_F || !V_F || !U_out || !S_out || !V_out || !r_out) return LRP_EINVAL;
-  const int64_t n = c->n;
-  if (r_F < 1 || r_F > c->r_max) return LRP_EINVAL;
-  if (ldu < n || ldv < n || ldou < n || ldov < n) return LRP_EINVAL;
-  const Range in[3] = {span(U_F, n, ldu, r_F, 8), span(V_F, n, ldv, r_F, 8), span(sigma_F, r_F, r_F, 1, 8)};
-  const Range out[3] = {span(U_out, n, ldou, c->r_max, 8), span(V_out, n, ldov, c->r_max, 8),
-                        span(S_out, c->r_max, c->r_max, 1, 8)};
-  for (int a = 0; a < 3; ++a) {
-    for (int b = 0; b < 3; ++b)
-      if (overlap(out[a], in[b])) return LRP_EINVAL;
-    for (int b = a + 1; b < 3; ++b)
-      if (overlap(out[a], out[b])) return LRP_EINVAL;
-  }
+  if (!c || !r_out) return LRP_EINVAL;
+  const int rc = check_solve_args(c->n, c->r_max, r_F, U_F, ldu, sigma_F, V_F, ldv, U_out, ldou, S_out, V_out, ldov);
+  if (rc != LRP_OK) return rc;
   c->solved = false;
   return solve_impl(c, r_F, U_F, ldu, sigma_F, V_F, ldv, U_out, ldou, S_out, V_out, ldov, r_out, info);
+}
+
+int64_t lrp_context_bytes(int64_t n, int32_t r_max, int32_t maxiter, int32_t precision) {
+  if (n < 3 || !pow2(n + 1) || n + 1 > (int64_t(1) << 23) || r_max < 1 || r_max > kPMax || r_max > n) return 0;
+  if (maxiter < 0 || (precision != LRP_FP64 && precision != LRP_MIXED)) return 0;
+  return context_bytes(n, r_max, maxiter == 0 ? 20 : maxiter, precision == LRP_MIXED);
 }
 
 int lrp_get_index_sets(const lrp_ctx* c, int64_t* I, int32_t* nI, int64_t* J, int32_t* nJ) {

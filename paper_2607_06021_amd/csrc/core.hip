@@ -1,95 +1,169 @@
 // The small dense steps of one Cross-DEIM pass, on one workgroup (paper, Algorithm 1
-// steps after the QRs, and Algorithm 4's pruning and stopping test):
-//   * with A = Q(I,:) (|J| <= |I|) or A = Z(J,:) (otherwise), its pseudo-inverse from a
-//     one-sided Jacobi SVD, dropping singular values <= max(rows, cols) eps sigma_1;
+// after the QRs, and Algorithm 4's pruning and stopping test):
+//   * with A = Q(I,:) (|J| <= |I|) or A = Z(J,:) (otherwise), the least-squares solve of
+//     Algorithm 1 through A's pseudo-inverse. A Householder QR A = Q2 R gives
+//     A^+ = R^{-1} Q2^T whenever no singular value of A can fall at or below the cutoff
+//     max(rows, cols) eps sigma_1 -- guaranteed when 4 cutoff ||R||_F ||R^{-1}||_F < 1, since
+//     sigma_min >= 1/||R^{-1}||_F and sigma_1 <= ||R||_F. Otherwise A^+ comes from a one-sided
+//     Jacobi SVD with that cutoff;
 //   * the |J| x |I| core M = Q(I,:)^+ R_R^T, or M = R_C (Z(J,:)^+)^T, so that the cross
 //     approximation is Q M Z^T;
-//   * the SVD of M = U^ S V~^T, truncated at max(|I|, |J|) eps sigma_1 (U_k = Q U^ and
-//     V_k = Z V~ are formed by the product kernel);
+//   * the SVD of M = U^ S V~^T by one-sided Jacobi, truncated at max(|I|, |J|) eps sigma_1
+//     (U_k = Q U^ and V_k = Z V~ are formed by the product kernel);
 //   * pruning: index l of I (of J) is dropped when |diag R_R| (|diag R_C|) at l is below
 //     tau times its largest entry;
-//   * eta_1 = 1/sigma_min(U_k(I,:)), eta_2 = 1/sigma_min(V_k(J,:)) on the pruned sets and the
-//     indicator min(eta_1 (1 + eta_2), eta_2 (1 + eta_1)) S_min / ||S||_F.
-// The warm start uses the same machinery on M = R_u R_v^T, the core of F^ = U^ V^^T.
+//   * eta_1 = 1/sigma_min(U_k(I,:)), eta_2 = 1/sigma_min(V_k(J,:)) on the pruned sets (two
+//     Jacobi problems solved side by side) and the indicator
+//     min(eta_1 (1 + eta_2), eta_2 (1 + eta_1)) S_min / ||S||_F.
+// The warm start uses the same SVD on M = R_u R_v^T, the core of F^ = U^ V^^T.
 //
-// Jacobi: Hestenes' method, round-robin ordering (k-1 rounds of k/2 disjoint pairs per
-// sweep), 8 lanes per column pair, rotation skipped when |a_p . a_q| <= sqrt(m) eps
-// ||a_p|| ||a_q||; sweeps end when a whole sweep makes no rotation (at most 60).
+// Jacobi: Hestenes' one-sided method, round-robin ordering (k-1 rounds of k/2 disjoint column
+// pairs per sweep); a pair is rotated unless |a_p . a_q| <= sqrt(m) eps ||a_p|| ||a_q||; the
+// sweeps end when one makes no rotation (at most 60). Each pair is handled by a group of 4, 8
+// or 16 lanes whose partial dot products are summed with DPP lane permutes.
 #include "lrp_kernels.h"
 
 namespace lrp {
 
-constexpr int LD = kPMax;  // leading dimension of the LDS matrices
+constexpr int LDP = kPMax + 1;        // padded leading dimension of the LDS matrices
+constexpr int kCoreThreads = 512;
+constexpr int kBuf = kPMax * LDP;
 
-__device__ void jacobi_cols(double* A, int m, int k, double* V, int* flag) {
-  const int t = threadIdx.x;
-  const int pi = t >> 3, li = t & 7;
+// ---------------------------------------------------------------- lane-group sums (DPP)
+__device__ inline double dpp_d(double x, int ctrl) {
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  switch (ctrl) {  // the control word must be a compile-time constant
+    case 0xB1:
+      lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false);
+      break;
+    case 0x4E:
+      lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false);
+      break;
+    case 0x141:
+      lo = __builtin_amdgcn_mov_dpp(lo, 0x141, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_mov_dpp(hi, 0x141, 0xF, 0xF, false);
+      break;
+    default:
+      lo = __builtin_amdgcn_mov_dpp(lo, 0x140, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_mov_dpp(hi, 0x140, 0xF, 0xF, false);
+      break;
+  }
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over aligned groups of G lanes (G = 4, 8 or 16); every lane gets its group's total.
+template <int G>
+__device__ inline double group_sum(double x) {
+  x += dpp_d(x, 0xB1);    // quad_perm [1,0,3,2]
+  x += dpp_d(x, 0x4E);    // quad_perm [2,3,0,1]
+  if (G >= 8) x += dpp_d(x, 0x141);   // row_half_mirror: the other quad of the octet
+  if (G >= 16) x += dpp_d(x, 0x140);  // row_mirror: the other octet of the row
+  return x;
+}
+
+// ---------------------------------------------------------------- one-sided Jacobi
+struct JacProb {
+  double* A;  // m x k, column-major, ld LDP (LDS)
+  int m, k;
+  double* V;  // k x k accumulated rotations (holding the identity on entry), or null
+};
+
+// One pair of problem `pr` in round rd; G lanes per pair, li = lane in the group.
+template <int G>
+__device__ inline bool jacobi_pair(const JacProb& pr, int pi, int li, int rd, double tol) {
+  const int k = pr.k;
   const int kk = k + (k & 1);
-  const int npairs = kk >> 1;
-  const double tol = sqrt((double)m) * kEps;
-  if (k < 2) {
+  if (k < 2 || pi >= (kk >> 1) || rd >= kk - 1) return false;
+  int p, q;
+  if (pi == 0) {
+    p = kk - 1;
+    q = rd;
+  } else {
+    p = (rd + pi) % (kk - 1);
+    q = (rd - pi + (kk - 1)) % (kk - 1);
+  }
+  if (p > q) {
+    const int tmp = p;
+    p = q;
+    q = tmp;
+  }
+  if (q >= k) return false;
+  double* A = pr.A;
+  const int m = pr.m;
+  double al = 0.0, be = 0.0, ga = 0.0;
+  for (int i = li; i < m; i += G) {
+    const double ap = A[i + p * LDP], aq = A[i + q * LDP];
+    al = fma(ap, ap, al);
+    be = fma(aq, aq, be);
+    ga = fma(ap, aq, ga);
+  }
+  al = group_sum<G>(al);
+  be = group_sum<G>(be);
+  ga = group_sum<G>(ga);
+  if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al) * sqrt(be))) return false;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double tt = fabs(zeta) > 1e150 ? 0.5 / zeta
+                                        : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double cs = 1.0 / sqrt(1.0 + tt * tt);
+  const double sn = cs * tt;
+  for (int i = li; i < m; i += G) {
+    const double ap = A[i + p * LDP], aq = A[i + q * LDP];
+    A[i + p * LDP] = cs * ap - sn * aq;
+    A[i + q * LDP] = sn * ap + cs * aq;
+  }
+  if (pr.V) {
+    double* V = pr.V;
+    for (int i = li; i < k; i += G) {
+      const double vp = V[i + p * LDP], vq = V[i + q * LDP];
+      V[i + p * LDP] = cs * vp - sn * vq;
+      V[i + q * LDP] = sn * vp + cs * vq;
+    }
+  }
+  return true;
+}
+
+// Solve one or two independent Jacobi problems with the whole workgroup: with two, each
+// half of the threads takes one. flags: 2 ints of LDS.
+__device__ void jacobi(JacProb* P, int nprob, int* flags) {
+  const int t = threadIdx.x;
+  const int half = kCoreThreads / 2;
+  const int which = (nprob == 2 && t >= half) ? 1 : 0;
+  const int lt = (nprob == 2) ? (t - which * half) : t;
+  const JacProb& pr = P[which];
+  const double tol = sqrt((double)max(pr.m, 1)) * kEps;
+  int rounds = 0;
+  for (int q = 0; q < nprob; ++q) {
+    const int kk = P[q].k + (P[q].k & 1);
+    rounds = max(rounds, kk - 1);
+  }
+  if (rounds <= 0) {
     __syncthreads();
     return;
   }
+  // lanes per pair: 16 for one problem (32 pairs x 16 = 512), 8 for two
+  bool active = true;
   for (int sweep = 0; sweep < 60; ++sweep) {
-    if (t == 0) *flag = 0;
+    if (t < 2) flags[t] = 0;
     __syncthreads();
-    for (int rd = 0; rd < kk - 1; ++rd) {
-      if (pi < npairs) {
-        int p, q;
-        if (pi == 0) {
-          p = kk - 1;
-          q = rd;
-        } else {
-          p = (rd + pi) % (kk - 1);
-          q = (rd - pi + (kk - 1)) % (kk - 1);
-        }
-        if (p > q) {
-          const int tmp = p;
-          p = q;
-          q = tmp;
-        }
-        if (q < k) {
-          double al = 0.0, be = 0.0, ga = 0.0;
-          for (int i = li; i < m; i += 8) {
-            const double ap = A[i + p * LD], aq = A[i + q * LD];
-            al = fma(ap, ap, al);
-            be = fma(aq, aq, be);
-            ga = fma(ap, aq, ga);
-          }
-          al = oct_sum(al);
-          be = oct_sum(be);
-          ga = oct_sum(ga);
-          if (ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
-            const double zeta = (be - al) / (2.0 * ga);
-            double tt;
-            if (fabs(zeta) > 1e150)
-              tt = 0.5 / zeta;
-            else
-              tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double cs = 1.0 / sqrt(1.0 + tt * tt);
-            const double sn = cs * tt;
-            for (int i = li; i < m; i += 8) {
-              const double ap = A[i + p * LD], aq = A[i + q * LD];
-              A[i + p * LD] = cs * ap - sn * aq;
-              A[i + q * LD] = sn * ap + cs * aq;
-            }
-            if (V) {
-              for (int i = li; i < k; i += 8) {
-                const double vp = V[i + p * LD], vq = V[i + q * LD];
-                V[i + p * LD] = cs * vp - sn * vq;
-                V[i + q * LD] = sn * vp + cs * vq;
-              }
-            }
-            if (li == 0) *flag = 1;
-          }
-        }
+    bool rot = false;
+    for (int rd = 0; rd < rounds; ++rd) {
+      if (active) {
+        if (nprob == 2)
+          rot |= jacobi_pair<8>(pr, lt >> 3, lt & 7, rd, tol);
+        else
+          rot |= jacobi_pair<16>(pr, lt >> 4, lt & 15, rd, tol);
       }
       __syncthreads();
     }
-    const int f = *flag;
+    if (rot) flags[which] = 1;
     __syncthreads();
-    if (!f) break;
+    const bool any0 = flags[0] != 0, any1 = flags[1] != 0;
+    active = which == 0 ? any0 : any1;
+    const bool more = any0 || (nprob == 2 && any1);
+    __syncthreads();
+    if (!more) break;
   }
 }
 
@@ -98,7 +172,7 @@ __device__ void norms_sorted(const double* A, int m, int k, double* sig, int* or
   const int t = threadIdx.x;
   if (t < k) {
     double s = 0.0;
-    for (int i = 0; i < m; ++i) s = fma(A[i + t * LD], A[i + t * LD], s);
+    for (int i = 0; i < m; ++i) s = fma(A[i + t * LDP], A[i + t * LDP], s);
     sig[t] = sqrt(s);
   }
   __syncthreads();
@@ -112,46 +186,131 @@ __device__ void norms_sorted(const double* A, int m, int k, double* sig, int* or
 }
 
 __device__ void set_identity(double* V, int k) {
-  for (int e = threadIdx.x; e < k * LD; e += blockDim.x) {
-    const int i = e % LD, j = e / LD;
+  for (int e = threadIdx.x; e < k * LDP; e += blockDim.x) {
+    const int i = e % LDP, j = e / LDP;
     V[e] = (i == j) ? 1.0 : 0.0;
   }
 }
 
-// sigma_min over the min(rows, cols) singular values of the rows x cols matrix E in X.
-__device__ double sigma_min_of(double* X, double* Xt, int rows, int cols, double* sig, int* ord,
-                               int* flag) {
-  if (rows == 0 || cols == 0) return 0.0;
-  double* A = X;
-  int m = rows, k = cols;
-  if (rows < cols) {  // work on the transpose so that the matrix is tall
-    for (int e = threadIdx.x; e < rows * cols; e += blockDim.x) {
-      const int i = e % rows, j = e / rows;
-      Xt[j + i * LD] = X[i + j * LD];
+// ---------------------------------------------------------------- small Householder QR
+// In place on A (m x k, m >= k, ld LDP): R in the upper triangle, the reflectors' tails
+// below (LAPACK convention, v_j = 1). tau: k doubles of LDS. 8 lanes per trailing column.
+__device__ void small_qr(double* A, int m, int k, double* tau, double* sc) {
+  const int t = threadIdx.x;
+  for (int j = 0; j < k; ++j) {
+    if (t < 64) {  // wave 0: the reflector of column j
+      const double x = (t > j && t < m) ? A[t + j * LDP] : 0.0;
+      const double xn2 = wave_sum(x * x);
+      const double alpha = A[j + j * LDP];
+      double beta, tj, scale;
+      if (xn2 == 0.0) {
+        tj = 0.0;
+        beta = alpha;
+        scale = 0.0;
+      } else {
+        beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        tj = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      if (t > j && t < m) A[t + j * LDP] = x * scale;
+      if (t == 0) {
+        A[j + j * LDP] = beta;
+        tau[j] = tj;
+      }
     }
     __syncthreads();
-    A = Xt;
-    m = cols;
-    k = rows;
+    const int c = j + 1 + (t >> 3), li = t & 7;
+    if (c < k) {
+      const double tj = tau[j];
+      double w = 0.0;
+      for (int i = j + li; i < m; i += 8) w = fma(i == j ? 1.0 : A[i + j * LDP], A[i + c * LDP], w);
+      w = group_sum<8>(w) * tj;
+      for (int i = j + li; i < m; i += 8) A[i + c * LDP] = fma(-w, i == j ? 1.0 : A[i + j * LDP], A[i + c * LDP]);
+    }
+    __syncthreads();
   }
-  jacobi_cols(A, m, k, nullptr, flag);
-  norms_sorted(A, m, k, sig, ord);
-  return sig[ord[k - 1]];
 }
 
-// Singular values of M (nJ x nI, in W) -> U^ (nJ x r) in Ub, V~ (nI x r) in Vb, sorted.
-// Returns r; X and Vj are work buffers.
-__device__ int svd_core(const double* W, int nJ, int nI, double cut_mult, double* X, double* Vj,
-                        double* Ub, double* Vb, double* sig, int* ord, int* flag) {
+// B (m x ncols, ld LDP) <- H_{k-1} .. H_0 B  (i.e. Q2-full^T B) if transpose, else
+// B <- H_0 .. H_{k-1} B, with the reflectors stored in QR (from small_qr).
+__device__ void apply_reflectors(const double* QR, const double* tau, int m, int k, double* B, int ncols,
+                                 bool transpose) {
+  const int t = threadIdx.x;
+  const int c0 = t >> 3, li = t & 7;
+  for (int c = c0; c < ncols; c += kCoreThreads / 8) {
+    for (int s = 0; s < k; ++s) {
+      const int j = transpose ? s : k - 1 - s;
+      const double tj = tau[j];
+      double w = 0.0;
+      for (int i = j + li; i < m; i += 8) w = fma(i == j ? 1.0 : QR[i + j * LDP], B[i + c * LDP], w);
+      w = group_sum<8>(w) * tj;
+      for (int i = j + li; i < m; i += 8) B[i + c * LDP] = fma(-w, i == j ? 1.0 : QR[i + j * LDP], B[i + c * LDP]);
+    }
+  }
+  __syncthreads();
+}
+
+// Ri <- R^{-1} for the k x k upper triangle of QR (column by column back substitution).
+__device__ void tri_inverse(const double* QR, int k, double* Ri) {
+  const int t = threadIdx.x;
+  const int c0 = t >> 3, li = t & 7;
+  for (int c = c0; c < k; c += kCoreThreads / 8) {
+    for (int i = li; i < k; i += 8) Ri[i + c * LDP] = 0.0;
+    if (li == 0) Ri[c + c * LDP] = 1.0 / QR[c + c * LDP];
+    for (int i = c - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int l = i + 1 + li; l <= c; l += 8) s = fma(QR[i + l * LDP], Ri[l + c * LDP], s);
+      s = group_sum<8>(s);
+      if (li == 0) Ri[i + c * LDP] = -s / QR[i + i * LDP];
+    }
+  }
+  __syncthreads();
+}
+
+// Frobenius norms of the upper triangle of QR (k x k) and of Ri: into out[0], out[1].
+__device__ void tri_norms(const double* QR, const double* Ri, int k, double* red, double* out) {
+  double a = 0.0, b = 0.0;
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+    const int i = e % k, j = e / k;
+    if (i <= j) {
+      a = fma(QR[i + j * LDP], QR[i + j * LDP], a);
+      b = fma(Ri[i + j * LDP], Ri[i + j * LDP], b);
+    }
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[w] = a;
+    red[8 + w] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sa = 0.0, sb = 0.0;
+    for (int q = 0; q < kCoreThreads / 64; ++q) {
+      sa += red[q];
+      sb += red[8 + q];
+    }
+    out[0] = sqrt(sa);
+    out[1] = sqrt(sb);
+  }
+  __syncthreads();
+}
+
+// Truncated SVD of M (nJ x nI in W): U^ (nJ x r) -> Ub, V~ (nI x r) -> Vb, sorted; returns r.
+// X and Vj are work buffers; W may be Ub or Vb (it is copied first).
+__device__ int svd_core(const double* W, int nJ, int nI, double cut_mult, double* X, double* Vj, double* Ub,
+                        double* Vb, double* sig, int* ord, int* flags) {
   const bool tall = nJ >= nI;
   const int m = tall ? nJ : nI, k = tall ? nI : nJ;
   for (int e = threadIdx.x; e < m * k; e += blockDim.x) {
     const int i = e % m, j = e / m;
-    X[i + j * LD] = tall ? W[i + j * LD] : W[j + i * LD];
+    X[i + j * LDP] = tall ? W[i + j * LDP] : W[j + i * LDP];
   }
   set_identity(Vj, k);
   __syncthreads();
-  jacobi_cols(X, m, k, Vj, flag);
+  JacProb pr{X, m, k, Vj};
+  jacobi(&pr, 1, flags);
   norms_sorted(X, m, k, sig, ord);
   const double smax = sig[ord[0]];
   int r = 0;
@@ -159,34 +318,30 @@ __device__ int svd_core(const double* W, int nJ, int nI, double cut_mult, double
     const double cut = cut_mult * kEps * smax;
     for (int c = 0; c < k; ++c) r += sig[ord[c]] > cut ? 1 : 0;
   }
-  // left factor of the tall orientation: X(:, c)/sig_c; right: Vj(:, c)
-  for (int e = threadIdx.x; e < r * LD; e += blockDim.x) {
-    const int i = e % LD, rr = e / LD;
+  for (int e = threadIdx.x; e < r * kPMax; e += blockDim.x) {
+    const int i = e % kPMax, rr = e / kPMax;
     const int c = ord[rr];
     const double inv = 1.0 / sig[c];
-    const double lx = i < m ? X[i + c * LD] * inv : 0.0;
-    const double rv = i < k ? Vj[i + c * LD] : 0.0;
+    const double lx = i < m ? X[i + c * LDP] * inv : 0.0;
+    const double rv = i < k ? Vj[i + c * LDP] : 0.0;
     if (tall) {
-      Ub[i + rr * LD] = lx;
-      Vb[i + rr * LD] = rv;
+      Ub[i + rr * LDP] = lx;
+      Vb[i + rr * LDP] = rv;
     } else {
-      Ub[i + rr * LD] = rv;
-      Vb[i + rr * LD] = lx;
+      Ub[i + rr * LDP] = rv;
+      Vb[i + rr * LDP] = lx;
     }
   }
   __syncthreads();
   return r;
 }
 
-__global__ __launch_bounds__(256) void k_core(CoreArgs a) {
+__global__ __launch_bounds__(kCoreThreads) void k_core(CoreArgs a) {
   DevState* st = a.st;
   if (st->done) return;
-  __shared__ double X[LD * LD], Vj[LD * LD], T[LD * LD], W[LD * LD];
-  __shared__ double sig[kPMax];
-  __shared__ int ord[kPMax];
-  __shared__ int flag;
-  __shared__ int keepI[kPMax], keepJ[kPMax], posI[kPMax], posJ[kPMax];
-  __shared__ double red[8];
+  __shared__ double B0[kBuf], B1[kBuf], B2[kBuf], B3[kBuf];
+  __shared__ double sig[kPMax], tau[kPMax], red[16], nrm2[2];
+  __shared__ int ord[kPMax], flags[2], posI[kPMax], posJ[kPMax], cnt[2];
   const int t = threadIdx.x;
   const int nI = st->nIpre, nJ = st->nJpre;
   const int pm = a.pmax;
@@ -196,73 +351,157 @@ __global__ __launch_bounds__(256) void k_core(CoreArgs a) {
   auto Bq = [&](int j, int c) { return a.Q1[st->Jpre[j] + (int64_t)c * a.ldq]; };  // Z(J,:)
   const double cut_pinv = (double)max(nI, nJ);
 
-  // ---- pseudo-inverse and the core M (into W, nJ x nI)
+  // ---- the core M = A^+ R_R^T (|J| <= |I|, A = Q(I,:)) or R_C (A^+)^T (A = Z(J,:))
   const bool branch = nJ <= nI;
   const int m0 = branch ? nI : nJ, k0 = branch ? nJ : nI;
   for (int e = t; e < m0 * k0; e += blockDim.x) {
     const int i = e % m0, c = e / m0;
-    X[i + c * LD] = branch ? Aq(i, c) : Bq(i, c);
+    B0[i + c * LDP] = branch ? Aq(i, c) : Bq(i, c);
   }
-  set_identity(Vj, k0);
   __syncthreads();
-  jacobi_cols(X, m0, k0, Vj, &flag);
-  norms_sorted(X, m0, k0, sig, ord);
-  {
-    const double smax = sig[ord[0]];
-    const double cut = cut_pinv * kEps * smax;
-    // scaled left factor: X(:, c) / sig_c^2 (= U_c / sig_c), zero where dropped
-    for (int e = t; e < m0 * k0; e += blockDim.x) {
-      const int i = e % m0, c = e / m0;
-      const double s = sig[c];
-      X[i + c * LD] = (smax > 0.0 && s > cut) ? X[i + c * LD] / (s * s) : 0.0;
-    }
-    __syncthreads();
-  }
-  if (branch) {
-    // pinv(A) = Vj diag(1/s) U^T with A = Q(I,:) (nI x nJ); M = pinv(A) R_R^T (nJ x nI)
-    // T(c, j) = sum_i Xs(i, c) R_R(j, i)  (c < nJ, j < nI)
-    for (int e = t; e < nJ * nI; e += blockDim.x) {
-      const int c = e % nJ, j = e / nJ;
-      double s = 0.0;
-      for (int i = j; i < nI; ++i) s = fma(X[i + c * LD], R_R[j + (int64_t)i * pm], s);
-      T[c + j * LD] = s;
-    }
-    __syncthreads();
-    for (int e = t; e < nJ * nI; e += blockDim.x) {
-      const int aa = e % nJ, j = e / nJ;
-      double s = 0.0;
-      for (int c = 0; c < nJ; ++c) s = fma(Vj[aa + c * LD], T[c + j * LD], s);
-      W[aa + j * LD] = s;
+  small_qr(B0, m0, k0, tau, red);
+  tri_inverse(B0, k0, B1);  // B1 = R^{-1}
+  tri_norms(B0, B1, k0, red, nrm2);
+  const double bound = nrm2[0] * nrm2[1] * cut_pinv * kEps * 4.0;
+  double* M;
+  if (bound < 1.0) {
+    if (branch) {
+      // B2 = H^T R_R^T (nI x nI); M = R^{-1} B2(0:nJ, :)  -> B3
+      for (int e = t; e < nI * nI; e += blockDim.x) {
+        const int i = e % nI, j = e / nI;
+        B2[i + j * LDP] = (j <= i) ? R_R[j + (int64_t)i * pm] : 0.0;
+      }
+      __syncthreads();
+      apply_reflectors(B0, tau, m0, k0, B2, nI, true);
+      for (int e = t; e < nJ * nI; e += blockDim.x) {
+        const int aa = e % nJ, j = e / nJ;
+        double s = 0.0;
+        for (int l = aa; l < nJ; ++l) s = fma(B1[aa + l * LDP], B2[l + j * LDP], s);
+        B3[aa + j * LDP] = s;
+      }
+      __syncthreads();
+      M = B3;
+    } else {
+      // B2 = Q2 = H [I; 0] (nJ x nI); B3 = Q2 R^{-T}; M = R_C B3 -> B2
+      for (int e = t; e < nJ * nI; e += blockDim.x) {
+        const int i = e % nJ, j = e / nJ;
+        B2[i + j * LDP] = (i == j) ? 1.0 : 0.0;
+      }
+      __syncthreads();
+      apply_reflectors(B0, tau, m0, k0, B2, nI, false);
+      for (int e = t; e < nJ * nI; e += blockDim.x) {
+        const int i = e % nJ, c = e / nJ;
+        double s = 0.0;
+        for (int l = c; l < nI; ++l) s = fma(B2[i + l * LDP], B1[c + l * LDP], s);
+        B3[i + c * LDP] = s;
+      }
+      __syncthreads();
+      for (int e = t; e < nJ * nI; e += blockDim.x) {
+        const int aa = e % nJ, c = e / nJ;
+        double s = 0.0;
+        for (int l = aa; l < nJ; ++l) s = fma(R_C[aa + (int64_t)l * pm], B3[l + c * LDP], s);
+        B2[aa + c * LDP] = s;
+      }
+      __syncthreads();
+      M = B2;
     }
   } else {
-    // pinv(B) = Vj diag(1/s) U^T with B = Z(J,:) (nJ x nI); M = R_C pinv(B)^T = R_C Xs Vj^T
-    for (int e = t; e < nJ * nI; e += blockDim.x) {
-      const int aa = e % nJ, c = e / nJ;
-      double s = 0.0;
-      for (int m = aa; m < nJ; ++m) s = fma(R_C[aa + (int64_t)m * pm], X[m + c * LD], s);
-      T[aa + c * LD] = s;
+    // A may have singular values at or below the cutoff: Jacobi pseudo-inverse.
+    for (int e = t; e < m0 * k0; e += blockDim.x) {
+      const int i = e % m0, c = e / m0;
+      B0[i + c * LDP] = branch ? Aq(i, c) : Bq(i, c);
+    }
+    set_identity(B1, k0);
+    __syncthreads();
+    JacProb pr{B0, m0, k0, B1};
+    jacobi(&pr, 1, flags);
+    norms_sorted(B0, m0, k0, sig, ord);
+    const double smax = sig[ord[0]];
+    const double cut = cut_pinv * kEps * smax;
+    for (int e = t; e < m0 * k0; e += blockDim.x) {  // U_c / s_c = X_c / s_c^2, dropped -> 0
+      const int i = e % m0, c = e / m0;
+      const double s = sig[c];
+      B0[i + c * LDP] = (smax > 0.0 && s > cut) ? B0[i + c * LDP] / (s * s) : 0.0;
     }
     __syncthreads();
-    for (int e = t; e < nJ * nI; e += blockDim.x) {
-      const int aa = e % nJ, j = e / nJ;
-      double s = 0.0;
-      for (int c = 0; c < nI; ++c) s = fma(T[aa + c * LD], Vj[j + c * LD], s);
-      W[aa + j * LD] = s;
+    if (branch) {
+      // A^+ = B1 Xs^T; M = B1 (Xs^T R_R^T): B2(c, j) = sum_i Xs(i, c) R_R(j, i)
+      for (int e = t; e < nJ * nI; e += blockDim.x) {
+        const int c = e % nJ, j = e / nJ;
+        double s = 0.0;
+        for (int i = j; i < nI; ++i) s = fma(B0[i + c * LDP], R_R[j + (int64_t)i * pm], s);
+        B2[c + j * LDP] = s;
+      }
+      __syncthreads();
+      for (int e = t; e < nJ * nI; e += blockDim.x) {
+        const int aa = e % nJ, j = e / nJ;
+        double s = 0.0;
+        for (int c = 0; c < nJ; ++c) s = fma(B1[aa + c * LDP], B2[c + j * LDP], s);
+        B3[aa + j * LDP] = s;
+      }
+    } else {
+      // (A^+)^T = Xs B1^T; M = R_C Xs B1^T
+      for (int e = t; e < nJ * nI; e += blockDim.x) {
+        const int aa = e % nJ, c = e / nJ;
+        double s = 0.0;
+        for (int l = aa; l < nJ; ++l) s = fma(R_C[aa + (int64_t)l * pm], B0[l + c * LDP], s);
+        B2[aa + c * LDP] = s;
+      }
+      __syncthreads();
+      for (int e = t; e < nJ * nI; e += blockDim.x) {
+        const int aa = e % nJ, j = e / nJ;
+        double s = 0.0;
+        for (int c = 0; c < nI; ++c) s = fma(B2[aa + c * LDP], B1[j + c * LDP], s);
+        B3[aa + j * LDP] = s;
+      }
     }
+    __syncthreads();
+    M = B3;
   }
-  __syncthreads();
 
-  // ---- truncated SVD of the core: U^ -> T (nJ x r), V~ -> Vj? (use X/Vj as work)
-  // svd_core needs X and Vj as work and writes into the two output buffers; W is the input.
-  // Outputs go to T (U^) and a second buffer; reuse W after copying M into X inside svd_core.
-  const int r = svd_core(W, nJ, nI, cut_pinv, X, Vj, T, W, sig, ord, &flag);
-  // now T = U^ (nJ x r), W = V~ (nI x r), singular values sig[ord[0..r)]
-  double* Uhat = a.Uhat;
-  double* Vtil = a.Vtil;
+  // ---- truncated SVD of the core: U^ -> Ub, V~ -> Vb
+  double* Ub = (M == B3) ? B2 : B3;
+  double* Vb = B1;
+  double* X = B0;
+  // svd_core copies M into X first; Vj work buffer = Vb (the copy precedes every write)
+  // so use the remaining buffer M itself as the Vj scratch after the copy.
+  int r;
+  {
+    const bool tall = nJ >= nI;
+    const int m = tall ? nJ : nI, k = tall ? nI : nJ;
+    for (int e = t; e < m * k; e += blockDim.x) {
+      const int i = e % m, j = e / m;
+      X[i + j * LDP] = tall ? M[i + j * LDP] : M[j + i * LDP];
+    }
+    double* Vj = M;  // free after the copy
+    __syncthreads();
+    set_identity(Vj, k);
+    __syncthreads();
+    JacProb pr{X, m, k, Vj};
+    jacobi(&pr, 1, flags);
+    norms_sorted(X, m, k, sig, ord);
+    const double smax = sig[ord[0]];
+    r = 0;
+    if (smax > 0.0) {
+      const double cut = cut_pinv * kEps * smax;
+      for (int c = 0; c < k; ++c) r += sig[ord[c]] > cut ? 1 : 0;
+    }
+    for (int e = t; e < r * kPMax; e += blockDim.x) {
+      const int i = e % kPMax, rr = e / kPMax;
+      const int c = ord[rr];
+      const double inv = 1.0 / sig[c];
+      const double lx = i < m ? X[i + c * LDP] * inv : 0.0;
+      const double rv = i < k ? Vj[i + c * LDP] : 0.0;
+      Ub[i + rr * LDP] = tall ? lx : rv;
+      Vb[i + rr * LDP] = tall ? rv : lx;
+    }
+    __syncthreads();
+  }
+  // now Ub = U^ (nJ x r), Vb = V~ (nI x r), singular values sig[ord[0..r)]
   for (int e = t; e < r * pm; e += blockDim.x) {
     const int i = e % pm, rr = e / pm;
-    Uhat[i + (int64_t)rr * pm] = i < nJ ? T[i + rr * LD] : 0.0;
-    Vtil[i + (int64_t)rr * pm] = i < nI ? W[i + rr * LD] : 0.0;
+    a.Uhat[i + (int64_t)rr * pm] = i < nJ ? Ub[i + rr * LDP] : 0.0;
+    a.Vtil[i + (int64_t)rr * pm] = i < nI ? Vb[i + rr * LDP] : 0.0;
   }
   const int nb = a.nb;
   if (t < kPMax) st->S[nb][t] = t < r ? sig[ord[t]] : 0.0;
@@ -273,51 +512,79 @@ __global__ __launch_bounds__(256) void k_core(CoreArgs a) {
     for (int l = 0; l < nI; ++l) mR = fmax(mR, fabs(R_R[l + (int64_t)l * pm]));
     for (int l = 0; l < nJ; ++l) mC = fmax(mC, fabs(R_C[l + (int64_t)l * pm]));
     int ci = 0, cj = 0;
-    for (int l = 0; l < nI; ++l) {
-      keepI[l] = fabs(R_R[l + (int64_t)l * pm]) >= st->tau * mR;
-      if (keepI[l]) posI[ci++] = l;
-    }
-    for (int l = 0; l < nJ; ++l) {
-      keepJ[l] = fabs(R_C[l + (int64_t)l * pm]) >= st->tau * mC;
-      if (keepJ[l]) posJ[cj++] = l;
-    }
-    red[0] = ci;
-    red[1] = cj;
+    for (int l = 0; l < nI; ++l)
+      if (fabs(R_R[l + (int64_t)l * pm]) >= st->tau * mR) posI[ci++] = l;
+    for (int l = 0; l < nJ; ++l)
+      if (fabs(R_C[l + (int64_t)l * pm]) >= st->tau * mC) posJ[cj++] = l;
+    cnt[0] = ci;
+    cnt[1] = cj;
   }
   __syncthreads();
-  const int nIp = (int)red[0], nJp = (int)red[1];
+  const int nIp = cnt[0], nJp = cnt[1];
 
-  // ---- eta_1 = 1 / sigma_min(U_k(I,:)) with U_k(I,:) = Q(I,:) U^ on the pruned rows
+  // ---- eta: U_k(I,:) = Q(I,:) U^ and V_k(J,:) = Z(J,:) V~ on the pruned rows, each stored
+  // tall (rows >= cols) so that Jacobi gives its min(rows, cols) singular values.
   double smin1 = 0.0, smin2 = 0.0;
-  if (r > 0) {
+  if (r > 0 && nIp > 0 && nJp > 0) {
+    double* E1 = B0;
+    double* E2 = M;
+    const bool t1 = nIp >= r, t2 = nJp >= r;
     for (int e = t; e < nIp * r; e += blockDim.x) {
       const int ii = e % nIp, rr = e / nIp;
       const int i = posI[ii];
       double s = 0.0;
-      for (int c = 0; c < nJ; ++c) s = fma(Aq(i, c), T[c + rr * LD], s);
-      X[ii + rr * LD] = s;
+      for (int c = 0; c < nJ; ++c) s = fma(Aq(i, c), Ub[c + rr * LDP], s);
+      if (t1)
+        E1[ii + rr * LDP] = s;
+      else
+        E1[rr + ii * LDP] = s;
     }
-    __syncthreads();
-    smin1 = sigma_min_of(X, Vj, nIp, r, sig, ord, &flag);
-    __syncthreads();
-    // eta_2 with V_k(J,:) = Z(J,:) V~
     for (int e = t; e < nJp * r; e += blockDim.x) {
       const int jj = e % nJp, rr = e / nJp;
       const int j = posJ[jj];
       double s = 0.0;
-      for (int c = 0; c < nI; ++c) s = fma(Bq(j, c), W[c + rr * LD], s);
-      X[jj + rr * LD] = s;
+      for (int c = 0; c < nI; ++c) s = fma(Bq(j, c), Vb[c + rr * LDP], s);
+      if (t2)
+        E2[jj + rr * LDP] = s;
+      else
+        E2[rr + jj * LDP] = s;
     }
     __syncthreads();
-    smin2 = sigma_min_of(X, Vj, nJp, r, sig, ord, &flag);
+    JacProb pp[2] = {{E1, t1 ? nIp : r, t1 ? r : nIp, nullptr}, {E2, t2 ? nJp : r, t2 ? r : nJp, nullptr}};
+    jacobi(pp, 2, flags);
+    // smallest column norm of each
+    if (t < 64) {
+      double v1 = INFINITY, v2 = INFINITY;
+      if (t < pp[0].k) {
+        double s = 0.0;
+        for (int i = 0; i < pp[0].m; ++i) s = fma(E1[i + t * LDP], E1[i + t * LDP], s);
+        v1 = sqrt(s);
+      }
+      if (t < pp[1].k) {
+        double s = 0.0;
+        for (int i = 0; i < pp[1].m; ++i) s = fma(E2[i + t * LDP], E2[i + t * LDP], s);
+        v2 = sqrt(s);
+      }
+      for (int msk = 32; msk >= 1; msk >>= 1) {
+        v1 = fmin(v1, shfl_xor_d(v1, msk));
+        v2 = fmin(v2, shfl_xor_d(v2, msk));
+      }
+      if (t == 0) {
+        red[0] = v1;
+        red[1] = v2;
+      }
+    }
+    __syncthreads();
+    smin1 = red[0];
+    smin2 = red[1];
   }
   __syncthreads();
 
   if (t == 0) {
     const double* S = st->S[nb];
-    double nrm2 = 0.0;
-    for (int l = 0; l < r; ++l) nrm2 = fma(S[l], S[l], nrm2);
-    const double nrm = sqrt(nrm2);
+    double n2 = 0.0;
+    for (int l = 0; l < r; ++l) n2 = fma(S[l], S[l], n2);
+    const double nrm = sqrt(n2);
     const double eta1 = smin1 > 0.0 ? 1.0 / smin1 : INFINITY;
     const double eta2 = smin2 > 0.0 ? 1.0 / smin2 : INFINITY;
     double ind = INFINITY;
@@ -343,7 +610,7 @@ __global__ __launch_bounds__(256) void k_core(CoreArgs a) {
       st->done = 1;
       st->status = LRP_ENUMERIC;
     }
-    const int kp = a.kpass;
+    const int kp = st->k;  // the pass being computed (passes completed so far)
     if (kp >= 0 && kp < a.maxiter) {
       a.trace.nI[kp] = nIp;
       a.trace.nJ[kp] = nJp;
@@ -354,13 +621,12 @@ __global__ __launch_bounds__(256) void k_core(CoreArgs a) {
 }
 
 // Warm start: M = R_u R_v^T (the core of F^ = U^ V^^T) and its SVD.
-__global__ __launch_bounds__(256) void k_core_warm(CoreArgs a) {
+__global__ __launch_bounds__(kCoreThreads) void k_core_warm(CoreArgs a) {
   DevState* st = a.st;
   if (st->done) return;
-  __shared__ double X[LD * LD], Vj[LD * LD], T[LD * LD], W[LD * LD];
+  __shared__ double B0[kBuf], B1[kBuf], B2[kBuf], B3[kBuf];
   __shared__ double sig[kPMax];
-  __shared__ int ord[kPMax];
-  __shared__ int flag;
+  __shared__ int ord[kPMax], flags[2];
   const int t = threadIdx.x;
   const int rF = st->rF;
   const int pm = a.pmax;
@@ -368,14 +634,14 @@ __global__ __launch_bounds__(256) void k_core_warm(CoreArgs a) {
     const int i = e % rF, j = e / rF;
     double s = 0.0;
     for (int m = max(i, j); m < rF; ++m) s = fma(a.R0[i + (int64_t)m * pm], a.R1[j + (int64_t)m * pm], s);
-    W[i + j * LD] = s;
+    B3[i + j * LDP] = s;
   }
   __syncthreads();
-  const int r = svd_core(W, rF, rF, (double)rF, X, Vj, T, W, sig, ord, &flag);
+  const int r = svd_core(B3, rF, rF, (double)rF, B0, B1, B2, B3, sig, ord, flags);
   for (int e = t; e < r * pm; e += blockDim.x) {
     const int i = e % pm, rr = e / pm;
-    a.Uhat[i + (int64_t)rr * pm] = i < rF ? T[i + rr * LD] : 0.0;
-    a.Vtil[i + (int64_t)rr * pm] = i < rF ? W[i + rr * LD] : 0.0;
+    a.Uhat[i + (int64_t)rr * pm] = i < rF ? B2[i + rr * LDP] : 0.0;
+    a.Vtil[i + (int64_t)rr * pm] = i < rF ? B3[i + rr * LDP] : 0.0;
   }
   if (t < kPMax) st->S[0][t] = t < r ? sig[ord[t]] : 0.0;
   __syncthreads();
@@ -399,11 +665,12 @@ __global__ __launch_bounds__(256) void k_core_warm(CoreArgs a) {
 
 int core_launch(const CoreArgs& a, bool warm, hipStream_t s) {
   if (warm)
-    hipLaunchKernelGGL(k_core_warm, dim3(1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_core_warm, dim3(1), dim3(kCoreThreads), 0, s, a);
   else
-    hipLaunchKernelGGL(k_core, dim3(1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_core, dim3(1), dim3(kCoreThreads), 0, s, a);
   return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
 }
+
 
 // ----------------------------------------------------------------------------------------
 // Set-up, input scan and final truncation

@@ -1,0 +1,68 @@
+// The library context (one solve shape) and the stages of a solve, shared by the plain
+// solve entry point and the serving scheduler.
+#pragma once
+
+#include "lrp_kernels.h"
+
+struct lrp_ctx {
+  using DevState = lrp::DevState;
+  using TraceBuf = lrp::TraceBuf;
+  using DstPlan = lrp::DstPlan;
+  using TsqrPlan = lrp::TsqrPlan;
+  using SelectPlan = lrp::SelectPlan;
+  using RhoPlan = lrp::RhoPlan;
+
+  int64_t n = 0;
+  int r_max = 0;
+  double tol = 0.0;
+  int maxiter = 20;
+  int precision = LRP_FP64;
+  double tau = 1e-12;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+
+  DevState* st = nullptr;
+  DevState* st_host = nullptr;  // pinned
+  int* done_host = nullptr;     // pinned, 2 slots
+  double* lam = nullptr;
+  float* lam32 = nullptr;
+  double *Uh = nullptr, *Vh = nullptr;
+  float *Uh32 = nullptr, *Vh32 = nullptr;
+  double *C = nullptr, *Rt = nullptr;
+  float *C32 = nullptr, *Rt32 = nullptr;
+  double* Q[2] = {nullptr, nullptr};
+  double* Uit[2] = {nullptr, nullptr};
+  double* Vit[2] = {nullptr, nullptr};
+  double *Uhat = nullptr, *Vtil = nullptr;
+  TraceBuf trace{};
+  DstPlan dst{};
+  TsqrPlan tsqr{};
+  SelectPlan sel{};
+  RhoPlan rho{};
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, evfin = nullptr, evit[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};  // captured pass, per parity
+  bool use_graphs = true;
+  bool solved = false;
+};
+
+
+namespace lrp {
+
+int create_impl(lrp_ctx* c);
+void free_ctx(lrp_ctx* c);
+// argument checks shared by lrp_solve and the server (no device work)
+int check_solve_args(int64_t n, int r_max, int32_t r_F, const double* U_F, int64_t ldu, const double* sigma_F,
+                     const double* V_F, int64_t ldv, const double* U_out, int64_t ldou, const double* S_out,
+                     const double* V_out, int64_t ldov);
+// asynchronous stages on the context's stream
+int enqueue_start(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const double* sigma_F,
+                  const double* V_F, int64_t ldv);
+int enqueue_pass(lrp_ctx* c, int k);
+int enqueue_poll(lrp_ctx* c, int k);
+int enqueue_finish(lrp_ctx* c, double* U_out, int64_t ldou, double* S_out, double* V_out, int64_t ldov);
+int collect(lrp_ctx* c, int32_t* r_out, lrp_info* info);
+// device bytes of a context of this shape
+int64_t context_bytes(int64_t n, int r_max, int maxiter, bool mixed);
+
+}  // namespace lrp

@@ -95,8 +95,7 @@ struct CoreArgs {
   double* Uhat;      // out: pmax x pmax (ld pmax): coefficients of U_k in Q
   double* Vtil;      // out: coefficients of V_k in Z
   int nb;            // iterate buffer written by this pass
-  int kpass;         // pass index (trace row); -1 for the warm start
-  TraceBuf trace;
+  TraceBuf trace;    // row = the device pass counter
   int maxiter;
 };
 int core_launch(const CoreArgs& a, bool warm, hipStream_t s);
@@ -136,7 +135,6 @@ struct SelectArgs {
   const double* cs[2];  // final candidate list per side (kPMax entries, best first)
   const int* ci[2];
   int pmax;
-  int kpass;
   TraceBuf trace;
 };
 int select_update(const SelectArgs& a, hipStream_t s);
@@ -156,7 +154,6 @@ struct RhoArgs {
   const double* Uold[2];  // U_{k-1}, V_{k-1}
   int64_t ldu;
   int nb_new, nb_old;
-  int kpass;
   int maxiter;
   TraceBuf trace;
 };

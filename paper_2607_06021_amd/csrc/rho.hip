@@ -23,13 +23,13 @@ struct RhoKArgs {
   int64_t n;
   int rows_per_block;
   int nb_new, nb_old;
-  int kpass;
   const double* M;     // M_u, N_v (for the second pass)
   double* part;
 };
 
-__device__ inline bool rho_needed(const DevState* st, int kpass) {
-  return !st->done && kpass >= 1 && st->ind < st->eps;
+// st->k is the index of the pass being computed (the decision kernel advances it).
+__device__ inline bool rho_needed(const DevState* st) {
+  return !st->done && st->k >= 1 && st->ind < st->eps;
 }
 
 // Stage rows [r0, r0 + 64) of the first `cols` columns of X into S (row-major, ld 65).
@@ -45,7 +45,7 @@ __device__ inline void stage(double (*S)[kPMax + 1], const double* X, int64_t ld
 // Pass A: partial M = A^T B over the block's rows, 4x4 output tile per thread.
 __global__ __launch_bounds__(256) void k_rho_a(RhoKArgs a) {
   DevState* st = a.st;
-  if (!rho_needed(st, a.kpass)) return;
+  if (!rho_needed(st)) return;
   const int side = blockIdx.y;
   const int r = st->r[a.nb_new], ro = st->r[a.nb_old];
   __shared__ double As[kRhoChunk][kPMax + 1], Bs[kRhoChunk][kPMax + 1];
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void k_rho_a(RhoKArgs a) {
 // Pass B: Y = B - A M (rows of the chunk), partial G = Y^T Y.
 __global__ __launch_bounds__(256) void k_rho_b(RhoKArgs a) {
   DevState* st = a.st;
-  if (!rho_needed(st, a.kpass)) return;
+  if (!rho_needed(st)) return;
   const int side = blockIdx.y;
   const int r = st->r[a.nb_new], ro = st->r[a.nb_old];
   __shared__ double As[kRhoChunk][kPMax + 1], Bs[kRhoChunk][kPMax + 1];
@@ -125,15 +125,25 @@ __global__ __launch_bounds__(256) void k_rho_b(RhoKArgs a) {
 }
 
 // Sum the per-block partials in block order: out[side][e] = sum_b part[b][side][e].
-__global__ __launch_bounds__(256) void k_rho_reduce(const DevState* st, int kpass, const double* part,
-                                                    int nblocks, double* out) {
-  if (!rho_needed(st, kpass)) return;
+__global__ __launch_bounds__(256) void k_rho_reduce(const DevState* st, const double* part, int nblocks,
+                                                    double* out) {
+  if (!rho_needed(st)) return;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;  // 0 .. 2*4096
   if (e >= 2 * kPMax * kPMax) return;
   const int side = e / (kPMax * kPMax), q = e % (kPMax * kPMax);
-  double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += part[((int64_t)b * 2 + side) * kPMax * kPMax + q];
-  out[e] = s;
+  // four independent partial sums keep several loads in flight; fixed order
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  const double* src = part + (int64_t)side * kPMax * kPMax + q;
+  const int64_t stride = 2 * kPMax * kPMax;
+  int b = 0;
+  for (; b + 3 < nblocks; b += 4) {
+    s0 += src[(int64_t)b * stride];
+    s1 += src[(int64_t)(b + 1) * stride];
+    s2 += src[(int64_t)(b + 2) * stride];
+    s3 += src[(int64_t)(b + 3) * stride];
+  }
+  for (; b < nblocks; ++b) s0 += src[(int64_t)b * stride];
+  out[e] = (s0 + s1) + (s2 + s3);
 }
 
 struct RhoFinalArgs {
@@ -141,14 +151,14 @@ struct RhoFinalArgs {
   const double* M;  // M_u, N_v   (row a: new column, col m: old column)
   const double* G;  // G_u = Y^T Y, G_v = Y'^T Y'
   int nb_new, nb_old;
-  int kpass, maxiter;
+  int maxiter;
   TraceBuf trace;
 };
 
 __global__ __launch_bounds__(256) void k_rho_final(RhoFinalArgs a) {
   DevState* st = a.st;
   if (st->done) return;
-  const bool need = rho_needed(st, a.kpass);
+  const bool need = rho_needed(st);
   __shared__ double red[4];
   __shared__ double Am[kPMax][kPMax + 1], Bm[kPMax][kPMax + 1];
   double rho = INFINITY;
@@ -191,7 +201,7 @@ __global__ __launch_bounds__(256) void k_rho_final(RhoFinalArgs a) {
     rho = sqrt(fmax(tot, 0.0)) / st->nrm;
   }
   if (threadIdx.x == 0) {
-    const int kp = a.kpass;
+    const int kp = st->k;
     st->rho = rho;
     st->rhob[a.nb_new] = rho;
     st->ret = a.nb_new;
@@ -233,21 +243,19 @@ int rho_launch(const RhoPlan& p, const RhoArgs& ra, hipStream_t s) {
   a.rows_per_block = (int)(per * 256);
   a.nb_new = ra.nb_new;
   a.nb_old = ra.nb_old;
-  a.kpass = ra.kpass;
   a.part = p.part;
   const int red_blocks = (2 * kPMax * kPMax + 255) / 256;
   hipLaunchKernelGGL(k_rho_a, dim3(p.nblocks, 2), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_rho_reduce, dim3(red_blocks), dim3(256), 0, s, ra.st, ra.kpass, p.part, p.nblocks, p.M);
+  hipLaunchKernelGGL(k_rho_reduce, dim3(red_blocks), dim3(256), 0, s, ra.st, p.part, p.nblocks, p.M);
   a.M = p.M;
   hipLaunchKernelGGL(k_rho_b, dim3(p.nblocks, 2), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_rho_reduce, dim3(red_blocks), dim3(256), 0, s, ra.st, ra.kpass, p.part, p.nblocks, p.G);
+  hipLaunchKernelGGL(k_rho_reduce, dim3(red_blocks), dim3(256), 0, s, ra.st, p.part, p.nblocks, p.G);
   RhoFinalArgs f{};
   f.st = ra.st;
   f.M = p.M;
   f.G = p.G;
   f.nb_new = ra.nb_new;
   f.nb_old = ra.nb_old;
-  f.kpass = ra.kpass;
   f.maxiter = ra.maxiter;
   f.trace = ra.trace;
   hipLaunchKernelGGL(k_rho_final, dim3(1), dim3(256), 0, s, f);

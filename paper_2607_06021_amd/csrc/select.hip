@@ -8,8 +8,9 @@
 // cross approximation would repeat, and the previous iterate is the result.
 //
 // Kernels: k_pi (scores and per-block maxima), k_gmax (global maximum), k_topk_block
-// (bitonic sort of each 256-row block, its best 64 kept), k_topk_merge (16 lists of 64 per
-// block until one list is left), k_select (set update, fixed-point test, trace).
+// (the best 64 of each 256-row block, ranked by counting), k_topk_merge (16 sorted lists of
+// 64 per block merged by rank until one list is left), k_select (set update, fixed-point
+// test, trace).
 #include "lrp_kernels.h"
 
 namespace lrp {
@@ -22,27 +23,6 @@ struct Cand {
 // a comes before b: higher score, then smaller index
 __device__ inline bool before(const Cand& a, const Cand& b) {
   return a.s > b.s || (a.s == b.s && a.i < b.i);
-}
-
-template <int N>
-__device__ void bitonic(Cand* e) {
-  for (int k = 2; k <= N; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const bool up = (i & k) == 0;
-          const Cand a = e[i], b = e[ixj];
-          const bool sw = up ? before(b, a) : before(a, b);
-          if (sw) {
-            e[i] = b;
-            e[ixj] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
 }
 
 struct PiArgs {
@@ -114,16 +94,18 @@ __global__ __launch_bounds__(256) void k_topk_block(TopkArgs a) {
     for (int q = 0; q < ne; ++q) ex |= (excl[q] == (int)i);
     c.s = ex ? -1.0 : (p <= floor_v ? 0.0 : p);
     c.i = (int)i;
-  } else {
+  } else {  // padding: below every real entry, distinct indices
     c.s = -2.0;
-    c.i = 0x7fffffff;
+    c.i = 0x40000000 + (int)threadIdx.x;
   }
   e[threadIdx.x] = c;
   __syncthreads();
-  bitonic<kSelRows>(e);
-  if (threadIdx.x < kPMax) {
-    a.cs[side][(int64_t)blockIdx.x * kPMax + threadIdx.x] = e[threadIdx.x].s;
-    a.ci[side][(int64_t)blockIdx.x * kPMax + threadIdx.x] = e[threadIdx.x].i;
+  // rank of this entry in the (score desc, index asc) order; the best kPMax are kept
+  int rk = 0;
+  for (int q = 0; q < kSelRows; ++q) rk += before(e[q], c) ? 1 : 0;
+  if (rk < kPMax) {
+    a.cs[side][(int64_t)blockIdx.x * kPMax + rk] = c.s;
+    a.ci[side][(int64_t)blockIdx.x * kPMax + rk] = c.i;
   }
 }
 
@@ -136,6 +118,9 @@ struct MergeArgs {
   int* out_i[2];
 };
 
+// Each of the kMergeFan input lists is sorted; an entry's rank in the merged order is its
+// position in its own list plus, for every other list, the number of entries before it
+// (binary search). Entries of rank < kPMax are written to the output list.
 __global__ __launch_bounds__(256) void k_topk_merge(MergeArgs a) {
   if (a.st->done) return;
   const int side = blockIdx.y;
@@ -150,71 +135,115 @@ __global__ __launch_bounds__(256) void k_topk_merge(MergeArgs a) {
       c.i = a.in_i[side][(int64_t)first * kPMax + q];
     } else {
       c.s = -2.0;
-      c.i = 0x7fffffff;
+      c.i = 0x50000000 + q;
     }
+    if (c.s == -2.0) c.i = 0x50000000 + q;  // padding entries: distinct indices
     e[q] = c;
   }
   __syncthreads();
-  bitonic<NE>(e);
-  if (threadIdx.x < kPMax) {
-    a.out_s[side][(int64_t)blockIdx.x * kPMax + threadIdx.x] = e[threadIdx.x].s;
-    a.out_i[side][(int64_t)blockIdx.x * kPMax + threadIdx.x] = e[threadIdx.x].i;
+  for (int q = threadIdx.x; q < NE; q += blockDim.x) {
+    const Cand c = e[q];
+    const int mine = q / kPMax;
+    int rk = q % kPMax;
+    for (int l = 0; l < kMergeFan; ++l) {
+      if (l == mine) continue;
+      const Cand* L = e + l * kPMax;
+      int lo = 0, hi = kPMax;  // first position whose entry is not before c
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (before(L[mid], c))
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      rk += lo;
+    }
+    if (rk < kPMax) {
+      a.out_s[side][(int64_t)blockIdx.x * kPMax + rk] = c.s;
+      a.out_i[side][(int64_t)blockIdx.x * kPMax + rk] = c.i;
+    }
   }
 }
 
-__global__ void k_select(SelectArgs a) {
+__global__ __launch_bounds__(64) void k_select(SelectArgs a) {
   DevState* st = a.st;
   if (st->done) return;
-  if (threadIdx.x != 0) return;
-  const int pm = a.pmax;
-  for (int side = 0; side < 2; ++side) {
-    const double* cs = a.cs[side];
-    const int* ci = a.ci[side];
-    const int nold = side == 0 ? st->nI : st->nJ;
-    const int* old = side == 0 ? st->I : st->J;
-    int* pre = side == 0 ? st->Ipre : st->Jpre;
-    int take = min(st->r_sig, pm - nold);
-    int nv = 0;
-    while (nv < kPMax && cs[nv] >= 0.0) ++nv;
-    take = max(0, min(take, nv));
-    for (int q = 0; q < nold; ++q) pre[q] = old[q];
-    // the new indices in ascending order (insertion sort of at most 64 values)
-    for (int q = 0; q < take; ++q) {
-      const int v = ci[q];
-      int pos = nold + q;
-      while (pos > nold && pre[pos - 1] > v) {
-        pre[pos] = pre[pos - 1];
-        --pos;
-      }
-      pre[pos] = v;
-    }
-    if (side == 0)
-      st->nIpre = nold + take;
-    else
-      st->nJpre = nold + take;
+  const int t = threadIdx.x;
+  __shared__ int oldI[kPMax], oldJ[kPMax], prevI[kPMax], prevJ[kPMax], newv[2][kPMax];
+  __shared__ int pre[2][kPMax];
+  __shared__ int take_s[2], nold_s[2], nv_s[2];
+  __shared__ int same;
+  const int nI = st->nI, nJ = st->nJ;
+  const int nIprev = st->nIprev, nJprev = st->nJprev;
+  const int rsig = st->r_sig;
+  oldI[t] = st->I[t];
+  oldJ[t] = st->J[t];
+  prevI[t] = st->Iprev[t];
+  prevJ[t] = st->Jprev[t];
+  const double s0 = a.cs[0][t], s1 = a.cs[1][t];
+  newv[0][t] = a.ci[0][t];
+  newv[1][t] = a.ci[1][t];
+  // number of valid (score >= 0) candidates: the lists are sorted, so count them
+  const unsigned long long b0 = __ballot(s0 >= 0.0), b1 = __ballot(s1 >= 0.0);
+  if (t == 0) {
+    nv_s[0] = __popcll(b0);
+    nv_s[1] = __popcll(b1);
+    same = 1;
   }
+  __syncthreads();
+  for (int side = 0; side < 2; ++side) {
+    const int nold = side == 0 ? nI : nJ;
+    const int take = max(0, min(min(rsig, a.pmax - nold), nv_s[side]));
+    // the new indices in ascending order: rank among the first `take` candidates
+    if (t < take) {
+      const int v = newv[side][t];
+      int rk = 0;
+      for (int q = 0; q < take; ++q) rk += newv[side][q] < v ? 1 : 0;
+      pre[side][nold + rk] = v;
+    }
+    if (t < nold) pre[side][t] = side == 0 ? oldI[t] : oldJ[t];
+    if (t == 0) {
+      take_s[side] = take;
+      nold_s[side] = nold;
+    }
+  }
+  __syncthreads();
+  const int nIpre = nold_s[0] + take_s[0], nJpre = nold_s[1] + take_s[1];
   // fixed point: the pass would repeat the previous cross approximation exactly
-  bool same = st->nIprev == st->nIpre && st->nJprev == st->nJpre;
-  for (int q = 0; same && q < st->nIpre; ++q) same = st->Iprev[q] == st->Ipre[q];
-  for (int q = 0; same && q < st->nJpre; ++q) same = st->Jprev[q] == st->Jpre[q];
-  if (same) {
-    st->done = 1;
-    st->status = LRP_STAGNATED;
+  const bool sizes_same = nIprev == nIpre && nJprev == nJpre;
+  if (sizes_same) {
+    if (t < nIpre && prevI[t] != pre[0][t]) same = 0;
+    if (t < nJpre && prevJ[t] != pre[1][t]) same = 0;
+  }
+  __syncthreads();
+  if (sizes_same && same) {
+    if (t == 0) {
+      st->done = 1;
+      st->status = LRP_STAGNATED;
+    }
     return;
   }
-  for (int q = 0; q < st->nIpre; ++q) st->Iprev[q] = st->Ipre[q];
-  for (int q = 0; q < st->nJpre; ++q) st->Jprev[q] = st->Jpre[q];
-  st->nIprev = st->nIpre;
-  st->nJprev = st->nJpre;
-  st->ncols[0] = st->nJpre;
-  st->ncols[1] = st->nIpre;
-  const int kp = a.kpass;
-  for (int q = 0; q < kPMax; ++q) {
-    a.trace.Ipre[kp * kPMax + q] = q < st->nIpre ? st->Ipre[q] : -1;
-    a.trace.Jpre[kp * kPMax + q] = q < st->nJpre ? st->Jpre[q] : -1;
+  if (t < nIpre) {
+    st->Ipre[t] = pre[0][t];
+    st->Iprev[t] = pre[0][t];
   }
-  a.trace.nIpre[kp] = st->nIpre;
-  a.trace.nJpre[kp] = st->nJpre;
+  if (t < nJpre) {
+    st->Jpre[t] = pre[1][t];
+    st->Jprev[t] = pre[1][t];
+  }
+  const int kp = st->k;  // the pass being computed
+  a.trace.Ipre[kp * kPMax + t] = t < nIpre ? pre[0][t] : -1;
+  a.trace.Jpre[kp * kPMax + t] = t < nJpre ? pre[1][t] : -1;
+  if (t == 0) {
+    st->nIpre = nIpre;
+    st->nJpre = nJpre;
+    st->nIprev = nIpre;
+    st->nJprev = nJpre;
+    st->ncols[0] = nJpre;
+    st->ncols[1] = nIpre;
+    a.trace.nIpre[kp] = nIpre;
+    a.trace.nJpre[kp] = nJpre;
+  }
 }
 
 // ----------------------------------------------------------------------------------------
@@ -291,7 +320,7 @@ int select_candidates(const SelectPlan& p, const DevState* st, const double* U[2
 }
 
 int select_update(const SelectArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(kPMax), 0, s, a);
   return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
 }
 

@@ -1,0 +1,422 @@
+// Serving: a queue of Poisson solves with continuous admission (the lrp_server_* ABI).
+//
+// A scheduler thread owns a pool of contexts ("slots"), each with its own non-blocking HIP
+// stream. Requests are admitted in arrival order as soon as a slot of their shape is idle,
+// or a new one fits in the device-memory budget (idle slots of other shapes are freed, least
+// recently used first, to make room). An admitted request runs the same stages as lrp_solve
+// -- start, passes, finish -- but the scheduler advances all active requests together: it
+// enqueues the next pass of a request while at most two of its passes are unchecked, reads
+// each pass's stop flag through an event query (never blocking), and enqueues the finish
+// stage once the flag is set or maxiter passes were made. Passes of different requests thus
+// overlap on the device, and a finished request frees its slot at once for the next one.
+// A request's kernels and their arguments are exactly those of a solo lrp_solve, so its
+// result does not depend on what else is in flight.
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "ctx.h"
+
+using namespace lrp;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Key {
+  int64_t n;
+  int r_max;
+  double tol;
+  int maxiter;
+  int precision;
+  bool operator==(const Key& o) const {
+    return n == o.n && r_max == o.r_max && tol == o.tol && maxiter == o.maxiter && precision == o.precision;
+  }
+};
+
+struct Job {
+  int64_t ticket = 0;
+  lrp_request req{};
+  Key key{};
+  int64_t bytes = 0;
+  Clock::time_point t_submit, t_done;
+  bool done = false;
+  int status = 0;
+  int rank = 0;
+  lrp_info info{};
+};
+
+struct Slot {
+  lrp_ctx* ctx = nullptr;
+  hipStream_t stream = nullptr;
+  Key key{};
+  int64_t bytes = 0;
+  Job* job = nullptr;  // null: idle
+  int phase = 0;       // 0: start not enqueued, 1: passes, 2: finishing
+  int k = 0;           // passes enqueued
+  int checked = 0;     // passes whose stop flag has been read
+  bool stop = false;
+  uint64_t last_used = 0;
+};
+
+}  // namespace
+
+struct lrp_server {
+  int device = 0;
+  int64_t budget = 0;
+  int max_active = 1;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Job*> queue;
+  std::map<int64_t, Job*> jobs;
+  std::vector<Slot> slots;  // touched only by the scheduler thread (sizes read under mu)
+  int64_t bytes_in_use = 0;
+  int64_t next_ticket = 1;
+  int64_t submitted = 0, completed = 0, failed = 0, active = 0;
+  bool stopping = false;
+  uint64_t tick = 0;
+  std::thread th;
+};
+
+namespace {
+
+void finish_job(lrp_server* s, Job* j, int status, int rank, const lrp_info* info) {
+  std::lock_guard<std::mutex> g(s->mu);
+  j->status = status;
+  j->rank = rank;
+  if (info) j->info = *info;
+  j->info.status = status;
+  j->t_done = Clock::now();
+  j->done = true;
+  if (status < 0)
+    ++s->failed;
+  else
+    ++s->completed;
+  --s->active;
+  s->cv_done.notify_all();
+}
+
+void release_slot_job(Slot& sl, uint64_t tick) {
+  sl.job = nullptr;
+  sl.phase = 0;
+  sl.k = sl.checked = 0;
+  sl.stop = false;
+  sl.last_used = tick;
+}
+
+// Advance one active slot without blocking; true if anything was enqueued or completed.
+bool advance(lrp_server* s, Slot& sl) {
+  lrp_ctx* c = sl.ctx;
+  Job* j = sl.job;
+  const lrp_request& q = j->req;
+  if (sl.phase == 0) {
+    const int rc = enqueue_start(c, q.r_F, q.U_F, q.ldu, q.sigma_F, q.V_F, q.ldv);
+    if (rc != LRP_OK) {
+      (void)hipStreamSynchronize(sl.stream);
+      finish_job(s, j, rc, 0, nullptr);
+      release_slot_job(sl, ++s->tick);
+      return true;
+    }
+    sl.phase = 1;
+    return true;
+  }
+  if (sl.phase == 1) {
+    bool progress = false;
+    if (sl.checked < sl.k) {
+      const hipError_t e = hipEventQuery(c->evit[sl.checked & 1]);
+      if (e == hipSuccess) {
+        if (c->done_host[sl.checked & 1]) sl.stop = true;
+        ++sl.checked;
+        progress = true;
+      } else if (e != hipErrorNotReady) {
+        (void)hipStreamSynchronize(sl.stream);
+        finish_job(s, j, LRP_EDEVICE, 0, nullptr);
+        release_slot_job(sl, ++s->tick);
+        return true;
+      }
+    }
+    if (!sl.stop && sl.k < c->maxiter && sl.k - sl.checked < 2) {
+      int rc = enqueue_pass(c, sl.k);
+      if (rc == LRP_OK) rc = enqueue_poll(c, sl.k);
+      if (rc != LRP_OK) {
+        (void)hipStreamSynchronize(sl.stream);
+        finish_job(s, j, rc, 0, nullptr);
+        release_slot_job(sl, ++s->tick);
+        return true;
+      }
+      ++sl.k;
+      progress = true;
+    }
+    if (sl.stop || (sl.k == c->maxiter && sl.checked == sl.k)) {
+      const int rc = enqueue_finish(c, q.U_out, q.ldou, q.S_out, q.V_out, q.ldov);
+      if (rc != LRP_OK) {
+        (void)hipStreamSynchronize(sl.stream);
+        finish_job(s, j, rc, 0, nullptr);
+        release_slot_job(sl, ++s->tick);
+        return true;
+      }
+      sl.phase = 2;
+      progress = true;
+    }
+    return progress;
+  }
+  // phase 2: wait (without blocking) for the finish stage
+  const hipError_t e = hipEventQuery(c->evfin);
+  if (e == hipErrorNotReady) return false;
+  int32_t rank = 0;
+  lrp_info info{};
+  const int status = (e == hipSuccess) ? collect(c, &rank, &info) : LRP_EDEVICE;
+  finish_job(s, j, status, rank, &info);
+  release_slot_job(sl, ++s->tick);
+  return true;
+}
+
+void destroy_slot(lrp_server* s, Slot& sl) {
+  if (sl.ctx) {
+    (void)hipStreamSynchronize(sl.stream);
+    lrp_destroy(sl.ctx);
+  }
+  if (sl.stream) (void)hipStreamDestroy(sl.stream);
+  s->bytes_in_use -= sl.bytes;
+  sl = Slot{};
+}
+
+// Admit queued requests in order while slots and memory allow. Called with mu held.
+bool admit(lrp_server* s) {
+  bool progress = false;
+  while (!s->queue.empty() && s->active < s->max_active) {
+    Job* j = s->queue.front();
+    Slot* use = nullptr;
+    for (Slot& sl : s->slots)
+      if (sl.ctx && !sl.job && sl.key == j->key) {
+        use = &sl;
+        break;
+      }
+    if (!use && s->bytes_in_use + j->bytes > s->budget) {
+      // free the least recently used idle slot of another shape, then try again
+      Slot* victim = nullptr;
+      for (Slot& sl : s->slots)
+        if (sl.ctx && !sl.job && (!victim || sl.last_used < victim->last_used)) victim = &sl;
+      if (!victim) break;  // wait for a running request to finish
+      destroy_slot(s, *victim);
+      continue;
+    }
+    if (!use) {
+      Slot sl;
+      sl.key = j->key;
+      sl.bytes = j->bytes;
+      int rc = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess ? LRP_OK : LRP_EDEVICE;
+      if (rc == LRP_OK) {
+        lrp_opts o{};
+        o.maxiter = j->key.maxiter;
+        o.precision = j->key.precision;
+        o.stream = sl.stream;
+        rc = lrp_create(&sl.ctx, j->key.n, j->key.r_max, j->key.tol, &o);
+      }
+      if (rc != LRP_OK) {
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        s->queue.pop_front();
+        j->status = rc;
+        j->info.status = rc;
+        j->t_done = Clock::now();
+        j->done = true;
+        ++s->failed;
+        s->cv_done.notify_all();
+        progress = true;
+        continue;
+      }
+      s->bytes_in_use += sl.bytes;
+      // reuse an empty entry if there is one
+      bool placed = false;
+      for (Slot& e : s->slots)
+        if (!e.ctx) {
+          e = sl;
+          use = &e;
+          placed = true;
+          break;
+        }
+      if (!placed) {
+        s->slots.push_back(sl);
+        use = &s->slots.back();
+      }
+    }
+    s->queue.pop_front();
+    use->job = j;
+    use->phase = 0;
+    use->k = use->checked = 0;
+    use->stop = false;
+    ++s->active;
+    progress = true;
+  }
+  return progress;
+}
+
+void scheduler(lrp_server* s) {
+  (void)hipSetDevice(s->device);
+  for (;;) {
+    bool progress;
+    {
+      std::unique_lock<std::mutex> g(s->mu);
+      if (s->stopping) {
+        // drop queued requests; running ones are finished below
+        while (!s->queue.empty()) {
+          Job* j = s->queue.front();
+          s->queue.pop_front();
+          j->status = LRP_EDEVICE;
+          j->info.status = LRP_EDEVICE;
+          j->t_done = Clock::now();
+          j->done = true;
+          ++s->failed;
+        }
+        s->cv_done.notify_all();
+        if (s->active == 0) break;
+      }
+      progress = admit(s);
+    }
+    for (Slot& sl : s->slots)
+      if (sl.job) progress |= advance(s, sl);
+    if (!progress) {
+      std::unique_lock<std::mutex> g(s->mu);
+      if (s->queue.empty() || s->active >= s->max_active)
+        s->cv_work.wait_for(g, std::chrono::microseconds(20));
+    }
+  }
+  for (Slot& sl : s->slots) destroy_slot(s, sl);
+  s->slots.clear();
+}
+
+Job* find_job(lrp_server* s, int64_t ticket) {
+  auto it = s->jobs.find(ticket);
+  return it == s->jobs.end() ? nullptr : it->second;
+}
+
+void report(const Job* j, int32_t* status, int32_t* rank, lrp_info* info, double* latency_ms) {
+  if (status) *status = j->status;
+  if (rank) *rank = j->rank;
+  if (info) *info = j->info;
+  if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(j->t_done - j->t_submit).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+int lrp_server_create(lrp_server** out, int64_t budget_bytes, int32_t max_active) {
+  if (!out || budget_bytes <= 0 || max_active < 1 || max_active > 64) return LRP_EINVAL;
+  *out = nullptr;
+  lrp_server* s = new (std::nothrow) lrp_server();
+  if (!s) return LRP_ENOMEM;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return LRP_EDEVICE;
+  }
+  s->budget = budget_bytes;
+  s->max_active = max_active;
+  s->slots.reserve(64);
+  s->th = std::thread(scheduler, s);
+  *out = s;
+  return LRP_OK;
+}
+
+int lrp_server_submit(lrp_server* s, const lrp_request* r, int64_t* ticket) {
+  if (!s || !r || !ticket) return LRP_EINVAL;
+  const int64_t n = r->n;
+  if (n < 3 || (n & (n + 1)) != 0 || n + 1 > (int64_t(1) << 23)) return LRP_EINVAL;
+  if (r->r_max < 1 || r->r_max > kPMax || r->r_max > n) return LRP_EINVAL;
+  if (!(r->tol >= 0.0) || r->maxiter < 0 || r->maxiter > 1000) return LRP_EINVAL;
+  if (r->precision != LRP_FP64 && r->precision != LRP_MIXED) return LRP_EINVAL;
+  const int rc = check_solve_args(n, r->r_max, r->r_F, r->U_F, r->ldu, r->sigma_F, r->V_F, r->ldv, r->U_out,
+                                  r->ldou, r->S_out, r->V_out, r->ldov);
+  if (rc != LRP_OK) return rc;
+  Job* j = new (std::nothrow) Job();
+  if (!j) return LRP_ENOMEM;
+  j->req = *r;
+  j->key = Key{n, r->r_max, r->tol, r->maxiter == 0 ? 20 : r->maxiter, r->precision};
+  j->bytes = context_bytes(n, r->r_max, j->key.maxiter, r->precision == LRP_MIXED);
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    if (j->bytes > s->budget) {
+      delete j;
+      return LRP_ENOMEM;
+    }
+    if (s->stopping) {
+      delete j;
+      return LRP_EINVAL;
+    }
+    j->ticket = s->next_ticket++;
+    j->t_submit = Clock::now();
+    s->jobs[j->ticket] = j;
+    s->queue.push_back(j);
+    ++s->submitted;
+    *ticket = j->ticket;
+  }
+  s->cv_work.notify_one();
+  return LRP_OK;
+}
+
+int lrp_server_poll(lrp_server* s, int64_t ticket, int32_t* done, int32_t* status, int32_t* rank,
+                    lrp_info* info, double* latency_ms) {
+  if (!s || !done) return LRP_EINVAL;
+  std::lock_guard<std::mutex> g(s->mu);
+  Job* j = find_job(s, ticket);
+  if (!j) return LRP_EINVAL;
+  *done = j->done ? 1 : 0;
+  if (j->done) report(j, status, rank, info, latency_ms);
+  return LRP_OK;
+}
+
+int lrp_server_wait(lrp_server* s, int64_t ticket, int32_t* status, int32_t* rank, lrp_info* info,
+                    double* latency_ms) {
+  if (!s) return LRP_EINVAL;
+  std::unique_lock<std::mutex> g(s->mu);
+  Job* j = find_job(s, ticket);
+  if (!j) return LRP_EINVAL;
+  s->cv_done.wait(g, [&] { return j->done; });
+  report(j, status, rank, info, latency_ms);
+  return LRP_OK;
+}
+
+int lrp_server_release(lrp_server* s, int64_t ticket) {
+  if (!s) return LRP_EINVAL;
+  std::lock_guard<std::mutex> g(s->mu);
+  Job* j = find_job(s, ticket);
+  if (!j || !j->done) return LRP_EINVAL;
+  s->jobs.erase(ticket);
+  delete j;
+  return LRP_OK;
+}
+
+int lrp_server_get_stats(lrp_server* s, lrp_server_stats* out) {
+  if (!s || !out) return LRP_EINVAL;
+  std::lock_guard<std::mutex> g(s->mu);
+  out->submitted = s->submitted;
+  out->completed = s->completed;
+  out->failed = s->failed;
+  out->queued = (int64_t)s->queue.size();
+  out->active = s->active;
+  out->bytes_in_use = s->bytes_in_use;
+  out->bytes_budget = s->budget;
+  int nc = 0;
+  for (const Slot& sl : s->slots) nc += sl.ctx ? 1 : 0;
+  out->contexts = nc;
+  return LRP_OK;
+}
+
+int lrp_server_destroy(lrp_server* s) {
+  if (!s) return LRP_OK;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stopping = true;
+  }
+  s->cv_work.notify_all();
+  if (s->th.joinable()) s->th.join();
+  for (auto& kv : s->jobs) delete kv.second;
+  delete s;
+  return LRP_OK;
+}
+
+}  // extern "C"

@@ -7,10 +7,7 @@
 // Q is formed top-down: each block applies its reflectors to [T; 0], where T is its p x p
 // piece of the parent level's Q.
 //
-// Register layout of a block: thread t owns column c = t/4 and rows 64 (t%4) .. 64 (t%4)+63,
-// so the column dot products of a Householder step reduce over the 4 lanes of a quad. The
-// current Householder vector is shared through LDS. Two sides (e.g. C and R^T) are processed
-// by the same launch (blockIdx.y).
+// Two sides (e.g. C and R^T) are processed by the same launch (blockIdx.y).
 #include "lrp_kernels.h"
 
 namespace lrp {
@@ -50,6 +47,30 @@ __device__ inline int side_cols(const DevState* st, const int* fixed, int side) 
   return st ? st->ncols[side] : fixed[side];
 }
 
+// Sum over the 16 lanes of a DPP row (lanes 16q .. 16q+15); every lane gets the total.
+__device__ inline double row16_sum(double x) {
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  x += __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false),
+                        __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false));  // quad_perm [1,0,3,2]
+  lo = __double2loint(x);
+  hi = __double2hiint(x);
+  x += __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false),
+                        __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false));  // quad_perm [2,3,0,1]
+  lo = __double2loint(x);
+  hi = __double2hiint(x);
+  x += __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0x141, 0xF, 0xF, false),
+                        __builtin_amdgcn_mov_dpp(lo, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  lo = __double2loint(x);
+  hi = __double2hiint(x);
+  x += __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0x140, 0xF, 0xF, false),
+                        __builtin_amdgcn_mov_dpp(lo, 0x140, 0xF, 0xF, false));  // row_mirror
+  return x;
+}
+
+// Thread layout of a 256-row block: column c = t/16, rows 16 (t%16) .. 16 (t%16)+15, so the
+// 16 lanes of a DPP row hold one column. The lanes of column j build reflector j themselves
+// (norm and diagonal by row sums), publish it in LDS (double-buffered) and one barrier later
+// every trailing column applies it.
 __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) {
   const int side = blockIdx.y;
   if (a.st && a.st->done) return;
@@ -57,23 +78,23 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) {
   const int64_t row0 = (int64_t)blockIdx.x * a.block_rows;
   const int nr = (int)min((int64_t)a.block_rows, a.rows - row0);
   if (p <= 0 || nr <= 0) return;
-  const int t = threadIdx.x, c = t >> 2, sub = t & 3;
-  __shared__ double colbuf[kTsqrRows];
-  __shared__ double vbuf[kTsqrRows];
-  __shared__ double part[4];
+  const int t = threadIdx.x, c = t >> 4, sub = t & 15;
+  const int rbase = sub * kTsqrRowsPerThread;
+  __shared__ double vbuf[2][kTsqrRows];
+  __shared__ double tbuf[2];
 
-  double x[64];
+  double x[kTsqrRowsPerThread];
   {
-    const int64_t base = row0 + (int64_t)c * a.ldin + sub * 64;
+    const int64_t base = row0 + (int64_t)c * a.ldin + rbase;
     const bool colok = c < p;
     if (a.in_f32) {
       const float* X = (const float*)a.in[side];
 #pragma unroll
-      for (int i = 0; i < 64; ++i) x[i] = (colok && sub * 64 + i < nr) ? (double)X[base + i] : 0.0;
+      for (int i = 0; i < kTsqrRowsPerThread; ++i) x[i] = (colok && rbase + i < nr) ? (double)X[base + i] : 0.0;
     } else {
       const double* X = (const double*)a.in[side];
 #pragma unroll
-      for (int i = 0; i < 64; ++i) x[i] = (colok && sub * 64 + i < nr) ? X[base + i] : 0.0;
+      for (int i = 0; i < kTsqrRowsPerThread; ++i) x[i] = (colok && rbase + i < nr) ? X[base + i] : 0.0;
     }
   }
   double* V = a.V[side];
@@ -81,45 +102,53 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) {
   double* taub = a.tau[side] + (int64_t)blockIdx.x * a.pmax;
 
   for (int j = 0; j < p; ++j) {
+    double* vb = vbuf[j & 1];
     if (c == j) {
+      double nn = 0.0, al = 0.0;
 #pragma unroll
-      for (int i = 0; i < 64; ++i) colbuf[sub * 64 + i] = x[i];
+      for (int i = 0; i < kTsqrRowsPerThread; ++i) {
+        const int r = rbase + i;
+        nn = (r > j) ? fma(x[i], x[i], nn) : nn;
+        al = (r == j) ? x[i] : al;
+      }
+      const double xnorm2 = row16_sum(nn);
+      const double alpha = row16_sum(al);
+      double beta, tau, scale;
+      if (xnorm2 == 0.0) {
+        tau = 0.0;
+        beta = alpha;
+        scale = 0.0;
+      } else {
+        beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+#pragma unroll
+      for (int i = 0; i < kTsqrRowsPerThread; ++i) {
+        const int r = rbase + i;
+        const double v = (r > j) ? x[i] * scale : (r == j ? 1.0 : 0.0);
+        vb[r] = v;
+        if (r < nr) V[row0 + r + (int64_t)j * a.ldv] = v;
+        if (r < a.pmax) Rb[r + (int64_t)j * a.ldr] = (r < j) ? x[i] : (r == j ? beta : 0.0);
+      }
+      if (sub == 0) {
+        tbuf[j & 1] = tau;
+        taub[j] = tau;
+      }
     }
-    __syncthreads();
-    const double xv = colbuf[t];
-    double nn = (t > j) ? xv * xv : 0.0;
-    nn = wave_sum(nn);
-    if ((t & 63) == 0) part[t >> 6] = nn;
-    __syncthreads();
-    const double xnorm2 = (part[0] + part[1]) + (part[2] + part[3]);
-    const double alpha = colbuf[j];
-    double beta, tau, scale;
-    if (xnorm2 == 0.0) {
-      tau = 0.0;
-      beta = alpha;
-      scale = 0.0;
-    } else {
-      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-      tau = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
-    }
-    const double vt = (t > j) ? xv * scale : (t == j ? 1.0 : 0.0);
-    vbuf[t] = vt;
-    if (t < nr) V[row0 + t + (int64_t)j * a.ldv] = vt;
-    if (t < a.pmax) Rb[t + (int64_t)j * a.ldr] = (t < j) ? xv : (t == j ? beta : 0.0);
-    if (t == 0) taub[j] = tau;
     __syncthreads();
     if (c > j && c < p) {
-      const double* vb = vbuf + sub * 64;
+      const double tau = tbuf[j & 1];
+      const double* vs = vb + rbase;
       double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-      for (int i = 0; i < 64; i += 2) {
-        d0 = fma(vb[i], x[i], d0);
-        d1 = fma(vb[i + 1], x[i + 1], d1);
+      for (int i = 0; i < kTsqrRowsPerThread; i += 2) {
+        d0 = fma(vs[i], x[i], d0);
+        d1 = fma(vs[i + 1], x[i + 1], d1);
       }
-      const double w = quad_sum(d0 + d1) * tau;
+      const double w = row16_sum(d0 + d1) * tau;
 #pragma unroll
-      for (int i = 0; i < 64; ++i) x[i] = fma(-w, vb[i], x[i]);
+      for (int i = 0; i < kTsqrRowsPerThread; ++i) x[i] = fma(-w, vs[i], x[i]);
     }
   }
 }
@@ -131,15 +160,16 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_apply(ApplyArgs a) {
   const int64_t row0 = (int64_t)blockIdx.x * a.block_rows;
   const int nr = (int)min((int64_t)a.block_rows, a.rows - row0);
   if (p <= 0 || nr <= 0) return;
-  const int t = threadIdx.x, c = t >> 2, sub = t & 3;
+  const int t = threadIdx.x, c = t >> 4, sub = t & 15;
+  const int rbase = sub * kTsqrRowsPerThread;
   __shared__ double vbuf[2][kTsqrRows];
 
-  double y[64];
+  double y[kTsqrRowsPerThread];
   const double* T = a.T[side];
   const int64_t toff = (int64_t)blockIdx.x * a.pmax;
 #pragma unroll
-  for (int i = 0; i < 64; ++i) {
-    const int lr = sub * 64 + i;
+  for (int i = 0; i < kTsqrRowsPerThread; ++i) {
+    const int lr = rbase + i;
     double v0 = 0.0;
     if (c < p && lr < p) v0 = T ? T[toff + lr + (int64_t)c * a.ldt] : (lr == c ? 1.0 : 0.0);
     y[i] = v0;
@@ -148,27 +178,27 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_apply(ApplyArgs a) {
   const double* taub = a.tau[side] + (int64_t)blockIdx.x * a.pmax;
   for (int j = p - 1; j >= 0; --j) {
     double* vb = vbuf[j & 1];
-    vb[t] = (t < nr) ? V[row0 + t + (int64_t)j * a.ldv] : 0.0;
+    if (t < kTsqrRows) vb[t] = (t < nr) ? V[row0 + t + (int64_t)j * a.ldv] : 0.0;
     const double tj = taub[j];
     __syncthreads();
     if (c < p && tj != 0.0) {
-      const double* vs = vb + sub * 64;
+      const double* vs = vb + rbase;
       double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-      for (int i = 0; i < 64; i += 2) {
+      for (int i = 0; i < kTsqrRowsPerThread; i += 2) {
         d0 = fma(vs[i], y[i], d0);
         d1 = fma(vs[i + 1], y[i + 1], d1);
       }
-      const double w = quad_sum(d0 + d1) * tj;
+      const double w = row16_sum(d0 + d1) * tj;
 #pragma unroll
-      for (int i = 0; i < 64; ++i) y[i] = fma(-w, vs[i], y[i]);
+      for (int i = 0; i < kTsqrRowsPerThread; ++i) y[i] = fma(-w, vs[i], y[i]);
     }
   }
   if (c < p) {
-    double* Y = a.Y[side] + row0 + (int64_t)c * a.ldy + sub * 64;
+    double* Y = a.Y[side] + row0 + (int64_t)c * a.ldy + rbase;
 #pragma unroll
-    for (int i = 0; i < 64; ++i)
-      if (sub * 64 + i < nr) Y[i] = y[i];
+    for (int i = 0; i < kTsqrRowsPerThread; ++i)
+      if (rbase + i < nr) Y[i] = y[i];
   }
 }
 

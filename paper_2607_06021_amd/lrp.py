@@ -47,6 +47,23 @@ class Info(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class Request(ctypes.Structure):
+    _fields_ = [
+        ("n", _c_i64), ("r_F", _c_i32), ("r_max", _c_i32), ("tol", _c_dbl), ("maxiter", _c_i32),
+        ("precision", _c_i32), ("U_F", _c_vp), ("ldu", _c_i64), ("sigma_F", _c_vp), ("V_F", _c_vp),
+        ("ldv", _c_i64), ("U_out", _c_vp), ("ldou", _c_i64), ("S_out", _c_vp), ("V_out", _c_vp),
+        ("ldov", _c_i64),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", _c_i64), ("completed", _c_i64), ("failed", _c_i64), ("queued", _c_i64),
+                ("active", _c_i64), ("bytes_in_use", _c_i64), ("bytes_budget", _c_i64), ("contexts", _c_i32)]
+
+    def as_dict(self) -> Dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class LrpError(RuntimeError):
     def __init__(self, code: int, where: str):
         super().__init__(f"{where}: {strerror(code)} (code {code})")
@@ -90,6 +107,22 @@ def lib() -> ctypes.CDLL:
     L.lrp_dst1.restype = ctypes.c_int
     L.lrp_tsqr.argtypes = [_c_vp, _c_i32, _c_vp, _c_i64, _c_vp, _c_i64, _c_vp, _c_i64]
     L.lrp_tsqr.restype = ctypes.c_int
+    L.lrp_server_create.argtypes = [P(_c_vp), _c_i64, _c_i32]
+    L.lrp_server_create.restype = ctypes.c_int
+    L.lrp_server_submit.argtypes = [_c_vp, P(Request), P(_c_i64)]
+    L.lrp_server_submit.restype = ctypes.c_int
+    L.lrp_server_poll.argtypes = [_c_vp, _c_i64, P(_c_i32), P(_c_i32), P(_c_i32), P(Info), P(_c_dbl)]
+    L.lrp_server_poll.restype = ctypes.c_int
+    L.lrp_server_wait.argtypes = [_c_vp, _c_i64, P(_c_i32), P(_c_i32), P(Info), P(_c_dbl)]
+    L.lrp_server_wait.restype = ctypes.c_int
+    L.lrp_server_release.argtypes = [_c_vp, _c_i64]
+    L.lrp_server_release.restype = ctypes.c_int
+    L.lrp_server_get_stats.argtypes = [_c_vp, P(ServerStats)]
+    L.lrp_server_get_stats.restype = ctypes.c_int
+    L.lrp_server_destroy.argtypes = [_c_vp]
+    L.lrp_server_destroy.restype = ctypes.c_int
+    L.lrp_context_bytes.argtypes = [_c_i64, _c_i32, _c_i32, _c_i32]
+    L.lrp_context_bytes.restype = ctypes.c_int64
     _LIB = L
     return L
 
@@ -261,3 +294,90 @@ class Solver:
         self._order()
         _check(lib().lrp_tsqr(self._h, c, pa, lda, pq, ldq, R.data_ptr(), c), "lrp_tsqr")
         return Q, R
+
+
+class Server:
+    """A solve queue with continuous admission (lrp_server_*): submit requests, poll them."""
+
+    def __init__(self, budget_bytes: int, max_active: int = 8):
+        h = _c_vp()
+        _check(lib().lrp_server_create(ctypes.byref(h), int(budget_bytes), int(max_active)), "lrp_server_create")
+        self._h = h
+        self._keep: Dict[int, tuple] = {}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().lrp_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit(self, n: int, U_F, sigma, V_F, r_max: int, tol: float, maxiter: int = 20,
+               precision: str = "fp64", out=None, sync: bool = True) -> int:
+        """Queue one solve; returns its ticket. Outputs default to new (n, r_max) tensors.
+
+        The inputs must be complete on the device when the server reads them: with sync=True
+        the caller's current stream is synchronized first.
+        """
+        import torch
+
+        pu, ldu = _colmajor(U_F, n)
+        pv, ldv = _colmajor(V_F, n)
+        if out is None:
+            Uo = empty_fortran(n, r_max, torch.float64, U_F.device)
+            Vo = empty_fortran(n, r_max, torch.float64, U_F.device)
+            So = torch.empty(r_max, dtype=torch.float64, device=U_F.device)
+        else:
+            Uo, So, Vo = out
+        puo, lduo = _colmajor(Uo, n)
+        pvo, ldvo = _colmajor(Vo, n)
+        if sync:
+            torch.cuda.current_stream().synchronize()
+        req = Request(n, U_F.shape[1], r_max, tol, maxiter, LRP_MIXED if precision == "mixed" else LRP_FP64,
+                      pu, ldu, sigma.data_ptr(), pv, ldv, puo, lduo, So.data_ptr(), pvo, ldvo)
+        t = _c_i64()
+        _check(lib().lrp_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)), "lrp_server_submit")
+        self._keep[t.value] = (U_F, sigma, V_F, Uo, So, Vo)
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while running; else (U, S, V, rank, status, info, latency_ms)."""
+        done, st, rk, lat = _c_i32(), _c_i32(), _c_i32(), _c_dbl()
+        info = Info()
+        _check(lib().lrp_server_poll(self._h, ticket, ctypes.byref(done), ctypes.byref(st), ctypes.byref(rk),
+                                     ctypes.byref(info), ctypes.byref(lat)), "lrp_server_poll")
+        if not done.value:
+            return None
+        return self._result(ticket, st.value, rk.value, info, lat.value)
+
+    def wait(self, ticket: int):
+        st, rk, lat = _c_i32(), _c_i32(), _c_dbl()
+        info = Info()
+        _check(lib().lrp_server_wait(self._h, ticket, ctypes.byref(st), ctypes.byref(rk), ctypes.byref(info),
+                                     ctypes.byref(lat)), "lrp_server_wait")
+        return self._result(ticket, st.value, rk.value, info, lat.value)
+
+    def _result(self, ticket, status, rank, info, lat):
+        bufs = self._keep.pop(ticket)
+        lib().lrp_server_release(self._h, ticket)
+        return bufs[3], bufs[4], bufs[5], rank, status, info, lat
+
+    def stats(self) -> Dict:
+        st = ServerStats()
+        _check(lib().lrp_server_get_stats(self._h, ctypes.byref(st)), "lrp_server_get_stats")
+        return st.as_dict()
+
+
+def context_bytes(n: int, r_max: int, maxiter: int = 20, precision: str = "fp64") -> int:
+    return int(lib().lrp_context_bytes(n, r_max, maxiter, LRP_MIXED if precision == "mixed" else LRP_FP64))

@@ -58,3 +58,31 @@ def test_struct_layouts_match_header():
     assert L.Opts.prune_tau.offset == 8 and L.Opts.stream.offset == 16
     assert ctypes.sizeof(L.Info) == 48
     assert L.Info.rho.offset == 24 and L.Info.indicator.offset == 32 and L.Info.ms.offset == 40
+
+
+def test_server_rejects_bad_arguments():
+    lib = L.lib()
+    h = ctypes.c_void_p()
+    assert lib.lrp_server_create(ctypes.byref(h), 0, 4) == L.LRP_EINVAL
+    assert lib.lrp_server_create(ctypes.byref(h), 1 << 30, 0) == L.LRP_EINVAL
+    assert lib.lrp_server_create(ctypes.byref(h), 1 << 30, 65) == L.LRP_EINVAL
+    assert lib.lrp_server_create(None, 1 << 30, 4) == L.LRP_EINVAL
+    t = ctypes.c_int64()
+    assert lib.lrp_server_submit(None, None, ctypes.byref(t)) == L.LRP_EINVAL
+    assert lib.lrp_server_destroy(None) == L.LRP_OK
+    st = L.ServerStats()
+    assert lib.lrp_server_get_stats(None, ctypes.byref(st)) == L.LRP_EINVAL
+
+
+def test_context_bytes_scale():
+    small = L.lib().lrp_context_bytes(4095, 32, 20, 0)
+    big = L.lib().lrp_context_bytes(65535, 32, 20, 0)
+    assert 0 < small < big
+    assert L.lib().lrp_context_bytes(4094, 32, 20, 0) == 0
+    # the mixed path keeps the spectral factors and fibers in FP32
+    assert L.lib().lrp_context_bytes(65535, 32, 20, 1) < big
+
+
+def test_request_struct_layout():
+    assert ctypes.sizeof(L.Request) == 112
+    assert L.Request.tol.offset == 16 and L.Request.U_F.offset == 32 and L.Request.ldov.offset == 104

@@ -123,3 +123,40 @@ def test_tsqr_matches_householder(n, p, kind):
         # R agrees with LAPACK's up to the sign of each row
         sg = np.sign(np.diag(R)) * np.sign(np.diag(Rref))
         assert np.linalg.norm(R - sg[:, None] * Rref) <= 1e-12 * math.sqrt(p) * nrm * (1e4 if kind == "ill" else 1)
+
+
+def test_tsqr_on_rank_deficient_fibers_of_a_solve():
+    """The QR inputs of a rank-1 solve at the rank cap (6 of 16 columns exactly dependent):
+    Q must stay orthonormal and the cross approximation built from it must match the one
+    built from LAPACK's Q."""
+    from paper_2607_06021_amd import Solver
+
+    n = 255
+    U, s, V = workloads.make("n255_r5_fp64", 0, n=n)
+    U, s, V = U[:, :1], s[:1], V[:, :1]
+    mats = []
+    orig = cd.thin_qr
+
+    def cap(X):
+        mats.append(X.copy())
+        return orig(X)
+
+    cd.thin_qr = cap
+    try:
+        cd.solve(n, U, s, V, 16, 1e-10, 10)
+    finally:
+        cd.thin_qr = orig
+    print(f"captured {len(mats)} QR inputs", flush=True)
+    _torch()
+    worst = 0.0
+    with Solver(n, 16, 1e-10) as sol:
+        for X in mats:
+            Qd, Rd = sol.tsqr(to_dev(X))
+            Q, R = to_np(Qd), to_np(Rd)
+            p = X.shape[1]
+            orth = np.linalg.norm(Q.T @ Q - np.eye(p))
+            recon = np.linalg.norm(Q @ R - X) / np.linalg.norm(X)
+            worst = max(worst, orth)
+            assert orth <= 1e-13 * math.sqrt(p), (p, orth)
+            assert recon <= 1e-14 * math.sqrt(p) * 10, (p, recon)
+    print(f"  worst |QtQ-I| {worst:.2e}")

@@ -1,0 +1,71 @@
+"""The serving queue: every request's result is bit-identical to a solo lrp_solve of the same
+request, whatever else is in flight; admission respects the memory budget."""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+
+    from paper_2607_06021_amd import fortran
+
+    t = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    return fortran(t) if a.ndim == 2 else t
+
+
+def test_served_results_equal_solo_results():
+    import torch
+
+    from paper_2607_06021_amd import Solver
+    from paper_2607_06021_amd.lrp import Server
+
+    reqs = []
+    sizes = [1023, 4095, 16383, 1023, 65535, 4095, 255, 16383, 1023, 4095, 65535, 255]
+    for i, n in enumerate(sizes):
+        U, s, V, _ = workloads.bump_rhs(n, 1000 + i, 2 + (i * 7) % 19, 0.05, 0.2)
+        prec = "mixed" if i % 2 else "fp64"
+        reqs.append((n, _dev(U), _dev(s), _dev(V), prec))
+    torch.cuda.synchronize()
+    print(f"serving {len(reqs)} requests", flush=True)
+    with Server(budget_bytes=8 << 30, max_active=6) as srv:
+        tickets = [srv.submit(n, U, s, V, 48, 1e-10, 20, prec) for (n, U, s, V, prec) in reqs]
+        served = [srv.wait(t) for t in tickets]
+        stats = srv.stats()
+    print("  stats", stats, flush=True)
+    assert stats["completed"] == len(reqs) and stats["failed"] == 0
+    assert stats["bytes_in_use"] <= 8 << 30
+    lat = [r[6] for r in served]
+    print(f"  latency ms: median {np.median(lat):.2f} max {np.max(lat):.2f}")
+    for (n, U, s, V, prec), (Us, Ss, Vs, rank, status, info, _) in zip(reqs, served):
+        with Solver(n, 48, 1e-10, maxiter=20, precision=prec) as sol:
+            Uo, So, Vo, r, inf = sol.solve(U, s, V)
+        assert status == inf.status and rank == r and info.iters == inf.iters
+        assert torch.equal(Uo, Us) and torch.equal(So, Ss) and torch.equal(Vo, Vs), (n, prec)
+
+
+def test_small_budget_serializes_but_completes():
+    import torch
+
+    from paper_2607_06021_amd.lrp import Server, context_bytes
+
+    n = 4095
+    budget = int(context_bytes(n, 48) * 1.5)  # room for one context at a time
+    reqs = []
+    for i in range(4):
+        U, s, V, _ = workloads.bump_rhs(n, 50 + i, 5, 0.05, 0.2)
+        reqs.append((_dev(U), _dev(s), _dev(V)))
+    torch.cuda.synchronize()
+    print("serving under a one-context budget", flush=True)
+    with Server(budget_bytes=budget, max_active=4) as srv:
+        tickets = [srv.submit(n, U, s, V, 48, 1e-10, 20, "fp64") for (U, s, V) in reqs]
+        # a different shape forces the idle context to be freed
+        U, s, V, _ = workloads.bump_rhs(1023, 99, 4, 0.05, 0.2)
+        t2 = srv.submit(1023, _dev(U), _dev(s), _dev(V), 48, 1e-10, 20, "fp64")
+        res = [srv.wait(t) for t in tickets + [t2]]
+        st = srv.stats()
+    assert all(r[4] >= 0 for r in res)
+    assert st["completed"] == 5 and st["contexts"] <= 1

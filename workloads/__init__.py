@@ -123,6 +123,34 @@ def bump_rhs(
     return U, sigma, V, info
 
 
+def bump_rhs_device(n: int, seed: int, n_bumps: int, width_lo: float, width_hi: float, device,
+                    centre_lo: float = 0.2, centre_hi: float = 0.8):
+    """bump_rhs drawn with the same seeded parameters, evaluated on a torch device in FP64.
+
+    Returns (U, sigma, V) as column-major (n, r) CUDA tensors; used where thousands of
+    right-hand sides are needed at once (the served stream).
+    """
+    import torch
+
+    rng = np.random.default_rng(seed)
+    K = n_bumps
+    cx = rng.uniform(centre_lo, centre_hi, K)
+    cy = rng.uniform(centre_lo, centre_hi, K)
+    wx = rng.uniform(width_lo, width_hi, K)
+    wy = rng.uniform(width_lo, width_hi, K)
+    a = rng.standard_normal(K)
+    x = torch.arange(1, n + 1, dtype=torch.float64, device=device) * (1.0 / (n + 1))
+
+    def cols(c, w):
+        c = torch.as_tensor(c, dtype=torch.float64, device=device)[:, None]
+        w = torch.as_tensor(w, dtype=torch.float64, device=device)[:, None]
+        return torch.exp(-((x[None, :] - c) ** 2) / (2.0 * w * w))  # (K, n): column-major (n, K)
+
+    U = cols(cx, wx).t()
+    V = cols(cy, wy).t()
+    return U, torch.as_tensor(a, dtype=torch.float64, device=device), V
+
+
 def sine_rhs(n: int, modes: Sequence[tuple]):
     """RHS made only of separable sine modes [(kx, ky, amplitude), ...]."""
     x = grid(n)
