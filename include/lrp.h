@@ -69,7 +69,8 @@ typedef struct lrp_info {
   int32_t rank;      /* rank of the returned solution */
   int32_t nI, nJ;    /* sizes of the final (pruned) index sets */
   double rho;        /* ||X_k - X_{k-1}||_F / ||S_k||_F of the last pass (inf if not computed) */
-  double indicator;  /* min(eta1 (1+eta2), eta2 (1+eta1)) S_min / ||S_k||_F of the last pass */
+  double indicator;  /* min(eta1 (1+eta2), eta2 (1+eta1)) S_min / ||S_k||_F of the last pass;
+                        +inf where it cannot pass the test (pass 0, or 2 S_min/||S_k|| >= tol) */
   float ms;          /* device time of the whole solve, milliseconds (HIP events) */
 } lrp_info;
 
@@ -119,7 +120,7 @@ int lrp_get_index_sets(const lrp_ctx* ctx, int64_t* I, int32_t* nI, int64_t* J, 
  *   Ipre, Jpre  host, count x r_max: the index sets handed to the cross approximation;
  *   nIpre, nJpre, nI, nJ  host, count: their sizes before and after pruning;
  *   rank        host, count: rank of the pass's cross approximation;
- *   indicator, rho  host, count (rho is +inf where it was not needed).
+ *   indicator, rho  host, count (+inf where the stopping test did not need them).
  *   count       host in/out: capacity in passes on input, passes recorded on output.
  * Any array pointer may be NULL. Returns LRP_OK or LRP_EINVAL.
  */

@@ -172,7 +172,7 @@ int create_impl(lrp_ctx* c) {
     TRY(dalloc(&c->dst.tl_64, c2));
     TRY(dalloc(&c->dst.tl_32, c2));
     if (c->dst.four_step) {
-      if (hipMalloc(&c->dst.work, (size_t)c->dst.max_pairs * 2 * (n + 1) * 16) != hipSuccess) return LRP_ENOMEM;
+      if (hipMalloc(&c->dst.work, (size_t)c->dst.work_bytes) != hipSuccess) return LRP_ENOMEM;
     }
   }
   TRY(tsqr_plan(&c->tsqr, n, pm));
@@ -469,7 +469,7 @@ int64_t context_bytes(int64_t n, int pm, int maxiter, bool mixed) {
   DstPlan dp{};
   if (dst_plan(&dp, n, 2 * pm) == LRP_OK) {
     b += 24 * (int64_t)(dp.t1_count + 2 * std::max(dp.t2_count, 1));
-    if (dp.four_step) b += (int64_t)dp.max_pairs * 2 * (n + 1) * 16;
+    b += dp.work_bytes;
   }
   int64_t rows = n, br = kTsqrRows;                                // TSQR tree, two sides
   const int g = kTsqrRows / pm;

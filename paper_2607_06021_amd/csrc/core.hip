@@ -524,8 +524,17 @@ __global__ __launch_bounds__(kCoreThreads) void k_core(CoreArgs a) {
 
   // ---- eta: U_k(I,:) = Q(I,:) U^ and V_k(J,:) = Z(J,:) V~ on the pruned rows, each stored
   // tall (rows >= cols) so that Jacobi gives its min(rows, cols) singular values.
+  // Rows of an orthonormal basis have singular values <= 1, so eta_1, eta_2 >= 1 and the
+  // indicator is at least 2 S_min/||S||: when that bound already fails the stopping test (and
+  // at pass 0, where no stop is allowed) the indicator is not needed and is left at +inf.
   double smin1 = 0.0, smin2 = 0.0;
-  if (r > 0 && nIp > 0 && nJp > 0) {
+  bool need_eta;
+  {
+    double n2 = 0.0;
+    for (int l = 0; l < r; ++l) n2 = fma(sig[ord[l]], sig[ord[l]], n2);
+    need_eta = r > 0 && st->k >= 1 && 1.9 * sig[ord[r - 1]] < st->eps * sqrt(n2);
+  }
+  if (need_eta && nIp > 0 && nJp > 0) {
     double* E1 = B0;
     double* E2 = M;
     const bool t1 = nIp >= r, t2 = nJp >= r;
@@ -588,7 +597,7 @@ __global__ __launch_bounds__(kCoreThreads) void k_core(CoreArgs a) {
     const double eta1 = smin1 > 0.0 ? 1.0 / smin1 : INFINITY;
     const double eta2 = smin2 > 0.0 ? 1.0 / smin2 : INFINITY;
     double ind = INFINITY;
-    if (r > 0 && nrm > 0.0) ind = fmin(eta1 * (1.0 + eta2), eta2 * (1.0 + eta1)) * S[r - 1] / nrm;
+    if (need_eta && nrm > 0.0) ind = fmin(eta1 * (1.0 + eta2), eta2 * (1.0 + eta1)) * S[r - 1] / nrm;
     st->nrm = nrm;
     st->eta1 = eta1;
     st->eta2 = eta2;

@@ -11,14 +11,15 @@ namespace lrp {
 // ---------------------------------------------------------------- DST-I (dst.hip)
 struct DstPlan {
   int64_t n;
-  int logL, logL1, logL2;
+  int logL, logL1, logL2;  // L = 2(n+1); four-step: L = L1 L2 (pass 2 length L1, pass 1 length L2)
   int four_step;
-  int tile1, tile2;
   int max_pairs;
   int t1_count, t2_count;
+  int64_t s1;              // row stride (complex elements) of the four-step intermediate
+  int64_t work_bytes;      // bytes of the intermediate for max_pairs column pairs (FP64)
   double2 *t1_64, *t2_64, *tl_64;
   float2 *t1_32, *t2_32, *tl_32;
-  void* work;  // four-step intermediate: max_pairs x 2(n+1) complex doubles
+  void* work;
 };
 
 struct DstArgs {
@@ -35,7 +36,8 @@ struct DstArgs {
   const DevState* st;   // optional: skip after an error; pick_ret selects source/rank
   int pick_ret;
   // filled by the launcher
-  int logL, logL1, logL2, tile1, tile2;
+  int logL, logL1, logL2;
+  int64_t s1;
   const void *t1, *t2, *tl;
   void* work;
 };

@@ -53,7 +53,8 @@ def test_small_budget_serializes_but_completes():
     from paper_2607_06021_amd.lrp import Server, context_bytes
 
     n = 4095
-    budget = int(context_bytes(n, 48) * 1.5)  # room for one context at a time
+    # room for one n=4095 context, but not for it and an n=1023 one together
+    budget = context_bytes(n, 48) + context_bytes(1023, 48) - 1
     reqs = []
     for i in range(4):
         U, s, V, _ = workloads.bump_rhs(n, 50 + i, 5, 0.05, 0.2)
