@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -56,29 +57,90 @@ def time_solves(sol, args_dev, steps, warmup):
     return wall * 1e3 / steps, infos
 
 
-def dst_roofline(sol, n, ncols, reps=20):
-    """Live HIP-event timing of the batched DST-I (FP64) on an n x ncols matrix."""
-    import torch
+# MI355X published peaks
+FP64_PEAK_TFLOPS = 78.6
 
-    from paper_2607_06021_amd import fortran
 
-    X = fortran(torch.randn(n, ncols, dtype=torch.float64, device="cuda"))
-    for _ in range(3):
-        sol.dst1(X)
-    stream = sol.stream
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        sol.dst1(X)
-    e1.record(stream)
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    bytes_alg = 2.0 * n * ncols * 8
-    gbs = bytes_alg / (ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "dst1 (pass1+pass2)",
-            "ms_per_launch": round(ms, 4), "alg_bytes_per_launch": bytes_alg}
+def profile_solve(w, prec, args_dev):
+    """One solve in profile mode: per-kernel device time from HIP events recorded around every
+    launch on the solve's stream, plus the pass sizes needed for the algorithmic counts."""
+    from paper_2607_06021_amd import Solver
+
+    with Solver(w.n, w.r_max, w.tol, maxiter=w.maxiter, precision=prec, profile=True) as sol:
+        sol.solve(*args_dev)  # warm
+        _, _, _, r, info = sol.solve(*args_dev)
+        prof = sol.profile()
+        trace = sol.trace()
+    return prof, trace, info
+
+
+def kernel_model(w, prec, trace, info, rF):
+    """Algorithmic bytes and flops of each kernel class over one solve (what the method must
+    move or compute; counted from the pass sizes of the trace)."""
+    n, pm = w.n, w.r_max
+    wb = 4 if prec == "mixed" else 8           # width of the spectral factors and fibers
+    r = info.rank
+    passes = trace                              # passes actually computed
+    out = {}
+    # DST: forward U_F, V_F (read FP64, write w); back: read rank columns, write all r_max
+    out["dst"] = {"bytes": 2 * n * rF * (8 + wb) + 2 * (n * r * 8 + n * pm * 8)}
+    fb = 0
+    pb = 0
+    pf = 0
+    cf = 0.0
+    for t in passes:
+        pI, pJ = len(t["I_pre"]), len(t["J_pre"])
+        rk = t["rank"]
+        fb += 2 * n * rF * wb + n * (pI + pJ) * wb + 2 * n * wb
+        pb += n * (pI + pJ) * 8 + 2 * n * rk * 8
+        pf += 2 * n * (pI + pJ) * rk
+        # core: Householder QR of the m0 x k0 interpolation rows, triangular inverse, the core
+        # product, the SVD of the |J| x |I| core (Golub-Van Loan count 4m^2n + 8mn^2 + 9n^3) and,
+        # when the indicator was evaluated, two singular-value-only SVDs (4mn^2 - 4n^3/3)
+        m0, k0 = max(pI, pJ), min(pI, pJ)
+        mm, kk = max(pI, pJ), min(pI, pJ)
+        cf += 2 * m0 * k0 ** 2 - 2 * k0 ** 3 / 3 + k0 ** 3 / 3 + 2 * pI * pJ * k0
+        cf += 4 * mm ** 2 * kk + 8 * mm * kk ** 2 + 9 * kk ** 3
+        if math.isfinite(t["indicator"]):
+            for a, b in ((t["nI"], rk), (t["nJ"], rk)):
+                a, b = max(a, b), min(a, b)
+                cf += 4 * a * b * b - 4 * b ** 3 / 3
+    out["fiber"] = {"bytes": fb}
+    pb += 2 * (n * rF * 8 + n * rF * 8)       # warm start: U_-1 = Q U^, V_-1 = Z V~ (rank <= r_F)
+    pf += 2 * 2 * n * rF * rF
+    out["prod"] = {"bytes": pb, "flops": pf}
+    out["core"] = {"flops": cf}
+    return out
+
+
+def rooflines(w, prec, prof, trace, info, rF):
+    """Roofline per kernel class over one profiled solve: total algorithmic bytes (flops) of
+    the class divided by its total device time (HIP events); launches that found the solve
+    already finished count in the time, not in the work."""
+    m = kernel_model(w, prec, trace, info, rF)
+
+    def t(*names):
+        return (sum(prof.get(nm, (0, 0.0))[1] for nm in names),
+                max([prof.get(nm, (0, 0.0))[0] for nm in names]))
+
+    def hbm(bytes_, ms, launches, kernel):
+        gbs = bytes_ / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernel,
+                "ms_per_launch": round(ms / max(launches, 1), 5), "launches": launches,
+                "alg_bytes_per_launch": round(bytes_ / max(launches, 1))}
+
+    res = {"dst": hbm(m["dst"]["bytes"], *t("k_dst_pass1", "k_dst_pass2", "k_dst_single"),
+                      "k_dst_pass1 + k_dst_pass2 (four-step), or k_dst_single"),
+           "fiber": hbm(m["fiber"]["bytes"], *t("k_fiber"), "k_fiber"),
+           "prod": hbm(m["prod"]["bytes"], *t("k_prod"), "k_prod (FP64 MFMA)")}
+    ms, launches = t("k_core")
+    tf = m["core"]["flops"] / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    res["core"] = {"bound": "alu", "achieved": round(tf, 6), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                   "frac": round(tf / FP64_PEAK_TFLOPS, 7), "traffic": None, "kernel": "k_core (one workgroup)",
+                   "ms_per_launch": round(ms / max(launches, 1), 4), "launches": launches,
+                   "alg_flops_per_launch": round(m["core"]["flops"] / max(launches, 1))}
+    return res
 
 
 def served_leg(count, seed, budget_gb, max_active, rate=None):
@@ -144,6 +206,18 @@ def cpu_baseline(w, U, s, V):
                "sample": f"one full FP64 solve of the same workload (seed 0, {o.iters} passes)"}
 
 
+def dominant_roofline(res):
+    """Roofline of the kernel with the largest device time in the profiled solve."""
+    key = {"k_core": "core", "k_dst_pass1": "dst", "k_dst_pass2": "dst", "k_dst_single": "dst",
+           "k_fiber": "fiber", "k_prod": "prod"}.get(res["dominant"])
+    if key is None:
+        return {"bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None,
+                "traffic": None, "kernel": res["dominant"], "note": "no algorithmic model for this kernel"}
+    r = dict(res["rooflines"][key])
+    r["share_of_solve"] = res["profile"][res["dominant"]]["share"]
+    return r
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -172,9 +246,14 @@ def main():
         Uo, So, Vo, r, info = sol.solve(*args_dev)
         outs[prec] = (Uo[:, :r].cpu().numpy(), So[:r].cpu().numpy(), Vo[:, :r].cpu().numpy())
         results[prec] = {"ms": ms, "info": info.as_dict(), "dev_ms": float(np.median([i["ms"] for i in infos]))}
-        if prec == "fp64":
-            results["roofline"] = dst_roofline(sol, w.n, w.r_max)
         sol.close()
+        prof, trace, pinfo = profile_solve(w, prec, args_dev)
+        total = sum(ms for _, ms in prof.values())
+        results[prec]["profile"] = {k: {"launches": v[0], "ms": round(v[1], 4), "share": round(v[1] / total, 4)}
+                                    for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
+        results[prec]["rooflines"] = rooflines(w, prec, prof, trace, pinfo, U.shape[1])
+        dom = max(prof.items(), key=lambda kv: kv[1][1])[0]
+        results[prec]["dominant"] = dom
         log(f"  {prec}: {ms:.3f} ms/solve (device {results[prec]['dev_ms']:.3f} ms) "
             f"iters {info.iters} rank {info.rank} status {info.status}")
     served = None
@@ -221,7 +300,9 @@ def main():
         "served_p50_ms": served["p50_ms"] if served else None,
         "served_p99_ms": served["p99_ms"] if served else None,
         "served": served,
-        "roofline": results.get("roofline"),
+        "roofline": dominant_roofline(results[head]),
+        "kernels": {p: {"rooflines": results[p]["rooflines"], "profile": results[p]["profile"]}
+                    for p in ("mixed", "fp64") if p in results},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

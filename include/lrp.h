@@ -60,7 +60,17 @@ typedef struct lrp_opts {
   double prune_tau;  /* relative threshold on |diag R| for dropping redundant indices
                         (Algorithm 4); 0 -> 1e-12 (FP64) or 1e-7 (mixed) */
   void* stream;      /* hipStream_t to order all work on; NULL -> a stream owned by the context */
+  int32_t flags;     /* bitwise OR of enum lrp_flags; other bits -> LRP_EINVAL */
+  int32_t reserved;  /* must be 0 */
 } lrp_opts;
+
+enum lrp_flags {
+  LRP_FLAG_PROFILE = 1  /* record the device time of every kernel launch of each solve with
+                           HIP events on the solve's stream (read with lrp_get_profile). The
+                           passes are then launched one kernel at a time instead of as graphs,
+                           and the stream is held for about 0.5 ms at the start of each solve
+                           so that the host is ahead of the device; results are unchanged. */
+};
 
 /* Per-solve report (host struct), filled by lrp_solve when non-NULL. */
 typedef struct lrp_info {
@@ -127,6 +137,25 @@ int lrp_get_index_sets(const lrp_ctx* ctx, int64_t* I, int32_t* nI, int64_t* J, 
 int lrp_get_trace(const lrp_ctx* ctx, int32_t* count, int32_t* Ipre, int32_t* nIpre, int32_t* Jpre,
                   int32_t* nJpre, int32_t* nI, int32_t* nJ, int32_t* rank, double* indicator,
                   double* rho);
+
+/* One kernel class of a profiled solve (host struct filled by lrp_get_profile). */
+typedef struct lrp_kernel_time {
+  const char* name;  /* kernel name (static string owned by the library) */
+  int32_t launches;  /* launches in the last solve */
+  double ms;         /* their summed device time, milliseconds: from the HIP event recorded
+                        before the launch to the one recorded before the next operation */
+} lrp_kernel_time;
+
+/*
+ * lrp_get_profile -- per-kernel device time of the last lrp_solve of a context created with
+ * LRP_FLAG_PROFILE.
+ *   count  host, in: capacity of out; out: number of kernel classes that ran (entries beyond
+ *          the capacity are counted but not written).
+ *   out    host array of *count entries (may be NULL when *count is 0).
+ * Returns LRP_OK (count 0 for a context without the flag), or LRP_EINVAL (NULL arguments, or a
+ * profiled context that has not completed a solve).
+ */
+int lrp_get_profile(const lrp_ctx* ctx, int32_t* count, lrp_kernel_time* out);
 
 /* lrp_destroy -- frees the context and its workspace (NULL is a no-op). */
 int lrp_destroy(lrp_ctx* ctx);

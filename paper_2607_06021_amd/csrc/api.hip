@@ -86,6 +86,8 @@ void free_ctx(lrp_ctx* c) {
   dfree(c->dst.t2_32);
   dfree(c->dst.tl_32);
   dfree(c->dst.work);
+  for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
+  c->prof_ev.clear();
   for (int L = 0; L < c->tsqr.nlevels; ++L)
     for (int s = 0; s < 2; ++s) {
       dfree(c->tsqr.lev[L].V[s]);
@@ -187,6 +189,44 @@ int create_impl(lrp_ctx* c) {
   TRY(dst_tables(&c->dst, c->stream));
   if (hipStreamSynchronize(c->stream) != hipSuccess) return LRP_EDEVICE;
   return LRP_OK;
+}
+
+// ---------------------------------------------------------------- launch profile
+static thread_local lrp_ctx* g_prof = nullptr;  // context recording a profile on this thread
+
+void prof_mark(hipStream_t s, int id) {
+  lrp_ctx* c = g_prof;
+  if (!c || c->stream != s) return;
+  if (c->prof_used == c->prof_ev.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    c->prof_ev.push_back(e);
+    c->prof_id.push_back(-1);
+  }
+  if (hipEventRecord(c->prof_ev[c->prof_used], s) != hipSuccess) return;
+  c->prof_id[c->prof_used] = id;
+  ++c->prof_used;
+}
+
+// Holds the stream for a bounded time (about 0.5 ms) so that the host enqueues the first
+// stages before the device reaches them; launch gaps then do not enter the profile.
+__global__ void k_hold(int iters) {
+  for (int i = 0; i < iters; ++i) __builtin_amdgcn_s_sleep(127);
+}
+
+static void prof_reduce(lrp_ctx* c) {
+  for (int q = 0; q < K_COUNT; ++q) {
+    c->prof_ms[q] = 0.0;
+    c->prof_n[q] = 0;
+  }
+  for (size_t i = 0; i + 1 < c->prof_used; ++i) {
+    const int id = c->prof_id[i];
+    if (id < 0 || id >= K_COUNT) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->prof_ev[i], c->prof_ev[i + 1]) != hipSuccess) continue;
+    c->prof_ms[id] += ms;
+    c->prof_n[id] += 1;
+  }
 }
 
 int enqueue_pass_kernels(lrp_ctx* c, int k) {
@@ -362,7 +402,7 @@ int enqueue_start(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const doub
 // possible the kernels are launched directly.
 int enqueue_pass(lrp_ctx* c, int k) {
   const int par = k & 1;
-  if (c->use_graphs && !c->gexec[par]) {
+  if (c->use_graphs && !c->profile && !c->gexec[par]) {
     hipGraph_t g = nullptr;
     bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed) == hipSuccess;
     const int rc = ok ? enqueue_pass_kernels(c, k) : LRP_EDEVICE;
@@ -375,7 +415,7 @@ int enqueue_pass(lrp_ctx* c, int k) {
       (void)hipGetLastError();
     }
   }
-  if (c->use_graphs && c->gexec[par])
+  if (c->use_graphs && !c->profile && c->gexec[par])
     return hipGraphLaunch(c->gexec[par], c->stream) == hipSuccess ? LRP_OK : LRP_EDEVICE;
   return enqueue_pass_kernels(c, k);
 }
@@ -383,6 +423,7 @@ int enqueue_pass(lrp_ctx* c, int k) {
 // After pass k: copy the stop flag to pinned memory and mark the point with an event.
 int enqueue_poll(lrp_ctx* c, int k) {
   const int slot = k & 1;
+  prof_mark(c->stream, K_COPY);
   if (hipMemcpyAsync(&c->done_host[slot], &c->st->done, sizeof(int), hipMemcpyDeviceToHost, c->stream) !=
       hipSuccess)
     return LRP_EDEVICE;
@@ -413,6 +454,7 @@ int enqueue_finish(lrp_ctx* c, double* U_out, int64_t ldou, double* S_out, doubl
   db.Y = V_out;
   db.ldy = ldov;
   TRY(dst_launch(c->dst, db, mixed, s));
+  prof_mark(s, K_COPY);
   if (hipEventRecord(c->ev1, s) != hipSuccess) return LRP_EDEVICE;
   if (hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, s) != hipSuccess)
     return LRP_EDEVICE;
@@ -490,6 +532,18 @@ int64_t context_bytes(int64_t n, int pm, int maxiter, bool mixed) {
 int solve_impl(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const double* sigma_F,
                const double* V_F, int64_t ldv, double* U_out, int64_t ldou, double* S_out,
                double* V_out, int64_t ldov, int32_t* r_out, lrp_info* info) {
+  struct ProfScope {  // ends the recording on every return path
+    lrp_ctx* c;
+    ~ProfScope() {
+      if (c) g_prof = nullptr;
+    }
+  } scope{c->profile ? c : nullptr};
+  if (c->profile) {
+    c->prof_used = 0;
+    hipLaunchKernelGGL(k_hold, dim3(1), dim3(64), 0, c->stream, 150);
+    if (hipGetLastError() != hipSuccess) return LRP_EDEVICE;
+    g_prof = c;
+  }
   TRY(enqueue_start(c, rF, U_F, ldu, sigma_F, V_F, ldv));
   // passes; the stop flag is read one pass behind the device
   for (int k = 0; k < c->maxiter; ++k) {
@@ -503,6 +557,10 @@ int solve_impl(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const double*
   }
   TRY(enqueue_finish(c, U_out, ldou, S_out, V_out, ldov));
   if (hipEventSynchronize(c->evfin) != hipSuccess) return LRP_EDEVICE;
+  if (c->profile) {
+    g_prof = nullptr;
+    prof_reduce(c);
+  }
   return collect(c, r_out, info);
 }
 
@@ -534,6 +592,7 @@ int lrp_create(lrp_ctx** ctx, int64_t n, int32_t r_max, double tol, const lrp_op
   if (o.maxiter < 0 || o.maxiter > 1000) return LRP_EINVAL;
   if (o.precision != LRP_FP64 && o.precision != LRP_MIXED) return LRP_EINVAL;
   if (!(o.prune_tau >= 0.0) || o.prune_tau >= 1.0) return LRP_EINVAL;
+  if ((o.flags & ~LRP_FLAG_PROFILE) || o.reserved != 0) return LRP_EINVAL;
   lrp_ctx* c = new (std::nothrow) lrp_ctx();
   if (!c) return LRP_ENOMEM;
   c->n = n;
@@ -542,6 +601,7 @@ int lrp_create(lrp_ctx** ctx, int64_t n, int32_t r_max, double tol, const lrp_op
   c->maxiter = o.maxiter == 0 ? 20 : o.maxiter;
   c->precision = o.precision;
   c->tau = o.prune_tau > 0.0 ? o.prune_tau : (o.precision == LRP_MIXED ? 1e-7 : 1e-12);
+  c->profile = (o.flags & LRP_FLAG_PROFILE) != 0;
   if (o.stream) {
     c->stream = (hipStream_t)o.stream;
   } else {
@@ -574,6 +634,31 @@ int64_t lrp_context_bytes(int64_t n, int32_t r_max, int32_t maxiter, int32_t pre
   if (n < 3 || !pow2(n + 1) || n + 1 > (int64_t(1) << 23) || r_max < 1 || r_max > kPMax || r_max > n) return 0;
   if (maxiter < 0 || (precision != LRP_FP64 && precision != LRP_MIXED)) return 0;
   return context_bytes(n, r_max, maxiter == 0 ? 20 : maxiter, precision == LRP_MIXED);
+}
+
+int lrp_get_profile(const lrp_ctx* c, int32_t* count, lrp_kernel_time* out) {
+  static const char* const names[K_COUNT] = {
+      "k_init_state", "k_scan", "k_dst_single", "k_dst_pass1", "k_dst_pass2", "k_fiber",
+      "k_tsqr_factor", "k_tsqr_apply", "k_core_warm", "k_core", "k_prod", "k_pi", "k_gmax",
+      "k_topk_block", "k_topk_merge", "k_select", "k_rho_a", "k_rho_b", "k_rho_reduce",
+      "k_rho_final", "k_finalize", "copy"};
+  if (!c || !count || *count < 0 || (*count > 0 && !out)) return LRP_EINVAL;
+  if (!c->profile || !c->solved) {
+    *count = 0;
+    return c->profile ? LRP_EINVAL : LRP_OK;
+  }
+  int m = 0;
+  for (int q = 0; q < K_COUNT; ++q) {
+    if (c->prof_n[q] == 0) continue;
+    if (m < *count) {
+      out[m].name = names[q];
+      out[m].launches = c->prof_n[q];
+      out[m].ms = c->prof_ms[q];
+    }
+    ++m;
+  }
+  *count = m;
+  return LRP_OK;
 }
 
 int lrp_get_index_sets(const lrp_ctx* c, int64_t* I, int32_t* nI, int64_t* J, int32_t* nJ) {

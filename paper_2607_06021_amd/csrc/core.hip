@@ -673,10 +673,13 @@ __global__ __launch_bounds__(kCoreThreads) void k_core_warm(CoreArgs a) {
 }
 
 int core_launch(const CoreArgs& a, bool warm, hipStream_t s) {
-  if (warm)
+  if (warm) {
+    prof_mark(s, K_CORE_WARM);
     hipLaunchKernelGGL(k_core_warm, dim3(1), dim3(kCoreThreads), 0, s, a);
-  else
+  } else {
+    prof_mark(s, K_CORE);
     hipLaunchKernelGGL(k_core, dim3(1), dim3(kCoreThreads), 0, s, a);
+  }
   return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
 }
 
@@ -712,6 +715,7 @@ __global__ void k_init_state(DevState* st, int rF, double eps, double tau) {
 }
 
 int init_state_launch(DevState* st, int rF, double eps, double tau, hipStream_t s) {
+  prof_mark(s, K_INIT);
   hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, st, rF, eps, tau);
   return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
 }
@@ -736,6 +740,7 @@ int scan_inputs_launch(DevState* st, const double* U, int64_t ldu, const double*
                        const double* sig, int64_t n, int rF, hipStream_t s) {
   const int64_t total = n * rF;
   const int blocks = (int)std::min<int64_t>(1024, (total + 255) / 256);
+  prof_mark(s, K_SCAN);
   hipLaunchKernelGGL(k_scan, dim3(std::max(blocks, 1)), dim3(256), 0, s, st, U, ldu, V, ldv, sig, n, rF);
   return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
 }
@@ -768,6 +773,7 @@ __global__ void k_finalize(DevState* st, double* S_out, int r_max) {
 }
 
 int finalize_launch(DevState* st, double* S_out, int r_max, hipStream_t s) {
+  prof_mark(s, K_FINALIZE);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, st, S_out, r_max);
   return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
 }

@@ -2,6 +2,8 @@
 // solve entry point and the serving scheduler.
 #pragma once
 
+#include <vector>
+
 #include "lrp_kernels.h"
 
 struct lrp_ctx {
@@ -44,6 +46,13 @@ struct lrp_ctx {
   hipGraphExec_t gexec[2] = {nullptr, nullptr};  // captured pass, per parity
   bool use_graphs = true;
   bool solved = false;
+  // optional per-kernel timing (LRP_FLAG_PROFILE): events recorded before every launch
+  bool profile = false;
+  std::vector<hipEvent_t> prof_ev;
+  std::vector<int> prof_id;
+  size_t prof_used = 0;
+  double prof_ms[lrp::K_COUNT] = {};
+  int prof_n[lrp::K_COUNT] = {};
 };
 
 

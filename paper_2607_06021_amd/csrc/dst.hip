@@ -289,13 +289,27 @@ __device__ __forceinline__ void put_pair(const DstArgs& a, int ca, int cb, int n
 __host__ __device__ constexpr int single_seqs(int logL) {
   return (1 << logL) / 16 >= 64 ? 1 : 64 / ((1 << logL) >= 16 ? (1 << logL) / 16 : 1);
 }
-__host__ __device__ constexpr int tile1_of(int log2) { return (4096 >> log2) < 1 ? 1 : ((4096 >> log2) > 16 ? 16 : (4096 >> log2)); }
-template <typename T>
-__host__ __device__ constexpr int tile2_of(int log1) {
-  return ((4096 * 16 / (int)sizeof(cx<T>)) >> log1) > 16 ? 16
-         : ((4096 * 16 / (int)sizeof(cx<T>)) >> log1) < 1 ? 1
-         : ((4096 * 16 / (int)sizeof(cx<T>)) >> log1);
+// Largest power-of-two tile (columns per workgroup) with at most `cap` columns, at most 512
+// threads (16 elements each) and at most kLdsMax bytes of LDS.
+constexpr int kLdsMax = 80 * 1024;  // two workgroups per CU
+__host__ __device__ constexpr int lds_pass1(int log2, int tj, int esz) { return tj * seq_len(1 << log2) * esz; }
+__host__ __device__ constexpr int lds_pass2(int log1, int tk, int esz) {
+  return (tk * seq_len(1 << log1) > (1 << log1) * (tk + 1) ? tk * seq_len(1 << log1) : (1 << log1) * (tk + 1)) * esz;
 }
+__host__ __device__ constexpr int tile1_for(int log2, int esz, int cap) {
+  int t = cap;
+  while (t > 1 && (lds_pass1(log2, t, esz) > kLdsMax || t * ((1 << log2) / 16) > 512)) t >>= 1;
+  return t;
+}
+__host__ __device__ constexpr int tile2_for(int log1, int esz, int cap) {
+  int t = cap;
+  while (t > 1 && (lds_pass2(log1, t, esz) > kLdsMax || t * ((1 << log1) / 16) > 512)) t >>= 1;
+  return t;
+}
+template <typename T>
+__host__ __device__ constexpr int tile1_of(int log2) { return tile1_for(log2, (int)sizeof(cx<T>), 32); }
+template <typename T>
+__host__ __device__ constexpr int tile2_of(int log1) { return tile2_for(log1, (int)sizeof(cx<T>), 16); }
 
 // ---------------------------------------------------------------- L <= 4096: one pass
 template <typename T, int LOGL>
@@ -326,22 +340,29 @@ __global__ __launch_bounds__(512) void k_dst_single(DstArgs a) {
 }
 
 // ---------------------------------------------------------------- four-step pass 1
-// Block: TJ columns j1 (lane-fastest, so global reads and writes are coalesced) x L2/16 threads.
+// Block: TJ columns j1 (lane-fastest, so global reads and writes are coalesced) x L2/16 threads;
+// TJ = 16 (FP64) or 32 (FP32) columns, so each row of the input is read in 128- or 256-byte pieces.
 template <typename T, int LOG2>
 __global__ __launch_bounds__(512) void k_dst_pass1(DstArgs a) {
   constexpr int L2 = 1 << LOG2, E = 16, TP = L2 / E;
-  constexpr int TJ = tile1_of(LOG2), SEQ = seq_len(L2);
+  constexpr int TJ = tile1_of<T>(LOG2), SEQ = seq_len(L2);
   __shared__ cx<T> lds[TJ * SEQ];
   const double* X;
   int ncols;
   if (!dst_resolve(a, X, ncols)) return;
-  const int pair = blockIdx.y;
+  const int L1 = 1 << a.logL1;
+  // blocks: the L1/(2 TJ) full column tiles of every pair first, then the tile holding the
+  // single column j1 = L1/2 of every pair, so that the light tiles form the tail of the grid
+  const int nfull = (L1 / 2) / TJ;
+  const int npairs = gridDim.x / (nfull + 1);
+  const int b = blockIdx.x;
+  const int tile = b < nfull * npairs ? b % nfull : nfull;
+  const int pair = b < nfull * npairs ? b / nfull : b - nfull * npairs;
   const int ca = 2 * pair, cb = ca + 1;
   if (ca >= a.ncols_out || ca >= ncols) return;  // all-zero pairs are written by pass 2 alone
   const int cl = threadIdx.x % TJ, tt = threadIdx.x / TJ;
-  const int L1 = 1 << a.logL1;
   const int64_t M = (int64_t)L1 * L2 / 2;
-  const int j1 = blockIdx.x * TJ + cl;
+  const int j1 = tile * TJ + cl;
   const bool valid = j1 <= L1 / 2;
   const double* xa = valid ? X + (int64_t)ca * a.ldx : nullptr;
   const double* xb = valid && cb < ncols ? X + (int64_t)cb * a.ldx : nullptr;
@@ -376,11 +397,16 @@ __global__ __launch_bounds__(512) void k_dst_pass2(DstArgs a) {
   const double* X;
   int ncols;
   if (!dst_resolve(a, X, ncols)) return;
-  const int pair = blockIdx.y;
+  const int L2 = 1 << a.logL2;
+  // blocks ordered as in pass 1: full tiles of k2 < L2/2 first, the k2 = L2/2 tiles last
+  const int nfull = (L2 / 2) / TK;
+  const int npairs = gridDim.x / (nfull + 1);
+  const int b = blockIdx.x;
+  const int tile = b < nfull * npairs ? b % nfull : nfull;
+  const int pair = b < nfull * npairs ? b / nfull : b - nfull * npairs;
   const int ca = 2 * pair, cb = ca + 1;
   if (ca >= a.ncols_out) return;
-  const int L2 = 1 << a.logL2;
-  const int k0 = blockIdx.x * TK;
+  const int k0 = tile * TK;
   const int nthreads = TK * TP;
   double sa, sb;
   col_scales(a, ca, cb, ncols, sa, sb);
@@ -496,6 +522,7 @@ static void launch_single(int logL, int npairs, const DstArgs& a, hipStream_t s)
 #define LRP_SINGLE(LG)                                                                      \
   case LG: {                                                                                \
     constexpr int seqs = single_seqs(LG), tp = (1 << LG) < 16 ? 1 : (1 << LG) / 16;        \
+    prof_mark(s, K_DST_SINGLE);                                                             \
     hipLaunchKernelGGL((k_dst_single<T, LG>), dim3((npairs + seqs - 1) / seqs), dim3(seqs * tp), 0, s, a); \
     break;                                                                                  \
   }
@@ -512,15 +539,17 @@ static void launch_four_step(int logL1, int logL2, int npairs, const DstArgs& a,
   const int L1 = 1 << logL1, L2 = 1 << logL2;
 #define LRP_P1(LG)                                                                          \
   case LG: {                                                                                \
-    constexpr int tj = tile1_of(LG);                                                        \
-    hipLaunchKernelGGL((k_dst_pass1<T, LG>), dim3((L1 / 2 + 1 + tj - 1) / tj, npairs),      \
+    constexpr int tj = tile1_of<T>(LG);                                                     \
+    prof_mark(s, K_DST_PASS1);                                                              \
+    hipLaunchKernelGGL((k_dst_pass1<T, LG>), dim3((L1 / 2 / tj + 1) * npairs),              \
                        dim3(tj * ((1 << LG) / 16)), 0, s, a);                               \
     break;                                                                                  \
   }
 #define LRP_P2(LG)                                                                          \
   case LG: {                                                                                \
     constexpr int tk = tile2_of<T>(LG);                                                     \
-    hipLaunchKernelGGL((k_dst_pass2<T, LG>), dim3((L2 / 2 + 1 + tk - 1) / tk, npairs),      \
+    prof_mark(s, K_DST_PASS2);                                                              \
+    hipLaunchKernelGGL((k_dst_pass2<T, LG>), dim3((L2 / 2 / tk + 1) * npairs),              \
                        dim3(tk * ((1 << LG) / 16)), 0, s, a);                               \
     break;                                                                                  \
   }

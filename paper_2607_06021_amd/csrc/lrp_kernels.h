@@ -9,6 +9,17 @@
 namespace lrp {
 
 // ---------------------------------------------------------------- DST-I (dst.hip)
+// ---------------------------------------------------------------- launch profile
+// Kernel classes for the optional per-kernel timing of a solve (api.hip).
+enum KernelId {
+  K_INIT, K_SCAN, K_DST_SINGLE, K_DST_PASS1, K_DST_PASS2, K_FIBER, K_TSQR_FACTOR, K_TSQR_APPLY,
+  K_CORE_WARM, K_CORE, K_PROD, K_PI, K_GMAX, K_TOPK_BLOCK, K_TOPK_MERGE, K_SELECT, K_RHO_A,
+  K_RHO_B, K_RHO_REDUCE, K_RHO_FINAL, K_FINALIZE, K_COPY, K_COUNT
+};
+// Called right before a launch (or copy) on stream s: when this thread is recording a
+// profile on s, records an event that ends the previous entry and starts this one.
+void prof_mark(hipStream_t s, int id);
+
 struct DstPlan {
   int64_t n;
   int logL, logL1, logL2;  // L = 2(n+1); four-step: L = L1 L2 (pass 2 length L1, pass 1 length L2)

@@ -285,7 +285,9 @@ int select_candidates(const SelectPlan& p, const DevState* st, const double* U[2
     pa.pi[q] = p.pi[q];
     pa.bmax[q] = p.bmax[q];
   }
+  prof_mark(s, K_PI);
   hipLaunchKernelGGL(k_pi, dim3(p.nblocks, 2), dim3(256), 0, s, pa);
+  prof_mark(s, K_GMAX);
   hipLaunchKernelGGL(k_gmax, dim3(2), dim3(256), 0, s, st, nullptr, p.bmax[0], p.bmax[1], p.nblocks,
                      p.gmax);
   TopkArgs ta{};
@@ -298,6 +300,7 @@ int select_candidates(const SelectPlan& p, const DevState* st, const double* U[2
     ta.cs[q] = p.cand_s[0][q];
     ta.ci[q] = p.cand_i[0][q];
   }
+  prof_mark(s, K_TOPK_BLOCK);
   hipLaunchKernelGGL(k_topk_block, dim3(p.nblocks, 2), dim3(256), 0, s, ta);
   int slot = 0;
   for (int L = 0; L < p.nlevels; ++L) {
@@ -312,6 +315,7 @@ int select_candidates(const SelectPlan& p, const DevState* st, const double* U[2
       ma.out_s[q] = p.cand_s[slot ^ 1][q];
       ma.out_i[q] = p.cand_i[slot ^ 1][q];
     }
+    prof_mark(s, K_TOPK_MERGE);
     hipLaunchKernelGGL(k_topk_merge, dim3(outl, 2), dim3(256), 0, s, ma);
     slot ^= 1;
   }
@@ -320,6 +324,7 @@ int select_candidates(const SelectPlan& p, const DevState* st, const double* U[2
 }
 
 int select_update(const SelectArgs& a, hipStream_t s) {
+  prof_mark(s, K_SELECT);
   hipLaunchKernelGGL(k_select, dim3(1), dim3(kPMax), 0, s, a);
   return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
 }

@@ -28,7 +28,15 @@ _c_vp = ctypes.c_void_p
 
 
 class Opts(ctypes.Structure):
-    _fields_ = [("maxiter", _c_i32), ("precision", _c_i32), ("prune_tau", _c_dbl), ("stream", _c_vp)]
+    _fields_ = [("maxiter", _c_i32), ("precision", _c_i32), ("prune_tau", _c_dbl), ("stream", _c_vp),
+                ("flags", _c_i32), ("reserved", _c_i32)]
+
+
+LRP_FLAG_PROFILE = 1
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("launches", _c_i32), ("ms", _c_dbl)]
 
 
 class Info(ctypes.Structure):
@@ -123,6 +131,8 @@ def lib() -> ctypes.CDLL:
     L.lrp_server_destroy.restype = ctypes.c_int
     L.lrp_context_bytes.argtypes = [_c_i64, _c_i32, _c_i32, _c_i32]
     L.lrp_context_bytes.restype = ctypes.c_int64
+    L.lrp_get_profile.argtypes = [_c_vp, P(_c_i32), P(KernelTime)]
+    L.lrp_get_profile.restype = ctypes.c_int
     _LIB = L
     return L
 
@@ -161,7 +171,7 @@ class Solver:
     """A library context: grid size n (n+1 a power of two), rank cap r_max, tolerance tol."""
 
     def __init__(self, n: int, r_max: int, tol: float, maxiter: int = 20, precision: str = "fp64",
-                 prune_tau: float = 0.0, stream=None):
+                 prune_tau: float = 0.0, stream=None, profile: bool = False):
         import torch
 
         self.n, self.r_max, self.tol = int(n), int(r_max), float(tol)
@@ -173,7 +183,7 @@ class Solver:
             stream = torch.cuda.Stream()
         self.stream = stream
         o = Opts(self.maxiter, LRP_MIXED if precision == "mixed" else LRP_FP64, float(prune_tau),
-                 _c_vp(stream.cuda_stream))
+                 _c_vp(stream.cuda_stream), LRP_FLAG_PROFILE if profile else 0, 0)
         h = _c_vp()
         _check(lib().lrp_create(ctypes.byref(h), self.n, self.r_max, self.tol, ctypes.byref(o)), "lrp_create")
         self._h = h
@@ -194,6 +204,15 @@ class Solver:
 
     def __exit__(self, *exc):
         self.close()
+
+    def profile(self) -> dict:
+        """Per-kernel device time of the last solve (context created with profile=True):
+        {name: (launches, ms)}, from HIP events recorded around every launch."""
+        cap = 64
+        arr = (KernelTime * cap)()
+        cnt = _c_i32(cap)
+        _check(lib().lrp_get_profile(self._h, ctypes.byref(cnt), arr), "lrp_get_profile")
+        return {arr[q].name.decode(): (int(arr[q].launches), float(arr[q].ms)) for q in range(min(cnt.value, cap))}
 
     # ------------------------------------------------------------------------------------
     def solve(self, U_F, sigma, V_F, out=None):

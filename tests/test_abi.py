@@ -37,7 +37,8 @@ def test_create_rejects_bad_sizes(n, rmax, tol):
 
 def test_create_rejects_bad_options():
     h = ctypes.c_void_p()
-    for o in (L.Opts(-1, 0, 0.0, None), L.Opts(5, 7, 0.0, None), L.Opts(5, 0, 2.0, None)):
+    for o in (L.Opts(-1, 0, 0.0, None), L.Opts(5, 7, 0.0, None), L.Opts(5, 0, 2.0, None),
+              L.Opts(5, 0, 0.0, None, 2, 0), L.Opts(5, 0, 0.0, None, 0, 1)):
         assert L.lib().lrp_create(ctypes.byref(h), 255, 8, 1e-10, ctypes.byref(o)) == L.LRP_EINVAL
 
 
@@ -51,11 +52,13 @@ def test_null_context_and_arguments():
     assert lib.lrp_get_index_sets(None, None, None, None, None) == L.LRP_EINVAL
     assert lib.lrp_dst1(None, 1, None, 0, None, 0, None, 1.0, 0) == L.LRP_EINVAL
     assert lib.lrp_tsqr(None, 1, None, 0, None, 0, None, 0) == L.LRP_EINVAL
+    assert lib.lrp_get_profile(None, ctypes.byref(cnt), None) == L.LRP_EINVAL
 
 
 def test_struct_layouts_match_header():
-    assert ctypes.sizeof(L.Opts) == 24
-    assert L.Opts.prune_tau.offset == 8 and L.Opts.stream.offset == 16
+    assert ctypes.sizeof(L.Opts) == 32
+    assert L.Opts.prune_tau.offset == 8 and L.Opts.stream.offset == 16 and L.Opts.flags.offset == 24
+    assert ctypes.sizeof(L.KernelTime) == 24 and L.KernelTime.ms.offset == 16
     assert ctypes.sizeof(L.Info) == 48
     assert L.Info.rho.offset == 24 and L.Info.indicator.offset == 32 and L.Info.ms.offset == 40
 

@@ -192,6 +192,37 @@ def test_repeat_solves_are_bitwise_identical():
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_profile_mode_same_result_and_kernel_times(precision):
+    """A context with the profile flag launches the passes kernel by kernel (no graphs) with
+    HIP events around every launch: the result must be bitwise the same as with graphs, and
+    the per-kernel times must cover the solve."""
+    w = workloads.CONFIGS["n65535_r20_fp64"]
+    U, s, V = workloads.make(w, 0)
+    from paper_2607_06021_amd import Solver
+
+    print(f"profile mode {precision}", flush=True)
+    args = (dev(U), dev(s), dev(V))
+    with Solver(w.n, 64, w.tol, maxiter=w.maxiter, precision=precision) as sol:
+        a = sol.solve(*args)
+        A = [t.cpu().numpy().copy() for t in a[:3]]
+    with Solver(w.n, 64, w.tol, maxiter=w.maxiter, precision=precision, profile=True) as sol:
+        b = sol.solve(*args)
+        B = [t.cpu().numpy() for t in b[:3]]
+        prof = sol.profile()
+        info = b[4]
+    for x, y in zip(A, B):
+        assert np.array_equal(x, y)
+    assert a[3] == b[3] and a[4].iters == info.iters
+    for name in ("k_core", "k_core_warm", "k_tsqr_factor", "k_tsqr_apply", "k_fiber", "k_prod",
+                 "k_dst_pass1", "k_dst_pass2", "k_select", "k_topk_block"):
+        assert name in prof and prof[name][0] >= 1 and prof[name][1] > 0.0, name
+    assert prof["k_core"][0] >= info.iters and prof["k_core_warm"][0] == 1
+    total = sum(ms for _, ms in prof.values())
+    print(f"  solve {info.ms:.3f} ms, kernels {total:.3f} ms", flush=True)
+    assert 0.5 * info.ms < total < 1.05 * info.ms
+
+
 def test_n1048575_fp64_against_golden():
     """Full-size n = 2^20 - 1: the oracle takes minutes, so its index sets, ranks, singular
     values and sampled rows were stored by tests/golden/make_golden.py (oracle only)."""
