@@ -309,6 +309,18 @@ int enqueue_pass_kernels(lrp_ctx* c, int k) {
   ra.maxiter = c->maxiter;
   ra.trace = c->trace;
   TRY(rho_launch(c->rho, ra, s));
+  EtaArgs ea{};
+  ea.st = c->st;
+  ea.Q0 = c->Q[0];
+  ea.Q1 = c->Q[1];
+  ea.ldq = n;
+  ea.Uhat = c->Uhat;
+  ea.Vtil = c->Vtil;
+  ea.pmax = pm;
+  ea.nb = nb_new;
+  ea.maxiter = c->maxiter;
+  ea.trace = c->trace;
+  TRY(eta_launch(ea, s));
   const double* U[2] = {c->Uit[nb_new], c->Vit[nb_new]};
   int fslot = 0;
   TRY(select_candidates(c->sel, c->st, U, n, s, &fslot));
@@ -641,7 +653,7 @@ int lrp_get_profile(const lrp_ctx* c, int32_t* count, lrp_kernel_time* out) {
       "k_init_state", "k_scan", "k_dst_single", "k_dst_pass1", "k_dst_pass2", "k_fiber",
       "k_tsqr_factor", "k_tsqr_apply", "k_core_warm", "k_core", "k_prod", "k_pi", "k_gmax",
       "k_topk_block", "k_topk_merge", "k_select", "k_rho_a", "k_rho_b", "k_rho_reduce",
-      "k_rho_final", "k_finalize", "copy"};
+      "k_rho_final", "k_eta", "k_finalize", "copy"};
   if (!c || !count || *count < 0 || (*count > 0 && !out)) return LRP_EINVAL;
   if (!c->profile || !c->solved) {
     *count = 0;

@@ -12,15 +12,17 @@
 //     (U_k = Q U^ and V_k = Z V~ are formed by the product kernel);
 //   * pruning: index l of I (of J) is dropped when |diag R_R| (|diag R_C|) at l is below
 //     tau times its largest entry;
-//   * eta_1 = 1/sigma_min(U_k(I,:)), eta_2 = 1/sigma_min(V_k(J,:)) on the pruned sets (two
-//     Jacobi problems solved side by side) and the indicator
-//     min(eta_1 (1 + eta_2), eta_2 (1 + eta_1)) S_min / ||S||_F.
+//   * the cheap bound 2 S_min / ||S||_F < eps that the indicator
+//     min(eta_1 (1 + eta_2), eta_2 (1 + eta_1)) S_min / ||S||_F must pass for a stop; the
+//     indicator itself (eta_1 = 1/sigma_min(U_k(I,:)), eta_2 = 1/sigma_min(V_k(J,:)) on the
+//     pruned sets, two Jacobi problems solved side by side) and the stop decision are made by
+//     k_eta once rho is known, and only when a stop is possible.
 // The warm start uses the same SVD on M = R_u R_v^T, the core of F^ = U^ V^^T.
 //
 // Jacobi: Hestenes' one-sided method, round-robin ordering (k-1 rounds of k/2 disjoint column
 // pairs per sweep); a pair is rotated unless |a_p . a_q| <= sqrt(m) eps ||a_p|| ||a_q||; the
-// sweeps end when one makes no rotation (at most 60). Each pair is handled by a group of 4, 8
-// or 16 lanes whose partial dot products are summed with DPP lane permutes.
+// sweeps end when one makes no rotation (at most 60). Each pair is handled by a group of 8 or
+// 16 lanes whose partial dot products are summed with DPP lane permutes.
 #include "lrp_kernels.h"
 
 namespace lrp {
@@ -70,69 +72,82 @@ struct JacProb {
   double* V;  // k x k accumulated rotations (holding the identity on entry), or null
 };
 
-// One pair of problem `pr` in round rd; G lanes per pair, li = lane in the group.
-template <int G>
-__device__ inline bool jacobi_pair(const JacProb& pr, int pi, int li, int rd, double tol) {
-  const int k = pr.k;
-  const int kk = k + (k & 1);
-  if (k < 2 || pi >= (kk >> 1) || rd >= kk - 1) return false;
-  int p, q;
+// 1/x and 1/sqrt(x) from the hardware approximations refined by two Newton steps (each
+// step squares the relative error), for normal positive x.
+__device__ inline double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ inline double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  double e = fma(-h * y, y, 0.5);
+  y = fma(y, e, y);
+  e = fma(-h * y, y, 0.5);
+  return fma(y, e, y);
+}
+
+// Rotation (c, s) that makes columns p, q orthogonal: with al = |a_p|^2, be = |a_q|^2,
+// ga = a_p . a_q, d = be - al, t = sign(d) 2ga / (|d| + sqrt(d^2 + 4ga^2)) (Rutishauser's
+// smaller root, written without forming (be - al) / (2ga)), c = 1/sqrt(1 + t^2), s = c t.
+__device__ inline void jacobi_rotation(double al, double be, double ga, double& c, double& s) {
+  const double d = be - al, g2 = 2.0 * ga;
+  const double h2 = fma(d, d, g2 * g2);
+  double t;
+  if (h2 > 1e-290 && h2 < 1e290) {
+    const double h = h2 * rsq_nr(h2);
+    t = copysign(1.0, d) * g2 * rcp_nr(fabs(d) + h);
+    c = rsq_nr(fma(t, t, 1.0));
+  } else {  // extreme magnitudes: the correctly rounded library operations
+    const double zeta = d / g2;
+    t = fabs(zeta) > 1e150 ? 0.5 / zeta : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    c = 1.0 / sqrt(1.0 + t * t);
+  }
+  s = c * t;
+}
+
+// Column pair of pair slot pi in round rd of the round-robin ordering of kk (even) columns:
+// slot 0 pairs the fixed column kk-1 with rd, slot pi > 0 pairs rd+pi and rd-pi (mod kk-1).
+__device__ inline void rr_pair(int kk, int pi, int rd, int& p, int& q) {
+  const int n1 = kk - 1;
   if (pi == 0) {
-    p = kk - 1;
+    p = n1;
     q = rd;
   } else {
-    p = (rd + pi) % (kk - 1);
-    q = (rd - pi + (kk - 1)) % (kk - 1);
+    p = rd + pi;
+    if (p >= n1) p -= n1;
+    q = rd - pi;
+    if (q < 0) q += n1;
   }
   if (p > q) {
     const int tmp = p;
     p = q;
     q = tmp;
   }
-  if (q >= k) return false;
-  double* A = pr.A;
-  const int m = pr.m;
-  double al = 0.0, be = 0.0, ga = 0.0;
-  for (int i = li; i < m; i += G) {
-    const double ap = A[i + p * LDP], aq = A[i + q * LDP];
-    al = fma(ap, ap, al);
-    be = fma(aq, aq, be);
-    ga = fma(ap, aq, ga);
-  }
-  al = group_sum<G>(al);
-  be = group_sum<G>(be);
-  ga = group_sum<G>(ga);
-  if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al) * sqrt(be))) return false;
-  const double zeta = (be - al) / (2.0 * ga);
-  const double tt = fabs(zeta) > 1e150 ? 0.5 / zeta
-                                        : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double cs = 1.0 / sqrt(1.0 + tt * tt);
-  const double sn = cs * tt;
-  for (int i = li; i < m; i += G) {
-    const double ap = A[i + p * LDP], aq = A[i + q * LDP];
-    A[i + p * LDP] = cs * ap - sn * aq;
-    A[i + q * LDP] = sn * ap + cs * aq;
-  }
-  if (pr.V) {
-    double* V = pr.V;
-    for (int i = li; i < k; i += G) {
-      const double vp = V[i + p * LDP], vq = V[i + q * LDP];
-      V[i + p * LDP] = cs * vp - sn * vq;
-      V[i + q * LDP] = sn * vp + cs * vq;
-    }
-  }
-  return true;
 }
 
 // Solve one or two independent Jacobi problems with the whole workgroup: with two, each
 // half of the threads takes one. flags: 2 ints of LDS.
-__device__ void jacobi(JacProb* P, int nprob, int* flags) {
+//
+// Each column pair of a round is handled by G lanes (16 for one problem, 8 for two); lane li
+// holds rows li + G u of both columns in registers for the dot products and the update. The
+// rotation of V (when requested) is applied one round late by the same lanes: rounds touch
+// disjoint columns, so the V update of round rd overlaps the A work of round rd + 1 and only
+// has to precede the barrier that ends it.
+template <int G>
+__device__ void jacobi_g(JacProb* P, int nprob, int* flags) {
+  constexpr int U = kPMax / G;  // rows per lane
   const int t = threadIdx.x;
   const int half = kCoreThreads / 2;
   const int which = (nprob == 2 && t >= half) ? 1 : 0;
   const int lt = (nprob == 2) ? (t - which * half) : t;
-  const JacProb& pr = P[which];
+  const JacProb pr = P[which];
+  const int pi = lt / G, li = lt % G;
   const double tol = sqrt((double)max(pr.m, 1)) * kEps;
+  const double tol2 = tol * tol;
   int rounds = 0;
   for (int q = 0; q < nprob; ++q) {
     const int kk = P[q].k + (P[q].k & 1);
@@ -142,20 +157,79 @@ __device__ void jacobi(JacProb* P, int nprob, int* flags) {
     __syncthreads();
     return;
   }
-  // lanes per pair: 16 for one problem (32 pairs x 16 = 512), 8 for two
+  const int kk = pr.k + (pr.k & 1);
+  const bool slot_ok = pr.k >= 2 && pi < (kk >> 1);
+  double* A = pr.A;
+  double* V = pr.V;
   bool active = true;
   for (int sweep = 0; sweep < 60; ++sweep) {
     if (t < 2) flags[t] = 0;
     __syncthreads();
     bool rot = false;
+    int vp = -1, vq = -1;
+    double vc = 1.0, vs = 0.0;
     for (int rd = 0; rd < rounds; ++rd) {
-      if (active) {
-        if (nprob == 2)
-          rot |= jacobi_pair<8>(pr, lt >> 3, lt & 7, rd, tol);
-        else
-          rot |= jacobi_pair<16>(pr, lt >> 4, lt & 15, rd, tol);
+      if (active && vp >= 0) {  // V update of the previous round
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = li + G * u;
+          if (i < pr.k) {
+            const double x = V[i + vp * LDP], y = V[i + vq * LDP];
+            V[i + vp * LDP] = vc * x - vs * y;
+            V[i + vq * LDP] = vs * x + vc * y;
+          }
+        }
+      }
+      vp = -1;
+      int p = 0, q = 0;
+      if (active && slot_ok && rd < kk - 1) rr_pair(kk, pi, rd, p, q);
+      if (active && slot_ok && rd < kk - 1 && q < pr.k) {
+        double ap[U], aq[U];
+        double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = li + G * u;
+          ap[u] = i < pr.m ? A[i + p * LDP] : 0.0;
+          aq[u] = i < pr.m ? A[i + q * LDP] : 0.0;
+          al = fma(ap[u], ap[u], al);
+          be = fma(aq[u], aq[u], be);
+          ga = fma(ap[u], aq[u], ga);
+        }
+        al = group_sum<G>(al);
+        be = group_sum<G>(be);
+        ga = group_sum<G>(ga);
+        if (ga != 0.0 && ga * ga > tol2 * al * be) {
+          double c, sn;
+          jacobi_rotation(al, be, ga, c, sn);
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int i = li + G * u;
+            if (i < pr.m) {
+              A[i + p * LDP] = c * ap[u] - sn * aq[u];
+              A[i + q * LDP] = sn * ap[u] + c * aq[u];
+            }
+          }
+          rot = true;
+          if (V) {
+            vp = p;
+            vq = q;
+            vc = c;
+            vs = sn;
+          }
+        }
       }
       __syncthreads();
+    }
+    if (active && vp >= 0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = li + G * u;
+        if (i < pr.k) {
+          const double x = V[i + vp * LDP], y = V[i + vq * LDP];
+          V[i + vp * LDP] = vc * x - vs * y;
+          V[i + vq * LDP] = vs * x + vc * y;
+        }
+      }
     }
     if (rot) flags[which] = 1;
     __syncthreads();
@@ -165,6 +239,13 @@ __device__ void jacobi(JacProb* P, int nprob, int* flags) {
     __syncthreads();
     if (!more) break;
   }
+}
+
+__device__ void jacobi(JacProb* P, int nprob, int* flags) {
+  if (nprob == 2)
+    jacobi_g<8>(P, 2, flags);
+  else
+    jacobi_g<16>(P, 1, flags);
 }
 
 // sig[c] = ||A(:, c)||, ord[r] = column of rank r (descending, ties to the smaller index).
@@ -522,47 +603,101 @@ __global__ __launch_bounds__(kCoreThreads) void k_core(CoreArgs a) {
   __syncthreads();
   const int nIp = cnt[0], nJp = cnt[1];
 
-  // ---- eta: U_k(I,:) = Q(I,:) U^ and V_k(J,:) = Z(J,:) V~ on the pruned rows, each stored
-  // tall (rows >= cols) so that Jacobi gives its min(rows, cols) singular values.
-  // Rows of an orthonormal basis have singular values <= 1, so eta_1, eta_2 >= 1 and the
-  // indicator is at least 2 S_min/||S||: when that bound already fails the stopping test (and
-  // at pass 0, where no stop is allowed) the indicator is not needed and is left at +inf.
-  double smin1 = 0.0, smin2 = 0.0;
+  // ---- the indicator min(eta_1 (1 + eta_2), eta_2 (1 + eta_1)) S_min / ||S||_F is evaluated by
+  // k_eta after rho, and only when it can matter: rows of an orthonormal basis have singular
+  // values <= 1, so eta_1, eta_2 >= 1 and the indicator is at least 2 S_min / ||S||_F; when that
+  // bound already fails the test (or at pass 0, where no stop is allowed) no stop is possible.
   bool need_eta;
   {
     double n2 = 0.0;
     for (int l = 0; l < r; ++l) n2 = fma(sig[ord[l]], sig[ord[l]], n2);
-    need_eta = r > 0 && st->k >= 1 && 1.9 * sig[ord[r - 1]] < st->eps * sqrt(n2);
+    need_eta = r > 0 && st->k >= 1 && nIp > 0 && nJp > 0 && 1.9 * sig[ord[r - 1]] < st->eps * sqrt(n2);
   }
-  if (need_eta && nIp > 0 && nJp > 0) {
-    double* E1 = B0;
-    double* E2 = M;
-    const bool t1 = nIp >= r, t2 = nJp >= r;
-    for (int e = t; e < nIp * r; e += blockDim.x) {
-      const int ii = e % nIp, rr = e / nIp;
-      const int i = posI[ii];
+  __syncthreads();
+
+  if (t == 0) {
+    const double* S = st->S[nb];
+    double n2 = 0.0;
+    for (int l = 0; l < r; ++l) n2 = fma(S[l], S[l], n2);
+    const double nrm = sqrt(n2);
+    st->nrm = nrm;
+    st->eta1 = INFINITY;
+    st->eta2 = INFINITY;
+    st->ind = INFINITY;
+    st->eta_need = need_eta ? 1 : 0;
+    st->r[nb] = r;
+    int rs = 0;
+    for (int l = 0; l < r; ++l) rs += S[l] > st->eps * S[0] ? 1 : 0;
+    st->r_sig = rs;
+    for (int ii = 0; ii < nIp; ++ii) st->I[ii] = st->Ipre[posI[ii]];
+    for (int jj = 0; jj < nJp; ++jj) st->J[jj] = st->Jpre[posJ[jj]];
+    st->nI = nIp;
+    st->nJ = nJp;
+    for (int ii = 0; ii < nIp; ++ii) st->Ib[nb][ii] = st->I[ii];
+    for (int jj = 0; jj < nJp; ++jj) st->Jb[nb][jj] = st->J[jj];
+    st->nIb[nb] = nIp;
+    st->nJb[nb] = nJp;
+    st->indb[nb] = INFINITY;
+    if (r == 0) {  // the sampled fibers vanish: nothing to continue from
+      st->done = 1;
+      st->status = LRP_ENUMERIC;
+    }
+    const int kp = st->k;  // the pass being computed (passes completed so far)
+    if (kp >= 0 && kp < a.maxiter) {
+      a.trace.nI[kp] = nIp;
+      a.trace.nJ[kp] = nJp;
+      a.trace.rank[kp] = r;
+      a.trace.ind[kp] = INFINITY;
+    }
+  }
+}
+
+// Indicator and stop decision of a pass (Algorithm 4, after rho): when a stop is possible
+// (cheap bound passed, rho < eps), eta_1 = 1/sigma_min(U_k(I,:)) and eta_2 =
+// 1/sigma_min(V_k(J,:)) on the pruned sets, with U_k(I,:) = Q(I,:) U^ and V_k(J,:) = Z(J,:) V~
+// each stored tall (rows >= cols) so that Jacobi gives its min(rows, cols) singular values;
+// the two problems are solved side by side. Then the pass is accepted as the new iterate and
+// the solve stops when max(rho, indicator) < eps, or after maxiter passes.
+__global__ __launch_bounds__(kCoreThreads) void k_eta(EtaArgs a) {
+  DevState* st = a.st;
+  if (st->done) return;
+  __shared__ double E1[kBuf], E2[kBuf];
+  __shared__ double red[2];
+  __shared__ int flags[2];
+  const int t = threadIdx.x;
+  const int nb = a.nb;
+  const int r = st->r[nb];
+  const bool need = st->k >= 1 && st->eta_need && st->rho < st->eps;
+  double smin1 = 0.0, smin2 = 0.0;
+  if (need) {
+    const int nI = st->nI, nJ = st->nJ;      // pruned sets
+    const int kJ = st->ncols[0], kI = st->ncols[1];  // columns of Q and Z
+    const int pm = a.pmax;
+    const bool t1 = nI >= r, t2 = nJ >= r;
+    for (int e = t; e < nI * r; e += blockDim.x) {
+      const int ii = e % nI, rr = e / nI;
+      const double* q = a.Q0 + st->I[ii];
       double s = 0.0;
-      for (int c = 0; c < nJ; ++c) s = fma(Aq(i, c), Ub[c + rr * LDP], s);
+      for (int c = 0; c < kJ; ++c) s = fma(q[(int64_t)c * a.ldq], a.Uhat[c + (int64_t)rr * pm], s);
       if (t1)
         E1[ii + rr * LDP] = s;
       else
         E1[rr + ii * LDP] = s;
     }
-    for (int e = t; e < nJp * r; e += blockDim.x) {
-      const int jj = e % nJp, rr = e / nJp;
-      const int j = posJ[jj];
+    for (int e = t; e < nJ * r; e += blockDim.x) {
+      const int jj = e % nJ, rr = e / nJ;
+      const double* z = a.Q1 + st->J[jj];
       double s = 0.0;
-      for (int c = 0; c < nI; ++c) s = fma(Bq(j, c), Vb[c + rr * LDP], s);
+      for (int c = 0; c < kI; ++c) s = fma(z[(int64_t)c * a.ldq], a.Vtil[c + (int64_t)rr * pm], s);
       if (t2)
         E2[jj + rr * LDP] = s;
       else
         E2[rr + jj * LDP] = s;
     }
     __syncthreads();
-    JacProb pp[2] = {{E1, t1 ? nIp : r, t1 ? r : nIp, nullptr}, {E2, t2 ? nJp : r, t2 ? r : nJp, nullptr}};
+    JacProb pp[2] = {{E1, t1 ? nI : r, t1 ? r : nI, nullptr}, {E2, t2 ? nJ : r, t2 ? r : nJ, nullptr}};
     jacobi(pp, 2, flags);
-    // smallest column norm of each
-    if (t < 64) {
+    if (t < 64) {  // smallest column norm of each
       double v1 = INFINITY, v2 = INFINITY;
       if (t < pp[0].k) {
         double s = 0.0;
@@ -587,46 +722,35 @@ __global__ __launch_bounds__(kCoreThreads) void k_core(CoreArgs a) {
     smin1 = red[0];
     smin2 = red[1];
   }
-  __syncthreads();
-
   if (t == 0) {
-    const double* S = st->S[nb];
-    double n2 = 0.0;
-    for (int l = 0; l < r; ++l) n2 = fma(S[l], S[l], n2);
-    const double nrm = sqrt(n2);
-    const double eta1 = smin1 > 0.0 ? 1.0 / smin1 : INFINITY;
-    const double eta2 = smin2 > 0.0 ? 1.0 / smin2 : INFINITY;
+    const int kp = st->k;
     double ind = INFINITY;
-    if (need_eta && nrm > 0.0) ind = fmin(eta1 * (1.0 + eta2), eta2 * (1.0 + eta1)) * S[r - 1] / nrm;
-    st->nrm = nrm;
-    st->eta1 = eta1;
-    st->eta2 = eta2;
-    st->ind = ind;
-    st->r[nb] = r;
-    int rs = 0;
-    for (int l = 0; l < r; ++l) rs += S[l] > st->eps * S[0] ? 1 : 0;
-    st->r_sig = rs;
-    for (int ii = 0; ii < nIp; ++ii) st->I[ii] = st->Ipre[posI[ii]];
-    for (int jj = 0; jj < nJp; ++jj) st->J[jj] = st->Jpre[posJ[jj]];
-    st->nI = nIp;
-    st->nJ = nJp;
-    for (int ii = 0; ii < nIp; ++ii) st->Ib[nb][ii] = st->I[ii];
-    for (int jj = 0; jj < nJp; ++jj) st->Jb[nb][jj] = st->J[jj];
-    st->nIb[nb] = nIp;
-    st->nJb[nb] = nJp;
-    st->indb[nb] = ind;
-    if (r == 0) {  // the sampled fibers vanish: nothing to continue from
-      st->done = 1;
-      st->status = LRP_ENUMERIC;
+    if (need) {
+      const double eta1 = smin1 > 0.0 ? 1.0 / smin1 : INFINITY;
+      const double eta2 = smin2 > 0.0 ? 1.0 / smin2 : INFINITY;
+      st->eta1 = eta1;
+      st->eta2 = eta2;
+      if (st->nrm > 0.0) ind = fmin(eta1 * (1.0 + eta2), eta2 * (1.0 + eta1)) * st->S[nb][r - 1] / st->nrm;
     }
-    const int kp = st->k;  // the pass being computed (passes completed so far)
-    if (kp >= 0 && kp < a.maxiter) {
-      a.trace.nI[kp] = nIp;
-      a.trace.nJ[kp] = nJp;
-      a.trace.rank[kp] = r;
-      a.trace.ind[kp] = ind;
+    st->ind = ind;
+    st->indb[nb] = ind;
+    if (kp < a.maxiter) a.trace.ind[kp] = ind;
+    st->ret = nb;
+    st->k = kp + 1;
+    if (kp >= 1 && fmax(st->rho, ind) < st->eps) {
+      st->done = 1;
+      st->status = LRP_OK;
+    } else if (kp == a.maxiter - 1) {
+      st->done = 1;
+      st->status = LRP_NOT_CONVERGED;
     }
   }
+}
+
+int eta_launch(const EtaArgs& a, hipStream_t s) {
+  prof_mark(s, K_ETA);
+  hipLaunchKernelGGL(k_eta, dim3(1), dim3(kCoreThreads), 0, s, a);
+  return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
 }
 
 // Warm start: M = R_u R_v^T (the core of F^ = U^ V^^T) and its SVD.
@@ -706,6 +830,7 @@ __global__ void k_init_state(DevState* st, int rF, double eps, double tau) {
   st->ind = INFINITY;
   st->rho = INFINITY;
   st->eta1 = st->eta2 = INFINITY;
+  st->eta_need = 0;
   st->eps = eps;
   st->tau = tau;
   st->r[0] = st->r[1] = 0;

@@ -34,7 +34,7 @@ struct DevState {
   int nIprev, nJprev;  // pre-prune sets of the previous pass (fixed-point test)
   int r_sig;    // leading singular vectors used by the next selection
   int r_final;  // rank of the returned solution
-  int pad0;
+  int eta_need;  // 1: the last core passed the cheap bound on the indicator (a stop is possible)
   double nrm, ind, rho, eta1, eta2;
   double eps;   // effective tolerance
   double tau;   // prune threshold

@@ -14,7 +14,7 @@ namespace lrp {
 enum KernelId {
   K_INIT, K_SCAN, K_DST_SINGLE, K_DST_PASS1, K_DST_PASS2, K_FIBER, K_TSQR_FACTOR, K_TSQR_APPLY,
   K_CORE_WARM, K_CORE, K_PROD, K_PI, K_GMAX, K_TOPK_BLOCK, K_TOPK_MERGE, K_SELECT, K_RHO_A,
-  K_RHO_B, K_RHO_REDUCE, K_RHO_FINAL, K_FINALIZE, K_COPY, K_COUNT
+  K_RHO_B, K_RHO_REDUCE, K_RHO_FINAL, K_ETA, K_FINALIZE, K_COPY, K_COUNT
 };
 // Called right before a launch (or copy) on stream s: when this thread is recording a
 // profile on s, records an event that ends the previous entry and starts this one.
@@ -126,6 +126,20 @@ struct ProdArgs {
   int nb;              // buffer index whose rank st->r[nb] gives the columns
 };
 int prod_launch(const ProdArgs& a, hipStream_t s);
+
+struct EtaArgs {
+  DevState* st;
+  const double* Q0;  // Q of side 0 (ncols[0] columns), ld ldq
+  const double* Q1;  // Z of side 1 (ncols[1] columns)
+  int64_t ldq;
+  const double* Uhat;  // pmax x pmax coefficients (U_k = Q U^), ld pmax
+  const double* Vtil;
+  int pmax;
+  int nb;              // iterate buffer of this pass
+  int maxiter;
+  TraceBuf trace;
+};
+int eta_launch(const EtaArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- selection (select.hip)
 struct SelectPlan {

@@ -7,8 +7,9 @@
 // four mutually orthogonal terms, so rho^2 ||S_k||^2 is the sum of
 //   ||S_k - M_u S' N_v^T||^2, tr(M_u S' G' S' M_u^T), tr(N_v S' G S' N_v^T), tr(S' G S' G'),
 // with G = Y^T Y and G' = Y'^T Y' Gram matrices of explicitly formed small numbers.
-// rho is only needed when the indicator already passes (the decision needs both), so the
-// n-length kernels return at once otherwise. All reductions have a fixed order.
+// rho is only needed when the core's cheap bound on the indicator allows a stop (the decision
+// needs both), so the n-length kernels return at once otherwise; the indicator itself and the
+// decision follow in k_eta. All reductions have a fixed order.
 #include "lrp_kernels.h"
 
 namespace lrp {
@@ -29,7 +30,7 @@ struct RhoKArgs {
 
 // st->k is the index of the pass being computed (the decision kernel advances it).
 __device__ inline bool rho_needed(const DevState* st) {
-  return !st->done && st->k >= 1 && st->ind < st->eps;
+  return !st->done && st->k >= 1 && st->eta_need;
 }
 
 // Stage rows [r0, r0 + 64) of the first `cols` columns of X into S (row-major, ld 65).
@@ -204,16 +205,7 @@ __global__ __launch_bounds__(256) void k_rho_final(RhoFinalArgs a) {
     const int kp = st->k;
     st->rho = rho;
     st->rhob[a.nb_new] = rho;
-    st->ret = a.nb_new;
-    st->k = kp + 1;
     if (kp < a.maxiter) a.trace.rho[kp] = rho;
-    if (kp >= 1 && fmax(rho, st->ind) < st->eps) {
-      st->done = 1;
-      st->status = LRP_OK;
-    } else if (kp == a.maxiter - 1) {
-      st->done = 1;
-      st->status = LRP_NOT_CONVERGED;
-    }
   }
 }
 
