@@ -110,6 +110,24 @@ def kernel_model(w, prec, trace, info, rF):
     pf += 2 * 2 * n * rF * rF
     out["prod"] = {"bytes": pb, "flops": pf}
     out["core"] = {"flops": cf}
+    # thin QRs (Householder, LAPACK counts): factorization 2 n p^2 - 2 p^3 / 3 per side and the
+    # same again to form the explicit Q; the warm start factors U^, V^ (p = r_F)
+    qf = 2 * (2 * n * rF ** 2 - 2 * rF ** 3 / 3)
+    for t in passes:
+        for pp in (len(t["I_pre"]), len(t["J_pre"])):
+            qf += 2 * n * pp ** 2 - 2 * pp ** 3 / 3
+    out["tsqr"] = {"flops": qf}
+    # rho (passes where it was evaluated): M = A^T B (pass a), then Y = B - A M and Y^T Y (pass b)
+    ra = rb = 0.0
+    prev = None
+    for t in passes:
+        rk = t["rank"]
+        if prev is not None and math.isfinite(t["rho"]):
+            ra += 2 * 2 * n * rk * prev
+            rb += 2 * (2 * n * rk * prev + 2 * n * prev * prev)
+        prev = rk
+    out["rho_a"] = {"flops": ra}
+    out["rho_b"] = {"flops": rb}
     return out
 
 
@@ -134,12 +152,19 @@ def rooflines(w, prec, prof, trace, info, rF):
                       "k_dst_pass1 + k_dst_pass2 (four-step), or k_dst_single"),
            "fiber": hbm(m["fiber"]["bytes"], *t("k_fiber"), "k_fiber"),
            "prod": hbm(m["prod"]["bytes"], *t("k_prod"), "k_prod (FP64 MFMA)")}
-    ms, launches = t("k_core")
-    tf = m["core"]["flops"] / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
-    res["core"] = {"bound": "alu", "achieved": round(tf, 6), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                   "frac": round(tf / FP64_PEAK_TFLOPS, 7), "traffic": None, "kernel": "k_core (one workgroup)",
-                   "ms_per_launch": round(ms / max(launches, 1), 4), "launches": launches,
-                   "alg_flops_per_launch": round(m["core"]["flops"] / max(launches, 1))}
+    def alu(flops, ms, launches, kernel):
+        tf = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        return {"bound": "alu", "achieved": round(tf, 6), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tf / FP64_PEAK_TFLOPS, 7), "traffic": None, "kernel": kernel,
+                "ms_per_launch": round(ms / max(launches, 1), 5), "launches": launches,
+                "alg_flops_per_launch": round(flops / max(launches, 1))}
+
+    res["core"] = alu(m["core"]["flops"], *t("k_core"), "k_core (one workgroup)")
+    # the factorization and the formation of Q each carry the Householder count
+    res["tsqr_factor"] = alu(m["tsqr"]["flops"], *t("k_tsqr_factor"), "k_tsqr_factor (all tree levels)")
+    res["tsqr_apply"] = alu(m["tsqr"]["flops"], *t("k_tsqr_apply"), "k_tsqr_apply (all tree levels)")
+    res["rho_a"] = alu(m["rho_a"]["flops"], *t("k_rho_a"), "k_rho_a")
+    res["rho_b"] = alu(m["rho_b"]["flops"], *t("k_rho_b"), "k_rho_b")
     return res
 
 
@@ -209,7 +234,8 @@ def cpu_baseline(w, U, s, V):
 def dominant_roofline(res):
     """Roofline of the kernel with the largest device time in the profiled solve."""
     key = {"k_core": "core", "k_dst_pass1": "dst", "k_dst_pass2": "dst", "k_dst_single": "dst",
-           "k_fiber": "fiber", "k_prod": "prod"}.get(res["dominant"])
+           "k_fiber": "fiber", "k_prod": "prod", "k_tsqr_factor": "tsqr_factor",
+           "k_tsqr_apply": "tsqr_apply", "k_rho_a": "rho_a", "k_rho_b": "rho_b"}.get(res["dominant"])
     if key is None:
         return {"bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None,
                 "traffic": None, "kernel": res["dominant"], "note": "no algorithmic model for this kernel"}

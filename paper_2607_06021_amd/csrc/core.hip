@@ -72,24 +72,6 @@ struct JacProb {
   double* V;  // k x k accumulated rotations (holding the identity on entry), or null
 };
 
-// 1/x and 1/sqrt(x) from the hardware approximations refined by two Newton steps (each
-// step squares the relative error), for normal positive x.
-__device__ inline double rcp_nr(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, y, 1.0);
-  y = fma(y, e, y);
-  e = fma(-x, y, 1.0);
-  return fma(y, e, y);
-}
-__device__ inline double rsq_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double h = 0.5 * x;
-  double e = fma(-h * y, y, 0.5);
-  y = fma(y, e, y);
-  e = fma(-h * y, y, 0.5);
-  return fma(y, e, y);
-}
-
 // Rotation (c, s) that makes columns p, q orthogonal: with al = |a_p|^2, be = |a_q|^2,
 // ga = a_p . a_q, d = be - al, t = sign(d) 2ga / (|d| + sqrt(d^2 + 4ga^2)) (Rutishauser's
 // smaller root, written without forming (be - al) / (2ga)), c = 1/sqrt(1 + t^2), s = c t.

@@ -75,6 +75,24 @@ struct TsqrLevel {
 // ----------------------------------------------------------------------------------------
 // Wavefront helpers (64 lanes)
 // ----------------------------------------------------------------------------------------
+// 1/x and 1/sqrt(x) from the hardware approximations refined by two Newton steps (each
+// step squares the relative error), for normal positive x (rcp_nr: normal nonzero x).
+__device__ inline double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ inline double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  double e = fma(-h * y, y, 0.5);
+  y = fma(y, e, y);
+  e = fma(-h * y, y, 0.5);
+  return fma(y, e, y);
+}
+
 __device__ inline double shfl_xor_d(double x, int mask) {
   int lo = __double2loint(x);
   int hi = __double2hiint(x);

@@ -69,8 +69,9 @@ __device__ inline double row16_sum(double x) {
 
 // Thread layout of a 256-row block: column c = t/16, rows 16 (t%16) .. 16 (t%16)+15, so the
 // 16 lanes of a DPP row hold one column. The lanes of column j build reflector j themselves
-// (norm and diagonal by row sums), publish it in LDS (double-buffered) and one barrier later
-// every trailing column applies it.
+// (norm and diagonal by row sums), publish it in LDS (double-buffered; element 16 s + i of the
+// column is stored at 16 i + s, so that the 16 lanes of a column read 16 consecutive words)
+// and one barrier later every trailing column applies it.
 __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) {
   const int side = blockIdx.y;
   if (a.st && a.st->done) return;
@@ -81,7 +82,6 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) {
   const int t = threadIdx.x, c = t >> 4, sub = t & 15;
   const int rbase = sub * kTsqrRowsPerThread;
   __shared__ double vbuf[2][kTsqrRows];
-  __shared__ double tbuf[2];
 
   double x[kTsqrRowsPerThread];
   {
@@ -100,24 +100,37 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) {
   double* V = a.V[side];
   double* Rb = a.Rout[side] + (int64_t)blockIdx.x * a.pmax;  // this block's R, rows 0..pmax-1
   double* taub = a.tau[side] + (int64_t)blockIdx.x * a.pmax;
+  __shared__ double tsh[kPMax];
+  // After its own step, column c is final: its registers keep R(0..c-1, c) above the diagonal
+  // and the reflector below it, and rdiag = R(c, c). Nothing is written to global memory
+  // inside the loop, so the per-step barrier waits on LDS only.
+  double rdiag = 0.0;
 
   for (int j = 0; j < p; ++j) {
     double* vb = vbuf[j & 1];
     if (c == j) {
-      double nn = 0.0, al = 0.0;
+      // two partial sums shorten the dependent chain of the norm
+      double n0 = 0.0, n1 = 0.0, al = 0.0;
 #pragma unroll
-      for (int i = 0; i < kTsqrRowsPerThread; ++i) {
+      for (int i = 0; i < kTsqrRowsPerThread; i += 2) {
         const int r = rbase + i;
-        nn = (r > j) ? fma(x[i], x[i], nn) : nn;
+        n0 = (r > j) ? fma(x[i], x[i], n0) : n0;
+        n1 = (r + 1 > j) ? fma(x[i + 1], x[i + 1], n1) : n1;
         al = (r == j) ? x[i] : al;
+        al = (r + 1 == j) ? x[i + 1] : al;
       }
-      const double xnorm2 = row16_sum(nn);
+      const double xnorm2 = row16_sum(n0 + n1);
       const double alpha = row16_sum(al);
       double beta, tau, scale;
+      const double h2 = fma(alpha, alpha, xnorm2);
       if (xnorm2 == 0.0) {
         tau = 0.0;
         beta = alpha;
         scale = 0.0;
+      } else if (h2 > 1e-290 && h2 < 1e290) {  // hardware rsq/rcp refined by Newton steps
+        beta = -copysign(h2 * rsq_nr(h2), alpha);
+        tau = (beta - alpha) * rcp_nr(beta);
+        scale = rcp_nr(alpha - beta);
       } else {
         beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
         tau = (beta - alpha) / beta;
@@ -127,32 +140,43 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) {
       for (int i = 0; i < kTsqrRowsPerThread; ++i) {
         const int r = rbase + i;
         const double v = (r > j) ? x[i] * scale : (r == j ? 1.0 : 0.0);
-        vb[r] = v;
-        if (r < nr) V[row0 + r + (int64_t)j * a.ldv] = v;
-        if (r < a.pmax) Rb[r + (int64_t)j * a.ldr] = (r < j) ? x[i] : (r == j ? beta : 0.0);
+        vb[i * 16 + sub] = v;  // transposed: the 16 lanes of a column read consecutive words
+        if (r > j) x[i] = v;
       }
-      if (sub == 0) {
-        tbuf[j & 1] = tau;
-        taub[j] = tau;
-      }
+      rdiag = beta;
+      if (sub == 0) tsh[j] = tau;
     }
     __syncthreads();
     if (c > j && c < p) {
-      const double tau = tbuf[j & 1];
-      const double* vs = vb + rbase;
+      const double tau = tsh[j];
+      const double* vs = vb + sub;
       double d0 = 0.0, d1 = 0.0;
 #pragma unroll
       for (int i = 0; i < kTsqrRowsPerThread; i += 2) {
-        d0 = fma(vs[i], x[i], d0);
-        d1 = fma(vs[i + 1], x[i + 1], d1);
+        d0 = fma(vs[i * 16], x[i], d0);
+        d1 = fma(vs[(i + 1) * 16], x[i + 1], d1);
       }
       const double w = row16_sum(d0 + d1) * tau;
 #pragma unroll
-      for (int i = 0; i < kTsqrRowsPerThread; ++i) x[i] = fma(-w, vs[i], x[i]);
+      for (int i = 0; i < kTsqrRowsPerThread; ++i) x[i] = fma(-w, vs[i * 16], x[i]);
     }
   }
+  // write the reflectors, R and tau once
+  if (c < p) {
+#pragma unroll
+    for (int i = 0; i < kTsqrRowsPerThread; ++i) {
+      const int r = rbase + i;
+      if (r < nr) V[row0 + r + (int64_t)c * a.ldv] = (r > c) ? x[i] : (r == c ? 1.0 : 0.0);
+      if (r < a.pmax) Rb[r + (int64_t)c * a.ldr] = (r < c) ? x[i] : (r == c ? rdiag : 0.0);
+    }
+  }
+  if (t < p) taub[t] = tsh[t];
 }
 
+// Same thread layout as the factorization: thread (c, sub) keeps rows 16 sub .. 16 sub + 15 of
+// output column c and, loaded once at the start, the same rows of reflector c. Reflectors are
+// applied in reverse order; at step j the lanes of column j publish v_j in LDS
+// (double-buffered) and one barrier later every column applies it.
 __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_apply(ApplyArgs a) {
   const int side = blockIdx.y;
   if (a.st && a.st->done) return;
@@ -163,35 +187,41 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_apply(ApplyArgs a) {
   const int t = threadIdx.x, c = t >> 4, sub = t & 15;
   const int rbase = sub * kTsqrRowsPerThread;
   __shared__ double vbuf[2][kTsqrRows];
+  __shared__ double tsh[kPMax];
 
-  double y[kTsqrRowsPerThread];
+  const double* taub = a.tau[side] + (int64_t)blockIdx.x * a.pmax;
+  if (t < p) tsh[t] = taub[t];
+  double y[kTsqrRowsPerThread], v[kTsqrRowsPerThread];
   const double* T = a.T[side];
   const int64_t toff = (int64_t)blockIdx.x * a.pmax;
+  const double* V = a.V[side] + row0 + (int64_t)c * a.ldv + rbase;
 #pragma unroll
   for (int i = 0; i < kTsqrRowsPerThread; ++i) {
     const int lr = rbase + i;
     double v0 = 0.0;
     if (c < p && lr < p) v0 = T ? T[toff + lr + (int64_t)c * a.ldt] : (lr == c ? 1.0 : 0.0);
     y[i] = v0;
+    v[i] = (c < p && lr < nr) ? V[i] : 0.0;
   }
-  const double* V = a.V[side];
-  const double* taub = a.tau[side] + (int64_t)blockIdx.x * a.pmax;
   for (int j = p - 1; j >= 0; --j) {
     double* vb = vbuf[j & 1];
-    if (t < kTsqrRows) vb[t] = (t < nr) ? V[row0 + t + (int64_t)j * a.ldv] : 0.0;
-    const double tj = taub[j];
+    if (c == j) {
+#pragma unroll
+      for (int i = 0; i < kTsqrRowsPerThread; ++i) vb[i * 16 + sub] = v[i];
+    }
     __syncthreads();
+    const double tj = tsh[j];
     if (c < p && tj != 0.0) {
-      const double* vs = vb + rbase;
+      const double* vs = vb + sub;
       double d0 = 0.0, d1 = 0.0;
 #pragma unroll
       for (int i = 0; i < kTsqrRowsPerThread; i += 2) {
-        d0 = fma(vs[i], y[i], d0);
-        d1 = fma(vs[i + 1], y[i + 1], d1);
+        d0 = fma(vs[i * 16], y[i], d0);
+        d1 = fma(vs[(i + 1) * 16], y[i + 1], d1);
       }
       const double w = row16_sum(d0 + d1) * tj;
 #pragma unroll
-      for (int i = 0; i < kTsqrRowsPerThread; ++i) y[i] = fma(-w, vs[i], y[i]);
+      for (int i = 0; i < kTsqrRowsPerThread; ++i) y[i] = fma(-w, vs[i * 16], y[i]);
     }
   }
   if (c < p) {
