@@ -33,96 +33,110 @@ __device__ inline bool rho_needed(const DevState* st) {
   return !st->done && st->k >= 1 && st->eta_need;
 }
 
-// Stage rows [r0, r0 + 64) of the first `cols` columns of X into S (row-major, ld 65).
-__device__ inline void stage(double (*S)[kPMax + 1], const double* X, int64_t ldu, int64_t n,
-                             int64_t r0, int cols) {
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int kRS = kPMax + 1;  // row stride of the LDS chunks
+
+// Stage rows [r0, r0 + 64) of the first `cols` columns of X into S (row-major, stride 65),
+// zero beyond cols and beyond n.
+__device__ inline void stage(double* S, const double* X, int64_t ldu, int64_t n, int64_t r0, int cols) {
   for (int e = threadIdx.x; e < kRhoChunk * kPMax; e += blockDim.x) {
     const int row = e % kRhoChunk, c = e / kRhoChunk;
     const int64_t i = r0 + row;
-    S[row][c] = (c < cols && i < n) ? X[i + (int64_t)c * ldu] : 0.0;
+    S[row * kRS + c] = (c < cols && i < n) ? X[i + (int64_t)c * ldu] : 0.0;
   }
 }
 
-// Pass A: partial M = A^T B over the block's rows, 4x4 output tile per thread.
+// acc[nt] += X^T Y over the 64 rows of a chunk for output rows 16 w .. 16 w + 15 and all 64
+// output columns (FP64 MFMA 16x16x4; the chunk rows are the contraction index).
+// A operand: X^T(16 w + l%16, k0 + l/16) = X[k0 + l/16][16 w + l%16]; B operand:
+// Y[k0 + l/16][16 nt + l%16]; result item v of lane l: row 16 w + l/16 + 4 v, column 16 nt + l%16.
+__device__ inline void gram_chunk(const double* X, const double* Y, int w, int lr, int lk, d4 (&acc)[4]) {
+#pragma unroll
+  for (int ks = 0; ks < kRhoChunk / 4; ++ks) {
+    const int row = 4 * ks + lk;
+    const double xa = X[row * kRS + 16 * w + lr];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+      acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, Y[row * kRS + 16 * nt + lr], acc[nt], 0, 0, 0);
+  }
+}
+
+__device__ inline void store_partial(double* out, int w, int lr, int lk, const d4 (&acc)[4]) {
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) out[(16 * w + lk + 4 * v) * kPMax + 16 * nt + lr] = acc[nt][v];
+}
+
+// Pass A: partial M = A^T B over the block's rows.
 __global__ __launch_bounds__(256) void k_rho_a(RhoKArgs a) {
   DevState* st = a.st;
   if (!rho_needed(st)) return;
   const int side = blockIdx.y;
   const int r = st->r[a.nb_new], ro = st->r[a.nb_old];
-  __shared__ double As[kRhoChunk][kPMax + 1], Bs[kRhoChunk][kPMax + 1];
-  const int t = threadIdx.x, ta = t >> 4, tb = t & 15;
-  double acc[4][4] = {};
+  __shared__ double As[kRhoChunk * kRS], Bs[kRhoChunk * kRS];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
+  d4 acc[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) acc[nt] = d4{0.0, 0.0, 0.0, 0.0};
   const int64_t row0 = (int64_t)blockIdx.x * a.rows_per_block;
   const int64_t rend = min(a.n, row0 + a.rows_per_block);
   for (int64_t r0 = row0; r0 < rend; r0 += kRhoChunk) {
     stage(As, a.A[side], a.ldu, rend, r0, r);
     stage(Bs, a.B[side], a.ldu, rend, r0, ro);
     __syncthreads();
-    for (int row = 0; row < kRhoChunk; ++row) {
-      double x[4], y[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        x[q] = As[row][4 * ta + q];
-        y[q] = Bs[row][4 * tb + q];
-      }
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] = fma(x[p], y[q], acc[p][q]);
-    }
+    gram_chunk(As, Bs, w, lr, lk, acc);
     __syncthreads();
   }
-  double* out = a.part + ((int64_t)blockIdx.x * 2 + side) * kPMax * kPMax;
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) out[(4 * ta + p) * kPMax + 4 * tb + q] = acc[p][q];
+  store_partial(a.part + ((int64_t)blockIdx.x * 2 + side) * kPMax * kPMax, w, lr, lk, acc);
 }
 
-// Pass B: Y = B - A M (rows of the chunk), partial G = Y^T Y.
+// Pass B: Y = B - A M (rows of the chunk, MFMA with M as the second operand), then partial
+// G = Y^T Y.
 __global__ __launch_bounds__(256) void k_rho_b(RhoKArgs a) {
   DevState* st = a.st;
   if (!rho_needed(st)) return;
   const int side = blockIdx.y;
   const int r = st->r[a.nb_new], ro = st->r[a.nb_old];
-  __shared__ double As[kRhoChunk][kPMax + 1], Bs[kRhoChunk][kPMax + 1];
-  __shared__ double Ms[kPMax][kPMax + 1];
+  __shared__ double As[kRhoChunk * kRS], Bs[kRhoChunk * kRS];
+  __shared__ double Ms[kPMax * kRS];
   const double* Mg = a.M + (int64_t)side * kPMax * kPMax;
-  for (int e = threadIdx.x; e < kPMax * kPMax; e += blockDim.x) Ms[e / kPMax][e % kPMax] = Mg[e];
-  const int t = threadIdx.x, ta = t >> 4, tb = t & 15;
-  double acc[4][4] = {};
+  for (int e = threadIdx.x; e < kPMax * kPMax; e += blockDim.x) Ms[(e / kPMax) * kRS + e % kPMax] = Mg[e];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
+  d4 acc[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) acc[nt] = d4{0.0, 0.0, 0.0, 0.0};
   const int64_t row0 = (int64_t)blockIdx.x * a.rows_per_block;
   const int64_t rend = min(a.n, row0 + a.rows_per_block);
   for (int64_t r0 = row0; r0 < rend; r0 += kRhoChunk) {
     stage(As, a.A[side], a.ldu, rend, r0, r);
     stage(Bs, a.B[side], a.ldu, rend, r0, ro);
     __syncthreads();
-    for (int e = t; e < kRhoChunk * kPMax; e += blockDim.x) {
-      const int row = e / kPMax, b = e % kPMax;
-      double s = Bs[row][b];
-      for (int q = 0; q < r; ++q) s = fma(-As[row][q], Ms[q][b], s);
-      Bs[row][b] = b < ro ? s : 0.0;
-    }
-    __syncthreads();
-    for (int row = 0; row < kRhoChunk; ++row) {
-      double x[4], y[4];
+    // T = A M for chunk rows 16 w .. 16 w + 15: A operand A[16 w + l%16][k0 + l/16], B operand
+    // M[k0 + l/16][16 nt + l%16]; result item v: row 16 w + l/16 + 4 v, column 16 nt + l%16
+    d4 tm[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        x[q] = Bs[row][4 * ta + q];
-        y[q] = Bs[row][4 * tb + q];
+    for (int nt = 0; nt < 4; ++nt) tm[nt] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < kPMax / 4; ++ks) {
+      const double xa = As[(16 * w + lr) * kRS + 4 * ks + lk];
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+        tm[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, Ms[(4 * ks + lk) * kRS + 16 * nt + lr], tm[nt], 0, 0, 0);
+    }
+    // Y = B - T in place of B (each element is read and written by its own lane)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double* y = &Bs[(16 * w + lk + 4 * v) * kRS + 16 * nt + lr];
+        *y = *y - tm[nt][v];
       }
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] = fma(x[p], y[q], acc[p][q]);
-    }
+    __syncthreads();
+    gram_chunk(Bs, Bs, w, lr, lk, acc);
     __syncthreads();
   }
-  double* out = a.part + ((int64_t)blockIdx.x * 2 + side) * kPMax * kPMax;
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) out[(4 * ta + p) * kPMax + 4 * tb + q] = acc[p][q];
+  store_partial(a.part + ((int64_t)blockIdx.x * 2 + side) * kPMax * kPMax, w, lr, lk, acc);
 }
 
 // Sum the per-block partials in block order: out[side][e] = sum_b part[b][side][e].
