@@ -143,7 +143,9 @@ typedef struct lrp_kernel_time {
   const char* name;  /* kernel name (static string owned by the library) */
   int32_t launches;  /* launches in the last solve */
   double ms;         /* their summed device time, milliseconds: from the HIP event recorded
-                        before the launch to the one recorded before the next operation */
+                        before the launch to the one recorded before the next operation, less
+                        the mean such delta of 16 empty launches made at the start of the solve
+                        (reported as the entry "launch overhead (empty kernel)") */
 } lrp_kernel_time;
 
 /*

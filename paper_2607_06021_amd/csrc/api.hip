@@ -214,6 +214,8 @@ __global__ void k_hold(int iters) {
   for (int i = 0; i < iters; ++i) __builtin_amdgcn_s_sleep(127);
 }
 
+// Event deltas include the dispatch and completion of each launch; the mean delta of the
+// empty launches (K_EMPTY) measures that overhead and is subtracted from every other launch.
 static void prof_reduce(lrp_ctx* c) {
   for (int q = 0; q < K_COUNT; ++q) {
     c->prof_ms[q] = 0.0;
@@ -227,6 +229,9 @@ static void prof_reduce(lrp_ctx* c) {
     c->prof_ms[id] += ms;
     c->prof_n[id] += 1;
   }
+  const double ov = c->prof_n[K_EMPTY] > 0 ? c->prof_ms[K_EMPTY] / c->prof_n[K_EMPTY] : 0.0;
+  for (int q = 0; q < K_COUNT; ++q)
+    if (q != K_EMPTY) c->prof_ms[q] = std::max(0.0, c->prof_ms[q] - ov * c->prof_n[q]);
 }
 
 int enqueue_pass_kernels(lrp_ctx* c, int k) {
@@ -555,6 +560,11 @@ int solve_impl(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const double*
     hipLaunchKernelGGL(k_hold, dim3(1), dim3(64), 0, c->stream, 150);
     if (hipGetLastError() != hipSuccess) return LRP_EDEVICE;
     g_prof = c;
+    for (int q = 0; q < 16; ++q) {  // empty launches: the per-launch event overhead
+      prof_mark(c->stream, K_EMPTY);
+      hipLaunchKernelGGL(k_hold, dim3(1), dim3(64), 0, c->stream, 0);
+    }
+    if (hipGetLastError() != hipSuccess) return LRP_EDEVICE;
   }
   TRY(enqueue_start(c, rF, U_F, ldu, sigma_F, V_F, ldv));
   // passes; the stop flag is read one pass behind the device
@@ -653,7 +663,7 @@ int lrp_get_profile(const lrp_ctx* c, int32_t* count, lrp_kernel_time* out) {
       "k_init_state", "k_scan", "k_dst_single", "k_dst_pass1", "k_dst_pass2", "k_fiber",
       "k_tsqr_factor", "k_tsqr_apply", "k_core_warm", "k_core", "k_prod", "k_pi", "k_gmax",
       "k_topk_block", "k_topk_merge", "k_select", "k_rho_a", "k_rho_b", "k_rho_reduce",
-      "k_rho_final", "k_eta", "k_finalize", "copy"};
+      "k_rho_final", "k_eta", "k_finalize", "copy", "launch overhead (empty kernel)"};
   if (!c || !count || *count < 0 || (*count > 0 && !out)) return LRP_EINVAL;
   if (!c->profile || !c->solved) {
     *count = 0;

@@ -14,7 +14,7 @@ namespace lrp {
 enum KernelId {
   K_INIT, K_SCAN, K_DST_SINGLE, K_DST_PASS1, K_DST_PASS2, K_FIBER, K_TSQR_FACTOR, K_TSQR_APPLY,
   K_CORE_WARM, K_CORE, K_PROD, K_PI, K_GMAX, K_TOPK_BLOCK, K_TOPK_MERGE, K_SELECT, K_RHO_A,
-  K_RHO_B, K_RHO_REDUCE, K_RHO_FINAL, K_ETA, K_FINALIZE, K_COPY, K_COUNT
+  K_RHO_B, K_RHO_REDUCE, K_RHO_FINAL, K_ETA, K_FINALIZE, K_COPY, K_EMPTY, K_COUNT
 };
 // Called right before a launch (or copy) on stream s: when this thread is recording a
 // profile on s, records an event that ends the previous entry and starts this one.

@@ -119,49 +119,58 @@ struct MergeArgs {
 };
 
 // Each of the kMergeFan input lists is sorted; an entry's rank in the merged order is its
-// position in its own list plus, for every other list, the number of entries before it
-// (binary search). Entries of rank < kPMax are written to the output list.
-__global__ __launch_bounds__(256) void k_topk_merge(MergeArgs a) {
+// position in its own list plus, for every other list, the number of entries before it.
+// One thread per entry; the kMergeFan binary searches (7 steps each) advance in
+// lockstep, so each step issues kMergeFan independent LDS reads. Entries of rank < kPMax are
+// written to the output list.
+constexpr int kMergeThreads = kMergeFan * kPMax;  // 1024
+__global__ __launch_bounds__(kMergeThreads) void k_topk_merge(MergeArgs a) {
   if (a.st->done) return;
   const int side = blockIdx.y;
   constexpr int NE = kMergeFan * kPMax;
   __shared__ Cand e[NE];
   const int first = blockIdx.x * kMergeFan;
-  for (int q = threadIdx.x; q < NE; q += blockDim.x) {
+  const int q = threadIdx.x;
+  {
     const int l = first + q / kPMax;
     Cand c;
+    c.s = -2.0;
+    c.i = 0x50000000 + q;  // padding entries: distinct indices, below every real entry
     if (l < a.nlists) {
       c.s = a.in_s[side][(int64_t)first * kPMax + q];
       c.i = a.in_i[side][(int64_t)first * kPMax + q];
-    } else {
-      c.s = -2.0;
-      c.i = 0x50000000 + q;
+      if (c.s == -2.0) c.i = 0x50000000 + q;
     }
-    if (c.s == -2.0) c.i = 0x50000000 + q;  // padding entries: distinct indices
     e[q] = c;
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < NE; q += blockDim.x) {
-    const Cand c = e[q];
-    const int mine = q / kPMax;
-    int rk = q % kPMax;
+  const Cand c = e[q];
+  const int mine = q / kPMax;
+  int lo[kMergeFan], hi[kMergeFan];
+#pragma unroll
+  for (int l = 0; l < kMergeFan; ++l) {
+    lo[l] = 0;
+    hi[l] = kPMax;  // first position whose entry is not before c
+  }
+#pragma unroll
+  for (int step = 0; step < 7; ++step) {  // ceil(log2(kPMax + 1)) steps empty every range
+#pragma unroll
     for (int l = 0; l < kMergeFan; ++l) {
-      if (l == mine) continue;
-      const Cand* L = e + l * kPMax;
-      int lo = 0, hi = kPMax;  // first position whose entry is not before c
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (before(L[mid], c))
-          lo = mid + 1;
+      const int mid = (lo[l] + hi[l]) >> 1;
+      if (lo[l] < hi[l]) {
+        if (before(e[l * kPMax + mid], c))
+          lo[l] = mid + 1;
         else
-          hi = mid;
+          hi[l] = mid;
       }
-      rk += lo;
     }
-    if (rk < kPMax) {
-      a.out_s[side][(int64_t)blockIdx.x * kPMax + rk] = c.s;
-      a.out_i[side][(int64_t)blockIdx.x * kPMax + rk] = c.i;
-    }
+  }
+  int rk = q % kPMax;
+#pragma unroll
+  for (int l = 0; l < kMergeFan; ++l) rk += (l == mine) ? 0 : lo[l];
+  if (rk < kPMax) {
+    a.out_s[side][(int64_t)blockIdx.x * kPMax + rk] = c.s;
+    a.out_i[side][(int64_t)blockIdx.x * kPMax + rk] = c.i;
   }
 }
 
@@ -316,7 +325,7 @@ int select_candidates(const SelectPlan& p, const DevState* st, const double* U[2
       ma.out_i[q] = p.cand_i[slot ^ 1][q];
     }
     prof_mark(s, K_TOPK_MERGE);
-    hipLaunchKernelGGL(k_topk_merge, dim3(outl, 2), dim3(256), 0, s, ma);
+    hipLaunchKernelGGL(k_topk_merge, dim3(outl, 2), dim3(kMergeThreads), 0, s, ma);
     slot ^= 1;
   }
   *final_list_slot = slot;
