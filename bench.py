@@ -197,7 +197,7 @@ def served_leg(count, seed, budget_gb, max_active, rate=None):
             wall = time.perf_counter() - t0
             st = srv.stats()
         lat = np.array([x[6] for x in res])
-        bad = sum(1 for x in res if x[4] < 0)
+        bad = [(r.idx, r.n, r.rank, r.precision, int(x[4])) for r, x in zip(reqs, res) if x[4] < 0]
         return wall, lat, bad, st
 
     # warm the contexts of every shape once, then measure the saturated rate
@@ -211,7 +211,9 @@ def served_leg(count, seed, budget_gb, max_active, rate=None):
     wall, lat, bad, st = run(reqs, use_rate)
     return {"requests": count, "arrival_rate_per_s": round(use_rate, 2), "saturated_solves_per_s": round(sat, 2),
             "solves_per_s": round(count / wall, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
-            "p99_ms": round(float(np.percentile(lat, 99)), 3), "failed": int(bad),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3), "failed": len(bad),
+            "failures": [{"request": i, "n": nn, "rank": rk, "precision": pr, "status": stt}
+                         for i, nn, rk, pr, stt in bad[:10]],
             "mix": "n in {1023,4095,16383,65535,262143} w.p. .3/.3/.2/.15/.05, rank U{2..20}, cap 48, "
                    "FP64 or mixed w.p. 0.5", "max_active": max_active, "contexts": st["contexts"]}
 
