@@ -108,7 +108,8 @@ int lrp_create(lrp_ctx** ctx, int64_t n, int32_t r_max, double tol, const lrp_op
  *   S_out    device, r_max values: the rank singular values in descending order, then 0.
  *   V_out    device, n x r_max, leading dimension ldov >= n, as U_out.
  *   r_out    host, receives the rank (1 <= rank <= r_max).
- *   info     host, may be NULL.
+ *   info     host, may be NULL. On a negative return only status and iters (the passes
+ *            completed before the failure) are set.
  * Blocks until the result is complete. Returns LRP_OK, LRP_NOT_CONVERGED or LRP_STAGNATED
  * with a valid result, or LRP_EINVAL / LRP_ENUMERIC / LRP_EDEVICE without one. A zero
  * right-hand side gives the zero solution with rank 1 and LRP_OK.

@@ -483,7 +483,14 @@ int collect(lrp_ctx* c, int32_t* r_out, lrp_info* info) {
   const DevState& h_st = *c->st_host;
   c->solved = true;
   const int status = h_st.status;
-  if (status < 0) return status;
+  if (status < 0) {  // no result; report how far the solve got
+    if (info) {
+      *info = lrp_info{};
+      info->status = status;
+      info->iters = h_st.k;
+    }
+    return status;
+  }
   if (r_out) *r_out = h_st.r_final;
   if (info) {
     float ms = 0.f;
@@ -558,13 +565,13 @@ int solve_impl(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const double*
   if (c->profile) {
     c->prof_used = 0;
     hipLaunchKernelGGL(k_hold, dim3(1), dim3(64), 0, c->stream, 150);
-    if (hipGetLastError() != hipSuccess) return LRP_EDEVICE;
+    if (launch_status() != LRP_OK) return LRP_EDEVICE;
     g_prof = c;
     for (int q = 0; q < 16; ++q) {  // empty launches: the per-launch event overhead
       prof_mark(c->stream, K_EMPTY);
       hipLaunchKernelGGL(k_hold, dim3(1), dim3(64), 0, c->stream, 0);
     }
-    if (hipGetLastError() != hipSuccess) return LRP_EDEVICE;
+    if (launch_status() != LRP_OK) return LRP_EDEVICE;
   }
   TRY(enqueue_start(c, rF, U_F, ldu, sigma_F, V_F, ldv));
   // passes; the stop flag is read one pass behind the device

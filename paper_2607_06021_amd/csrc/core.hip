@@ -732,7 +732,7 @@ __global__ __launch_bounds__(kCoreThreads) void k_eta(EtaArgs a) {
 int eta_launch(const EtaArgs& a, hipStream_t s) {
   prof_mark(s, K_ETA);
   hipLaunchKernelGGL(k_eta, dim3(1), dim3(kCoreThreads), 0, s, a);
-  return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
+  return launch_status();
 }
 
 // Warm start: M = R_u R_v^T (the core of F^ = U^ V^^T) and its SVD.
@@ -786,7 +786,7 @@ int core_launch(const CoreArgs& a, bool warm, hipStream_t s) {
     prof_mark(s, K_CORE);
     hipLaunchKernelGGL(k_core, dim3(1), dim3(kCoreThreads), 0, s, a);
   }
-  return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
+  return launch_status();
 }
 
 
@@ -824,7 +824,7 @@ __global__ void k_init_state(DevState* st, int rF, double eps, double tau) {
 int init_state_launch(DevState* st, int rF, double eps, double tau, hipStream_t s) {
   prof_mark(s, K_INIT);
   hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, st, rF, eps, tau);
-  return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
+  return launch_status();
 }
 
 __global__ void k_scan(DevState* st, const double* U, int64_t ldu, const double* V, int64_t ldv,
@@ -849,7 +849,7 @@ int scan_inputs_launch(DevState* st, const double* U, int64_t ldu, const double*
   const int blocks = (int)std::min<int64_t>(1024, (total + 255) / 256);
   prof_mark(s, K_SCAN);
   hipLaunchKernelGGL(k_scan, dim3(std::max(blocks, 1)), dim3(256), 0, s, st, U, ldu, V, ldv, sig, n, rF);
-  return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
+  return launch_status();
 }
 
 // r* = smallest r with sum_{l >= r} S_l^2 < (eps ||S||)^2 ; rank = max(min(r*, r_max), 1).
@@ -882,7 +882,7 @@ __global__ void k_finalize(DevState* st, double* S_out, int r_max) {
 int finalize_launch(DevState* st, double* S_out, int r_max, hipStream_t s) {
   prof_mark(s, K_FINALIZE);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, st, S_out, r_max);
-  return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
+  return launch_status();
 }
 
 // lambda_k = 4 sin^2(pi k / (2(n+1))), k = 1..n (Section 3, eigenvalues of T).
@@ -897,7 +897,7 @@ __global__ void k_lambda(double* lam, float* lam32, int64_t n) {
 
 int lambda_launch(double* lam, float* lam32, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_lambda, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, lam, lam32, n);
-  return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
+  return launch_status();
 }
 
 }  // namespace lrp

@@ -514,7 +514,7 @@ int dst_tables(DstPlan* p, hipStream_t s) {
     hipLaunchKernelGGL(k_twiddle, dim3((L2 + 255) / 256), dim3(256), 0, s, p->t2_64, p->t2_32, L2, L2);
     hipLaunchKernelGGL(k_twiddle, dim3((L2 + 255) / 256), dim3(256), 0, s, p->tl_64, p->tl_32, L, L2);
   }
-  return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
+  return launch_status();
 }
 
 template <typename T>
@@ -589,7 +589,7 @@ int dst_launch(const DstPlan& p, DstArgs a, bool fp32, hipStream_t s) {
     else
       launch_four_step<double>(p.logL1, p.logL2, npairs, a, s);
   }
-  return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
+  return launch_status();
 }
 
 }  // namespace lrp

@@ -79,7 +79,7 @@ int fiber_launch(const FiberArgs& a, bool fp32, hipStream_t s) {
     hipLaunchKernelGGL(k_fiber<float>, grid, dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL(k_fiber<double>, grid, dim3(256), 0, s, a);
-  return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
+  return launch_status();
 }
 
 }  // namespace lrp

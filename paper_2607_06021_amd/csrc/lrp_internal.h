@@ -77,6 +77,13 @@ struct TsqrLevel {
 // ----------------------------------------------------------------------------------------
 // 1/x and 1/sqrt(x) from the hardware approximations refined by two Newton steps (each
 // step squares the relative error), for normal positive x (rcp_nr: normal nonzero x).
+// Status of the launches just made on this thread. hipErrorNotReady (the answer of a
+// non-blocking hipEventQuery on unfinished work) is never a launch failure.
+inline int launch_status() {
+  const hipError_t e = hipGetLastError();
+  return (e == hipSuccess || e == hipErrorNotReady) ? LRP_OK : LRP_EDEVICE;
+}
+
 __device__ inline double rcp_nr(double x) {
   double y = __builtin_amdgcn_rcp(x);
   double e = fma(-x, y, 1.0);

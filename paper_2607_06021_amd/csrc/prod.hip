@@ -92,7 +92,7 @@ int prod_launch(const ProdArgs& a, hipStream_t s) {
   dim3 grid((unsigned)((a.n + kProdRowsPerBlock - 1) / kProdRowsPerBlock), 2);
   prof_mark(s, K_PROD);
   hipLaunchKernelGGL(k_prod, grid, dim3(256), 0, s, a);
-  return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
+  return launch_status();
 }
 
 }  // namespace lrp

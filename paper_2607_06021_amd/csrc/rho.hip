@@ -270,7 +270,7 @@ int rho_launch(const RhoPlan& p, const RhoArgs& ra, hipStream_t s) {
   f.trace = ra.trace;
   prof_mark(s, K_RHO_FINAL);
   hipLaunchKernelGGL(k_rho_final, dim3(1), dim3(256), 0, s, f);
-  return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
+  return launch_status();
 }
 
 }  // namespace lrp

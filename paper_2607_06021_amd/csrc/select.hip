@@ -329,13 +329,13 @@ int select_candidates(const SelectPlan& p, const DevState* st, const double* U[2
     slot ^= 1;
   }
   *final_list_slot = slot;
-  return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
+  return launch_status();
 }
 
 int select_update(const SelectArgs& a, hipStream_t s) {
   prof_mark(s, K_SELECT);
   hipLaunchKernelGGL(k_select, dim3(1), dim3(kPMax), 0, s, a);
-  return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
+  return launch_status();
 }
 
 }  // namespace lrp

@@ -137,6 +137,8 @@ bool advance(lrp_server* s, Slot& sl) {
         finish_job(s, j, LRP_EDEVICE, 0, nullptr);
         release_slot_job(sl, ++s->tick);
         return true;
+      } else {
+        (void)hipGetLastError();  // not ready is not an error; leave no error state behind
       }
     }
     if (!sl.stop && sl.k < c->maxiter && sl.k - sl.checked < 2) {
@@ -166,7 +168,10 @@ bool advance(lrp_server* s, Slot& sl) {
   }
   // phase 2: wait (without blocking) for the finish stage
   const hipError_t e = hipEventQuery(c->evfin);
-  if (e == hipErrorNotReady) return false;
+  if (e == hipErrorNotReady) {
+    (void)hipGetLastError();  // not ready is not an error; leave no error state behind
+    return false;
+  }
   int32_t rank = 0;
   lrp_info info{};
   const int status = (e == hipSuccess) ? collect(c, &rank, &info) : LRP_EDEVICE;

@@ -255,7 +255,9 @@ int tsqr_plan(TsqrPlan* p, int64_t n, int pmax) {
       if (hipMalloc(&lv.tau[s], tb) != hipSuccess) return LRP_ENOMEM;
       if (hipMalloc(&lv.Rout[s], rb) != hipSuccess) return LRP_ENOMEM;
       if (hipMalloc(&lv.Y[s], vb) != hipSuccess) return LRP_ENOMEM;
-      if (hipMemset(lv.Rout[s], 0, rb) != hipSuccess) return LRP_EDEVICE;
+      // no initialisation: every element of R that is read (columns below the active width,
+      // all pmax rows) is written by the factorization first. (A plain memset here would run
+      // on the null stream, unordered with the context's non-blocking stream.)
     }
     ++L;
     if (lv.nblocks == 1) break;
@@ -322,7 +324,7 @@ int tsqr_run(const TsqrPlan& p, const TsqrIO& io, hipStream_t s) {
     prof_mark(s, K_TSQR_APPLY);
     hipLaunchKernelGGL(k_tsqr_apply, dim3(lv.nblocks, ns), dim3(kTsqrThreads), 0, s, a);
   }
-  return hipGetLastError() == hipSuccess ? LRP_OK : LRP_EDEVICE;
+  return launch_status();
 }
 
 }  // namespace lrp
