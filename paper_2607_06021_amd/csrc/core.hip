@@ -19,16 +19,17 @@
 //     k_eta once rho is known, and only when a stop is possible.
 // The warm start uses the same SVD on M = R_u R_v^T, the core of F^ = U^ V^^T.
 //
-// Jacobi: Hestenes' one-sided method, round-robin ordering (k-1 rounds of k/2 disjoint column
-// pairs per sweep); a pair is rotated unless |a_p . a_q| <= sqrt(m) eps ||a_p|| ||a_q||; the
-// sweeps end when one makes no rotation (at most 60). Each pair is handled by a group of 8 or
-// 16 lanes whose partial dot products are summed with DPP lane permutes.
+// Jacobi: Hestenes' one-sided method; a pair is rotated unless
+// |a_p . a_q| <= sqrt(m) eps ||a_p|| ||a_q||, and the sweeps end when one makes no rotation (at
+// most 60). Every sweep visits each column pair once, in an order built for wavefronts (see
+// jacobi_waves): each wave keeps 8 columns in registers for 4 rounds at a time.
 #include "lrp_kernels.h"
 
 namespace lrp {
 
 constexpr int LDP = kPMax + 1;        // padded leading dimension of the LDS matrices
 constexpr int kCoreThreads = 512;
+constexpr int kEtaThreads = 1024;  // two Jacobi problems of up to 8 waves each
 constexpr int kBuf = kPMax * LDP;
 
 // ---------------------------------------------------------------- lane-group sums (DPP)
@@ -73,22 +74,26 @@ struct JacProb {
 };
 
 // Rotation (c, s) that makes columns p, q orthogonal: with al = |a_p|^2, be = |a_q|^2,
-// ga = a_p . a_q, d = be - al, t = sign(d) 2ga / (|d| + sqrt(d^2 + 4ga^2)) (Rutishauser's
-// smaller root, written without forming (be - al) / (2ga)), c = 1/sqrt(1 + t^2), s = c t.
+// ga = a_p . a_q, d = be - al, h = sqrt(d^2 + 4ga^2) and u = h + |d|, Rutishauser's smaller
+// root t = sign(d) 2ga / u gives c = 1/sqrt(1 + t^2) = u / sqrt(2hu) and
+// s = c t = sign(d) 2ga / sqrt(2hu) (u^2 + 4ga^2 = 2hu), so c^2 + s^2 = 1 holds by construction
+// and no quotient has to be formed.
 __device__ inline void jacobi_rotation(double al, double be, double ga, double& c, double& s) {
   const double d = be - al, g2 = 2.0 * ga;
   const double h2 = fma(d, d, g2 * g2);
-  double t;
   if (h2 > 1e-290 && h2 < 1e290) {
     const double h = h2 * rsq_nr(h2);
-    t = copysign(1.0, d) * g2 * rcp_nr(fabs(d) + h);
-    c = rsq_nr(fma(t, t, 1.0));
+    const double u = h + fabs(d);
+    const double r = rsq_nr(2.0 * h * u);
+    c = u * r;
+    s = copysign(1.0, d) * g2 * r;
   } else {  // extreme magnitudes: the correctly rounded library operations
     const double zeta = d / g2;
-    t = fabs(zeta) > 1e150 ? 0.5 / zeta : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    const double t =
+        fabs(zeta) > 1e150 ? 0.5 / zeta : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
     c = 1.0 / sqrt(1.0 + t * t);
+    s = c * t;
   }
-  s = c * t;
 }
 
 // Column pair of pair slot pi in round rd of the round-robin ordering of kk (even) columns:
@@ -111,112 +116,186 @@ __device__ inline void rr_pair(int kk, int pi, int rd, int& p, int& q) {
   }
 }
 
-// Solve one or two independent Jacobi problems with the whole workgroup: with two, each
-// half of the threads takes one. flags: 2 ints of LDS.
-//
-// Each column pair of a round is handled by G lanes (16 for one problem, 8 for two); lane li
-// holds rows li + G u of both columns in registers for the dot products and the update. The
-// rotation of V (when requested) is applied one round late by the same lanes: rounds touch
-// disjoint columns, so the V update of round rd overlaps the A work of round rd + 1 and only
-// has to precede the barrier that ends it.
-template <int G>
-__device__ void jacobi_g(JacProb* P, int nprob, int* flags) {
-  constexpr int U = kPMax / G;  // rows per lane
-  const int t = threadIdx.x;
-  const int half = kCoreThreads / 2;
-  const int which = (nprob == 2 && t >= half) ? 1 : 0;
-  const int lt = (nprob == 2) ? (t - which * half) : t;
-  const JacProb pr = P[which];
-  const int pi = lt / G, li = lt % G;
-  const double tol = sqrt((double)max(pr.m, 1)) * kEps;
-  const double tol2 = tol * tol;
-  int rounds = 0;
-  for (int q = 0; q < nprob; ++q) {
-    const int kk = P[q].k + (P[q].k & 1);
-    rounds = max(rounds, kk - 1);
+// Value of x held by lane src of the wave (ds_bpermute moves 32 bits per lane).
+__device__ inline double lane_fetch(double x, int src) {
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(x));
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+
+// Column groups of 4 for a k-column problem: an even count >= 2 (columns past k are empty).
+__device__ inline int jac_groups(int k) {
+  int g = (k + 3) >> 2;
+  g += g & 1;
+  return g < 2 ? 2 : g;
+}
+
+// One Jacobi pair step on the 16 lanes of a pair slot: lane li holds rows li + 16u (u < 4)
+// of the two columns (a, b) and of their V columns; rows past m (or k for V) are zero, and so is
+// an empty column, which is never rotated (its dot products vanish).
+template <bool WV>
+__device__ inline bool jac_pair(double (&a)[4], double (&b)[4], double (&va)[4], double (&vb)[4], double tol2) {
+  double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    al = fma(a[u], a[u], al);
+    be = fma(b[u], b[u], be);
+    ga = fma(a[u], b[u], ga);
   }
-  if (rounds <= 0) {
+  al = group_sum<16>(al);
+  be = group_sum<16>(be);
+  ga = group_sum<16>(ga);
+  const bool rot = ga != 0.0 && ga * ga > tol2 * al * be;
+  // Straight-line rotation for every slot (slots that do not rotate take c = 1, s = 0, which
+  // leaves the values of their columns unchanged); the extreme-range formula is a rare branch.
+  const double d = be - al, g2 = 2.0 * ga;
+  const double h2 = fma(d, d, g2 * g2);
+  const double h = h2 * rsq_nr(h2);
+  const double uu = h + fabs(d);
+  const double rr = rsq_nr(2.0 * h * uu);
+  double c = uu * rr, sn = copysign(1.0, d) * g2 * rr;
+  if (rot && !(h2 > 1e-290 && h2 < 1e290)) jacobi_rotation(al, be, ga, c, sn);
+  c = rot ? c : 1.0;
+  sn = rot ? sn : 0.0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const double x = a[u], y = b[u];
+    a[u] = c * x - sn * y;
+    b[u] = sn * x + c * y;
+  }
+  if (WV) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double x = va[u], y = vb[u];
+      va[u] = c * x - sn * y;
+      vb[u] = sn * x + c * y;
+    }
+  }
+  return rot;
+}
+
+// The second columns of every slot (and their V columns) move to the slot of lane ^ xmask.
+template <bool WV>
+__device__ inline void jac_move_b(double (&b)[4], double (&vb)[4], int src) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    b[u] = lane_fetch(b[u], src);
+    if (WV) vb[u] = lane_fetch(vb[u], src);
+  }
+}
+
+// Columns ca (into x, vx) from LDS, zero past the problem.
+template <bool WV>
+__device__ inline void jac_load(const JacProb& pr, int col, int li, double (&x)[4], double (&vx)[4]) {
+  const bool ok = col < pr.k;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = li + 16 * u;
+    x[u] = (ok && i < pr.m) ? pr.A[i + col * LDP] : 0.0;
+    if (WV) vx[u] = (ok && i < pr.k) ? pr.V[i + col * LDP] : 0.0;
+  }
+}
+
+template <bool WV>
+__device__ inline void jac_store(const JacProb& pr, int col, int li, const double (&x)[4], const double (&vx)[4]) {
+  if (col >= pr.k) return;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = li + 16 * u;
+    if (i < pr.m) pr.A[i + col * LDP] = x[u];
+    if (WV && i < pr.k) pr.V[i + col * LDP] = vx[u];
+  }
+}
+
+// Solve one or two independent Jacobi problems (A: m x k in LDS, m, k <= 64; V: the k x k
+// accumulated rotations, holding the identity on entry, or null for none) with the workgroup:
+// problem q runs on waves 8q .. 8q+7 (blockDim.x >= 512 nprob). flags: 2 ints of LDS.
+//
+// The k columns are split into NG groups of 4 (NG even, columns past k empty). A sweep is
+//   * NG - 1 group rounds: the round-robin (circle) schedule over the groups gives wave w the
+//     group pair (g, h); the wave loads the 8 columns into registers -- pair slot i (lanes
+//     16i .. 16i+15) takes columns 4g + i and 4h + i -- and runs 4 rounds pairing 4g + i with
+//     4h + (i ^ s), s = 0, 1, 3, 2, the second columns moving between slots by lane permutes,
+//     then stores them back (one workgroup barrier per group round);
+//   * an intra-group phase: wave w takes groups 2w and 2w+1 and pairs the 4 columns of each in 3
+//     rounds ((0,1)(2,3), (0,2)(1,3), (0,3)(1,2)).
+// Every column pair is visited once per sweep, no two pairs of a round share a column, and no
+// barrier is needed inside a group round.
+template <bool WV>
+__device__ void jacobi_waves(JacProb* P, int nprob, int* flags) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int q = (nprob == 2 && wv >= 8) ? 1 : 0;
+  const int lw = wv - 8 * q;
+  const JacProb pr = P[q];
+  const int slot = lane >> 4, li = lane & 15;
+  int ngmax = 0, kmax = 0;
+  for (int x = 0; x < nprob; ++x) {
+    kmax = max(kmax, P[x].k);
+    ngmax = max(ngmax, jac_groups(P[x].k));
+  }
+  if (kmax < 2) {
     __syncthreads();
     return;
   }
-  const int kk = pr.k + (pr.k & 1);
-  const bool slot_ok = pr.k >= 2 && pi < (kk >> 1);
-  double* A = pr.A;
-  double* V = pr.V;
+  const int ng = jac_groups(pr.k);
+  const bool mine = pr.k >= 2 && lw < (ng >> 1) && (nprob == 2 || wv < 8);
+  const double tol = sqrt((double)max(pr.m, 1)) * kEps;
+  const double tol2 = tol * tol;
+  double a[4], b[4], va[4], vb[4];
   bool active = true;
   for (int sweep = 0; sweep < 60; ++sweep) {
     if (t < 2) flags[t] = 0;
     __syncthreads();
     bool rot = false;
-    int vp = -1, vq = -1;
-    double vc = 1.0, vs = 0.0;
-    for (int rd = 0; rd < rounds; ++rd) {
-      if (active && vp >= 0) {  // V update of the previous round
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int i = li + G * u;
-          if (i < pr.k) {
-            const double x = V[i + vp * LDP], y = V[i + vq * LDP];
-            V[i + vp * LDP] = vc * x - vs * y;
-            V[i + vq * LDP] = vs * x + vc * y;
-          }
-        }
-      }
-      vp = -1;
-      int p = 0, q = 0;
-      if (active && slot_ok && rd < kk - 1) rr_pair(kk, pi, rd, p, q);
-      if (active && slot_ok && rd < kk - 1 && q < pr.k) {
-        double ap[U], aq[U];
-        double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int i = li + G * u;
-          ap[u] = i < pr.m ? A[i + p * LDP] : 0.0;
-          aq[u] = i < pr.m ? A[i + q * LDP] : 0.0;
-          al = fma(ap[u], ap[u], al);
-          be = fma(aq[u], aq[u], be);
-          ga = fma(ap[u], aq[u], ga);
-        }
-        al = group_sum<G>(al);
-        be = group_sum<G>(be);
-        ga = group_sum<G>(ga);
-        if (ga != 0.0 && ga * ga > tol2 * al * be) {
-          double c, sn;
-          jacobi_rotation(al, be, ga, c, sn);
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int i = li + G * u;
-            if (i < pr.m) {
-              A[i + p * LDP] = c * ap[u] - sn * aq[u];
-              A[i + q * LDP] = sn * ap[u] + c * aq[u];
-            }
-          }
-          rot = true;
-          if (V) {
-            vp = p;
-            vq = q;
-            vc = c;
-            vs = sn;
-          }
-        }
+    for (int gr = 0; gr < ngmax - 1; ++gr) {
+      if (active && mine && gr < ng - 1) {
+        int g, h;
+        rr_pair(ng, lw, gr, g, h);
+        jac_load<WV>(pr, 4 * g + slot, li, a, va);
+        jac_load<WV>(pr, 4 * h + slot, li, b, vb);
+        rot |= jac_pair<WV>(a, b, va, vb, tol2);  // s = 0
+        jac_move_b<WV>(b, vb, lane ^ 16);
+        rot |= jac_pair<WV>(a, b, va, vb, tol2);  // s = 1
+        jac_move_b<WV>(b, vb, lane ^ 32);
+        rot |= jac_pair<WV>(a, b, va, vb, tol2);  // s = 3
+        jac_move_b<WV>(b, vb, lane ^ 16);
+        rot |= jac_pair<WV>(a, b, va, vb, tol2);  // s = 2
+        jac_store<WV>(pr, 4 * g + slot, li, a, va);
+        jac_store<WV>(pr, 4 * h + (slot ^ 2), li, b, vb);
       }
       __syncthreads();
     }
-    if (active && vp >= 0) {
+    if (active && mine) {
+      const int c0 = 4 * (2 * lw + (slot >> 1));
+      const bool odd = slot & 1;
+      jac_load<WV>(pr, c0 + (odd ? 2 : 0), li, a, va);
+      jac_load<WV>(pr, c0 + (odd ? 3 : 1), li, b, vb);
+      rot |= jac_pair<WV>(a, b, va, vb, tol2);  // (0,1) (2,3)
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = li + G * u;
-        if (i < pr.k) {
-          const double x = V[i + vp * LDP], y = V[i + vq * LDP];
-          V[i + vp * LDP] = vc * x - vs * y;
-          V[i + vq * LDP] = vs * x + vc * y;
+      for (int u = 0; u < 4; ++u) {  // even slot: b <- partner's a; odd slot: a <- partner's b
+        const double ta = lane_fetch(a[u], lane ^ 16), tb = lane_fetch(b[u], lane ^ 16);
+        if (odd)
+          a[u] = tb;
+        else
+          b[u] = ta;
+        if (WV) {
+          const double tva = lane_fetch(va[u], lane ^ 16), tvb = lane_fetch(vb[u], lane ^ 16);
+          if (odd)
+            va[u] = tvb;
+          else
+            vb[u] = tva;
         }
       }
+      rot |= jac_pair<WV>(a, b, va, vb, tol2);  // (0,2) (1,3)
+      jac_move_b<WV>(b, vb, lane ^ 16);
+      rot |= jac_pair<WV>(a, b, va, vb, tol2);  // (0,3) (1,2)
+      jac_store<WV>(pr, c0 + (odd ? 1 : 0), li, a, va);
+      jac_store<WV>(pr, c0 + (odd ? 2 : 3), li, b, vb);
     }
-    if (rot) flags[which] = 1;
+    if (rot) flags[q] = 1;
     __syncthreads();
     const bool any0 = flags[0] != 0, any1 = flags[1] != 0;
-    active = which == 0 ? any0 : any1;
+    active = q == 0 ? any0 : any1;
     const bool more = any0 || (nprob == 2 && any1);
     __syncthreads();
     if (!more) break;
@@ -224,10 +303,12 @@ __device__ void jacobi_g(JacProb* P, int nprob, int* flags) {
 }
 
 __device__ void jacobi(JacProb* P, int nprob, int* flags) {
-  if (nprob == 2)
-    jacobi_g<8>(P, 2, flags);
+  bool wv = false;
+  for (int x = 0; x < nprob; ++x) wv |= P[x].V != nullptr;
+  if (wv)
+    jacobi_waves<true>(P, nprob, flags);
   else
-    jacobi_g<16>(P, 1, flags);
+    jacobi_waves<false>(P, nprob, flags);
 }
 
 // sig[c] = ||A(:, c)||, ord[r] = column of rank r (descending, ties to the smaller index).
@@ -640,7 +721,7 @@ __global__ __launch_bounds__(kCoreThreads) void k_core(CoreArgs a) {
 // each stored tall (rows >= cols) so that Jacobi gives its min(rows, cols) singular values;
 // the two problems are solved side by side. Then the pass is accepted as the new iterate and
 // the solve stops when max(rho, indicator) < eps, or after maxiter passes.
-__global__ __launch_bounds__(kCoreThreads) void k_eta(EtaArgs a) {
+__global__ __launch_bounds__(kEtaThreads) void k_eta(EtaArgs a) {
   DevState* st = a.st;
   if (st->done) return;
   __shared__ double E1[kBuf], E2[kBuf];
@@ -731,7 +812,7 @@ __global__ __launch_bounds__(kCoreThreads) void k_eta(EtaArgs a) {
 
 int eta_launch(const EtaArgs& a, hipStream_t s) {
   prof_mark(s, K_ETA);
-  hipLaunchKernelGGL(k_eta, dim3(1), dim3(kCoreThreads), 0, s, a);
+  hipLaunchKernelGGL(k_eta, dim3(1), dim3(kEtaThreads), 0, s, a);
   return launch_status();
 }
 

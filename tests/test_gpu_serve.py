@@ -47,6 +47,38 @@ def test_served_results_equal_solo_results():
         assert torch.equal(Uo, Us) and torch.equal(So, Ss) and torch.equal(Vo, Vs), (n, prec)
 
 
+def test_contexts_created_under_load_all_succeed():
+    """Many shapes submitted at once: contexts are created while other requests run on the
+    device (a set-up step that is not ordered with the contexts' own streams would race with
+    their first kernels). Every solve must succeed and equal its solo result."""
+    import torch
+
+    from paper_2607_06021_amd import Solver
+    from paper_2607_06021_amd.lrp import Server
+
+    shapes = [(1023, "fp64"), (4095, "fp64"), (16383, "fp64"), (65535, "fp64"), (1023, "mixed"),
+              (4095, "mixed"), (16383, "mixed"), (255, "fp64")]
+    reqs = []
+    for rnd in range(3):
+        for i, (n, prec) in enumerate(shapes):
+            U, s, V, _ = workloads.bump_rhs(n, 3000 + 10 * rnd + i, 3 + (5 * i + rnd) % 15, 0.05, 0.2)
+            reqs.append((n, _dev(U), _dev(s), _dev(V), prec))
+    torch.cuda.synchronize()
+    print(f"serving {len(reqs)} requests over fresh servers", flush=True)
+    served = []
+    for rnd in range(3):
+        part = reqs[rnd * len(shapes):(rnd + 1) * len(shapes)]
+        with Server(budget_bytes=16 << 30, max_active=8) as srv:
+            tickets = [srv.submit(n, U, s, V, 48, 1e-10, 20, prec) for (n, U, s, V, prec) in part]
+            served += [srv.wait(t) for t in tickets]
+    assert all(r[4] >= 0 for r in served), [r[4] for r in served]
+    for (n, U, s, V, prec), (Us, Ss, Vs, rank, status, info, _) in zip(reqs, served):
+        with Solver(n, 48, 1e-10, maxiter=20, precision=prec) as sol:
+            Uo, So, Vo, r, inf = sol.solve(U, s, V)
+        assert status == inf.status and rank == r
+        assert torch.equal(Uo, Us) and torch.equal(So, Ss) and torch.equal(Vo, Vs), (n, prec)
+
+
 def test_small_budget_serializes_but_completes():
     import torch
 
