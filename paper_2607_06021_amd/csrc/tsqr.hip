@@ -43,6 +43,12 @@ struct ApplyArgs {
   int64_t ldy;
 };
 
+// An empty asm statement that takes a loaded value as input and output: the load must then
+// complete unconditionally before it, so a following select on a lane condition cannot be
+// turned into a branch around the load (which would serialise the loads, each with its own wait).
+__device__ inline void keep_loaded(double& v) { asm volatile("" : "+v"(v)); }
+__device__ inline void keep_loaded(float& v) { asm volatile("" : "+v"(v)); }
+
 __device__ inline int side_cols(const DevState* st, const int* fixed, int side) {
   return st ? st->ncols[side] : fixed[side];
 }
@@ -67,11 +73,80 @@ __device__ inline double row16_sum(double x) {
   return x;
 }
 
+// Element c mod 16 of x for a column index c that is the same on every active lane: a switch on
+// a uniform value is a scalar branch, where indexing the register array would select through
+// all 16 elements on every lane.
+__device__ inline double element_uniform(const double (&x)[kTsqrRowsPerThread], int i) {
+  switch (i & (kTsqrRowsPerThread - 1)) {
+    case 0: return x[0];
+    case 1: return x[1];
+    case 2: return x[2];
+    case 3: return x[3];
+    case 4: return x[4];
+    case 5: return x[5];
+    case 6: return x[6];
+    case 7: return x[7];
+    case 8: return x[8];
+    case 9: return x[9];
+    case 10: return x[10];
+    case 11: return x[11];
+    case 12: return x[12];
+    case 13: return x[13];
+    case 14: return x[14];
+    default: return x[15];
+  }
+}
+
+// Householder vector of column c (held by its 16 lanes, rows 16 sub .. 16 sub + 15 in x, the
+// column already transformed by reflectors 0 .. c-1; c is the same for every active lane of the
+// wave). vb receives the whole reflector (v_c = 1, zeros above, the tail x * scale below) with
+// element 16 s + i stored at 16 i + s, so that the 16 lanes of a column read consecutive words;
+// x itself is left as it is (rows above c are R(0..c-1, c), and the tail is scaled by the caller
+// when the reflectors are written out).
+//
+// With h = sqrt(alpha^2 + |x_tail|^2) and s = sign(alpha): beta = -s h, tau = (beta - alpha) /
+// beta = 1 + |alpha| / h and 1 / (alpha - beta) = s / (|alpha| + h), so one reciprocal square
+// root and one reciprocal give all three; the diagonal element alpha is read from the one lane
+// that holds it. Only a zero tail or an extreme magnitude leave this straight-line path.
+__device__ inline void householder_column(const double (&x)[kTsqrRowsPerThread], int c, int rbase, int sub,
+                                          double* vb, double& beta, double& tau, double& scale) {
+  double y[kTsqrRowsPerThread], n[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < kTsqrRowsPerThread; ++i) {
+    y[i] = rbase + i > c ? x[i] : 0.0;
+    n[i & 3] = fma(y[i], y[i], n[i & 3]);
+  }
+  const double xnorm2 = row16_sum((n[0] + n[1]) + (n[2] + n[3]));
+  // lane of this column (lanes 16 (c mod 4) .. of the wave) holding row c, element c mod 16
+  const int src = ((c & 3) << 4) + (c >> 4);
+  const double xc = element_uniform(x, c);
+  const double alpha = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(xc), src),
+                                        __builtin_amdgcn_readlane(__double2loint(xc), src)) +
+                       0.0;  // a zero diagonal counts as +0
+  const double h2 = fma(alpha, alpha, xnorm2);
+  const double rh = rsq_nr(h2);
+  const double h = h2 * rh;
+  beta = -copysign(h, alpha);
+  tau = fma(fabs(alpha), rh, 1.0);
+  scale = copysign(rcp_nr(fabs(alpha) + h), alpha);
+  if (xnorm2 == 0.0) {
+    tau = 0.0;
+    beta = alpha;
+    scale = 0.0;
+  } else if (!(h2 > 1e-290 && h2 < 1e290)) {  // extreme magnitudes: correctly rounded operations
+    beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+    tau = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+#pragma unroll
+  for (int i = 0; i < kTsqrRowsPerThread; ++i) vb[i * 16 + sub] = y[i] * scale;
+  if (sub == (c >> 4)) vb[(c & 15) * 16 + sub] = 1.0;  // same lane, after its zero: in order
+}
+
 // Thread layout of a 256-row block: column c = t/16, rows 16 (t%16) .. 16 (t%16)+15, so the
-// 16 lanes of a DPP row hold one column. The lanes of column j build reflector j themselves
-// (norm and diagonal by row sums), publish it in LDS (double-buffered; element 16 s + i of the
-// column is stored at 16 i + s, so that the 16 lanes of a column read 16 consecutive words)
-// and one barrier later every trailing column applies it.
+// 16 lanes of a DPP row hold one column. Column 0 builds its reflector first; then at step j,
+// after the barrier that publishes v_j (double-buffered in LDS), every trailing column applies
+// it, and the lanes of column j+1 go on at once to build v_{j+1}: one barrier per reflector.
 __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) {
   const int side = blockIdx.y;
   if (a.st && a.st->done) return;
@@ -82,91 +157,73 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) {
   const int t = threadIdx.x, c = t >> 4, sub = t & 15;
   const int rbase = sub * kTsqrRowsPerThread;
   __shared__ double vbuf[2][kTsqrRows];
+  __shared__ double tsh[kPMax];
 
+  // Every load reads a valid element (row and column clamped into the block) and the unused ones
+  // are replaced by zeros afterwards, so that all 16 loads are in flight together.
   double x[kTsqrRowsPerThread];
   {
-    const int64_t base = row0 + (int64_t)c * a.ldin + rbase;
     const bool colok = c < p;
+    const int64_t base = row0 + (int64_t)(colok ? c : 0) * a.ldin;
     if (a.in_f32) {
       const float* X = (const float*)a.in[side];
+      float raw[kTsqrRowsPerThread];
 #pragma unroll
-      for (int i = 0; i < kTsqrRowsPerThread; ++i) x[i] = (colok && rbase + i < nr) ? (double)X[base + i] : 0.0;
+      for (int i = 0; i < kTsqrRowsPerThread; ++i) raw[i] = X[base + min(rbase + i, nr - 1)];
+#pragma unroll
+      for (int i = 0; i < kTsqrRowsPerThread; ++i) {
+        keep_loaded(raw[i]);
+        x[i] = (colok && rbase + i < nr) ? (double)raw[i] : 0.0;
+      }
     } else {
       const double* X = (const double*)a.in[side];
 #pragma unroll
-      for (int i = 0; i < kTsqrRowsPerThread; ++i) x[i] = (colok && rbase + i < nr) ? X[base + i] : 0.0;
+      for (int i = 0; i < kTsqrRowsPerThread; ++i) x[i] = X[base + min(rbase + i, nr - 1)];
+#pragma unroll
+      for (int i = 0; i < kTsqrRowsPerThread; ++i) {
+        keep_loaded(x[i]);
+        x[i] = (colok && rbase + i < nr) ? x[i] : 0.0;
+      }
     }
   }
   double* V = a.V[side];
   double* Rb = a.Rout[side] + (int64_t)blockIdx.x * a.pmax;  // this block's R, rows 0..pmax-1
   double* taub = a.tau[side] + (int64_t)blockIdx.x * a.pmax;
-  __shared__ double tsh[kPMax];
-  // After its own step, column c is final: its registers keep R(0..c-1, c) above the diagonal
-  // and the reflector below it, and rdiag = R(c, c). Nothing is written to global memory
-  // inside the loop, so the per-step barrier waits on LDS only.
-  double rdiag = 0.0;
-
+  // After its reflector is built, column c is final: its registers keep R(0..c-1, c) above the
+  // diagonal and the unscaled tail below it (the reflector is the tail times vscale), and
+  // rdiag = R(c, c). Nothing is written to global
+  // memory inside the loop, so the per-step barrier waits on LDS only.
+  double rdiag = 0.0, vscale = 0.0;
+  if (c == 0) {
+    double tau;
+    householder_column(x, 0, rbase, sub, vbuf[0], rdiag, tau, vscale);
+    if (sub == 0) tsh[0] = tau;
+  }
+  __syncthreads();
   for (int j = 0; j < p; ++j) {
-    double* vb = vbuf[j & 1];
-    if (c == j) {
-      // two partial sums shorten the dependent chain of the norm
-      double n0 = 0.0, n1 = 0.0, al = 0.0;
-#pragma unroll
-      for (int i = 0; i < kTsqrRowsPerThread; i += 2) {
-        const int r = rbase + i;
-        n0 = (r > j) ? fma(x[i], x[i], n0) : n0;
-        n1 = (r + 1 > j) ? fma(x[i + 1], x[i + 1], n1) : n1;
-        al = (r == j) ? x[i] : al;
-        al = (r + 1 == j) ? x[i + 1] : al;
-      }
-      const double xnorm2 = row16_sum(n0 + n1);
-      const double alpha = row16_sum(al);
-      double beta, tau, scale;
-      const double h2 = fma(alpha, alpha, xnorm2);
-      if (xnorm2 == 0.0) {
-        tau = 0.0;
-        beta = alpha;
-        scale = 0.0;
-      } else if (h2 > 1e-290 && h2 < 1e290) {  // hardware rsq/rcp refined by Newton steps
-        beta = -copysign(h2 * rsq_nr(h2), alpha);
-        tau = (beta - alpha) * rcp_nr(beta);
-        scale = rcp_nr(alpha - beta);
-      } else {
-        beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-        tau = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-      }
-#pragma unroll
-      for (int i = 0; i < kTsqrRowsPerThread; ++i) {
-        const int r = rbase + i;
-        const double v = (r > j) ? x[i] * scale : (r == j ? 1.0 : 0.0);
-        vb[i * 16 + sub] = v;  // transposed: the 16 lanes of a column read consecutive words
-        if (r > j) x[i] = v;
-      }
-      rdiag = beta;
-      if (sub == 0) tsh[j] = tau;
-    }
-    __syncthreads();
     if (c > j && c < p) {
+      const double* vs = vbuf[j & 1] + sub;
       const double tau = tsh[j];
-      const double* vs = vb + sub;
-      double d0 = 0.0, d1 = 0.0;
+      double d[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int i = 0; i < kTsqrRowsPerThread; i += 2) {
-        d0 = fma(vs[i * 16], x[i], d0);
-        d1 = fma(vs[(i + 1) * 16], x[i + 1], d1);
-      }
-      const double w = row16_sum(d0 + d1) * tau;
+      for (int i = 0; i < kTsqrRowsPerThread; ++i) d[i & 3] = fma(vs[i * 16], x[i], d[i & 3]);
+      const double w = row16_sum((d[0] + d[1]) + (d[2] + d[3])) * tau;
 #pragma unroll
       for (int i = 0; i < kTsqrRowsPerThread; ++i) x[i] = fma(-w, vs[i * 16], x[i]);
+      if (c == j + 1) {
+        double tnext;
+        householder_column(x, j + 1, rbase, sub, vbuf[(j + 1) & 1], rdiag, tnext, vscale);
+        if (sub == 0) tsh[c] = tnext;
+      }
     }
+    __syncthreads();
   }
   // write the reflectors, R and tau once
   if (c < p) {
 #pragma unroll
     for (int i = 0; i < kTsqrRowsPerThread; ++i) {
       const int r = rbase + i;
-      if (r < nr) V[row0 + r + (int64_t)c * a.ldv] = (r > c) ? x[i] : (r == c ? 1.0 : 0.0);
+      if (r < nr) V[row0 + r + (int64_t)c * a.ldv] = (r > c) ? x[i] * vscale : (r == c ? 1.0 : 0.0);
       if (r < a.pmax) Rb[r + (int64_t)c * a.ldr] = (r < c) ? x[i] : (r == c ? rdiag : 0.0);
     }
   }
@@ -194,14 +251,29 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_apply(ApplyArgs a) {
   double y[kTsqrRowsPerThread], v[kTsqrRowsPerThread];
   const double* T = a.T[side];
   const int64_t toff = (int64_t)blockIdx.x * a.pmax;
-  const double* V = a.V[side] + row0 + (int64_t)c * a.ldv + rbase;
+  // loads of clamped (always valid) elements, unused ones replaced by zeros: no load waits on a
+  // branch, so all of them are in flight together
+  const bool colok = c < p;
+  const int cc = colok ? c : 0;
+  const double* V = a.V[side] + row0 + (int64_t)cc * a.ldv;
+#pragma unroll
+  for (int i = 0; i < kTsqrRowsPerThread; ++i) v[i] = V[min(rbase + i, nr - 1)];
+  if (T) {
+    const double* Tc = T + toff + (int64_t)cc * a.ldt;
+#pragma unroll
+    for (int i = 0; i < kTsqrRowsPerThread; ++i) y[i] = Tc[min(rbase + i, p - 1)];
+#pragma unroll
+    for (int i = 0; i < kTsqrRowsPerThread; ++i) keep_loaded(y[i]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < kTsqrRowsPerThread; ++i) y[i] = rbase + i == c ? 1.0 : 0.0;
+  }
 #pragma unroll
   for (int i = 0; i < kTsqrRowsPerThread; ++i) {
     const int lr = rbase + i;
-    double v0 = 0.0;
-    if (c < p && lr < p) v0 = T ? T[toff + lr + (int64_t)c * a.ldt] : (lr == c ? 1.0 : 0.0);
-    y[i] = v0;
-    v[i] = (c < p && lr < nr) ? V[i] : 0.0;
+    keep_loaded(v[i]);
+    y[i] = (colok && lr < p) ? y[i] : 0.0;
+    v[i] = (colok && lr < nr) ? v[i] : 0.0;
   }
   for (int j = p - 1; j >= 0; --j) {
     double* vb = vbuf[j & 1];
@@ -213,13 +285,10 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_apply(ApplyArgs a) {
     const double tj = tsh[j];
     if (c < p && tj != 0.0) {
       const double* vs = vb + sub;
-      double d0 = 0.0, d1 = 0.0;
+      double d[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int i = 0; i < kTsqrRowsPerThread; i += 2) {
-        d0 = fma(vs[i * 16], y[i], d0);
-        d1 = fma(vs[(i + 1) * 16], y[i + 1], d1);
-      }
-      const double w = row16_sum(d0 + d1) * tj;
+      for (int i = 0; i < kTsqrRowsPerThread; ++i) d[i & 3] = fma(vs[i * 16], y[i], d[i & 3]);
+      const double w = row16_sum((d[0] + d[1]) + (d[2] + d[3])) * tj;
 #pragma unroll
       for (int i = 0; i < kTsqrRowsPerThread; ++i) y[i] = fma(-w, vs[i * 16], y[i]);
     }
