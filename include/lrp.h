@@ -143,10 +143,11 @@ int lrp_get_trace(const lrp_ctx* ctx, int32_t* count, int32_t* Ipre, int32_t* nI
 typedef struct lrp_kernel_time {
   const char* name;  /* kernel name (static string owned by the library) */
   int32_t launches;  /* launches in the last solve */
-  double ms;         /* their summed device time, milliseconds: from the HIP event recorded
-                        before the launch to the one recorded before the next operation, less
-                        the mean such delta of 16 empty launches made at the start of the solve
-                        (reported as the entry "launch overhead (empty kernel)") */
+  double ms;         /* their summed device time, milliseconds, each launch timed by start and
+                        stop events attached to its dispatch (hipExtLaunchKernelGGL; a copy by
+                        events recorded around it). The bracket adds a few microseconds per
+                        launch: 16 empty launches made at the start of the solve, reported as the
+                        entry "empty kernel", show its size */
 } lrp_kernel_time;
 
 /*

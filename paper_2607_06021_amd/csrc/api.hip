@@ -18,6 +18,8 @@
 #include <cstring>
 #include <new>
 
+#include <hip/hip_ext.h>
+
 #include "ctx.h"
 
 using namespace lrp;
@@ -88,6 +90,7 @@ void free_ctx(lrp_ctx* c) {
   dfree(c->dst.work);
   for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
   c->prof_ev.clear();
+
   for (int L = 0; L < c->tsqr.nlevels; ++L)
     for (int s = 0; s < 2; ++s) {
       dfree(c->tsqr.lev[L].V[s]);
@@ -194,18 +197,34 @@ int create_impl(lrp_ctx* c) {
 // ---------------------------------------------------------------- launch profile
 static thread_local lrp_ctx* g_prof = nullptr;  // context recording a profile on this thread
 
-void prof_mark(hipStream_t s, int id) {
+ProfEvents prof_launch(hipStream_t s, int id) {
   lrp_ctx* c = g_prof;
-  if (!c || c->stream != s) return;
-  if (c->prof_used == c->prof_ev.size()) {
+  if (!c || c->stream != s) return {};
+  while (c->prof_ev.size() < 2 * (c->prof_used + 1)) {
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return;
+    if (hipEventCreate(&e) != hipSuccess) return {};
     c->prof_ev.push_back(e);
-    c->prof_id.push_back(-1);
   }
-  if (hipEventRecord(c->prof_ev[c->prof_used], s) != hipSuccess) return;
+  if (c->prof_id.size() < c->prof_used + 1) c->prof_id.resize(c->prof_used + 1, -1);
+  ProfEvents pe{c->prof_ev[2 * c->prof_used], c->prof_ev[2 * c->prof_used + 1]};
   c->prof_id[c->prof_used] = id;
   ++c->prof_used;
+  return pe;
+}
+
+void prof_begin(hipStream_t s, int id) {
+  lrp_ctx* c = g_prof;
+  const ProfEvents pe = prof_launch(s, id);
+  if (!pe.start) return;
+  if (hipEventRecord(pe.start, s) != hipSuccess) return;
+  c->prof_open = pe.stop;
+}
+
+void prof_end(hipStream_t s) {
+  lrp_ctx* c = g_prof;
+  if (!c || c->stream != s || !c->prof_open) return;
+  (void)hipEventRecord(c->prof_open, s);
+  c->prof_open = nullptr;
 }
 
 // Holds the stream for a bounded time (about 0.5 ms) so that the host enqueues the first
@@ -214,24 +233,22 @@ __global__ void k_hold(int iters) {
   for (int i = 0; i < iters; ++i) __builtin_amdgcn_s_sleep(127);
 }
 
-// Event deltas include the dispatch and completion of each launch; the mean delta of the
-// empty launches (K_EMPTY) measures that overhead and is subtracted from every other launch.
+// Per-class time: every kernel launch carries start/stop events attached to its own dispatch
+// (hipExtLaunchKernelGGL), so each record is the kernel's duration from the start to the end of
+// its dispatch; copies are bracketed by events recorded around them.
 static void prof_reduce(lrp_ctx* c) {
   for (int q = 0; q < K_COUNT; ++q) {
     c->prof_ms[q] = 0.0;
     c->prof_n[q] = 0;
   }
-  for (size_t i = 0; i + 1 < c->prof_used; ++i) {
+  for (size_t i = 0; i < c->prof_used; ++i) {
     const int id = c->prof_id[i];
     if (id < 0 || id >= K_COUNT) continue;
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, c->prof_ev[i], c->prof_ev[i + 1]) != hipSuccess) continue;
+    if (hipEventElapsedTime(&ms, c->prof_ev[2 * i], c->prof_ev[2 * i + 1]) != hipSuccess) continue;
     c->prof_ms[id] += ms;
     c->prof_n[id] += 1;
   }
-  const double ov = c->prof_n[K_EMPTY] > 0 ? c->prof_ms[K_EMPTY] / c->prof_n[K_EMPTY] : 0.0;
-  for (int q = 0; q < K_COUNT; ++q)
-    if (q != K_EMPTY) c->prof_ms[q] = std::max(0.0, c->prof_ms[q] - ov * c->prof_n[q]);
 }
 
 int enqueue_pass_kernels(lrp_ctx* c, int k) {
@@ -440,10 +457,11 @@ int enqueue_pass(lrp_ctx* c, int k) {
 // After pass k: copy the stop flag to pinned memory and mark the point with an event.
 int enqueue_poll(lrp_ctx* c, int k) {
   const int slot = k & 1;
-  prof_mark(c->stream, K_COPY);
+  prof_begin(c->stream, K_COPY);
   if (hipMemcpyAsync(&c->done_host[slot], &c->st->done, sizeof(int), hipMemcpyDeviceToHost, c->stream) !=
       hipSuccess)
     return LRP_EDEVICE;
+  prof_end(c->stream);
   return hipEventRecord(c->evit[slot], c->stream) == hipSuccess ? LRP_OK : LRP_EDEVICE;
 }
 
@@ -471,10 +489,11 @@ int enqueue_finish(lrp_ctx* c, double* U_out, int64_t ldou, double* S_out, doubl
   db.Y = V_out;
   db.ldy = ldov;
   TRY(dst_launch(c->dst, db, mixed, s));
-  prof_mark(s, K_COPY);
   if (hipEventRecord(c->ev1, s) != hipSuccess) return LRP_EDEVICE;
+  prof_begin(s, K_COPY);
   if (hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, s) != hipSuccess)
     return LRP_EDEVICE;
+  prof_end(s);
   return hipEventRecord(c->evfin, s) == hipSuccess ? LRP_OK : LRP_EDEVICE;
 }
 
@@ -567,10 +586,8 @@ int solve_impl(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const double*
     hipLaunchKernelGGL(k_hold, dim3(1), dim3(64), 0, c->stream, 150);
     if (launch_status() != LRP_OK) return LRP_EDEVICE;
     g_prof = c;
-    for (int q = 0; q < 16; ++q) {  // empty launches: the per-launch event overhead
-      prof_mark(c->stream, K_EMPTY);
-      hipLaunchKernelGGL(k_hold, dim3(1), dim3(64), 0, c->stream, 0);
-    }
+    for (int q = 0; q < 16; ++q)  // empty launches: the floor of a kernel's dispatch duration
+      LRP_LAUNCH(K_EMPTY, k_hold, dim3(1), dim3(64), 0, c->stream, 0);
     if (launch_status() != LRP_OK) return LRP_EDEVICE;
   }
   TRY(enqueue_start(c, rF, U_F, ldu, sigma_F, V_F, ldv));
@@ -670,7 +687,7 @@ int lrp_get_profile(const lrp_ctx* c, int32_t* count, lrp_kernel_time* out) {
       "k_init_state", "k_scan", "k_dst_single", "k_dst_pass1", "k_dst_pass2", "k_fiber",
       "k_tsqr_factor", "k_tsqr_apply", "k_core_warm", "k_core", "k_prod", "k_pi", "k_gmax",
       "k_topk_block", "k_topk_merge", "k_select", "k_rho_a", "k_rho_b", "k_rho_reduce",
-      "k_rho_final", "k_eta", "k_finalize", "copy", "launch overhead (empty kernel)"};
+      "k_rho_final", "k_eta", "k_finalize", "copy", "empty kernel"};
   if (!c || !count || *count < 0 || (*count > 0 && !out)) return LRP_EINVAL;
   if (!c->profile || !c->solved) {
     *count = 0;

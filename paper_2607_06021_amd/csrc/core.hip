@@ -811,8 +811,7 @@ __global__ __launch_bounds__(kEtaThreads) void k_eta(EtaArgs a) {
 }
 
 int eta_launch(const EtaArgs& a, hipStream_t s) {
-  prof_mark(s, K_ETA);
-  hipLaunchKernelGGL(k_eta, dim3(1), dim3(kEtaThreads), 0, s, a);
+  LRP_LAUNCH(K_ETA, k_eta, dim3(1), dim3(kEtaThreads), 0, s, a);
   return launch_status();
 }
 
@@ -861,11 +860,9 @@ __global__ __launch_bounds__(kCoreThreads) void k_core_warm(CoreArgs a) {
 
 int core_launch(const CoreArgs& a, bool warm, hipStream_t s) {
   if (warm) {
-    prof_mark(s, K_CORE_WARM);
-    hipLaunchKernelGGL(k_core_warm, dim3(1), dim3(kCoreThreads), 0, s, a);
+    LRP_LAUNCH(K_CORE_WARM, k_core_warm, dim3(1), dim3(kCoreThreads), 0, s, a);
   } else {
-    prof_mark(s, K_CORE);
-    hipLaunchKernelGGL(k_core, dim3(1), dim3(kCoreThreads), 0, s, a);
+    LRP_LAUNCH(K_CORE, k_core, dim3(1), dim3(kCoreThreads), 0, s, a);
   }
   return launch_status();
 }
@@ -903,8 +900,7 @@ __global__ void k_init_state(DevState* st, int rF, double eps, double tau) {
 }
 
 int init_state_launch(DevState* st, int rF, double eps, double tau, hipStream_t s) {
-  prof_mark(s, K_INIT);
-  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, st, rF, eps, tau);
+  LRP_LAUNCH(K_INIT, k_init_state, dim3(1), dim3(64), 0, s, st, rF, eps, tau);
   return launch_status();
 }
 
@@ -928,8 +924,7 @@ int scan_inputs_launch(DevState* st, const double* U, int64_t ldu, const double*
                        const double* sig, int64_t n, int rF, hipStream_t s) {
   const int64_t total = n * rF;
   const int blocks = (int)std::min<int64_t>(1024, (total + 255) / 256);
-  prof_mark(s, K_SCAN);
-  hipLaunchKernelGGL(k_scan, dim3(std::max(blocks, 1)), dim3(256), 0, s, st, U, ldu, V, ldv, sig, n, rF);
+  LRP_LAUNCH(K_SCAN, k_scan, dim3(std::max(blocks, 1)), dim3(256), 0, s, st, U, ldu, V, ldv, sig, n, rF);
   return launch_status();
 }
 
@@ -961,8 +956,7 @@ __global__ void k_finalize(DevState* st, double* S_out, int r_max) {
 }
 
 int finalize_launch(DevState* st, double* S_out, int r_max, hipStream_t s) {
-  prof_mark(s, K_FINALIZE);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, st, S_out, r_max);
+  LRP_LAUNCH(K_FINALIZE, k_finalize, dim3(1), dim3(64), 0, s, st, S_out, r_max);
   return launch_status();
 }
 

@@ -50,6 +50,7 @@ struct lrp_ctx {
   bool profile = false;
   std::vector<hipEvent_t> prof_ev;
   std::vector<int> prof_id;
+  hipEvent_t prof_open = nullptr;  // stop event of the copy being timed
   size_t prof_used = 0;
   double prof_ms[lrp::K_COUNT] = {};
   int prof_n[lrp::K_COUNT] = {};

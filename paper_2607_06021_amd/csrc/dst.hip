@@ -522,8 +522,7 @@ static void launch_single(int logL, int npairs, const DstArgs& a, hipStream_t s)
 #define LRP_SINGLE(LG)                                                                      \
   case LG: {                                                                                \
     constexpr int seqs = single_seqs(LG), tp = (1 << LG) < 16 ? 1 : (1 << LG) / 16;        \
-    prof_mark(s, K_DST_SINGLE);                                                             \
-    hipLaunchKernelGGL((k_dst_single<T, LG>), dim3((npairs + seqs - 1) / seqs), dim3(seqs * tp), 0, s, a); \
+    LRP_LAUNCH(K_DST_SINGLE, (k_dst_single<T, LG>), dim3((npairs + seqs - 1) / seqs), dim3(seqs * tp), 0, s, a); \
     break;                                                                                  \
   }
   switch (logL) {
@@ -540,16 +539,14 @@ static void launch_four_step(int logL1, int logL2, int npairs, const DstArgs& a,
 #define LRP_P1(LG)                                                                          \
   case LG: {                                                                                \
     constexpr int tj = tile1_of<T>(LG);                                                     \
-    prof_mark(s, K_DST_PASS1);                                                              \
-    hipLaunchKernelGGL((k_dst_pass1<T, LG>), dim3((L1 / 2 / tj + 1) * npairs),              \
+    LRP_LAUNCH(K_DST_PASS1, (k_dst_pass1<T, LG>), dim3((L1 / 2 / tj + 1) * npairs),              \
                        dim3(tj * ((1 << LG) / 16)), 0, s, a);                               \
     break;                                                                                  \
   }
 #define LRP_P2(LG)                                                                          \
   case LG: {                                                                                \
     constexpr int tk = tile2_of<T>(LG);                                                     \
-    prof_mark(s, K_DST_PASS2);                                                              \
-    hipLaunchKernelGGL((k_dst_pass2<T, LG>), dim3((L2 / 2 / tk + 1) * npairs),              \
+    LRP_LAUNCH(K_DST_PASS2, (k_dst_pass2<T, LG>), dim3((L2 / 2 / tk + 1) * npairs),              \
                        dim3(tk * ((1 << LG) / 16)), 0, s, a);                               \
     break;                                                                                  \
   }

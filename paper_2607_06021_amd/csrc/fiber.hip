@@ -74,11 +74,10 @@ __global__ __launch_bounds__(256) void k_fiber(FiberArgs a) {
 
 int fiber_launch(const FiberArgs& a, bool fp32, hipStream_t s) {
   dim3 grid((unsigned)((a.n + 255) / 256), 2);
-  prof_mark(s, K_FIBER);
   if (fp32)
-    hipLaunchKernelGGL(k_fiber<float>, grid, dim3(256), 0, s, a);
+    LRP_LAUNCH(K_FIBER, k_fiber<float>, grid, dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL(k_fiber<double>, grid, dim3(256), 0, s, a);
+    LRP_LAUNCH(K_FIBER, k_fiber<double>, grid, dim3(256), 0, s, a);
   return launch_status();
 }
 

@@ -1,6 +1,8 @@
 // Kernel argument blocks and host-side launchers of the low-rank Poisson library.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <cmath>
 
@@ -18,7 +20,24 @@ enum KernelId {
 };
 // Called right before a launch (or copy) on stream s: when this thread is recording a
 // profile on s, records an event that ends the previous entry and starts this one.
-void prof_mark(hipStream_t s, int id);
+// Profile mode: the start/stop events of a launch of kernel class id on stream s, attached to the
+// dispatch itself (hipExtLaunchKernelGGL), or nulls when no profile is being recorded there.
+struct ProfEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+ProfEvents prof_launch(hipStream_t s, int id);
+// Events around a non-kernel operation (a copy) of class id: begin before it, end after it.
+void prof_begin(hipStream_t s, int id);
+void prof_end(hipStream_t s);
+
+#define LRP_LAUNCH(ID, KERNEL, GRID, BLOCK, SHM, STREAM, ...)                                        \
+  do {                                                                                              \
+    const ::lrp::ProfEvents pe_ = ::lrp::prof_launch((STREAM), (ID));                               \
+    if (pe_.start)                                                                                  \
+      hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHM, STREAM, pe_.start, pe_.stop, 0, __VA_ARGS__);  \
+    else                                                                                            \
+      hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHM, STREAM, __VA_ARGS__);                            \
+  } while (0)
 
 struct DstPlan {
   int64_t n;

@@ -90,8 +90,7 @@ __global__ __launch_bounds__(256) void k_prod(ProdArgs a) {
 
 int prod_launch(const ProdArgs& a, hipStream_t s) {
   dim3 grid((unsigned)((a.n + kProdRowsPerBlock - 1) / kProdRowsPerBlock), 2);
-  prof_mark(s, K_PROD);
-  hipLaunchKernelGGL(k_prod, grid, dim3(256), 0, s, a);
+  LRP_LAUNCH(K_PROD, k_prod, grid, dim3(256), 0, s, a);
   return launch_status();
 }
 

@@ -251,15 +251,11 @@ int rho_launch(const RhoPlan& p, const RhoArgs& ra, hipStream_t s) {
   a.nb_old = ra.nb_old;
   a.part = p.part;
   const int red_blocks = (2 * kPMax * kPMax + 255) / 256;
-  prof_mark(s, K_RHO_A);
-  hipLaunchKernelGGL(k_rho_a, dim3(p.nblocks, 2), dim3(256), 0, s, a);
-  prof_mark(s, K_RHO_REDUCE);
-  hipLaunchKernelGGL(k_rho_reduce, dim3(red_blocks), dim3(256), 0, s, ra.st, p.part, p.nblocks, p.M);
+  LRP_LAUNCH(K_RHO_A, k_rho_a, dim3(p.nblocks, 2), dim3(256), 0, s, a);
+  LRP_LAUNCH(K_RHO_REDUCE, k_rho_reduce, dim3(red_blocks), dim3(256), 0, s, ra.st, p.part, p.nblocks, p.M);
   a.M = p.M;
-  prof_mark(s, K_RHO_B);
-  hipLaunchKernelGGL(k_rho_b, dim3(p.nblocks, 2), dim3(256), 0, s, a);
-  prof_mark(s, K_RHO_REDUCE);
-  hipLaunchKernelGGL(k_rho_reduce, dim3(red_blocks), dim3(256), 0, s, ra.st, p.part, p.nblocks, p.G);
+  LRP_LAUNCH(K_RHO_B, k_rho_b, dim3(p.nblocks, 2), dim3(256), 0, s, a);
+  LRP_LAUNCH(K_RHO_REDUCE, k_rho_reduce, dim3(red_blocks), dim3(256), 0, s, ra.st, p.part, p.nblocks, p.G);
   RhoFinalArgs f{};
   f.st = ra.st;
   f.M = p.M;
@@ -268,8 +264,7 @@ int rho_launch(const RhoPlan& p, const RhoArgs& ra, hipStream_t s) {
   f.nb_old = ra.nb_old;
   f.maxiter = ra.maxiter;
   f.trace = ra.trace;
-  prof_mark(s, K_RHO_FINAL);
-  hipLaunchKernelGGL(k_rho_final, dim3(1), dim3(256), 0, s, f);
+  LRP_LAUNCH(K_RHO_FINAL, k_rho_final, dim3(1), dim3(256), 0, s, f);
   return launch_status();
 }
 

@@ -294,10 +294,8 @@ int select_candidates(const SelectPlan& p, const DevState* st, const double* U[2
     pa.pi[q] = p.pi[q];
     pa.bmax[q] = p.bmax[q];
   }
-  prof_mark(s, K_PI);
-  hipLaunchKernelGGL(k_pi, dim3(p.nblocks, 2), dim3(256), 0, s, pa);
-  prof_mark(s, K_GMAX);
-  hipLaunchKernelGGL(k_gmax, dim3(2), dim3(256), 0, s, st, nullptr, p.bmax[0], p.bmax[1], p.nblocks,
+  LRP_LAUNCH(K_PI, k_pi, dim3(p.nblocks, 2), dim3(256), 0, s, pa);
+  LRP_LAUNCH(K_GMAX, k_gmax, dim3(2), dim3(256), 0, s, st, nullptr, p.bmax[0], p.bmax[1], p.nblocks,
                      p.gmax);
   TopkArgs ta{};
   ta.st = st;
@@ -309,8 +307,7 @@ int select_candidates(const SelectPlan& p, const DevState* st, const double* U[2
     ta.cs[q] = p.cand_s[0][q];
     ta.ci[q] = p.cand_i[0][q];
   }
-  prof_mark(s, K_TOPK_BLOCK);
-  hipLaunchKernelGGL(k_topk_block, dim3(p.nblocks, 2), dim3(256), 0, s, ta);
+  LRP_LAUNCH(K_TOPK_BLOCK, k_topk_block, dim3(p.nblocks, 2), dim3(256), 0, s, ta);
   int slot = 0;
   for (int L = 0; L < p.nlevels; ++L) {
     const int lists = p.lists[L];
@@ -324,8 +321,7 @@ int select_candidates(const SelectPlan& p, const DevState* st, const double* U[2
       ma.out_s[q] = p.cand_s[slot ^ 1][q];
       ma.out_i[q] = p.cand_i[slot ^ 1][q];
     }
-    prof_mark(s, K_TOPK_MERGE);
-    hipLaunchKernelGGL(k_topk_merge, dim3(outl, 2), dim3(kMergeThreads), 0, s, ma);
+    LRP_LAUNCH(K_TOPK_MERGE, k_topk_merge, dim3(outl, 2), dim3(kMergeThreads), 0, s, ma);
     slot ^= 1;
   }
   *final_list_slot = slot;
@@ -333,8 +329,7 @@ int select_candidates(const SelectPlan& p, const DevState* st, const double* U[2
 }
 
 int select_update(const SelectArgs& a, hipStream_t s) {
-  prof_mark(s, K_SELECT);
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(kPMax), 0, s, a);
+  LRP_LAUNCH(K_SELECT, k_select, dim3(1), dim3(kPMax), 0, s, a);
   return launch_status();
 }
 

@@ -368,8 +368,7 @@ int tsqr_run(const TsqrPlan& p, const TsqrIO& io, hipStream_t s) {
       f.tau[q] = lv.tau[q];
       f.Rout[q] = lv.Rout[q];
     }
-    prof_mark(s, K_TSQR_FACTOR);
-    hipLaunchKernelGGL(k_tsqr_factor, dim3(lv.nblocks, ns), dim3(kTsqrThreads), 0, s, f);
+    LRP_LAUNCH(K_TSQR_FACTOR, k_tsqr_factor, dim3(lv.nblocks, ns), dim3(kTsqrThreads), 0, s, f);
   }
   // top-down formation of Q
   for (int L = p.nlevels - 1; L >= 0; --L) {
@@ -390,8 +389,7 @@ int tsqr_run(const TsqrPlan& p, const TsqrIO& io, hipStream_t s) {
     }
     a.ldt = (L == p.nlevels - 1) ? 0 : p.lev[L + 1].rows;
     a.ldy = (L == 0 && io.Q[0]) ? io.ldq : lv.rows;
-    prof_mark(s, K_TSQR_APPLY);
-    hipLaunchKernelGGL(k_tsqr_apply, dim3(lv.nblocks, ns), dim3(kTsqrThreads), 0, s, a);
+    LRP_LAUNCH(K_TSQR_APPLY, k_tsqr_apply, dim3(lv.nblocks, ns), dim3(kTsqrThreads), 0, s, a);
   }
   return launch_status();
 }
