@@ -336,77 +336,236 @@ __device__ void set_identity(double* V, int k) {
   }
 }
 
-// ---------------------------------------------------------------- small Householder QR
-// In place on A (m x k, m >= k, ld LDP): R in the upper triangle, the reflectors' tails
-// below (LAPACK convention, v_j = 1). tau: k doubles of LDS. 8 lanes per trailing column.
-__device__ void small_qr(double* A, int m, int k, double* tau, double* sc) {
-  const int t = threadIdx.x;
-  for (int j = 0; j < k; ++j) {
-    if (t < 64) {  // wave 0: the reflector of column j
-      const double x = (t > j && t < m) ? A[t + j * LDP] : 0.0;
-      const double xn2 = wave_sum(x * x);
-      const double alpha = A[j + j * LDP];
-      double beta, tj, scale;
-      if (xn2 == 0.0) {
-        tj = 0.0;
-        beta = alpha;
-        scale = 0.0;
-      } else {
-        beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-        tj = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-      }
-      if (t > j && t < m) A[t + j * LDP] = x * scale;
-      if (t == 0) {
-        A[j + j * LDP] = beta;
-        tau[j] = tj;
-      }
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// An empty asm statement taking a loaded value as input and output: the load completes before
+// it unconditionally, so a following select cannot become a branch around the load.
+__device__ inline void pin(double& v) { asm volatile("" : "+v"(v)); }
+
+// C = A B for 64 x 64 matrices in LDS (column-major, ld LDP, zero outside the used m x k and
+// k x n parts) on the FP64 matrix cores (v_mfma_f64_16x16x4: operand A lane l = A(l%16, l/16),
+// B lane l = B(l/16, l%16), result item v = C(l/16 + 4v, l%16)): the 16 tiles of 16 x 16 go
+// round the waves of the workgroup. C(i, j), i < m, j < n, is stored at C[i + j LDP], or at
+// C[j + i LDP] when trans. C must not overlap A or B.
+__device__ void lds_gemm(const double* A, const double* B, double* C, int m, int n, bool trans) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int q = wave; q < 16; q += nw) {
+    const int I = q >> 2, J = q & 3;
+    if (16 * I >= m || 16 * J >= n) continue;
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[16 * I + lr + (4 * ks + lk) * LDP],
+                                                  B[4 * ks + lk + (16 * J + lr) * LDP], acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * I + lk + 4 * v, j = 16 * J + lr;
+      if (i < m && j < n) C[trans ? j + i * LDP : i + j * LDP] = acc[v];
     }
-    __syncthreads();
-    const int c = j + 1 + (t >> 3), li = t & 7;
-    if (c < k) {
-      const double tj = tau[j];
-      double w = 0.0;
-      for (int i = j + li; i < m; i += 8) w = fma(i == j ? 1.0 : A[i + j * LDP], A[i + c * LDP], w);
-      w = group_sum<8>(w) * tj;
-      for (int i = j + li; i < m; i += 8) A[i + c * LDP] = fma(-w, i == j ? 1.0 : A[i + j * LDP], A[i + c * LDP]);
-    }
-    __syncthreads();
   }
 }
 
-// B (m x ncols, ld LDP) <- H_{k-1} .. H_0 B  (i.e. Q2-full^T B) if transpose, else
-// B <- H_0 .. H_{k-1} B, with the reflectors stored in QR (from small_qr).
-__device__ void apply_reflectors(const double* QR, const double* tau, int m, int k, double* B, int ncols,
-                                 bool transpose) {
-  const int t = threadIdx.x;
-  const int c0 = t >> 3, li = t & 7;
-  for (int c = c0; c < ncols; c += kCoreThreads / 8) {
-    for (int s = 0; s < k; ++s) {
-      const int j = transpose ? s : k - 1 - s;
-      const double tj = tau[j];
-      double w = 0.0;
-      for (int i = j + li; i < m; i += 8) w = fma(i == j ? 1.0 : QR[i + j * LDP], B[i + c * LDP], w);
-      w = group_sum<8>(w) * tj;
-      for (int i = j + li; i < m; i += 8) B[i + c * LDP] = fma(-w, i == j ? 1.0 : QR[i + j * LDP], B[i + c * LDP]);
+// Q(idx[i], c) for i < m, c < k into S (64 x 64, ld LDP, zero elsewhere); Q column-major with
+// leading dimension ldq. Every load reads a valid element and the loads of a thread are in
+// flight together.
+__device__ void gather_rows(const double* Q, int64_t ldq, const int* idx, int m, int k, double* S) {
+  for (int base = threadIdx.x; base < kPMax * kPMax; base += blockDim.x * 4) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = base + u * blockDim.x, i = e % kPMax, c = e / kPMax;
+      const int ii = min(i, max(m - 1, 0)), cc = min(c, max(k - 1, 0));
+      v[u] = (e < kPMax * kPMax && m > 0 && k > 0) ? Q[idx[ii] + (int64_t)cc * ldq] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = base + u * blockDim.x, i = e % kPMax, c = e / kPMax;
+      pin(v[u]);
+      if (e < kPMax * kPMax) S[i + c * LDP] = (i < m && c < k) ? v[u] : 0.0;
+    }
+  }
+}
+
+// B(r, c) = F[r + c ldf] for r < m, c < k into S (64 x 64, ld LDP, zero elsewhere).
+__device__ void load_block(const double* F, int64_t ldf, int m, int k, double* S) {
+  for (int base = threadIdx.x; base < kPMax * kPMax; base += blockDim.x * 4) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = base + u * blockDim.x, i = e % kPMax, c = e / kPMax;
+      const int ii = min(i, max(m - 1, 0)), cc = min(c, max(k - 1, 0));
+      v[u] = (e < kPMax * kPMax && m > 0 && k > 0) ? F[ii + (int64_t)cc * ldf] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = base + u * blockDim.x, i = e % kPMax, c = e / kPMax;
+      pin(v[u]);
+      if (e < kPMax * kPMax) S[i + c * LDP] = (i < m && c < k) ? v[u] : 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- small Householder QR
+// The small dense routines below keep one column per 8 lanes (rows li + 8u, u < 8, in
+// registers; with 512 threads the 64 columns are covered in one pass).
+
+// x[u] for a u that is the same on every active lane (a scalar branch, not a select chain).
+__device__ inline double pick8(const double (&x)[8], int u) {
+  switch (u & 7) {
+    case 0: return x[0];
+    case 1: return x[1];
+    case 2: return x[2];
+    case 3: return x[3];
+    case 4: return x[4];
+    case 5: return x[5];
+    case 6: return x[6];
+    default: return x[7];
+  }
+}
+
+// In place on A (m x k, m >= k, ld LDP): R in the upper triangle, the reflectors' tails below
+// (LAPACK convention: beta = -sign(alpha) ||x||, tau = (beta - alpha)/beta, v = x/(alpha - beta),
+// v_j = 1 implicit), tau[j] in LDS. Column j builds its reflector from its registers (tau =
+// 1 + |alpha|/h and 1/(alpha - beta) = sign(alpha)/(|alpha| + h) with h = ||x||, one rsq and one
+// rcp), publishes it in LDS (vb: 2 x 64 doubles, double-buffered) and after one barrier every
+// trailing column applies it. blockDim.x >= 512.
+__device__ void small_qr(double* A, int m, int k, double* tau, double* vb) {
+  const int t = threadIdx.x, c = t >> 3, li = t & 7;
+  const bool col = c < k;
+  double x[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int i = li + 8 * u;
+    x[u] = (col && i < m) ? A[i + c * LDP] : 0.0;
+  }
+  double rdiag = 0.0, vscale = 0.0;
+  for (int j = 0; j < k; ++j) {
+    double* vj = vb + (j & 1) * kPMax;
+    if (c == j) {
+      double y[8], n[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        y[u] = li + 8 * u > j ? x[u] : 0.0;
+        n[u & 3] = fma(y[u], y[u], n[u & 3]);
+      }
+      const double xnorm2 = oct_sum((n[0] + n[1]) + (n[2] + n[3]));
+      const double xj = pick8(x, j >> 3);
+      const int src = ((j & 7) << 3) + (j & 7);  // lane of row j within column j's octet
+      const double alpha = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(xj), src),
+                                            __builtin_amdgcn_readlane(__double2loint(xj), src)) +
+                           0.0;
+      const double h2 = fma(alpha, alpha, xnorm2);
+      const double rh = rsq_nr(h2);
+      const double h = h2 * rh;
+      double beta = -copysign(h, alpha);
+      double tj = fma(fabs(alpha), rh, 1.0);
+      double scale = copysign(rcp_nr(fabs(alpha) + h), alpha);
+      if (xnorm2 == 0.0) {
+        tj = 0.0;
+        beta = alpha;
+        scale = 0.0;
+      } else if (!(h2 > 1e-290 && h2 < 1e290)) {
+        beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+        tj = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) vj[li + 8 * u] = y[u] * scale;
+      if (li == (j & 7)) vj[j] = 1.0;  // same lane, after its zero: in order
+      rdiag = beta;
+      vscale = scale;
+      if (li == 0) tau[j] = tj;
+    }
+    __syncthreads();
+    if (c > j && col) {
+      double v[8], d[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        v[u] = vj[li + 8 * u];
+        d[u & 3] = fma(v[u], x[u], d[u & 3]);
+      }
+      const double w = oct_sum((d[0] + d[1]) + (d[2] + d[3])) * tau[j];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = fma(-w, v[u], x[u]);
+    }
+  }
+  if (col) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = li + 8 * u;
+      if (i < m) A[i + c * LDP] = i < c ? x[u] : (i == c ? rdiag : x[u] * vscale);
     }
   }
   __syncthreads();
 }
 
-// Ri <- R^{-1} for the k x k upper triangle of QR (column by column back substitution).
-__device__ void tri_inverse(const double* QR, int k, double* Ri) {
-  const int t = threadIdx.x;
-  const int c0 = t >> 3, li = t & 7;
-  for (int c = c0; c < k; c += kCoreThreads / 8) {
-    for (int i = li; i < k; i += 8) Ri[i + c * LDP] = 0.0;
-    if (li == 0) Ri[c + c * LDP] = 1.0 / QR[c + c * LDP];
-    for (int i = c - 1; i >= 0; --i) {
-      double s = 0.0;
-      for (int l = i + 1 + li; l <= c; l += 8) s = fma(QR[i + l * LDP], Ri[l + c * LDP], s);
-      s = group_sum<8>(s);
-      if (li == 0) Ri[i + c * LDP] = -s / QR[i + i * LDP];
+// B (m x ncols, ld LDP) <- H_{k-1} .. H_0 B (Q2-full^T B) if transpose, else H_0 .. H_{k-1} B,
+// with V holding the reflectors explicitly (unit diagonal, zeros above and below row m - 1: see
+// explicit_reflectors). Every column runs through the k reflectors on its own lanes.
+__device__ void apply_reflectors(const double* V, const double* tau, int m, int k, double* B, int ncols,
+                                 bool transpose) {
+  const int t = threadIdx.x, li = t & 7;
+  for (int c = t >> 3; c < ncols; c += blockDim.x >> 3) {
+    double x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = li + 8 * u;
+      x[u] = i < m ? B[i + c * LDP] : 0.0;
     }
+    for (int s = 0; s < k; ++s) {
+      const int j = transpose ? s : k - 1 - s;
+      const double* vj = V + j * LDP + li;
+      double v[8], d[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        v[u] = vj[8 * u];
+        d[u & 3] = fma(v[u], x[u], d[u & 3]);
+      }
+      const double w = oct_sum((d[0] + d[1]) + (d[2] + d[3])) * tau[j];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = fma(-w, v[u], x[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = li + 8 * u;
+      if (i < m) B[i + c * LDP] = x[u];
+    }
+  }
+  __syncthreads();
+}
+
+// Overwrites the R part of a small_qr result with the explicit reflectors: 1 on the diagonal,
+// 0 above it and below row m - 1 (all 64 x 64 entries written).
+__device__ void explicit_reflectors(double* QR, int m, int k) {
+  for (int e = threadIdx.x; e < kPMax * kPMax; e += blockDim.x) {
+    const int i = e % kPMax, j = e / kPMax;
+    if (i <= j || i >= m || j >= k) QR[i + j * LDP] = (i == j && j < k) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+}
+
+// Ri <- R^{-1} for the k x k upper triangle of QR, zero elsewhere in 64 x 64 (back substitution
+// per column, the diagonal reciprocals precomputed in dinv: kPMax doubles of LDS).
+__device__ void tri_inverse(const double* QR, int k, double* Ri, double* dinv) {
+  const int t = threadIdx.x, li = t & 7;
+  if (t < k) dinv[t] = 1.0 / QR[t + t * LDP];
+  __syncthreads();
+  for (int c = t >> 3; c < kPMax; c += blockDim.x >> 3) {
+    double x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = (c < k && li + 8 * u == c) ? dinv[c] : 0.0;
+    for (int i = (c < k ? c : 0) - 1; i >= 0; --i) {  // rows above the diagonal, bottom up
+      const double* qi = QR + i + li * LDP;
+      double d[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int u = 0; u < 8; ++u) d[u & 3] = fma(qi[8 * u * LDP], x[u], d[u & 3]);
+      const double xi = -oct_sum((d[0] + d[1]) + (d[2] + d[3])) * dinv[i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = li + 8 * u == i ? xi : x[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) Ri[li + 8 * u + c * LDP] = x[u];
   }
   __syncthreads();
 }
@@ -484,45 +643,43 @@ __global__ __launch_bounds__(kCoreThreads) void k_core(CoreArgs a) {
   DevState* st = a.st;
   if (st->done) return;
   __shared__ double B0[kBuf], B1[kBuf], B2[kBuf], B3[kBuf];
-  __shared__ double sig[kPMax], tau[kPMax], red[16], nrm2[2];
-  __shared__ int ord[kPMax], flags[2], posI[kPMax], posJ[kPMax], cnt[2];
+  __shared__ double sig[kPMax], tau[kPMax], red[16], nrm2[2], vbq[2 * kPMax], dinv[kPMax];
+  __shared__ int ord[kPMax], flags[2], posI[kPMax], posJ[kPMax], cnt[2], idxI[kPMax], idxJ[kPMax];
   const int t = threadIdx.x;
   const int nI = st->nIpre, nJ = st->nJpre;
   const int pm = a.pmax;
   const double* R_C = a.R0;  // nJ x nJ upper triangular, ld pm
   const double* R_R = a.R1;  // nI x nI
-  auto Aq = [&](int i, int c) { return a.Q0[st->Ipre[i] + (int64_t)c * a.ldq]; };  // Q(I,:)
-  auto Bq = [&](int j, int c) { return a.Q1[st->Jpre[j] + (int64_t)c * a.ldq]; };  // Z(J,:)
   const double cut_pinv = (double)max(nI, nJ);
+  if (t < kPMax) {
+    idxI[t] = t < nI ? st->Ipre[t] : 0;
+    idxJ[t] = t < nJ ? st->Jpre[t] : 0;
+  }
+  __syncthreads();
 
   // ---- the core M = A^+ R_R^T (|J| <= |I|, A = Q(I,:)) or R_C (A^+)^T (A = Z(J,:))
   const bool branch = nJ <= nI;
   const int m0 = branch ? nI : nJ, k0 = branch ? nJ : nI;
-  for (int e = t; e < m0 * k0; e += blockDim.x) {
-    const int i = e % m0, c = e / m0;
-    B0[i + c * LDP] = branch ? Aq(i, c) : Bq(i, c);
-  }
+  gather_rows(branch ? a.Q0 : a.Q1, a.ldq, branch ? idxI : idxJ, m0, k0, B0);  // zero-padded
   __syncthreads();
-  small_qr(B0, m0, k0, tau, red);
-  tri_inverse(B0, k0, B1);  // B1 = R^{-1}
+  small_qr(B0, m0, k0, tau, vbq);
+  tri_inverse(B0, k0, B1, dinv);  // B1 = R^{-1}, zero-padded
   tri_norms(B0, B1, k0, red, nrm2);
   const double bound = nrm2[0] * nrm2[1] * cut_pinv * kEps * 4.0;
   double* M;
   if (bound < 1.0) {
+    explicit_reflectors(B0, m0, k0);
     if (branch) {
-      // B2 = H^T R_R^T (nI x nI); M = R^{-1} B2(0:nJ, :)  -> B3
-      for (int e = t; e < nI * nI; e += blockDim.x) {
-        const int i = e % nI, j = e / nI;
-        B2[i + j * LDP] = (j <= i) ? R_R[j + (int64_t)i * pm] : 0.0;
+      // B2 = H^T R_R^T (nI x nI, zero-padded); M = R^{-1} B2(0:nJ, :) -> B3 (matrix cores)
+      load_block(R_R, pm, nI, nI, B3);
+      __syncthreads();
+      for (int e = t; e < kPMax * kPMax; e += blockDim.x) {
+        const int i = e % kPMax, j = e / kPMax;
+        B2[i + j * LDP] = (j <= i) ? B3[j + i * LDP] : 0.0;
       }
       __syncthreads();
       apply_reflectors(B0, tau, m0, k0, B2, nI, true);
-      for (int e = t; e < nJ * nI; e += blockDim.x) {
-        const int aa = e % nJ, j = e / nJ;
-        double s = 0.0;
-        for (int l = aa; l < nJ; ++l) s = fma(B1[aa + l * LDP], B2[l + j * LDP], s);
-        B3[aa + j * LDP] = s;
-      }
+      lds_gemm(B1, B2, B3, nJ, nI, false);
       __syncthreads();
       M = B3;
     } else {
@@ -551,10 +708,7 @@ __global__ __launch_bounds__(kCoreThreads) void k_core(CoreArgs a) {
     }
   } else {
     // A may have singular values at or below the cutoff: Jacobi pseudo-inverse.
-    for (int e = t; e < m0 * k0; e += blockDim.x) {
-      const int i = e % m0, c = e / m0;
-      B0[i + c * LDP] = branch ? Aq(i, c) : Bq(i, c);
-    }
+    gather_rows(branch ? a.Q0 : a.Q1, a.ldq, branch ? idxI : idxJ, m0, k0, B0);
     set_identity(B1, k0);
     __syncthreads();
     JacProb pr{B0, m0, k0, B1};
@@ -650,18 +804,18 @@ __global__ __launch_bounds__(kCoreThreads) void k_core(CoreArgs a) {
   const int nb = a.nb;
   if (t < kPMax) st->S[nb][t] = t < r ? sig[ord[t]] : 0.0;
 
-  // ---- pruning
-  if (t == 0) {
-    double mR = 0.0, mC = 0.0;
-    for (int l = 0; l < nI; ++l) mR = fmax(mR, fabs(R_R[l + (int64_t)l * pm]));
-    for (int l = 0; l < nJ; ++l) mC = fmax(mC, fabs(R_C[l + (int64_t)l * pm]));
-    int ci = 0, cj = 0;
-    for (int l = 0; l < nI; ++l)
-      if (fabs(R_R[l + (int64_t)l * pm]) >= st->tau * mR) posI[ci++] = l;
-    for (int l = 0; l < nJ; ++l)
-      if (fabs(R_C[l + (int64_t)l * pm]) >= st->tau * mC) posJ[cj++] = l;
-    cnt[0] = ci;
-    cnt[1] = cj;
+  // ---- pruning: wave 0 takes the diagonal of R_R, wave 1 that of R_C, one lane per index; the
+  // kept indices are compacted in order through a ballot
+  if (t < 2 * 64) {
+    const int w = t >> 6, l = t & 63;
+    const int nn = w == 0 ? nI : nJ;
+    const double* Rm = w == 0 ? R_R : R_C;
+    const double d = l < nn ? fabs(Rm[l + (int64_t)l * pm]) : 0.0;
+    const double mx = wave_max(d);
+    const bool keep = l < nn && d >= st->tau * mx;
+    const unsigned long long bal = __ballot(keep);
+    if (keep) (w == 0 ? posI : posJ)[__popcll(bal & ((1ull << l) - 1))] = l;
+    if (l == 0) cnt[w] = __popcll(bal);
   }
   __syncthreads();
   const int nIp = cnt[0], nJp = cnt[1];
@@ -678,10 +832,20 @@ __global__ __launch_bounds__(kCoreThreads) void k_core(CoreArgs a) {
   }
   __syncthreads();
 
+  // index sets of the new iterate, one thread per index
+  if (t < nIp) {
+    const int v = idxI[posI[t]];
+    st->I[t] = v;
+    st->Ib[nb][t] = v;
+  }
+  if (t >= kPMax && t - kPMax < nJp) {
+    const int v = idxJ[posJ[t - kPMax]];
+    st->J[t - kPMax] = v;
+    st->Jb[nb][t - kPMax] = v;
+  }
   if (t == 0) {
-    const double* S = st->S[nb];
     double n2 = 0.0;
-    for (int l = 0; l < r; ++l) n2 = fma(S[l], S[l], n2);
+    for (int l = 0; l < r; ++l) n2 = fma(sig[ord[l]], sig[ord[l]], n2);
     const double nrm = sqrt(n2);
     st->nrm = nrm;
     st->eta1 = INFINITY;
@@ -690,14 +854,10 @@ __global__ __launch_bounds__(kCoreThreads) void k_core(CoreArgs a) {
     st->eta_need = need_eta ? 1 : 0;
     st->r[nb] = r;
     int rs = 0;
-    for (int l = 0; l < r; ++l) rs += S[l] > st->eps * S[0] ? 1 : 0;
+    for (int l = 0; l < r; ++l) rs += sig[ord[l]] > st->eps * sig[ord[0]] ? 1 : 0;
     st->r_sig = rs;
-    for (int ii = 0; ii < nIp; ++ii) st->I[ii] = st->Ipre[posI[ii]];
-    for (int jj = 0; jj < nJp; ++jj) st->J[jj] = st->Jpre[posJ[jj]];
     st->nI = nIp;
     st->nJ = nJp;
-    for (int ii = 0; ii < nIp; ++ii) st->Ib[nb][ii] = st->I[ii];
-    for (int jj = 0; jj < nJp; ++jj) st->Jb[nb][jj] = st->J[jj];
     st->nIb[nb] = nIp;
     st->nJb[nb] = nJp;
     st->indb[nb] = INFINITY;
@@ -724,9 +884,9 @@ __global__ __launch_bounds__(kCoreThreads) void k_core(CoreArgs a) {
 __global__ __launch_bounds__(kEtaThreads) void k_eta(EtaArgs a) {
   DevState* st = a.st;
   if (st->done) return;
-  __shared__ double E1[kBuf], E2[kBuf];
+  __shared__ double E1[kBuf], E2[kBuf], Qs[kBuf], Us[kBuf];
   __shared__ double red[2];
-  __shared__ int flags[2];
+  __shared__ int flags[2], idx[2 * kPMax];
   const int t = threadIdx.x;
   const int nb = a.nb;
   const int r = st->r[nb];
@@ -737,26 +897,22 @@ __global__ __launch_bounds__(kEtaThreads) void k_eta(EtaArgs a) {
     const int kJ = st->ncols[0], kI = st->ncols[1];  // columns of Q and Z
     const int pm = a.pmax;
     const bool t1 = nI >= r, t2 = nJ >= r;
-    for (int e = t; e < nI * r; e += blockDim.x) {
-      const int ii = e % nI, rr = e / nI;
-      const double* q = a.Q0 + st->I[ii];
-      double s = 0.0;
-      for (int c = 0; c < kJ; ++c) s = fma(q[(int64_t)c * a.ldq], a.Uhat[c + (int64_t)rr * pm], s);
-      if (t1)
-        E1[ii + rr * LDP] = s;
-      else
-        E1[rr + ii * LDP] = s;
+    // E1 = Q(I,:) U^ and E2 = Z(J,:) V~ on the matrix cores, from rows and factors staged in
+    // LDS (each stored tall: transposed when the set is smaller than r)
+    if (t < kPMax) {
+      idx[t] = t < nI ? st->I[t] : 0;
+      idx[kPMax + t] = t < nJ ? st->J[t] : 0;
     }
-    for (int e = t; e < nJ * r; e += blockDim.x) {
-      const int jj = e % nJ, rr = e / nJ;
-      const double* z = a.Q1 + st->J[jj];
-      double s = 0.0;
-      for (int c = 0; c < kI; ++c) s = fma(z[(int64_t)c * a.ldq], a.Vtil[c + (int64_t)rr * pm], s);
-      if (t2)
-        E2[jj + rr * LDP] = s;
-      else
-        E2[rr + jj * LDP] = s;
-    }
+    __syncthreads();
+    gather_rows(a.Q0, a.ldq, idx, nI, kJ, Qs);
+    load_block(a.Uhat, pm, kJ, r, Us);
+    __syncthreads();
+    lds_gemm(Qs, Us, E1, nI, r, !t1);
+    __syncthreads();
+    gather_rows(a.Q1, a.ldq, idx + kPMax, nJ, kI, Qs);
+    load_block(a.Vtil, pm, kI, r, Us);
+    __syncthreads();
+    lds_gemm(Qs, Us, E2, nJ, r, !t2);
     __syncthreads();
     JacProb pp[2] = {{E1, t1 ? nI : r, t1 ? r : nI, nullptr}, {E2, t2 ? nJ : r, t2 ? r : nJ, nullptr}};
     jacobi(pp, 2, flags);

@@ -138,11 +138,20 @@ __device__ inline double wave_max(double x) {
   return x;
 }
 
-// Sum over groups of 8 consecutive lanes.
+// Sum over aligned groups of 8 consecutive lanes (DPP: lane ^ 1, lane ^ 2, then the other quad
+// of the octet); every lane gets its group's total.
 __device__ inline double oct_sum(double x) {
-  x += shfl_xor_d(x, 1);
-  x += shfl_xor_d(x, 2);
-  x += shfl_xor_d(x, 4);
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  x += __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false),
+                        __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false));  // quad_perm [1,0,3,2]
+  lo = __double2loint(x);
+  hi = __double2hiint(x);
+  x += __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false),
+                        __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false));  // quad_perm [2,3,0,1]
+  lo = __double2loint(x);
+  hi = __double2hiint(x);
+  x += __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0x141, 0xF, 0xF, false),
+                        __builtin_amdgcn_mov_dpp(lo, 0x141, 0xF, 0xF, false));  // row_half_mirror
   return x;
 }
 

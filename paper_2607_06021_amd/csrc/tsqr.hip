@@ -301,6 +301,258 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_apply(ApplyArgs a) {
   }
 }
 
+// Q formation in compact WY form on the FP64 matrix cores. The block's reflectors give
+// H_0 H_1 .. H_{p-1} = I - V T V^T with T upper triangular and T^{-1} = diag(1/tau) +
+// striu(V^T V) (the strictly upper part holds v_i . v_k), so with Y0 = [T_par; 0]:
+//   X = V^T Y0 = V(0:p, :)^T T_par                 (MFMA; the transpose of V's top at the root)
+//   (diag(1/tau) + striu(V^T V)) Z = X             (back substitution, row i from rows > i:
+//                                                   Z(i,:) = tau_i (X(i,:) - sum_k S(i,k) Z(k,:)),
+//                                                   so a zero tau gives a zero row)
+//   Y = Y0 - V Z                                   (MFMA)
+// MFMA v_mfma_f64_16x16x4: operand A lane l = A(l%16, l/16), B lane l = B(l/16, l%16), result
+// item v of lane l = D(l/16 + 4v, l%16). Y is formed transposed (Y^T = Y0^T - Z^T V^T) so that
+// each 16-lane group of a store writes 16 consecutive rows of one column.
+typedef double wy4 __attribute__((ext_vector_type(4)));
+constexpr int kWyThreads = 512;  // 8 waves
+constexpr int kWyLd = kPMax + 1;
+
+__global__ __launch_bounds__(kWyThreads) void k_tsqr_apply_wy(ApplyArgs a) {
+  const int side = blockIdx.y;
+  if (a.st && a.st->done) return;
+  const int p = side_cols(a.st, a.ncols, side);
+  const int64_t row0 = (int64_t)blockIdx.x * a.block_rows;
+  const int nr = (int)min((int64_t)a.block_rows, a.rows - row0);
+  if (p <= 0 || nr <= 0) return;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  constexpr int kHalf = kTsqrRows / 2;    // rows of V staged at a time
+  constexpr int kWaves = kWyThreads / 64;
+  __shared__ double Vs[kHalf * kWyLd];  // V(r, c) of one half at Vs[r kWyLd + c], zero past p / nr
+  __shared__ double S[kPMax * kWyLd];   // v_i . v_k (upper tiles; the rest zero)
+  __shared__ double XZ[kPMax * kWyLd];  // X, then Z in place; zero outside p x p
+  __shared__ double tsh[kPMax];
+  const double* V = a.V[side] + row0;  // V(r, c) = V[r + c ldv], r < nr, c < p
+  const int64_t ldv = a.ldv;
+  const double* T = a.T[side];
+  const int64_t toff = (int64_t)blockIdx.x * a.pmax;
+  const int pt = (p + 15) >> 4;  // 16-column tiles in use
+  const int pk = (p + 3) >> 2;   // 4-row steps over p
+  const int ntiles = pt * (pt + 1) / 2;
+
+  for (int e = t; e < kPMax * kWyLd; e += kWyThreads) {
+    S[e] = 0.0;
+    XZ[e] = 0.0;
+  }
+  if (t < kPMax) tsh[t] = t < p ? a.tau[side][toff + t] : 0.0;
+
+  // upper tiles q = wave, wave + 8 of S (I <= J), accumulated over both halves
+  int tI[2], tJ[2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    int q = wave + kWaves * m, I = 0;
+    while (q >= pt - I && I < pt) {
+      q -= pt - I;
+      ++I;
+    }
+    tI[m] = I;
+    tJ[m] = I + q;
+  }
+  wy4 sacc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+  wy4 xacc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+  double vb0[16], vb1[16];  // -V(16 R + lr, 4 s + lk) for this wave's row tiles R = wave, wave + 8
+
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int hr0 = h * kHalf;
+    if (hr0 < nr) {  // uniform
+    // stage rows hr0 .. hr0 + 127 of V: all loads of a thread in flight together
+    {
+      constexpr int kPer = kHalf * kPMax / kWyThreads;  // 16
+      double raw[kPer];
+#pragma unroll
+      for (int m = 0; m < kPer; ++m) {
+        const int e = t + kWyThreads * m, r = e % kHalf, c = e / kHalf;
+        raw[m] = V[min(hr0 + r, nr - 1) + (int64_t)min(c, p - 1) * ldv];
+      }
+#pragma unroll
+      for (int m = 0; m < kPer; ++m) {
+        const int e = t + kWyThreads * m, r = e % kHalf, c = e / kHalf;
+        keep_loaded(raw[m]);
+        Vs[r * kWyLd + c] = (hr0 + r < nr && c < p) ? raw[m] : 0.0;
+      }
+    }
+    __syncthreads();
+    const int nks = (min(nr - hr0, kHalf) + 3) >> 2;  // 4-row steps in this half
+    // S += V_h^T V_h on this wave's tiles (rows below 16 I are zero in the I columns)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      if (wave + kWaves * m >= ntiles) continue;
+      const int I = tI[m], J = tJ[m];
+      for (int ks = max(0, (16 * I - hr0) >> 2); ks < nks; ++ks) {
+        const double* row = Vs + (4 * ks + lk) * kWyLd;
+        sacc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(row[16 * I + lr], row[16 * J + lr], sacc[m], 0, 0, 0);
+      }
+    }
+    // X = V(0:p, :)^T T_par from the first half (p <= 64 rows)
+    if (h == 0 && T) {
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const int q = wave + kWaves * m;
+        if (q >= pt * pt) continue;
+        const int I = q / pt, J = q % pt;
+        for (int k0 = 4 * I; k0 < pk; k0 += 4) {
+          double tv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int r = 4 * (k0 + u) + lk;
+            tv[u] = T[toff + min(r, p - 1) + (int64_t)min(16 * J + lr, p - 1) * a.ldt];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int r = 4 * (k0 + u) + lk;
+            keep_loaded(tv[u]);
+            const double b = (r < p && 16 * J + lr < p) ? tv[u] : 0.0;
+            xacc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[r * kWyLd + 16 * I + lr], b, xacc[m], 0, 0, 0);
+          }
+        }
+      }
+    }
+    // operands of the final product for this wave's row tile in this half
+    {
+      const int R = wave + kWaves * h;
+      const int lrow = 16 * R + lr - hr0;  // row within the half
+#pragma unroll
+      for (int ks = 0; ks < 16; ++ks) {
+        const double x = -Vs[lrow * kWyLd + 4 * ks + lk];
+        if (h == 0)
+          vb0[ks] = x;
+        else
+          vb1[ks] = x;
+      }
+    }
+    __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    if (wave + kWaves * m >= ntiles) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S[(16 * tI[m] + lk + 4 * v) * kWyLd + 16 * tJ[m] + lr] = sacc[m][v];
+  }
+  if (T) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int q = wave + kWaves * m;
+      if (q >= pt * pt) continue;
+      const int I = q / pt, J = q % pt;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) XZ[(16 * I + lk + 4 * v) * kWyLd + 16 * J + lr] = xacc[m][v];
+    }
+  } else {
+    for (int e = t; e < p * p; e += kWyThreads) {
+      const int i = e / p, j = e % p;
+      XZ[i * kWyLd + j] = V[j + (int64_t)i * ldv];  // X = V(0:p, 0:p)^T; j, i < p <= nr
+    }
+  }
+  __syncthreads();
+
+  // ---- back substitution, one column of Z per 8 lanes (rows q + 8u in registers), by blocks of
+  // 8 rows from the bottom: the contributions of the rows already solved come from 8 interleaved
+  // octet sums, then the block's 8 x 8 triangle is solved by every lane of the octet
+  {
+    const int j = t >> 3, q = t & 7;
+    double z[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int bk = ((p + 7) >> 3) - 1; bk >= 0; --bk) {  // uniform
+      double P[8];
+#pragma unroll
+      for (int w = 0; w < 8; ++w) {
+        const double* Si = S + (8 * bk + w) * kWyLd + q;
+        double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) {  // rows not solved yet hold z = 0
+          d0 = fma(Si[8 * u], z[u], d0);
+          d1 = fma(Si[8 * (u + 1)], z[u + 1], d1);
+        }
+        P[w] = d0 + d1;
+      }
+#pragma unroll
+      for (int w = 0; w < 8; ++w) P[w] = oct_sum(P[w]);
+      double zb[8];
+#pragma unroll
+      for (int w = 7; w >= 0; --w) {
+        const int i = 8 * bk + w;
+        double v = XZ[i * kWyLd + j] - P[w];
+#pragma unroll
+        for (int w2 = w + 1; w2 < 8; ++w2) v = fma(-S[i * kWyLd + 8 * bk + w2], zb[w2], v);
+        zb[w] = tsh[i] * v;  // zero past p (tau and X are zero there)
+      }
+      double mine = zb[0];
+#pragma unroll
+      for (int w = 1; w < 8; ++w) mine = q == w ? zb[w] : mine;
+      switch (bk) {  // uniform index
+        case 0: z[0] = mine; break;
+        case 1: z[1] = mine; break;
+        case 2: z[2] = mine; break;
+        case 3: z[3] = mine; break;
+        case 4: z[4] = mine; break;
+        case 5: z[5] = mine; break;
+        case 6: z[6] = mine; break;
+        default: z[7] = mine; break;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) XZ[(q + 8 * u) * kWyLd + j] = z[u];
+  }
+  __syncthreads();
+
+  // ---- Y^T = Y0^T - Z^T V^T for this wave's row tiles
+  double* Y = a.Y[side] + row0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int R = wave + kWaves * h;
+    const int row = 16 * R + lr;
+    if (16 * R >= nr) continue;  // uniform
+    wy4 acc[4];
+    if (T) {
+#pragma unroll
+      for (int J = 0; J < 4; ++J)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          acc[J][v] = T[toff + min(row, p - 1) + (int64_t)min(16 * J + lk + 4 * v, p - 1) * a.ldt];
+#pragma unroll
+      for (int J = 0; J < 4; ++J)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double y0 = acc[J][v];
+          keep_loaded(y0);
+          acc[J][v] = (row < p && 16 * J + lk + 4 * v < p) ? y0 : 0.0;
+        }
+    } else {
+#pragma unroll
+      for (int J = 0; J < 4; ++J)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[J][v] = (row < p && row == 16 * J + lk + 4 * v) ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+      if (ks >= pk) break;
+      const double* Zk = XZ + (4 * ks + lk) * kWyLd + lr;
+#pragma unroll
+      for (int J = 0; J < 4; ++J)
+        if (J < pt) acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(Zk[16 * J], h == 0 ? vb0[ks] : vb1[ks], acc[J], 0, 0, 0);
+    }
+    if (row < nr) {
+#pragma unroll
+      for (int J = 0; J < 4; ++J)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int col = 16 * J + lk + 4 * v;
+          if (col < p) Y[row + (int64_t)col * a.ldy] = acc[J][v];
+        }
+    }
+  }
+}
+
 // ----------------------------------------------------------------------------------------
 int tsqr_plan(TsqrPlan* p, int64_t n, int pmax) {
   if (pmax < 1 || pmax > kPMax) return LRP_EINVAL;
@@ -389,7 +641,7 @@ int tsqr_run(const TsqrPlan& p, const TsqrIO& io, hipStream_t s) {
     }
     a.ldt = (L == p.nlevels - 1) ? 0 : p.lev[L + 1].rows;
     a.ldy = (L == 0 && io.Q[0]) ? io.ldq : lv.rows;
-    LRP_LAUNCH(K_TSQR_APPLY, k_tsqr_apply, dim3(lv.nblocks, ns), dim3(kTsqrThreads), 0, s, a);
+    LRP_LAUNCH(K_TSQR_APPLY, k_tsqr_apply_wy, dim3(lv.nblocks, ns), dim3(kWyThreads), 0, s, a);
   }
   return launch_status();
 }
