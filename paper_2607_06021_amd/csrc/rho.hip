@@ -36,13 +36,31 @@ __device__ inline bool rho_needed(const DevState* st) {
 typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kRS = kPMax + 1;  // row stride of the LDS chunks
 
-// Stage rows [r0, r0 + 64) of the first `cols` columns of X into S (row-major, stride 65),
-// zero beyond cols and beyond n.
-__device__ inline void stage(double* S, const double* X, int64_t ldu, int64_t n, int64_t r0, int cols) {
-  for (int e = threadIdx.x; e < kRhoChunk * kPMax; e += blockDim.x) {
-    const int row = e % kRhoChunk, c = e / kRhoChunk;
-    const int64_t i = r0 + row;
-    S[row * kRS + c] = (c < cols && i < n) ? X[i + (int64_t)c * ldu] : 0.0;
+constexpr int kRhoThreads = 256;
+
+// Stage rows [r0, r0 + 64) of the first ca columns of XA into SA and of the first cb columns of
+// XB into SB (row-major, stride 65), zero beyond the columns and beyond n. Every load reads a
+// valid element (clamped row and column); all 32 loads of a thread are issued before any is
+// used, so they are in flight together.
+__device__ inline void stage2(double* SA, const double* XA, int ca, double* SB, const double* XB, int cb,
+                              int64_t ldu, int64_t n, int64_t r0) {
+  constexpr int kPer = kRhoChunk * kPMax / kRhoThreads;  // 16
+  double va[kPer], vb[kPer];
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) {
+    const int e = threadIdx.x + kRhoThreads * m, row = e % kRhoChunk, c = e / kRhoChunk;
+    const int64_t i = min(r0 + row, n - 1);
+    va[m] = XA[i + (int64_t)min(c, max(ca - 1, 0)) * ldu];
+    vb[m] = XB[i + (int64_t)min(c, max(cb - 1, 0)) * ldu];
+  }
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) {
+    const int e = threadIdx.x + kRhoThreads * m, row = e % kRhoChunk, c = e / kRhoChunk;
+    const bool rok = r0 + row < n;
+    asm volatile("" : "+v"(va[m]));
+    asm volatile("" : "+v"(vb[m]));
+    SA[row * kRS + c] = (c < ca && rok) ? va[m] : 0.0;
+    SB[row * kRS + c] = (c < cb && rok) ? vb[m] : 0.0;
   }
 }
 
@@ -69,7 +87,7 @@ __device__ inline void store_partial(double* out, int w, int lr, int lk, const d
 }
 
 // Pass A: partial M = A^T B over the block's rows.
-__global__ __launch_bounds__(256) void k_rho_a(RhoKArgs a) {
+__global__ __launch_bounds__(kRhoThreads) void k_rho_a(RhoKArgs a) {
   DevState* st = a.st;
   if (!rho_needed(st)) return;
   const int side = blockIdx.y;
@@ -82,8 +100,7 @@ __global__ __launch_bounds__(256) void k_rho_a(RhoKArgs a) {
   const int64_t row0 = (int64_t)blockIdx.x * a.rows_per_block;
   const int64_t rend = min(a.n, row0 + a.rows_per_block);
   for (int64_t r0 = row0; r0 < rend; r0 += kRhoChunk) {
-    stage(As, a.A[side], a.ldu, rend, r0, r);
-    stage(Bs, a.B[side], a.ldu, rend, r0, ro);
+    stage2(As, a.A[side], r, Bs, a.B[side], ro, a.ldu, rend, r0);
     __syncthreads();
     gram_chunk(As, Bs, w, lr, lk, acc);
     __syncthreads();
@@ -93,7 +110,7 @@ __global__ __launch_bounds__(256) void k_rho_a(RhoKArgs a) {
 
 // Pass B: Y = B - A M (rows of the chunk, MFMA with M as the second operand), then partial
 // G = Y^T Y.
-__global__ __launch_bounds__(256) void k_rho_b(RhoKArgs a) {
+__global__ __launch_bounds__(kRhoThreads) void k_rho_b(RhoKArgs a) {
   DevState* st = a.st;
   if (!rho_needed(st)) return;
   const int side = blockIdx.y;
@@ -109,8 +126,7 @@ __global__ __launch_bounds__(256) void k_rho_b(RhoKArgs a) {
   const int64_t row0 = (int64_t)blockIdx.x * a.rows_per_block;
   const int64_t rend = min(a.n, row0 + a.rows_per_block);
   for (int64_t r0 = row0; r0 < rend; r0 += kRhoChunk) {
-    stage(As, a.A[side], a.ldu, rend, r0, r);
-    stage(Bs, a.B[side], a.ldu, rend, r0, ro);
+    stage2(As, a.A[side], r, Bs, a.B[side], ro, a.ldu, rend, r0);
     __syncthreads();
     // T = A M for chunk rows 16 w .. 16 w + 15: A operand A[16 w + l%16][k0 + l/16], B operand
     // M[k0 + l/16][16 nt + l%16]; result item v: row 16 w + l/16 + 4 v, column 16 nt + l%16
@@ -146,19 +162,20 @@ __global__ __launch_bounds__(256) void k_rho_reduce(const DevState* st, const do
   const int e = blockIdx.x * blockDim.x + threadIdx.x;  // 0 .. 2*4096
   if (e >= 2 * kPMax * kPMax) return;
   const int side = e / (kPMax * kPMax), q = e % (kPMax * kPMax);
-  // four independent partial sums keep several loads in flight; fixed order
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  // 16 loads in flight per step, added into four partial sums in a fixed order
+  double sm[4] = {0.0, 0.0, 0.0, 0.0};
   const double* src = part + (int64_t)side * kPMax * kPMax + q;
   const int64_t stride = 2 * kPMax * kPMax;
   int b = 0;
-  for (; b + 3 < nblocks; b += 4) {
-    s0 += src[(int64_t)b * stride];
-    s1 += src[(int64_t)(b + 1) * stride];
-    s2 += src[(int64_t)(b + 2) * stride];
-    s3 += src[(int64_t)(b + 3) * stride];
+  for (; b + 15 < nblocks; b += 16) {
+    double v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = src[(int64_t)(b + k) * stride];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) sm[k & 3] += v[k];
   }
-  for (; b < nblocks; ++b) s0 += src[(int64_t)b * stride];
-  out[e] = (s0 + s1) + (s2 + s3);
+  for (; b < nblocks; ++b) sm[0] += src[(int64_t)b * stride];
+  out[e] = (sm[0] + sm[1]) + (sm[2] + sm[3]);
 }
 
 struct RhoFinalArgs {
@@ -251,10 +268,10 @@ int rho_launch(const RhoPlan& p, const RhoArgs& ra, hipStream_t s) {
   a.nb_old = ra.nb_old;
   a.part = p.part;
   const int red_blocks = (2 * kPMax * kPMax + 255) / 256;
-  LRP_LAUNCH(K_RHO_A, k_rho_a, dim3(p.nblocks, 2), dim3(256), 0, s, a);
+  LRP_LAUNCH(K_RHO_A, k_rho_a, dim3(p.nblocks, 2), dim3(kRhoThreads), 0, s, a);
   LRP_LAUNCH(K_RHO_REDUCE, k_rho_reduce, dim3(red_blocks), dim3(256), 0, s, ra.st, p.part, p.nblocks, p.M);
   a.M = p.M;
-  LRP_LAUNCH(K_RHO_B, k_rho_b, dim3(p.nblocks, 2), dim3(256), 0, s, a);
+  LRP_LAUNCH(K_RHO_B, k_rho_b, dim3(p.nblocks, 2), dim3(kRhoThreads), 0, s, a);
   LRP_LAUNCH(K_RHO_REDUCE, k_rho_reduce, dim3(red_blocks), dim3(256), 0, s, ra.st, p.part, p.nblocks, p.G);
   RhoFinalArgs f{};
   f.st = ra.st;
