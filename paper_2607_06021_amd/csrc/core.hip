@@ -668,44 +668,22 @@ __global__ __launch_bounds__(kCoreThreads) void k_core(CoreArgs a) {
   const double bound = nrm2[0] * nrm2[1] * cut_pinv * kEps * 4.0;
   double* M;
   if (bound < 1.0) {
+    // With A = Q(I,:) and R_m = R_R (|J| <= |I|) the core is M = A^+ R_m^T; with A = Z(J,:) and
+    // R_m = R_C it is M = R_C (A^+)^T, i.e. M^T = A^+ R_m^T: the same product, stored
+    // transposed. A^+ R_m^T = R^{-1} (H^T R_m^T)(0:k0, :), H the QR's reflectors.
+    const double* Rm = branch ? R_R : R_C;  // m0 x m0 upper triangular, ld pm
     explicit_reflectors(B0, m0, k0);
-    if (branch) {
-      // B2 = H^T R_R^T (nI x nI, zero-padded); M = R^{-1} B2(0:nJ, :) -> B3 (matrix cores)
-      load_block(R_R, pm, nI, nI, B3);
-      __syncthreads();
-      for (int e = t; e < kPMax * kPMax; e += blockDim.x) {
-        const int i = e % kPMax, j = e / kPMax;
-        B2[i + j * LDP] = (j <= i) ? B3[j + i * LDP] : 0.0;
-      }
-      __syncthreads();
-      apply_reflectors(B0, tau, m0, k0, B2, nI, true);
-      lds_gemm(B1, B2, B3, nJ, nI, false);
-      __syncthreads();
-      M = B3;
-    } else {
-      // B2 = Q2 = H [I; 0] (nJ x nI); B3 = Q2 R^{-T}; M = R_C B3 -> B2
-      for (int e = t; e < nJ * nI; e += blockDim.x) {
-        const int i = e % nJ, j = e / nJ;
-        B2[i + j * LDP] = (i == j) ? 1.0 : 0.0;
-      }
-      __syncthreads();
-      apply_reflectors(B0, tau, m0, k0, B2, nI, false);
-      for (int e = t; e < nJ * nI; e += blockDim.x) {
-        const int i = e % nJ, c = e / nJ;
-        double s = 0.0;
-        for (int l = c; l < nI; ++l) s = fma(B2[i + l * LDP], B1[c + l * LDP], s);
-        B3[i + c * LDP] = s;
-      }
-      __syncthreads();
-      for (int e = t; e < nJ * nI; e += blockDim.x) {
-        const int aa = e % nJ, c = e / nJ;
-        double s = 0.0;
-        for (int l = aa; l < nJ; ++l) s = fma(R_C[aa + (int64_t)l * pm], B3[l + c * LDP], s);
-        B2[aa + c * LDP] = s;
-      }
-      __syncthreads();
-      M = B2;
+    load_block(Rm, pm, m0, m0, B3);
+    __syncthreads();
+    for (int e = t; e < kPMax * kPMax; e += blockDim.x) {  // B2 = R_m^T, zero-padded
+      const int i = e % kPMax, j = e / kPMax;
+      B2[i + j * LDP] = (j <= i) ? B3[j + i * LDP] : 0.0;
     }
+    __syncthreads();
+    apply_reflectors(B0, tau, m0, k0, B2, m0, true);
+    lds_gemm(B1, B2, B3, k0, m0, !branch);  // k0 x m0 product: M, or M^T stored transposed
+    __syncthreads();
+    M = B3;
   } else {
     // A may have singular values at or below the cutoff: Jacobi pseudo-inverse.
     gather_rows(branch ? a.Q0 : a.Q1, a.ldq, branch ? idxI : idxJ, m0, k0, B0);
