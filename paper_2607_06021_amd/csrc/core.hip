@@ -600,40 +600,50 @@ __device__ void tri_norms(const double* QR, const double* Ri, int k, double* red
   __syncthreads();
 }
 
-// Truncated SVD of M (nJ x nI in W): U^ (nJ x r) -> Ub, V~ (nI x r) -> Vb, sorted; returns r.
-// X and Vj are work buffers; W may be Ub or Vb (it is copied first).
-__device__ int svd_core(const double* W, int nJ, int nI, double cut_mult, double* X, double* Vj, double* Ub,
-                        double* Vb, double* sig, int* ord, int* flags) {
+// Truncated SVD of M (nJ x nI, ld LDP, in Mb), QR-preconditioned one-sided Jacobi: with X = M
+// (nJ >= nI) or M^T, m x k, X = Q R (small_qr) and Jacobi on R^T (R^T V = W, orthogonal columns
+// W_c = sigma_c w_c) gives X = (Q V) Sigma W'^T, W' = W Sigma^{-1}: the left singular vectors of X
+// are Q V (reflectors applied to [V; 0]) and the right ones the normalized columns of W. Jacobi on
+// the triangular factor of a graded matrix needs far fewer sweeps than on the matrix itself.
+// Columns are sorted by singular value (ties to the smaller index) and truncated at
+// cut_mult eps sigma_1. Outputs: U^ (nJ x r) in Cb, V~ (nI x r) in Xb; returns r. Mb, Xb, Vq, Cb
+// are distinct 64 x 64 LDS buffers (Mb, Vq are overwritten); tau: kPMax, vbq: 2 kPMax doubles.
+__device__ __forceinline__ int svd_qr(double* Mb, int nJ, int nI, double cut_mult, double* Xb, double* Vq, double* Cb,
+                      double* tau, double* vbq, double* sig, int* ord, int* flags) {
+  const int t = threadIdx.x;
   const bool tall = nJ >= nI;
   const int m = tall ? nJ : nI, k = tall ? nI : nJ;
-  for (int e = threadIdx.x; e < m * k; e += blockDim.x) {
-    const int i = e % m, j = e / m;
-    X[i + j * LDP] = tall ? W[i + j * LDP] : W[j + i * LDP];
+  for (int e = t; e < kPMax * kPMax; e += blockDim.x) {  // X, zero-padded
+    const int i = e % kPMax, j = e / kPMax;
+    Xb[i + j * LDP] = (i < m && j < k) ? (tall ? Mb[i + j * LDP] : Mb[j + i * LDP]) : 0.0;
   }
-  set_identity(Vj, k);
   __syncthreads();
-  JacProb pr{X, m, k, Vj};
+  small_qr(Xb, m, k, tau, vbq);
+  for (int e = t; e < kPMax * kPMax; e += blockDim.x) {  // R^T into Mb, identity into Vq
+    const int i = e % kPMax, j = e / kPMax;
+    Mb[i + j * LDP] = (i < k && j <= i) ? Xb[j + i * LDP] : 0.0;
+    Vq[i + j * LDP] = (i == j && i < k) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  JacProb pr{Mb, k, k, Vq};
   jacobi(&pr, 1, flags);
-  norms_sorted(X, m, k, sig, ord);
-  const double smax = sig[ord[0]];
+  norms_sorted(Mb, k, k, sig, ord);
+  const double smax = k > 0 ? sig[ord[0]] : 0.0;
   int r = 0;
   if (smax > 0.0) {
     const double cut = cut_mult * kEps * smax;
     for (int c = 0; c < k; ++c) r += sig[ord[c]] > cut ? 1 : 0;
   }
-  for (int e = threadIdx.x; e < r * kPMax; e += blockDim.x) {
+  explicit_reflectors(Xb, m, k);
+  apply_reflectors(Xb, tau, m, k, Vq, k, false);  // Vq <- Q [V; 0]
+  for (int e = t; e < r * kPMax; e += blockDim.x) {
     const int i = e % kPMax, rr = e / kPMax;
     const int c = ord[rr];
     const double inv = 1.0 / sig[c];
-    const double lx = i < m ? X[i + c * LDP] * inv : 0.0;
-    const double rv = i < k ? Vj[i + c * LDP] : 0.0;
-    if (tall) {
-      Ub[i + rr * LDP] = lx;
-      Vb[i + rr * LDP] = rv;
-    } else {
-      Ub[i + rr * LDP] = rv;
-      Vb[i + rr * LDP] = lx;
-    }
+    const double left = i < m ? Vq[i + c * LDP] : 0.0;
+    const double right = i < k ? Mb[i + c * LDP] * inv : 0.0;
+    Cb[i + rr * LDP] = tall ? left : right;
+    Xb[i + rr * LDP] = tall ? right : left;
   }
   __syncthreads();
   return r;
@@ -735,44 +745,10 @@ __global__ __launch_bounds__(kCoreThreads) void k_core(CoreArgs a) {
     M = B3;
   }
 
-  // ---- truncated SVD of the core: U^ -> Ub, V~ -> Vb
-  double* Ub = (M == B3) ? B2 : B3;
-  double* Vb = B1;
-  double* X = B0;
-  // svd_core copies M into X first; Vj work buffer = Vb (the copy precedes every write)
-  // so use the remaining buffer M itself as the Vj scratch after the copy.
-  int r;
-  {
-    const bool tall = nJ >= nI;
-    const int m = tall ? nJ : nI, k = tall ? nI : nJ;
-    for (int e = t; e < m * k; e += blockDim.x) {
-      const int i = e % m, j = e / m;
-      X[i + j * LDP] = tall ? M[i + j * LDP] : M[j + i * LDP];
-    }
-    double* Vj = M;  // free after the copy
-    __syncthreads();
-    set_identity(Vj, k);
-    __syncthreads();
-    JacProb pr{X, m, k, Vj};
-    jacobi(&pr, 1, flags);
-    norms_sorted(X, m, k, sig, ord);
-    const double smax = sig[ord[0]];
-    r = 0;
-    if (smax > 0.0) {
-      const double cut = cut_pinv * kEps * smax;
-      for (int c = 0; c < k; ++c) r += sig[ord[c]] > cut ? 1 : 0;
-    }
-    for (int e = t; e < r * kPMax; e += blockDim.x) {
-      const int i = e % kPMax, rr = e / kPMax;
-      const int c = ord[rr];
-      const double inv = 1.0 / sig[c];
-      const double lx = i < m ? X[i + c * LDP] * inv : 0.0;
-      const double rv = i < k ? Vj[i + c * LDP] : 0.0;
-      Ub[i + rr * LDP] = tall ? lx : rv;
-      Vb[i + rr * LDP] = tall ? rv : lx;
-    }
-    __syncthreads();
-  }
+  // ---- truncated SVD of the core (M is B3): U^ -> B2, V~ -> B0
+  double* Ub = B2;
+  double* Vb = B0;
+  const int r = svd_qr(M, nJ, nI, cut_pinv, B0, B1, B2, tau, vbq, sig, ord, flags);
   // now Ub = U^ (nJ x r), Vb = V~ (nI x r), singular values sig[ord[0..r)]
   for (int e = t; e < r * pm; e += blockDim.x) {
     const int i = e % pm, rr = e / pm;
@@ -954,7 +930,7 @@ __global__ __launch_bounds__(kCoreThreads) void k_core_warm(CoreArgs a) {
   DevState* st = a.st;
   if (st->done) return;
   __shared__ double B0[kBuf], B1[kBuf], B2[kBuf], B3[kBuf];
-  __shared__ double sig[kPMax];
+  __shared__ double sig[kPMax], tau[kPMax], vbq[2 * kPMax];
   __shared__ int ord[kPMax], flags[2];
   const int t = threadIdx.x;
   const int rF = st->rF;
@@ -966,11 +942,11 @@ __global__ __launch_bounds__(kCoreThreads) void k_core_warm(CoreArgs a) {
     B3[i + j * LDP] = s;
   }
   __syncthreads();
-  const int r = svd_core(B3, rF, rF, (double)rF, B0, B1, B2, B3, sig, ord, flags);
+  const int r = svd_qr(B3, rF, rF, (double)rF, B0, B1, B2, tau, vbq, sig, ord, flags);
   for (int e = t; e < r * pm; e += blockDim.x) {
     const int i = e % pm, rr = e / pm;
     a.Uhat[i + (int64_t)rr * pm] = i < rF ? B2[i + rr * LDP] : 0.0;
-    a.Vtil[i + (int64_t)rr * pm] = i < rF ? B3[i + rr * LDP] : 0.0;
+    a.Vtil[i + (int64_t)rr * pm] = i < rF ? B0[i + rr * LDP] : 0.0;
   }
   if (t < kPMax) st->S[0][t] = t < r ? sig[ord[t]] : 0.0;
   __syncthreads();
