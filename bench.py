@@ -42,6 +42,7 @@ def parse():
 
 
 def time_solves(sol, args_dev, steps, warmup):
+    import numpy as np
     import torch
 
     for _ in range(warmup):
@@ -49,11 +50,16 @@ def time_solves(sol, args_dev, steps, warmup):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
+    marks = []
     for _ in range(steps):
         _, _, _, r, info = sol.solve(*args_dev)
         infos.append(info.as_dict())
+        marks.append(time.perf_counter())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    per = np.diff([t0] + marks) * 1e3  # each solve returns after its device work has finished
+    log(f"  per-solve wall ms: min {per.min():.3f} median {np.median(per):.3f} max {per.max():.3f} "
+        f"(slowest: solve {int(per.argmax())})")
     return wall * 1e3 / steps, infos
 
 

@@ -10,8 +10,7 @@ namespace lrp {
 
 constexpr int kPMax = 64;          // largest index set / rank the kernels are built for
 constexpr int kTsqrRows = 256;     // rows of one block QR
-constexpr int kTsqrThreads = 1024;  // 16 threads per column
-constexpr int kTsqrRowsPerThread = kTsqrRows * kPMax / kTsqrThreads;  // 16
+constexpr int kTsqrThreads = 1024;  // 16 waves, four columns each
 constexpr int kSelRows = 256;      // rows per leverage-score block
 constexpr int kMergeFan = 16;      // candidate lists merged per block
 constexpr int kMaxLevels = 12;     // TSQR tree levels (n <= 2^23 needs 7 at p_max = 64)

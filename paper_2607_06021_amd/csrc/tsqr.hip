@@ -73,55 +73,64 @@ __device__ inline double row16_sum(double x) {
   return x;
 }
 
-// Element c mod 16 of x for a column index c that is the same on every active lane: a switch on
-// a uniform value is a scalar branch, where indexing the register array would select through
-// all 16 elements on every lane.
-__device__ inline double element_uniform(const double (&x)[kTsqrRowsPerThread], int i) {
-  switch (i & (kTsqrRowsPerThread - 1)) {
-    case 0: return x[0];
-    case 1: return x[1];
-    case 2: return x[2];
-    case 3: return x[3];
-    case 4: return x[4];
-    case 5: return x[5];
-    case 6: return x[6];
-    case 7: return x[7];
-    case 8: return x[8];
-    case 9: return x[9];
-    case 10: return x[10];
-    case 11: return x[11];
-    case 12: return x[12];
-    case 13: return x[13];
-    case 14: return x[14];
-    default: return x[15];
+// Sum over the 64 lanes of the wave; every lane gets the same total. After the row sums, a
+// 16-lane swap (odd rows of one copy exchanged with even rows of the other) pairs rows 0, 1 and
+// 2, 3, and a 32-lane swap pairs the two halves; both operand orders agree on every lane.
+__device__ inline double wave64_sum(double x) {
+  x = row16_sum(x);
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  const auto l16 = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto h16 = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  x = __hiloint2double(h16[0], l16[0]) + __hiloint2double(h16[1], l16[1]);
+  lo = __double2loint(x);
+  hi = __double2hiint(x);
+  const auto l32 = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto h32 = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double(h32[0], l32[0]) + __hiloint2double(h32[1], l32[1]);
+}
+
+// Thread layout of a 256-row block: wave w holds columns 4w .. 4w+3, lane l rows l, l+64,
+// l+128 and l+192 of each (x[k][q] = row 64k + l of column 4w + q). A column lives in one wave,
+// so its dot products and norms are wave reductions, and a reflector is read from LDS as four
+// consecutive-word loads per lane (a quarter of the traffic of a layout with 16 lanes per
+// column, where every lane re-reads 16 elements shared with three other columns).
+
+// Column q (the same on every lane of the wave) of the wave's four: a switch on a uniform value
+// is a scalar branch, where indexing the register array would select on every lane.
+__device__ inline void pick_column(const double (&x)[4][4], int q, double (&col)[4]) {
+  switch (q & 3) {
+    case 0:
+      for (int k = 0; k < 4; ++k) col[k] = x[k][0];
+      break;
+    case 1:
+      for (int k = 0; k < 4; ++k) col[k] = x[k][1];
+      break;
+    case 2:
+      for (int k = 0; k < 4; ++k) col[k] = x[k][2];
+      break;
+    default:
+      for (int k = 0; k < 4; ++k) col[k] = x[k][3];
   }
 }
 
-// Householder vector of column c (held by its 16 lanes, rows 16 sub .. 16 sub + 15 in x, the
-// column already transformed by reflectors 0 .. c-1; c is the same for every active lane of the
-// wave). vb receives the whole reflector (v_c = 1, zeros above, the tail x * scale below) with
-// element 16 s + i stored at 16 i + s, so that the 16 lanes of a column read consecutive words;
-// x itself is left as it is (rows above c are R(0..c-1, c), and the tail is scaled by the caller
-// when the reflectors are written out).
+// Householder vector of column c (rows 64k + l in col[k], already transformed by reflectors
+// 0 .. c-1; c < 64 and the same on every lane). vb receives the whole reflector (v_c = 1, zeros
+// above, the tail times scale below); col itself is left as it is (rows above c are
+// R(0..c-1, c), and the tail is scaled when the reflectors are written out).
 //
 // With h = sqrt(alpha^2 + |x_tail|^2) and s = sign(alpha): beta = -s h, tau = (beta - alpha) /
 // beta = 1 + |alpha| / h and 1 / (alpha - beta) = s / (|alpha| + h), so one reciprocal square
-// root and one reciprocal give all three; the diagonal element alpha is read from the one lane
-// that holds it. Only a zero tail or an extreme magnitude leave this straight-line path.
-__device__ inline void householder_column(const double (&x)[kTsqrRowsPerThread], int c, int rbase, int sub,
-                                          double* vb, double& beta, double& tau, double& scale) {
-  double y[kTsqrRowsPerThread], n[4] = {0.0, 0.0, 0.0, 0.0};
+// root and one reciprocal give all three; the diagonal element alpha (row c, lane c of the first
+// group) is read from the lane that holds it. Only a zero tail or an extreme magnitude leave this
+// straight-line path.
+__device__ inline void householder_column(const double (&col)[4], int c, int l, double* vb, double& beta,
+                                          double& tau, double& scale) {
+  double y[4];
 #pragma unroll
-  for (int i = 0; i < kTsqrRowsPerThread; ++i) {
-    y[i] = rbase + i > c ? x[i] : 0.0;
-    n[i & 3] = fma(y[i], y[i], n[i & 3]);
-  }
-  const double xnorm2 = row16_sum((n[0] + n[1]) + (n[2] + n[3]));
-  // lane of this column (lanes 16 (c mod 4) .. of the wave) holding row c, element c mod 16
-  const int src = ((c & 3) << 4) + (c >> 4);
-  const double xc = element_uniform(x, c);
-  const double alpha = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(xc), src),
-                                        __builtin_amdgcn_readlane(__double2loint(xc), src)) +
+  for (int k = 0; k < 4; ++k) y[k] = 64 * k + l > c ? col[k] : 0.0;
+  const double xnorm2 = wave64_sum(fma(y[0], y[0], y[1] * y[1]) + fma(y[2], y[2], y[3] * y[3]));
+  const double alpha = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(col[0]), c),
+                                        __builtin_amdgcn_readlane(__double2loint(col[0]), c)) +
                        0.0;  // a zero diagonal counts as +0
   const double h2 = fma(alpha, alpha, xnorm2);
   const double rh = rsq_nr(h2);
@@ -138,15 +147,16 @@ __device__ inline void householder_column(const double (&x)[kTsqrRowsPerThread],
     tau = (beta - alpha) / beta;
     scale = 1.0 / (alpha - beta);
   }
+  vb[l] = l == c ? 1.0 : y[0] * scale;
 #pragma unroll
-  for (int i = 0; i < kTsqrRowsPerThread; ++i) vb[i * 16 + sub] = y[i] * scale;
-  if (sub == (c >> 4)) vb[(c & 15) * 16 + sub] = 1.0;  // same lane, after its zero: in order
+  for (int k = 1; k < 4; ++k) vb[64 * k + l] = y[k] * scale;
 }
 
-// Thread layout of a 256-row block: column c = t/16, rows 16 (t%16) .. 16 (t%16)+15, so the
-// 16 lanes of a DPP row hold one column. Column 0 builds its reflector first; then at step j,
-// after the barrier that publishes v_j (double-buffered in LDS), every trailing column applies
-// it, and the lanes of column j+1 go on at once to build v_{j+1}: one barrier per reflector.
+// One workgroup per 256-row block. Column 0 builds its reflector first; then at step j, after
+// the barrier that publishes v_j (double-buffered in LDS), every wave with a trailing column
+// applies it to its four columns (four dot products reduced together), and the wave of column
+// j+1 goes on at once to build v_{j+1}: one barrier per reflector. Nothing is written to global
+// memory inside the loop, so the per-step barrier waits on LDS only.
 __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) {
   const int side = blockIdx.y;
   if (a.st && a.st->done) return;
@@ -154,151 +164,109 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) {
   const int64_t row0 = (int64_t)blockIdx.x * a.block_rows;
   const int nr = (int)min((int64_t)a.block_rows, a.rows - row0);
   if (p <= 0 || nr <= 0) return;
-  const int t = threadIdx.x, c = t >> 4, sub = t & 15;
-  const int rbase = sub * kTsqrRowsPerThread;
+  const int t = threadIdx.x, l = t & 63, c0 = 4 * (t >> 6);
   __shared__ double vbuf[2][kTsqrRows];
   __shared__ double tsh[kPMax];
 
   // Every load reads a valid element (row and column clamped into the block) and the unused ones
   // are replaced by zeros afterwards, so that all 16 loads are in flight together.
-  double x[kTsqrRowsPerThread];
+  double x[4][4];
   {
-    const bool colok = c < p;
-    const int64_t base = row0 + (int64_t)(colok ? c : 0) * a.ldin;
+    int64_t off[4][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        off[k][q] = row0 + min(64 * k + l, nr - 1) + (int64_t)min(c0 + q, p - 1) * a.ldin;
     if (a.in_f32) {
       const float* X = (const float*)a.in[side];
-      float raw[kTsqrRowsPerThread];
+      float raw[4][4];
 #pragma unroll
-      for (int i = 0; i < kTsqrRowsPerThread; ++i) raw[i] = X[base + min(rbase + i, nr - 1)];
+      for (int k = 0; k < 4; ++k)
 #pragma unroll
-      for (int i = 0; i < kTsqrRowsPerThread; ++i) {
-        keep_loaded(raw[i]);
-        x[i] = (colok && rbase + i < nr) ? (double)raw[i] : 0.0;
-      }
+        for (int q = 0; q < 4; ++q) raw[k][q] = X[off[k][q]];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          keep_loaded(raw[k][q]);
+          x[k][q] = (c0 + q < p && 64 * k + l < nr) ? (double)raw[k][q] : 0.0;
+        }
     } else {
       const double* X = (const double*)a.in[side];
 #pragma unroll
-      for (int i = 0; i < kTsqrRowsPerThread; ++i) x[i] = X[base + min(rbase + i, nr - 1)];
+      for (int k = 0; k < 4; ++k)
 #pragma unroll
-      for (int i = 0; i < kTsqrRowsPerThread; ++i) {
-        keep_loaded(x[i]);
-        x[i] = (colok && rbase + i < nr) ? x[i] : 0.0;
-      }
+        for (int q = 0; q < 4; ++q) x[k][q] = X[off[k][q]];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          keep_loaded(x[k][q]);
+          x[k][q] = (c0 + q < p && 64 * k + l < nr) ? x[k][q] : 0.0;
+        }
     }
   }
-  double* V = a.V[side];
-  double* Rb = a.Rout[side] + (int64_t)blockIdx.x * a.pmax;  // this block's R, rows 0..pmax-1
-  double* taub = a.tau[side] + (int64_t)blockIdx.x * a.pmax;
   // After its reflector is built, column c is final: its registers keep R(0..c-1, c) above the
   // diagonal and the unscaled tail below it (the reflector is the tail times vscale), and
-  // rdiag = R(c, c). Nothing is written to global
-  // memory inside the loop, so the per-step barrier waits on LDS only.
-  double rdiag = 0.0, vscale = 0.0;
-  if (c == 0) {
+  // rdiag = R(c, c).
+  double rdiag[4] = {0.0, 0.0, 0.0, 0.0}, vscale[4] = {0.0, 0.0, 0.0, 0.0};
+  if (c0 == 0) {
+    const double col[4] = {x[0][0], x[1][0], x[2][0], x[3][0]};
     double tau;
-    householder_column(x, 0, rbase, sub, vbuf[0], rdiag, tau, vscale);
-    if (sub == 0) tsh[0] = tau;
+    householder_column(col, 0, l, vbuf[0], rdiag[0], tau, vscale[0]);
+    if (l == 0) tsh[0] = tau;
   }
   __syncthreads();
   for (int j = 0; j < p; ++j) {
-    if (c > j && c < p) {
-      const double* vs = vbuf[j & 1] + sub;
+    if (c0 < p && c0 + 3 > j) {
+      const double* vs = vbuf[j & 1];
+      double v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] = vs[64 * k + l];
       const double tau = tsh[j];
-      double d[4] = {0.0, 0.0, 0.0, 0.0};
+      double d[4];
 #pragma unroll
-      for (int i = 0; i < kTsqrRowsPerThread; ++i) d[i & 3] = fma(vs[i * 16], x[i], d[i & 3]);
-      const double w = row16_sum((d[0] + d[1]) + (d[2] + d[3])) * tau;
+      for (int q = 0; q < 4; ++q)
+        d[q] = wave64_sum(fma(v[0], x[0][q], v[1] * x[1][q]) + fma(v[2], x[2][q], v[3] * x[3][q]));
 #pragma unroll
-      for (int i = 0; i < kTsqrRowsPerThread; ++i) x[i] = fma(-w, vs[i * 16], x[i]);
-      if (c == j + 1) {
-        double tnext;
-        householder_column(x, j + 1, rbase, sub, vbuf[(j + 1) & 1], rdiag, tnext, vscale);
-        if (sub == 0) tsh[c] = tnext;
+      for (int q = 0; q < 4; ++q) {
+        const double wq = c0 + q > j ? d[q] * tau : 0.0;  // columns up to j are final
+#pragma unroll
+        for (int k = 0; k < 4; ++k) x[k][q] = fma(-wq, v[k], x[k][q]);
+      }
+      const int cn = j + 1;
+      if (cn < p && (cn & ~3) == c0) {
+        double col[4], beta, tn, sc;
+        pick_column(x, cn, col);
+        householder_column(col, cn, l, vbuf[cn & 1], beta, tn, sc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if ((cn & 3) == q) {
+            rdiag[q] = beta;
+            vscale[q] = sc;
+          }
+        if (l == 0) tsh[cn] = tn;
       }
     }
     __syncthreads();
   }
   // write the reflectors, R and tau once
-  if (c < p) {
+  double* V = a.V[side];
+  double* Rb = a.Rout[side] + (int64_t)blockIdx.x * a.pmax;  // this block's R, rows 0..pmax-1
 #pragma unroll
-    for (int i = 0; i < kTsqrRowsPerThread; ++i) {
-      const int r = rbase + i;
-      if (r < nr) V[row0 + r + (int64_t)c * a.ldv] = (r > c) ? x[i] * vscale : (r == c ? 1.0 : 0.0);
-      if (r < a.pmax) Rb[r + (int64_t)c * a.ldr] = (r < c) ? x[i] : (r == c ? rdiag : 0.0);
+  for (int q = 0; q < 4; ++q) {
+    const int c = c0 + q;
+    if (c < p) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int r = 64 * k + l;
+        if (r < nr) V[row0 + r + (int64_t)c * a.ldv] = (r > c) ? x[k][q] * vscale[q] : (r == c ? 1.0 : 0.0);
+        if (r < a.pmax) Rb[r + (int64_t)c * a.ldr] = (r < c) ? x[k][q] : (r == c ? rdiag[q] : 0.0);
+      }
     }
   }
-  if (t < p) taub[t] = tsh[t];
-}
-
-// Same thread layout as the factorization: thread (c, sub) keeps rows 16 sub .. 16 sub + 15 of
-// output column c and, loaded once at the start, the same rows of reflector c. Reflectors are
-// applied in reverse order; at step j the lanes of column j publish v_j in LDS
-// (double-buffered) and one barrier later every column applies it.
-__global__ __launch_bounds__(kTsqrThreads) void k_tsqr_apply(ApplyArgs a) {
-  const int side = blockIdx.y;
-  if (a.st && a.st->done) return;
-  const int p = side_cols(a.st, a.ncols, side);
-  const int64_t row0 = (int64_t)blockIdx.x * a.block_rows;
-  const int nr = (int)min((int64_t)a.block_rows, a.rows - row0);
-  if (p <= 0 || nr <= 0) return;
-  const int t = threadIdx.x, c = t >> 4, sub = t & 15;
-  const int rbase = sub * kTsqrRowsPerThread;
-  __shared__ double vbuf[2][kTsqrRows];
-  __shared__ double tsh[kPMax];
-
-  const double* taub = a.tau[side] + (int64_t)blockIdx.x * a.pmax;
-  if (t < p) tsh[t] = taub[t];
-  double y[kTsqrRowsPerThread], v[kTsqrRowsPerThread];
-  const double* T = a.T[side];
-  const int64_t toff = (int64_t)blockIdx.x * a.pmax;
-  // loads of clamped (always valid) elements, unused ones replaced by zeros: no load waits on a
-  // branch, so all of them are in flight together
-  const bool colok = c < p;
-  const int cc = colok ? c : 0;
-  const double* V = a.V[side] + row0 + (int64_t)cc * a.ldv;
-#pragma unroll
-  for (int i = 0; i < kTsqrRowsPerThread; ++i) v[i] = V[min(rbase + i, nr - 1)];
-  if (T) {
-    const double* Tc = T + toff + (int64_t)cc * a.ldt;
-#pragma unroll
-    for (int i = 0; i < kTsqrRowsPerThread; ++i) y[i] = Tc[min(rbase + i, p - 1)];
-#pragma unroll
-    for (int i = 0; i < kTsqrRowsPerThread; ++i) keep_loaded(y[i]);
-  } else {
-#pragma unroll
-    for (int i = 0; i < kTsqrRowsPerThread; ++i) y[i] = rbase + i == c ? 1.0 : 0.0;
-  }
-#pragma unroll
-  for (int i = 0; i < kTsqrRowsPerThread; ++i) {
-    const int lr = rbase + i;
-    keep_loaded(v[i]);
-    y[i] = (colok && lr < p) ? y[i] : 0.0;
-    v[i] = (colok && lr < nr) ? v[i] : 0.0;
-  }
-  for (int j = p - 1; j >= 0; --j) {
-    double* vb = vbuf[j & 1];
-    if (c == j) {
-#pragma unroll
-      for (int i = 0; i < kTsqrRowsPerThread; ++i) vb[i * 16 + sub] = v[i];
-    }
-    __syncthreads();
-    const double tj = tsh[j];
-    if (c < p && tj != 0.0) {
-      const double* vs = vb + sub;
-      double d[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int i = 0; i < kTsqrRowsPerThread; ++i) d[i & 3] = fma(vs[i * 16], y[i], d[i & 3]);
-      const double w = row16_sum((d[0] + d[1]) + (d[2] + d[3])) * tj;
-#pragma unroll
-      for (int i = 0; i < kTsqrRowsPerThread; ++i) y[i] = fma(-w, vs[i * 16], y[i]);
-    }
-  }
-  if (c < p) {
-    double* Y = a.Y[side] + row0 + (int64_t)c * a.ldy + rbase;
-#pragma unroll
-    for (int i = 0; i < kTsqrRowsPerThread; ++i)
-      if (rbase + i < nr) Y[i] = y[i];
-  }
+  if (t < p) a.tau[side][(int64_t)blockIdx.x * a.pmax + t] = tsh[t];
 }
 
 // Q formation in compact WY form on the FP64 matrix cores. The block's reflectors give
