@@ -10,6 +10,7 @@ stopping test); the FP64 path is timed beside it. Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import math
 import os
@@ -48,15 +49,22 @@ def time_solves(sol, args_dev, steps, warmup):
     for _ in range(warmup):
         sol.solve(*args_dev)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = []
-    marks = []
-    for _ in range(steps):
-        _, _, _, r, info = sol.solve(*args_dev)
-        infos.append(info.as_dict())
-        marks.append(time.perf_counter())
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    # Python's cyclic garbage collector is paused over the timed loop (as timeit does): a full
+    # collection with torch loaded takes tens of milliseconds and otherwise lands on one solve.
+    gc.collect()
+    gc.disable()
+    try:
+        t0 = time.perf_counter()
+        infos = []
+        marks = []
+        for _ in range(steps):
+            _, _, _, r, info = sol.solve(*args_dev)
+            infos.append(info.as_dict())
+            marks.append(time.perf_counter())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    finally:
+        gc.enable()
     per = np.diff([t0] + marks) * 1e3  # each solve returns after its device work has finished
     log(f"  per-solve wall ms: min {per.min():.3f} median {np.median(per):.3f} max {per.max():.3f} "
         f"(slowest: solve {int(per.argmax())})")

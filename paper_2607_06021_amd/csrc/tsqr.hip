@@ -89,27 +89,65 @@ __device__ inline double wave64_sum(double x) {
   return __hiloint2double(h32[0], l32[0]) + __hiloint2double(h32[1], l32[1]);
 }
 
-// Thread layout of a 256-row block: wave w holds columns 4w .. 4w+3, lane l rows l, l+64,
-// l+128 and l+192 of each (x[k][q] = row 64k + l of column 4w + q). A column lives in one wave,
-// so its dot products and norms are wave reductions, and a reflector is read from LDS as four
-// consecutive-word loads per lane (a quarter of the traffic of a layout with 16 lanes per
-// column, where every lane re-reads 16 elements shared with three other columns).
+// Thread layout of a 256-row block: wave w holds columns 4w .. 4w+3 and lane l rows l, l+64,
+// l+128 and l+192 of each; register slot s of lane l holds column 4w + (s ^ m(l)), where
+// m(l) = 2 (l & 1) + ((l >> 1) & 1). A column lives in one wave, so its dot products are wave
+// reductions, and a reflector is read from LDS as four consecutive-word loads per lane (a
+// quarter of the traffic of a layout with 16 lanes per column, where every lane re-reads 16
+// elements shared with three other columns). The slot permutation lets the four dot products of
+// a step be reduced together by halving exchanges (wave4_sums): each exchange between lanes l and
+// l ^ 1, then l ^ 2, sends the slots that the partner keeps, with no per-lane selection.
 
-// Column q (the same on every lane of the wave) of the wave's four: a switch on a uniform value
-// is a scalar branch, where indexing the register array would select on every lane.
-__device__ inline void pick_column(const double (&x)[4][4], int q, double (&col)[4]) {
-  switch (q & 3) {
-    case 0:
-      for (int k = 0; k < 4; ++k) col[k] = x[k][0];
-      break;
-    case 1:
-      for (int k = 0; k < 4; ++k) col[k] = x[k][1];
-      break;
-    case 2:
-      for (int k = 0; k < 4; ++k) col[k] = x[k][2];
-      break;
-    default:
-      for (int k = 0; k < 4; ++k) col[k] = x[k][3];
+__device__ inline int slot_perm(int l) { return ((l & 1) << 1) | ((l >> 1) & 1); }
+
+template <int CTRL>
+__device__ inline double dpp_d(double x) {
+  return __hiloint2double(__builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false),
+                          __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, false));
+}
+
+// Sums over the wave of the four per-slot partials d[s] (slot s of lane l = column s ^ m(l));
+// on return d[s] is the total of that slot's column, the same value on every lane holding it.
+//   * lanes l, l^1 (m differs in bit 1): keep slots 0, 1, add the partner's slots 2, 3;
+//   * lanes l, l^2 (m differs in bit 0): keep slot 0, add the partner's slot 1; the lane now has
+//     the quad's partial of column m(l);
+//   * rotations by 8 and then 4 lanes inside each 16-lane row (both keep l mod 4, and the sums
+//     are formed in the same order on the four lanes of a residue), then the 16- and 32-lane
+//     swaps: every lane has the total of column m(l);
+//   * slots 1, 2, 3 (columns m^1, m^2, m^3) are read from lanes l^2, l^1, l^3.
+__device__ inline void wave4_sums(double (&d)[4]) {
+  const double r0 = d[0] + dpp_d<0xB1>(d[2]);  // quad_perm [1,0,3,2]
+  const double r1 = d[1] + dpp_d<0xB1>(d[3]);
+  double u = r0 + dpp_d<0x4E>(r1);             // quad_perm [2,3,0,1]
+  u += dpp_d<0x128>(u);                        // row_ror:8
+  u += dpp_d<0x124>(u);                        // row_ror:4
+  int lo = __double2loint(u), hi = __double2hiint(u);
+  const auto l16 = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto h16 = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  u = __hiloint2double(h16[0], l16[0]) + __hiloint2double(h16[1], l16[1]);
+  lo = __double2loint(u);
+  hi = __double2hiint(u);
+  const auto l32 = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto h32 = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  u = __hiloint2double(h32[0], l32[0]) + __hiloint2double(h32[1], l32[1]);
+  d[0] = u;
+  d[1] = dpp_d<0x4E>(u);  // lane l^2
+  d[2] = dpp_d<0xB1>(u);  // lane l^1
+  d[3] = dpp_d<0x1B>(u);  // lane l^3, quad_perm [3,2,1,0]
+}
+
+// Slot sl (per lane) of the lane's four columns, by two selects on its bits. The values pass
+// through an empty asm statement first, so that the selects stay selects of registers (a select
+// of two array elements may be turned into an element at a selected index, which would move the
+// whole array to scratch memory).
+__device__ inline void pick_slot(const double (&x)[4][4], int sl, double (&col)[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double x0 = x[k][0], x1 = x[k][1], x2 = x[k][2], x3 = x[k][3];
+    asm volatile("" : "+v"(x0), "+v"(x1), "+v"(x2), "+v"(x3));
+    const double lo = (sl & 1) ? x1 : x0;
+    const double hi = (sl & 1) ? x3 : x2;
+    col[k] = (sl & 2) ? hi : lo;
   }
 }
 
@@ -164,7 +202,7 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) {
   const int64_t row0 = (int64_t)blockIdx.x * a.block_rows;
   const int nr = (int)min((int64_t)a.block_rows, a.rows - row0);
   if (p <= 0 || nr <= 0) return;
-  const int t = threadIdx.x, l = t & 63, c0 = 4 * (t >> 6);
+  const int t = threadIdx.x, l = t & 63, c0 = 4 * (t >> 6), m = slot_perm(l);
   __shared__ double vbuf[2][kTsqrRows];
   __shared__ double tsh[kPMax];
 
@@ -172,38 +210,38 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) {
   // are replaced by zeros afterwards, so that all 16 loads are in flight together.
   double x[4][4];
   {
-    int64_t off[4][4];
+    int64_t cb[4];
+    int rk[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int q = 0; q < 4; ++q) cb[q] = row0 + (int64_t)min(c0 + (q ^ m), p - 1) * a.ldin;
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        off[k][q] = row0 + min(64 * k + l, nr - 1) + (int64_t)min(c0 + q, p - 1) * a.ldin;
+    for (int k = 0; k < 4; ++k) rk[k] = min(64 * k + l, nr - 1);
     if (a.in_f32) {
       const float* X = (const float*)a.in[side];
       float raw[4][4];
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) raw[k][q] = X[off[k][q]];
+        for (int q = 0; q < 4; ++q) raw[k][q] = X[cb[q] + rk[k]];
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           keep_loaded(raw[k][q]);
-          x[k][q] = (c0 + q < p && 64 * k + l < nr) ? (double)raw[k][q] : 0.0;
+          x[k][q] = (c0 + (q ^ m) < p && 64 * k + l < nr) ? (double)raw[k][q] : 0.0;
         }
     } else {
       const double* X = (const double*)a.in[side];
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) x[k][q] = X[off[k][q]];
+        for (int q = 0; q < 4; ++q) x[k][q] = X[cb[q] + rk[k]];
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           keep_loaded(x[k][q]);
-          x[k][q] = (c0 + q < p && 64 * k + l < nr) ? x[k][q] : 0.0;
+          x[k][q] = (c0 + (q ^ m) < p && 64 * k + l < nr) ? x[k][q] : 0.0;
         }
     }
   }
@@ -212,9 +250,15 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) {
   // rdiag = R(c, c).
   double rdiag[4] = {0.0, 0.0, 0.0, 0.0}, vscale[4] = {0.0, 0.0, 0.0, 0.0};
   if (c0 == 0) {
-    const double col[4] = {x[0][0], x[1][0], x[2][0], x[3][0]};
-    double tau;
-    householder_column(col, 0, l, vbuf[0], rdiag[0], tau, vscale[0]);
+    double col[4], beta, tau, sc;
+    pick_slot(x, m, col);  // column 0 is slot m
+    householder_column(col, 0, l, vbuf[0], beta, tau, sc);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q == m) {
+        rdiag[q] = beta;
+        vscale[q] = sc;
+      }
     if (l == 0) tsh[0] = tau;
   }
   __syncthreads();
@@ -227,22 +271,23 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) {
       const double tau = tsh[j];
       double d[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        d[q] = wave64_sum(fma(v[0], x[0][q], v[1] * x[1][q]) + fma(v[2], x[2][q], v[3] * x[3][q]));
+      for (int q = 0; q < 4; ++q) d[q] = fma(v[0], x[0][q], v[1] * x[1][q]) + fma(v[2], x[2][q], v[3] * x[3][q]);
+      wave4_sums(d);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const double wq = c0 + q > j ? d[q] * tau : 0.0;  // columns up to j are final
+        const double wq = c0 + (q ^ m) > j ? d[q] * tau : 0.0;  // columns up to j are final
 #pragma unroll
         for (int k = 0; k < 4; ++k) x[k][q] = fma(-wq, v[k], x[k][q]);
       }
       const int cn = j + 1;
       if (cn < p && (cn & ~3) == c0) {
+        const int sl = (cn & 3) ^ m;
         double col[4], beta, tn, sc;
-        pick_column(x, cn, col);
+        pick_slot(x, sl, col);
         householder_column(col, cn, l, vbuf[cn & 1], beta, tn, sc);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          if ((cn & 3) == q) {
+          if (q == sl) {
             rdiag[q] = beta;
             vscale[q] = sc;
           }
@@ -256,7 +301,7 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) {
   double* Rb = a.Rout[side] + (int64_t)blockIdx.x * a.pmax;  // this block's R, rows 0..pmax-1
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int c = c0 + q;
+    const int c = c0 + (q ^ m);
     if (c < p) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
