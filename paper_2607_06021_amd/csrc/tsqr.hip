@@ -469,54 +469,42 @@ __global__ __launch_bounds__(kWyThreads) void k_tsqr_apply_wy(ApplyArgs a) {
   }
   __syncthreads();
 
-  // ---- back substitution, one column of Z per 8 lanes (rows q + 8u in registers), by blocks of
-  // 8 rows from the bottom: the contributions of the rows already solved come from 8 interleaved
-  // octet sums, then the block's 8 x 8 triangle is solved by every lane of the octet
-  {
-    const int j = t >> 3, q = t & 7;
-    double z[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int bk = ((p + 7) >> 3) - 1; bk >= 0; --bk) {  // uniform
-      double P[8];
+  // ---- back substitution by 16-row blocks from the bottom. In block b, wave 0 solves the
+  // block's triangle with one lane per column (the 16 rows in registers; after z_w is known the
+  // rows above it in the block are updated at once, so the dependent chain is one multiply and one
+  // fma per row); then every wave takes output tiles of the update of the rows above the block,
+  // X(0:16b, :) -= S(0:16b, block) Z(block, :), on the matrix cores. S is read once per block,
+  // not once per column.
+  for (int b = pt - 1; b >= 0; --b) {  // uniform
+    const int r0 = 16 * b;
+    if (wave == 0) {
+      double x[16];
 #pragma unroll
-      for (int w = 0; w < 8; ++w) {
-        const double* Si = S + (8 * bk + w) * kWyLd + q;
-        double d0 = 0.0, d1 = 0.0;
+      for (int w = 0; w < 16; ++w) x[w] = XZ[(r0 + w) * kWyLd + lane];
 #pragma unroll
-        for (int u = 0; u < 8; u += 2) {  // rows not solved yet hold z = 0
-          d0 = fma(Si[8 * u], z[u], d0);
-          d1 = fma(Si[8 * (u + 1)], z[u + 1], d1);
-        }
-        P[w] = d0 + d1;
-      }
+      for (int w = 15; w >= 0; --w) {
+        const double z = tsh[r0 + w] * x[w];  // zero past p (tau and X are zero there)
+        XZ[(r0 + w) * kWyLd + lane] = z;
 #pragma unroll
-      for (int w = 0; w < 8; ++w) P[w] = oct_sum(P[w]);
-      double zb[8];
-#pragma unroll
-      for (int w = 7; w >= 0; --w) {
-        const int i = 8 * bk + w;
-        double v = XZ[i * kWyLd + j] - P[w];
-#pragma unroll
-        for (int w2 = w + 1; w2 < 8; ++w2) v = fma(-S[i * kWyLd + 8 * bk + w2], zb[w2], v);
-        zb[w] = tsh[i] * v;  // zero past p (tau and X are zero there)
-      }
-      double mine = zb[0];
-#pragma unroll
-      for (int w = 1; w < 8; ++w) mine = q == w ? zb[w] : mine;
-      switch (bk) {  // uniform index
-        case 0: z[0] = mine; break;
-        case 1: z[1] = mine; break;
-        case 2: z[2] = mine; break;
-        case 3: z[3] = mine; break;
-        case 4: z[4] = mine; break;
-        case 5: z[5] = mine; break;
-        case 6: z[6] = mine; break;
-        default: z[7] = mine; break;
+        for (int w2 = 0; w2 < w; ++w2) x[w2] = fma(-S[(r0 + w2) * kWyLd + r0 + w], z, x[w2]);
       }
     }
+    __syncthreads();
+    if (b == 0) break;
+    for (int q = wave; q < b * pt; q += kWaves) {  // tile (I, J): rows 16 I, columns 16 J
+      const int I = q / pt, J = q % pt;
+      wy4 acc;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) XZ[(q + 8 * u) * kWyLd + j] = z[u];
+      for (int v = 0; v < 4; ++v) acc[v] = XZ[(16 * I + lk + 4 * v) * kWyLd + 16 * J + lr];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-S[(16 * I + lr) * kWyLd + r0 + 4 * kk + lk],
+                                                   XZ[(r0 + 4 * kk + lk) * kWyLd + 16 * J + lr], acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) XZ[(16 * I + lk + 4 * v) * kWyLd + 16 * J + lr] = acc[v];
+    }
+    __syncthreads();
   }
-  __syncthreads();
 
   // ---- Y^T = Y0^T - Z^T V^T for this wave's row tiles
   double* Y = a.Y[side] + row0;
