@@ -9,7 +9,7 @@
 //
 // Kernels: k_pi (scores and per-block maxima), k_gmax (global maximum), k_topk_block
 // (the best 64 of each 256-row block, ranked by counting), k_topk_merge (16 sorted lists of
-// 64 per block merged by rank until one list is left), k_select (set update, fixed-point
+// 64 per block merged pairwise, by rank, until one list is left), k_select (set update, fixed-point
 // test, trace).
 #include "lrp_kernels.h"
 
@@ -118,59 +118,68 @@ struct MergeArgs {
   int* out_i[2];
 };
 
-// Each of the kMergeFan input lists is sorted; an entry's rank in the merged order is its
-// position in its own list plus, for every other list, the number of entries before it.
-// One thread per entry; the kMergeFan binary searches (7 steps each) advance in
-// lockstep, so each step issues kMergeFan independent LDS reads. Entries of rank < kPMax are
-// written to the output list.
+// Each of the kMergeFan input lists is sorted. They are merged pairwise in four rounds
+// (16 -> 8 -> 4 -> 2 -> 1 lists), each merged list keeping its first kPMax entries: an entry's
+// rank in its pair's order is its position in its own list plus the number of entries of the
+// other list that come before it (a 7-step binary search). The order is strict (indices are
+// distinct, padding included), so the ranks within a pair are distinct and ranks 0 .. kPMax-1
+// are each written once. One thread per entry; scores and indices are kept in separate LDS
+// arrays, double-buffered between rounds, and an index is read only on a tied score.
 constexpr int kMergeThreads = kMergeFan * kPMax;  // 1024
 __global__ __launch_bounds__(kMergeThreads) void k_topk_merge(MergeArgs a) {
   if (a.st->done) return;
   const int side = blockIdx.y;
   constexpr int NE = kMergeFan * kPMax;
-  __shared__ Cand e[NE];
+  __shared__ double es[2][NE];
+  __shared__ int ei[2][NE];
   const int first = blockIdx.x * kMergeFan;
   const int q = threadIdx.x;
   {
     const int l = first + q / kPMax;
-    Cand c;
-    c.s = -2.0;
-    c.i = 0x50000000 + q;  // padding entries: distinct indices, below every real entry
+    double cs = -2.0;
+    int ci = 0x50000000 + q;  // padding entries: distinct indices, below every real entry
     if (l < a.nlists) {
-      c.s = a.in_s[side][(int64_t)first * kPMax + q];
-      c.i = a.in_i[side][(int64_t)first * kPMax + q];
-      if (c.s == -2.0) c.i = 0x50000000 + q;
+      cs = a.in_s[side][(int64_t)first * kPMax + q];
+      ci = a.in_i[side][(int64_t)first * kPMax + q];
+      if (cs == -2.0) ci = 0x50000000 + q;
     }
-    e[q] = c;
+    es[0][q] = cs;
+    ei[0][q] = ci;
   }
   __syncthreads();
-  const Cand c = e[q];
-  const int mine = q / kPMax;
-  int lo[kMergeFan], hi[kMergeFan];
+  int cur = 0;
 #pragma unroll
-  for (int l = 0; l < kMergeFan; ++l) {
-    lo[l] = 0;
-    hi[l] = kPMax;  // first position whose entry is not before c
-  }
+  for (int r = 0; r < 4; ++r) {  // kMergeFan >> r lists of kPMax entries
+    if (q < (kMergeFan >> r) * kPMax) {
+      const int pr = q / (2 * kPMax), half = (q / kPMax) & 1, pos = q % kPMax;
+      const int mine = (2 * pr + half) * kPMax, other = (2 * pr + (half ^ 1)) * kPMax;
+      const double cs = es[cur][mine + pos];
+      const int ci = ei[cur][mine + pos];
+      int lo = 0, hi = kPMax;  // first position of the other list whose entry is not before c
 #pragma unroll
-  for (int step = 0; step < 7; ++step) {  // ceil(log2(kPMax + 1)) steps empty every range
-#pragma unroll
-    for (int l = 0; l < kMergeFan; ++l) {
-      const int mid = (lo[l] + hi[l]) >> 1;
-      if (lo[l] < hi[l]) {
-        if (before(e[l * kPMax + mid], c))
-          lo[l] = mid + 1;
-        else
-          hi[l] = mid;
+      for (int step = 0; step < 7; ++step) {
+        if (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          const double os = es[cur][other + mid];
+          const bool bef = os > cs || (os == cs && ei[cur][other + mid] < ci);
+          if (bef)
+            lo = mid + 1;
+          else
+            hi = mid;
+        }
+      }
+      const int rk = pos + lo;
+      if (rk < kPMax) {
+        es[cur ^ 1][pr * kPMax + rk] = cs;
+        ei[cur ^ 1][pr * kPMax + rk] = ci;
       }
     }
+    __syncthreads();
+    cur ^= 1;
   }
-  int rk = q % kPMax;
-#pragma unroll
-  for (int l = 0; l < kMergeFan; ++l) rk += (l == mine) ? 0 : lo[l];
-  if (rk < kPMax) {
-    a.out_s[side][(int64_t)blockIdx.x * kPMax + rk] = c.s;
-    a.out_i[side][(int64_t)blockIdx.x * kPMax + rk] = c.i;
+  if (q < kPMax) {
+    a.out_s[side][(int64_t)blockIdx.x * kPMax + q] = es[cur][q];
+    a.out_i[side][(int64_t)blockIdx.x * kPMax + q] = ei[cur][q];
   }
 }
 
