@@ -115,8 +115,11 @@ void free_ctx(lrp_ctx* c) {
   if (c->evfin) (void)hipEventDestroy(c->evfin);
   for (int s = 0; s < 2; ++s)
     if (c->evit[s]) (void)hipEventDestroy(c->evit[s]);
-  for (int s = 0; s < 2; ++s)
+  for (int s = 0; s < 2; ++s) {
     if (c->gexec[s]) (void)hipGraphExecDestroy(c->gexec[s]);
+    if (c->gexec_upd[s]) (void)hipGraphExecDestroy(c->gexec_upd[s]);
+    if (c->gexec_sel[s]) (void)hipGraphExecDestroy(c->gexec_sel[s]);
+  }
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -251,7 +254,9 @@ static void prof_reduce(lrp_ctx* c) {
   }
 }
 
-int enqueue_pass_kernels(lrp_ctx* c, int k) {
+// Pass k up to the stop decision: the set update from the previous candidates, fibers, the
+// two thin QRs, the core, the factor products, rho and the indicator.
+int enqueue_pass_update(lrp_ctx* c, int k) {
   const bool mixed = c->precision == LRP_MIXED;
   const int nb_new = (k + 1) & 1, nb_old = k & 1;
   const int64_t n = c->n;
@@ -343,10 +348,21 @@ int enqueue_pass_kernels(lrp_ctx* c, int k) {
   ea.maxiter = c->maxiter;
   ea.trace = c->trace;
   TRY(eta_launch(ea, s));
+  return LRP_OK;
+}
+
+// The tail of pass k: the leverage-score candidates of the new iterate, for the selection that
+// opens pass k+1 (every kernel returns at once once the stop flag is set).
+int enqueue_pass_select(lrp_ctx* c, int k) {
+  const int nb_new = (k + 1) & 1;
   const double* U[2] = {c->Uit[nb_new], c->Vit[nb_new]};
   int fslot = 0;
-  TRY(select_candidates(c->sel, c->st, U, n, s, &fslot));
-  return LRP_OK;
+  return select_candidates(c->sel, c->st, U, c->n, c->stream, &fslot);
+}
+
+int enqueue_pass_kernels(lrp_ctx* c, int k) {
+  TRY(enqueue_pass_update(c, k));
+  return enqueue_pass_select(c, k);
 }
 
 // Stage 1 of a solve: state reset, input scan, DST of the factors, warm start and the
@@ -434,24 +450,33 @@ int enqueue_start(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const doub
 // Pass k: the launch sequence depends only on the parity of k (which iterate buffer is
 // new), so each parity is captured once into a hipGraph and replayed; if capture is not
 // possible the kernels are launched directly.
-int enqueue_pass(lrp_ctx* c, int k) {
-  const int par = k & 1;
-  if (c->use_graphs && !c->profile && !c->gexec[par]) {
+static int enqueue_captured(lrp_ctx* c, int k, hipGraphExec_t* slot, int (*fn)(lrp_ctx*, int)) {
+  if (c->use_graphs && !c->profile && !*slot) {
     hipGraph_t g = nullptr;
     bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed) == hipSuccess;
-    const int rc = ok ? enqueue_pass_kernels(c, k) : LRP_EDEVICE;
+    const int rc = ok ? fn(c, k) : LRP_EDEVICE;
     ok = (hipStreamEndCapture(c->stream, &g) == hipSuccess) && ok && rc == LRP_OK;
-    if (ok) ok = hipGraphInstantiate(&c->gexec[par], g, nullptr, nullptr, 0) == hipSuccess;
+    if (ok) ok = hipGraphInstantiate(slot, g, nullptr, nullptr, 0) == hipSuccess;
     if (g) (void)hipGraphDestroy(g);
     if (!ok) {
-      c->gexec[par] = nullptr;
+      *slot = nullptr;
       c->use_graphs = false;
       (void)hipGetLastError();
     }
   }
-  if (c->use_graphs && !c->profile && c->gexec[par])
-    return hipGraphLaunch(c->gexec[par], c->stream) == hipSuccess ? LRP_OK : LRP_EDEVICE;
-  return enqueue_pass_kernels(c, k);
+  if (c->use_graphs && !c->profile && *slot)
+    return hipGraphLaunch(*slot, c->stream) == hipSuccess ? LRP_OK : LRP_EDEVICE;
+  return fn(c, k);
+}
+
+int enqueue_pass(lrp_ctx* c, int k) { return enqueue_captured(c, k, &c->gexec[k & 1], enqueue_pass_kernels); }
+
+// Pass k with the stop flag read between its two parts: the update part (captured per parity),
+// the flag copy and its event, then the candidate selection (captured per parity).
+int enqueue_pass_polled(lrp_ctx* c, int k) {
+  TRY(enqueue_captured(c, k, &c->gexec_upd[k & 1], enqueue_pass_update));
+  TRY(enqueue_poll(c, k));
+  return enqueue_captured(c, k, &c->gexec_sel[k & 1], enqueue_pass_select);
 }
 
 // After pass k: copy the stop flag to pinned memory and mark the point with an event.
@@ -591,15 +616,13 @@ int solve_impl(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const double*
     if (launch_status() != LRP_OK) return LRP_EDEVICE;
   }
   TRY(enqueue_start(c, rF, U_F, ldu, sigma_F, V_F, ldv));
-  // passes; the stop flag is read one pass behind the device
+  // passes; the stop flag of pass k is copied right after its decision, and the host reads it
+  // while the device runs pass k's candidate selection, so no pass is enqueued after the stop
+  // (only the selection of the last pass, whose kernels return at once)
   for (int k = 0; k < c->maxiter; ++k) {
-    TRY(enqueue_pass(c, k));
-    TRY(enqueue_poll(c, k));
-    if (k >= 1) {
-      const int prev = (k - 1) & 1;
-      if (hipEventSynchronize(c->evit[prev]) != hipSuccess) return LRP_EDEVICE;
-      if (c->done_host[prev]) break;
-    }
+    TRY(enqueue_pass_polled(c, k));
+    if (hipEventSynchronize(c->evit[k & 1]) != hipSuccess) return LRP_EDEVICE;
+    if (c->done_host[k & 1]) break;
   }
   TRY(enqueue_finish(c, U_out, ldou, S_out, V_out, ldov));
   if (hipEventSynchronize(c->evfin) != hipSuccess) return LRP_EDEVICE;

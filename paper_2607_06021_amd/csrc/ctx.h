@@ -43,7 +43,8 @@ struct lrp_ctx {
   SelectPlan sel{};
   RhoPlan rho{};
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evfin = nullptr, evit[2] = {nullptr, nullptr};
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};  // captured pass, per parity
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};  // captured pass, per parity (serving loop)
+  hipGraphExec_t gexec_upd[2] = {nullptr, nullptr}, gexec_sel[2] = {nullptr, nullptr};  // split pass (solve)
   bool use_graphs = true;
   bool solved = false;
   // optional per-kernel timing (LRP_FLAG_PROFILE): events recorded before every launch
