@@ -13,7 +13,9 @@
 //   final truncation of the returned iterate and DST-I back to physical space.
 // Every size, index set and flag stays in device memory; each kernel of a pass reads them
 // there and returns at once after the solve has stopped, so a pass is enqueued without any
-// read-back. The host polls the stop flag one pass behind the device.
+// read-back. The stop flag of a pass is copied right after its decision; the host reads it
+// while the device runs that pass's candidate selection (the serving loop reads it one pass
+// behind).
 #include <cstdio>
 #include <cstring>
 #include <new>
