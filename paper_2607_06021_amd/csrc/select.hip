@@ -15,15 +15,7 @@
 
 namespace lrp {
 
-struct Cand {
-  double s;
-  int i;
-};
-
-// a comes before b: higher score, then smaller index
-__device__ inline bool before(const Cand& a, const Cand& b) {
-  return a.s > b.s || (a.s == b.s && a.i < b.i);
-}
+// Candidate order throughout: a higher score first, then the smaller index.
 
 struct PiArgs {
   const DevState* st;
@@ -75,37 +67,54 @@ struct TopkArgs {
   int* ci[2];
 };
 
+// Rank of each entry of a 256-row block in the (score desc, index asc) order by counting the
+// entries before it; scores sit in their own LDS array and are read two per load (the same
+// address on every lane, a broadcast), indices only for a tied score.
 __global__ __launch_bounds__(256) void k_topk_block(TopkArgs a) {
   const DevState* st = a.st;
   if (st->done) return;
   const int side = blockIdx.y;
-  __shared__ Cand e[kSelRows];
-  __shared__ int excl[kPMax];
+  __shared__ double2 es2[kSelRows / 2];
+  __shared__ int ei[kSelRows];
+  __shared__ __align__(16) int excl[kPMax];
+  double* es = reinterpret_cast<double*>(es2);
   const int ne = side == 0 ? st->nI : st->nJ;
   const int* set = side == 0 ? st->I : st->J;
-  if (threadIdx.x < ne) excl[threadIdx.x] = set[threadIdx.x];
+  if (threadIdx.x < kPMax) excl[threadIdx.x] = threadIdx.x < ne ? set[threadIdx.x] : -1;
   __syncthreads();
   const double floor_v = kFloorRel * a.gmax[side];
   const int64_t i = (int64_t)blockIdx.x * kSelRows + threadIdx.x;
-  Cand c;
+  double cs;
+  int ci;
   if (i < a.n) {
     const double p = a.pi[side][i];
     bool ex = false;
-    for (int q = 0; q < ne; ++q) ex |= (excl[q] == (int)i);
-    c.s = ex ? -1.0 : (p <= floor_v ? 0.0 : p);
-    c.i = (int)i;
+    const int4* ex4 = reinterpret_cast<const int4*>(excl);
+#pragma unroll 4
+    for (int q = 0; q < kPMax / 4; ++q) {
+      const int4 e = ex4[q];
+      ex |= (e.x == (int)i) | (e.y == (int)i) | (e.z == (int)i) | (e.w == (int)i);
+    }
+    cs = ex ? -1.0 : (p <= floor_v ? 0.0 : p);
+    ci = (int)i;
   } else {  // padding: below every real entry, distinct indices
-    c.s = -2.0;
-    c.i = 0x40000000 + (int)threadIdx.x;
+    cs = -2.0;
+    ci = 0x40000000 + (int)threadIdx.x;
   }
-  e[threadIdx.x] = c;
+  es[threadIdx.x] = cs;
+  ei[threadIdx.x] = ci;
   __syncthreads();
-  // rank of this entry in the (score desc, index asc) order; the best kPMax are kept
   int rk = 0;
-  for (int q = 0; q < kSelRows; ++q) rk += before(e[q], c) ? 1 : 0;
+#pragma unroll 8
+  for (int q = 0; q < kSelRows / 2; ++q) {
+    const double2 o = es2[q];
+    rk += (o.x > cs) + (o.y > cs);
+    if (o.x == cs) rk += ei[2 * q] < ci;
+    if (o.y == cs) rk += ei[2 * q + 1] < ci;
+  }
   if (rk < kPMax) {
-    a.cs[side][(int64_t)blockIdx.x * kPMax + rk] = c.s;
-    a.ci[side][(int64_t)blockIdx.x * kPMax + rk] = c.i;
+    a.cs[side][(int64_t)blockIdx.x * kPMax + rk] = cs;
+    a.ci[side][(int64_t)blockIdx.x * kPMax + rk] = ci;
   }
 }
 
