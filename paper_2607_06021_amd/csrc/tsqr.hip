@@ -374,25 +374,38 @@ __global__ __launch_bounds__(kWyThreads) void k_tsqr_apply_wy(ApplyArgs a) {
   wy4 xacc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
   double vb0[16], vb1[16];  // -V(16 R + lr, 4 s + lk) for this wave's row tiles R = wave, wave + 8
 
+  // the loads of both halves of V are issued here, so that the second half's arrive while the
+  // first half's products run (clamped indices: every load reads a valid element)
+  constexpr int kPer = kHalf * kPMax / kWyThreads;  // 16
+  double raw[2][kPer];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+      const int e = t + kWyThreads * m, r = e % kHalf, c = e / kHalf;
+      raw[h][m] = V[min(h * kHalf + r, nr - 1) + (int64_t)min(c, p - 1) * ldv];
+    }
+  // and the parent piece T_par (p x p), kept in registers until V's staging buffer is free
+  constexpr int kTPer = kPMax * kPMax / kWyThreads;  // 8
+  double tpre[kTPer];
+  if (T) {
+#pragma unroll
+    for (int m = 0; m < kTPer; ++m) {
+      const int e = t + kWyThreads * m, r = e % kPMax, c = e / kPMax;
+      tpre[m] = T[toff + min(r, p - 1) + (int64_t)min(c, p - 1) * a.ldt];
+    }
+  }
+
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int hr0 = h * kHalf;
     if (hr0 < nr) {  // uniform
-    // stage rows hr0 .. hr0 + 127 of V: all loads of a thread in flight together
-    {
-      constexpr int kPer = kHalf * kPMax / kWyThreads;  // 16
-      double raw[kPer];
+    // stage rows hr0 .. hr0 + 127 of V
 #pragma unroll
-      for (int m = 0; m < kPer; ++m) {
-        const int e = t + kWyThreads * m, r = e % kHalf, c = e / kHalf;
-        raw[m] = V[min(hr0 + r, nr - 1) + (int64_t)min(c, p - 1) * ldv];
-      }
-#pragma unroll
-      for (int m = 0; m < kPer; ++m) {
-        const int e = t + kWyThreads * m, r = e % kHalf, c = e / kHalf;
-        keep_loaded(raw[m]);
-        Vs[r * kWyLd + c] = (hr0 + r < nr && c < p) ? raw[m] : 0.0;
-      }
+    for (int m = 0; m < kPer; ++m) {
+      const int e = t + kWyThreads * m, r = e % kHalf, c = e / kHalf;
+      keep_loaded(raw[h][m]);
+      Vs[r * kWyLd + c] = (hr0 + r < nr && c < p) ? raw[h][m] : 0.0;
     }
     __syncthreads();
     const int nks = (min(nr - hr0, kHalf) + 3) >> 2;  // 4-row steps in this half
@@ -444,6 +457,15 @@ __global__ __launch_bounds__(kWyThreads) void k_tsqr_apply_wy(ApplyArgs a) {
       }
     }
     __syncthreads();
+    }
+  }
+  // V's staging buffer now holds T_par (zero outside p x p) for the final product
+  if (T) {
+#pragma unroll
+    for (int m = 0; m < kTPer; ++m) {
+      const int e = t + kWyThreads * m, r = e % kPMax, c = e / kPMax;
+      keep_loaded(tpre[m]);
+      Vs[r * kWyLd + c] = (r < p && c < p) ? tpre[m] : 0.0;
     }
   }
 #pragma unroll
@@ -514,20 +536,11 @@ __global__ __launch_bounds__(kWyThreads) void k_tsqr_apply_wy(ApplyArgs a) {
     const int row = 16 * R + lr;
     if (16 * R >= nr) continue;  // uniform
     wy4 acc[4];
-    if (T) {
+    if (T) {  // Y0 = [T_par; 0], T_par staged in LDS (zero outside p x p)
 #pragma unroll
       for (int J = 0; J < 4; ++J)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          acc[J][v] = T[toff + min(row, p - 1) + (int64_t)min(16 * J + lk + 4 * v, p - 1) * a.ldt];
-#pragma unroll
-      for (int J = 0; J < 4; ++J)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          double y0 = acc[J][v];
-          keep_loaded(y0);
-          acc[J][v] = (row < p && 16 * J + lk + 4 * v < p) ? y0 : 0.0;
-        }
+        for (int v = 0; v < 4; ++v) acc[J][v] = row < p ? Vs[row * kWyLd + 16 * J + lk + 4 * v] : 0.0;
     } else {
 #pragma unroll
       for (int J = 0; J < 4; ++J)
