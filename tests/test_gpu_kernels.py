@@ -75,9 +75,13 @@ def _ill_conditioned(n, p, rng, kappa=1e12):
     return (Q * s[None, :]) @ W
 
 
+# widths that fill the four columns of a wave partly (2, 3, 33, 63), blocks shorter than one
+# 64-row group of lanes (n = 63) or ragged (255 rows in the last block), and a tree of several
+# levels over partly filled stacked factors (p < p_max)
 @pytest.mark.parametrize("n,p,kind", [(255, 5, "rand"), (4095, 32, "rand"), (4095, 64, "ill"), (65535, 64, "ill"),
                                       (65535, 20, "deficient"), (131071, 1, "rand"),
-                                      (1023, 64, "fibers")])
+                                      (1023, 64, "fibers"), (63, 3, "rand"), (63, 63, "rand"),
+                                      (127, 2, "rand"), (511, 63, "ill"), (16383, 33, "rand")])
 def test_tsqr_matches_householder(n, p, kind):
     from paper_2607_06021_amd import Solver
 
