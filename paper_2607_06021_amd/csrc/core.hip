@@ -184,15 +184,27 @@ __device__ inline void jac_move_b(double (&b)[4], double (&vb)[4], int src) {
   }
 }
 
-// Columns ca (into x, vx) from LDS, zero past the problem.
+// Column col (into x, vx) from LDS, zero past the problem. Every address lies in the 64 x LDP
+// buffer (col < 64, rows < 64), so all loads are issued unconditionally and the entries outside
+// the problem are replaced afterwards; the empty asm statements keep the selects from being
+// turned back into branches around single loads.
 template <bool WV>
 __device__ inline void jac_load(const JacProb& pr, int col, int li, double (&x)[4], double (&vx)[4]) {
   const bool ok = col < pr.k;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
+    x[u] = pr.A[li + 16 * u + col * LDP];
+    if (WV) vx[u] = pr.V[li + 16 * u + col * LDP];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
     const int i = li + 16 * u;
-    x[u] = (ok && i < pr.m) ? pr.A[i + col * LDP] : 0.0;
-    if (WV) vx[u] = (ok && i < pr.k) ? pr.V[i + col * LDP] : 0.0;
+    asm volatile("" : "+v"(x[u]));
+    x[u] = (ok && i < pr.m) ? x[u] : 0.0;
+    if (WV) {
+      asm volatile("" : "+v"(vx[u]));
+      vx[u] = (ok && i < pr.k) ? vx[u] : 0.0;
+    }
   }
 }
 
