@@ -39,7 +39,49 @@ def parse():
     ap.add_argument("--served", type=int, default=2000, help="requests in the served stream (0: skip)")
     ap.add_argument("--served-active", type=int, default=8)
     ap.add_argument("--served-budget-gb", type=float, default=64.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="copy one 256 MiB device tensor and exit (calibrates the HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_probe():
+    """A plain device copy of known size: 256 MiB read and 256 MiB written."""
+    import torch
+
+    a = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy probe: {a.numel() * 8} bytes copied")
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from a committed rocprofv3 counter summary
+    (profiles/*_traffic.md), or None if there is none or its kernel sources changed since the
+    counters were taken."""
+    import glob
+    import hashlib
+
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):
+        fields = {}
+        for line in open(path):
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].strip().split(": ", 1)
+                fields[k] = v
+        if fields.get("kernel") != kernel or fields.get("workload") != workload:
+            continue
+        h = hashlib.sha256()
+        for src in fields.get("sources", "").split():
+            try:
+                with open(os.path.join(ROOT, src), "rb") as f:
+                    h.update(f.read())
+            except OSError:
+                return None
+        if h.hexdigest() != fields.get("source_sha256"):
+            return None
+        return int(fields["hbm_bytes_per_launch"])
+    return None
 
 
 def time_solves(sol, args_dev, steps, warmup):
@@ -247,8 +289,9 @@ def cpu_baseline(w, U, s, V):
                "sample": f"one full FP64 solve of the same workload (seed 0, {o.iters} passes)"}
 
 
-def dominant_roofline(res):
-    """Roofline of the kernel with the largest device time in the profiled solve."""
+def dominant_roofline(res, workload):
+    """Roofline of the kernel with the largest device time in the profiled solve; `traffic` is
+    the kernel's measured HBM bytes per launch where a current counter summary exists."""
     key = {"k_core": "core", "k_dst_pass1": "dst", "k_dst_pass2": "dst", "k_dst_single": "dst",
            "k_fiber": "fiber", "k_prod": "prod", "k_tsqr_factor": "tsqr_factor",
            "k_tsqr_apply": "tsqr_apply", "k_rho_a": "rho_a", "k_rho_b": "rho_b"}.get(res["dominant"])
@@ -256,6 +299,7 @@ def dominant_roofline(res):
         return {"bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None,
                 "traffic": None, "kernel": res["dominant"], "note": "no algorithmic model for this kernel"}
     r = dict(res["rooflines"][key])
+    r["traffic"] = measured_traffic(res["dominant"], workload)
     r["share_of_solve"] = res["profile"][res["dominant"]]["share"]
     return r
 
@@ -265,6 +309,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
     import numpy as np
     import torch
 
@@ -342,7 +389,7 @@ def main():
         "served_p50_ms": served["p50_ms"] if served else None,
         "served_p99_ms": served["p99_ms"] if served else None,
         "served": served,
-        "roofline": dominant_roofline(results[head]),
+        "roofline": dominant_roofline(results[head], (wmx if head == "mixed" else w64).name),
         "kernels": {p: {"rooflines": results[p]["rooflines"], "profile": results[p]["profile"]}
                     for p in ("mixed", "fp64") if p in results},
         "cpu_baseline": cpu,
