@@ -557,29 +557,53 @@ __device__ void explicit_reflectors(double* QR, int m, int k) {
   __syncthreads();
 }
 
-// Ri <- R^{-1} for the k x k upper triangle of QR, zero elsewhere in 64 x 64 (back substitution
-// per column, the diagonal reciprocals precomputed in dinv: kPMax doubles of LDS).
+// Ri <- R^{-1} for the k x k upper triangle of QR, zero elsewhere in 64 x 64, by back
+// substitution on R X = I in 16-row blocks from the bottom (dinv: kPMax doubles of LDS, the
+// diagonal reciprocals). In block b, wave 0 solves the block's triangle with a lane per column
+// (the 16 rows in registers, updated right-looking after each row: one multiply and one fma per
+// row on the dependent chain); then the waves update the rows above the block,
+// X(0:16b, :) -= R(0:16b, block) X(block, :), as 16 x 16 MFMA tiles. Only the strict upper
+// triangle of QR is read (the reflector tails below it are not), and QR is zero past column k.
 __device__ void tri_inverse(const double* QR, int k, double* Ri, double* dinv) {
-  const int t = threadIdx.x, li = t & 7;
-  if (t < k) dinv[t] = 1.0 / QR[t + t * LDP];
-  __syncthreads();
-  for (int c = t >> 3; c < kPMax; c += blockDim.x >> 3) {
-    double x[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) x[u] = (c < k && li + 8 * u == c) ? dinv[c] : 0.0;
-    for (int i = (c < k ? c : 0) - 1; i >= 0; --i) {  // rows above the diagonal, bottom up
-      const double* qi = QR + i + li * LDP;
-      double d[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int u = 0; u < 8; ++u) d[u & 3] = fma(qi[8 * u * LDP], x[u], d[u & 3]);
-      const double xi = -oct_sum((d[0] + d[1]) + (d[2] + d[3])) * dinv[i];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) x[u] = li + 8 * u == i ? xi : x[u];
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) Ri[li + 8 * u + c * LDP] = x[u];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = blockDim.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  if (t < kPMax) dinv[t] = t < k ? 1.0 / QR[t + t * LDP] : 0.0;
+  for (int e = t; e < kPMax * kPMax; e += blockDim.x) {
+    const int i = e % kPMax, j = e / kPMax;
+    Ri[i + j * LDP] = (i == j && i < k) ? 1.0 : 0.0;
   }
   __syncthreads();
+  const int pt = (k + 15) >> 4;
+  for (int b = pt - 1; b >= 0; --b) {  // uniform
+    const int r0 = 16 * b;
+    if (wave == 0) {
+      double x[16];
+#pragma unroll
+      for (int w = 0; w < 16; ++w) x[w] = Ri[(r0 + w) + lane * LDP];
+#pragma unroll
+      for (int w = 15; w >= 0; --w) {
+        const double z = dinv[r0 + w] * x[w];  // zero past k
+        Ri[(r0 + w) + lane * LDP] = z;
+#pragma unroll
+        for (int w2 = 0; w2 < w; ++w2) x[w2] = fma(-QR[(r0 + w2) + (r0 + w) * LDP], z, x[w2]);
+      }
+    }
+    __syncthreads();
+    if (b == 0) break;
+    for (int q = wave; q < b * pt; q += nw) {  // tile (I, J): rows 16 I of X, columns 16 J
+      const int I = q / pt, J = q % pt;
+      f64x4 acc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] = Ri[(16 * I + lk + 4 * v) + (16 * J + lr) * LDP];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-QR[(16 * I + lr) + (r0 + 4 * kk + lk) * LDP],
+                                                   Ri[(r0 + 4 * kk + lk) + (16 * J + lr) * LDP], acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Ri[(16 * I + lk + 4 * v) + (16 * J + lr) * LDP] = acc[v];
+    }
+    __syncthreads();
+  }
 }
 
 // Frobenius norms of the upper triangle of QR (k x k) and of Ri: into out[0], out[1].
