@@ -193,6 +193,45 @@ def test_repeat_solves_are_bitwise_identical():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_one_context_serves_different_ranks_and_pass_counts(precision):
+    """The passes are captured once per context (two graphs per iterate parity) and replayed:
+    solves of different input rank, pass count and stop status on one context (the maxiter is
+    fixed per context, so the cases are grouped by it) must each be bitwise equal to the same
+    solve on a fresh context."""
+    from paper_2607_06021_amd import Solver
+
+    w = workloads.CONFIGS["n4095_r10_fp64"]
+    cases = []
+    for seed, rk, maxiter in ((5, 4, 20), (6, 12, 20), (7, 9, 2), (5, 4, 20)):
+        U, s, V = workloads.make(w, seed)
+        cases.append((U[:, :rk], s[:rk], V[:, :rk], maxiter))
+    print(f"one context, {precision}", flush=True)
+
+    def run(sol, case):
+        U, s, V, _ = case
+        Uo, So, Vo, r, info = sol.solve(dev(U), dev(s), dev(V))
+        return [Uo.cpu().numpy().copy(), So.cpu().numpy().copy(), Vo.cpu().numpy().copy()], r, info.as_dict()
+
+    fresh = []
+    for case in cases:
+        with Solver(w.n, w.r_max, w.tol, maxiter=case[3], precision=precision) as sol:
+            fresh.append(run(sol, case))
+    shared = {}
+    for maxiter in sorted({c[3] for c in cases}):
+        with Solver(w.n, w.r_max, w.tol, maxiter=maxiter, precision=precision) as sol:
+            for i, case in enumerate(cases):
+                if case[3] == maxiter:
+                    shared[i] = run(sol, case)
+    for i in range(len(cases)):
+        (A, ra, ia), (B, rb, ib) = fresh[i], shared[i]
+        print(f"  case {i}: rank {ra}/{rb} iters {ia['iters']}/{ib['iters']} status {ia['status']}/{ib['status']}",
+              flush=True)
+        assert ra == rb and ia["iters"] == ib["iters"] and ia["status"] == ib["status"]
+        for x, y in zip(A, B):
+            assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_profile_mode_same_result_and_kernel_times(precision):
     """A context with the profile flag launches the passes kernel by kernel (no graphs) with
     HIP events around every launch: the result must be bitwise the same as with graphs, and
