@@ -36,6 +36,19 @@ the design notes of the repository):
     truncation; the loop makes exactly maxiter passes; no stop at k = 0; when the
     pre-prune index sets repeat, the iteration has reached a fixed point and the
     previous iterate is returned.
+  * QDEIM selection (Algorithm 2, QDEIM branch, used in Algorithm 4 step 5): the
+    first r_sig pivots of the column-pivoted QR of U_{k-1}(:, :r_sig)^T, pivoting on
+    the largest remaining column norm (ties to the smaller index); the indices not
+    already in I_{k-1} are appended in pivot order (the union of step 6; QDEIM sets
+    are ordered). The safeguard of steps 7-12 appends one more index when nothing
+    was added or at k = 0; the paper draws it at random, here it is the index outside
+    the set with the largest leverage score (ties and noise to the smaller index),
+    and it is added to the current set rather than to I*_k alone.
+  * the initial guess U0, V0 of Algorithm 4 is given in physical space (the space of
+    the solver's output factors, e.g. a previous solution U_W, S, V_W) with optional
+    weights S0: the warm start is then the truncated SVD of
+    DST(U0) diag(S0) DST(V0)^T, computed exactly as the default warm start from the
+    right-hand side.
 """
 from __future__ import annotations
 
@@ -53,6 +66,8 @@ STATUS_STAGNATED = 2
 
 #: Leverage scores at or below FLOOR_REL * max(pi) are rounding noise; they count as 0.
 FLOOR_REL = (64.0 * EPS) ** 2
+#: Pivoted QR: squared column norms within this relative distance of the largest are ties.
+PIVOT_TIE_REL = 1e-12
 
 
 # ----------------------------------------------------------------------------------------
@@ -148,6 +163,7 @@ class Cross:
     V: np.ndarray  # n x r
     rC: np.ndarray  # diag(R_C), one per index of J
     rR: np.ndarray  # diag(R_R), one per index of I
+    branch: bool = True  # True: |J| <= |I| (solve with Q(I,:)); False: solve with Z(J,:)
 
 
 def scross(Uh, Vh, lam, I: Sequence[int], J: Sequence[int]) -> Cross:
@@ -175,7 +191,8 @@ def scross(Uh, Vh, lam, I: Sequence[int], J: Sequence[int]) -> Cross:
         r = 0
     else:
         r = int(np.count_nonzero(s > max(len(I), len(J)) * EPS * s[0]))
-    return Cross(Q @ A[:, :r], s[:r].copy(), Zq @ Bt[:r].T, np.diag(RC).copy(), np.diag(RR).copy())
+    return Cross(Q @ A[:, :r], s[:r].copy(), Zq @ Bt[:r].T, np.diag(RC).copy(), np.diag(RR).copy(),
+                 len(J) <= len(I))
 
 
 # ----------------------------------------------------------------------------------------
@@ -213,6 +230,82 @@ def select(U: np.ndarray, r_sig: int, I_prev: Sequence[int], p_max: int) -> Sele
     else:
         gap = math.inf
     return Selection(list(I_prev) + new, new, gap)
+
+
+def pivoted_qr_order(A: np.ndarray, count: int) -> tuple:
+    """First `count` pivots of Householder QR with column pivoting of A (m x n, Algorithm 2).
+
+    Step j picks, among the columns not yet pivoted, the one whose trailing part (rows j..m-1
+    after the j reflectors so far) has the largest squared norm. Squared norms within
+    PIVOT_TIE_REL of the largest count as equal, and those at or below FLOOR_REL times the
+    largest initial one as 0: ties go to the smaller column index (rounding in the updates
+    must not decide between columns that are equal in exact arithmetic). The norms are
+    recomputed at every step. Returns (pivots, gaps): gaps[j] is the relative margin of step
+    j's choice over the best column outside the tie (inf when there is none).
+    """
+    A = np.array(A, dtype=np.float64, copy=True)
+    m, n = A.shape
+    count = min(count, m, n)
+    cols = np.arange(n)
+    piv: List[int] = []
+    gaps: List[float] = []
+    floor = FLOOR_REL * float(np.max(np.sum(A * A, axis=0))) if A.size else 0.0
+    for j in range(count):
+        nrm2 = np.sum(A[j:, j:] ** 2, axis=0)
+        nrm2 = np.where(nrm2 <= floor, 0.0, nrm2)
+        best = float(nrm2.max())
+        tied = nrm2 >= best * (1.0 - PIVOT_TIE_REL)
+        c = j + int(np.argmin(np.where(tied, cols[j:], n + 1)))
+        rest = nrm2[~tied]
+        gaps.append(math.inf if rest.size == 0 or best == 0.0 else (best - float(rest.max())) / best)
+        A[:, [j, c]] = A[:, [c, j]]
+        cols[[j, c]] = cols[[c, j]]
+        piv.append(int(cols[j]))
+        x = A[j:, j].copy()
+        alpha = x[0]
+        xn = float(np.linalg.norm(x))
+        if xn == 0.0:
+            continue
+        beta = -math.copysign(xn, alpha)
+        v = x.copy()
+        v[0] = alpha - beta
+        v /= v[0]
+        tau = (beta - alpha) / beta
+        A[j:, j:] -= tau * np.outer(v, v @ A[j:, j:])
+    return piv, gaps
+
+
+def qdeim_select(U: np.ndarray, r_sig: int, I_prev: Sequence[int], p_max: int, first: bool) -> Selection:
+    """QDEIM index update (Algorithm 2 QDEIM branch, Algorithm 4 steps 5-12).
+
+    I* = the first r_sig pivots of the column-pivoted QR of U(:, :r_sig)^T; the pivots not in
+    I_prev are appended in pivot order. If that adds nothing, or at the first pass, the index
+    outside the set with the largest leverage score is appended as well (the safeguard; the
+    paper picks it at random). The set is capped at p_max.
+    """
+    n = U.shape[0]
+    piv, gaps = pivoted_qr_order(U[:, :r_sig].T, r_sig)
+    have = set(int(i) for i in I_prev)
+    out = list(int(i) for i in I_prev)
+    new: List[int] = []
+    for i in piv:
+        if len(out) >= p_max:
+            break
+        if i not in have:
+            out.append(i)
+            new.append(i)
+            have.add(i)
+    if (not new or first) and len(out) < p_max and len(out) < n:
+        pi = leverage_scores(U, r_sig)
+        top = float(pi.max()) if n else 0.0
+        score = np.where(pi <= FLOOR_REL * top, 0.0, pi)
+        cand = np.array([i for i in range(n) if i not in have], dtype=np.int64)
+        order = cand[np.lexsort((cand, -score[cand]))]
+        extra = int(order[0])
+        out.append(extra)
+        new.append(extra)
+    gap = min(gaps) if gaps else math.inf
+    return Selection(out, new, gap)
 
 
 def prune(idx: Sequence[int], diag: np.ndarray, tau: float) -> List[int]:
@@ -273,6 +366,7 @@ class IterRecord:
     eta2: float
     gapI: float
     gapJ: float
+    branch: bool = True  # |J_pre| <= |I_pre|: Algorithm 1 solves with Q(I,:)
 
 
 @dataclasses.dataclass
@@ -302,6 +396,19 @@ def warm_start(Uh: np.ndarray, Vh: np.ndarray):
         return None
     r = int(np.count_nonzero(s > Uh.shape[1] * EPS * s[0]))
     return Qu @ A[:, :r], s[:r].copy(), Qv @ Bt[:r].T
+
+
+def warm_start_from(n: int, U0: np.ndarray, S0: Optional[np.ndarray], V0: np.ndarray):
+    """Warm start from a given guess (Algorithm 4 inputs U0, V0), in physical space.
+
+    The guess is moved to the sine basis like the right-hand side (Section 3.2) and its
+    truncated SVD, DST(U0) diag(S0) DST(V0)^T = U_{-1} S_{-1} V_{-1}^T, is the starting
+    iterate; S0 = None means unit weights.
+    """
+    U0 = np.asarray(U0, dtype=np.float64)
+    V0 = np.asarray(V0, dtype=np.float64)
+    S0 = np.ones(U0.shape[1]) if S0 is None else np.asarray(S0, dtype=np.float64)
+    return warm_start(dst1(U0) * S0[None, :], dst1(V0))
 
 
 def indicator(U, S, V, I, J):
@@ -342,16 +449,29 @@ def solve(
     maxiter: int,
     prune_tau: float = 1e-12,
     stop_at_fixed_point: bool = True,
+    warm=None,
+    replay=None,
+    selector: str = "ls",
 ) -> Result:
     """Low-rank Poisson solve: -Lap u = f, u = 0 on the boundary of the unit square.
 
     Returns W ~= U diag(S) V^T on the n x n interior grid (Sections 3.2 and Algorithm 4).
+    warm: optional (U0, S0, V0), the initial guess of Algorithm 4 in physical space (S0 may be
+    None); default (and for a zero guess): the right-hand side itself. replay: optional list of (I, J) index sets
+    used for passes 0, 1, ... instead of selecting them (a diagnostic). selector: "ls"
+    (leverage scores, Algorithm 3) or "qdeim" (Algorithm 2).
     """
+    if selector not in ("ls", "qdeim"):
+        raise ValueError(f"unknown selector {selector!r}")
     U_F = np.asarray(U_F, dtype=np.float64)
     V_F = np.asarray(V_F, dtype=np.float64)
     lam = eigenvalues(n)
     Uh, Vh = spectral_factors(n, U_F, sigma, V_F)
     ws = warm_start(Uh, Vh)
+    if ws is not None and warm is not None:
+        guess = warm_start_from(n, *warm)
+        if guess is not None:  # a zero guess leaves the start from the right-hand side
+            ws = guess
     if ws is None:  # F = 0: the solution is 0
         z = np.zeros((n, 1))
         return Result(z, np.zeros(1), z.copy(), 1, STATUS_OK, 0, [], [], 0.0, 0.0, [])
@@ -366,8 +486,17 @@ def solve(
     iters = 0
     for k in range(maxiter):
         r_sig = int(np.count_nonzero(S_prev > tol * S_prev[0]))
-        selI = select(U_prev, r_sig, I, r_max)
-        selJ = select(V_prev, r_sig, J, r_max)
+        if replay is not None and k < len(replay):
+            rI = [int(i) for i in replay[k][0]]
+            rJ = [int(j) for j in replay[k][1]]
+            selI = Selection(rI, [i for i in rI if i not in I], math.inf)
+            selJ = Selection(rJ, [j for j in rJ if j not in J], math.inf)
+        elif selector == "qdeim":
+            selI = qdeim_select(U_prev, r_sig, I, r_max, k == 0)
+            selJ = qdeim_select(V_prev, r_sig, J, r_max, k == 0)
+        else:
+            selI = select(U_prev, r_sig, I, r_max)
+            selJ = select(V_prev, r_sig, J, r_max)
         pre = (selI.indices, selJ.indices)
         if stop_at_fixed_point and pre_prev is not None and pre == pre_prev:
             status = STATUS_STAGNATED
@@ -384,7 +513,7 @@ def solve(
             rho = lr_diff_norm(cr.U, cr.S, cr.V, U_prev, S_prev, V_prev) / nrm
         trace.append(
             IterRecord(k, selI.indices, selJ.indices, I, J, r_sig, cr.S.size, cr.S, rho, ind,
-                       eta1, eta2, selI.gap, selJ.gap)
+                       eta1, eta2, selI.gap, selJ.gap, cr.branch)
         )
         U_prev, S_prev, V_prev = cr.U, cr.S, cr.V
         pre_prev = pre
