@@ -16,7 +16,8 @@
  *     stands for the paper's 1-based mode i+1.
  *   - Pointers documented as "device" are HIP device pointers (hipMalloc or torch CUDA
  *     tensors); "host" pointers are ordinary CPU memory. The caller owns every buffer it
- *     passes; the library never frees them and keeps no pointer to them after a call returns.
+ *     passes; the library never frees them and keeps no pointer to them after a call returns
+ *     (except lrp_set_guess, whose pointers are read by the next lrp_solve).
  *   - Input buffers are read-only. Output buffers must not overlap inputs (LRP_EINVAL).
  *   - A context owns all of its device workspace; it is allocated in lrp_create and reused
  *     by every lrp_solve, which allocates nothing.
@@ -131,13 +132,55 @@ int lrp_get_index_sets(const lrp_ctx* ctx, int64_t* I, int32_t* nI, int64_t* J, 
  *   Ipre, Jpre  host, count x r_max: the index sets handed to the cross approximation;
  *   nIpre, nJpre, nI, nJ  host, count: their sizes before and after pruning;
  *   rank        host, count: rank of the pass's cross approximation;
- *   indicator, rho  host, count (+inf where the stopping test did not need them).
+ *   indicator, rho  host, count (+inf where the stopping test did not need them);
+ *   branch      host, count: 1 where |J| <= |I| (Algorithm 1 solves with Q(I,:)), 0 where it
+ *               solves with Z(J,:);
+ *   route       host, count: how the core's pseudo-inverse was formed: 0 through a Householder
+ *               QR (a bound showed that the cutoff drops no singular value, so the pseudo-inverse
+ *               is the left inverse), 1 through a Jacobi SVD with the cutoff.
  *   count       host in/out: capacity in passes on input, passes recorded on output.
  * Any array pointer may be NULL. Returns LRP_OK or LRP_EINVAL.
  */
 int lrp_get_trace(const lrp_ctx* ctx, int32_t* count, int32_t* Ipre, int32_t* nIpre, int32_t* Jpre,
                   int32_t* nJpre, int32_t* nI, int32_t* nJ, int32_t* rank, double* indicator,
-                  double* rho);
+                  double* rho, int32_t* branch, int32_t* route);
+
+/*
+ * lrp_set_guess -- the initial guess U0, V0 of Algorithm 4 (its signature takes them as input;
+ * Section 1 describes the solver as warm started) for the next lrp_solve on this context.
+ * The guess is given in physical space like the solver's output, for example the factors of
+ * a previous solution: that solve then starts from the truncated SVD of
+ * DST(U0) diag(S0) DST(V0)^T (computed in FP64 in both precisions, truncated at
+ * r0 eps sigma_1) instead of from the right-hand side.
+ *   r0   columns of the guess, 1 <= r0 <= r_max; 0 clears a guess set earlier.
+ *   U0   device, n x r0, leading dimension ldu0 >= n.
+ *   S0   device, r0 weights, or NULL for unit weights.
+ *   V0   device, n x r0, leading dimension ldv0 >= n.
+ * The pointers are read by the next lrp_solve only (they must stay valid and unchanged until
+ * it returns; they may be that solve's output buffers, which are written only after the
+ * guess has been read), and the guess is cleared when that solve returns. A guess whose
+ * product is zero is ignored (the solve starts from the right-hand side); non-finite values
+ * make that solve return LRP_ENUMERIC. Returns LRP_OK or LRP_EINVAL (nothing changed).
+ */
+int lrp_set_guess(lrp_ctx* ctx, int32_t r0, const double* U0, int64_t ldu0, const double* S0,
+                  const double* V0, int64_t ldv0);
+
+/*
+ * lrp_set_index_sets -- replay (a diagnostic): passes 0 .. npasses-1 of every following
+ * lrp_solve on this context take the given index sets as the sets handed to the cross
+ * approximation (Algorithm 4 step 6) instead of selecting them; later passes select from the
+ * iterate these produce, as usual. Run a mixed-precision solve on the sets of an FP64 solve to
+ * separate rounding from index-set divergence.
+ *   npasses  0 <= npasses <= maxiter; 0 switches replay off.
+ *   I        host, npasses x r_max, row-major: entries 0 .. nI[k]-1 of row k are the row set of
+ *            pass k, 0-based, < n, distinct within the row.
+ *   nI       host, npasses sizes, 1 <= nI[k] <= r_max.
+ *   J, nJ    host, the column sets, as I and nI.
+ * Synchronizes the context's stream. Returns LRP_OK, LRP_EINVAL (nothing changed) or
+ * LRP_EDEVICE.
+ */
+int lrp_set_index_sets(lrp_ctx* ctx, int32_t npasses, const int64_t* I, const int32_t* nI,
+                       const int64_t* J, const int32_t* nJ);
 
 /* One kernel class of a profiled solve (host struct filled by lrp_get_profile). */
 typedef struct lrp_kernel_time {

@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include <hip/hip_ext.h>
 
@@ -83,6 +84,12 @@ void free_ctx(lrp_ctx* c) {
   dfree(c->trace.rank);
   dfree(c->trace.ind);
   dfree(c->trace.rho);
+  dfree(c->trace.branch);
+  dfree(c->trace.route);
+  dfree(c->replay.I);
+  dfree(c->replay.J);
+  dfree(c->replay.nI);
+  dfree(c->replay.nJ);
   dfree(c->dst.t1_64);
   dfree(c->dst.t2_64);
   dfree(c->dst.tl_64);
@@ -171,6 +178,12 @@ int create_impl(lrp_ctx* c) {
   TRY(dalloc(&c->trace.rank, mi));
   TRY(dalloc(&c->trace.ind, mi));
   TRY(dalloc(&c->trace.rho, mi));
+  TRY(dalloc(&c->trace.branch, mi));
+  TRY(dalloc(&c->trace.route, mi));
+  TRY(dalloc(&c->replay.I, mi * kPMax));
+  TRY(dalloc(&c->replay.J, mi * kPMax));
+  TRY(dalloc(&c->replay.nI, mi));
+  TRY(dalloc(&c->replay.nJ, mi));
   // DST tables and work
   TRY(dst_plan(&c->dst, n, 2 * pm));
   {
@@ -269,6 +282,7 @@ int enqueue_pass_update(lrp_ctx* c, int k) {
   sa.st = c->st;
   sa.pmax = pm;
   sa.trace = c->trace;
+  sa.replay = c->replay;
   // the candidate slot depends only on the merge depth, which is fixed per context
   const int slot = c->sel.nlevels & 1;
   sa.cs[0] = c->sel.cand_s[slot][0];
@@ -367,8 +381,76 @@ int enqueue_pass_kernels(lrp_ctx* c, int k) {
   return enqueue_pass_select(c, k);
 }
 
-// Stage 1 of a solve: state reset, input scan, DST of the factors, warm start and the
-// candidates of the first selection. Asynchronous on the context's stream.
+// Warm start from the initial guess U0, S0, V0 of Algorithm 4 (physical space, like the output):
+// the truncated SVD of DST(U0) diag(S0) DST(V0)^T replaces the start from the right-hand side,
+// computed in FP64 in both precisions through the iterate buffers of pass 0's new side (free
+// until pass 0 writes them). A zero guess leaves the start from the right-hand side in place; the
+// right-hand side is still factored first, which also detects a zero right-hand side.
+int enqueue_guess(lrp_ctx* c) {
+  const int64_t n = c->n;
+  const int r0 = c->guess_r0;
+  hipStream_t s = c->stream;
+  TRY(scan_inputs_launch(c->st, c->guess_U, c->guess_ldu, c->guess_V, c->guess_ldv, c->guess_S, n, r0, s));
+  TRY(guess_begin_launch(c->st, r0, s));
+  DstArgs da{};
+  da.st = c->st;
+  da.X = c->guess_U;
+  da.ldx = c->guess_ldu;
+  da.ncols = r0;
+  da.ncols_out = r0;
+  da.Y = c->Uit[1];
+  da.ldy = n;
+  da.scale = c->guess_S;
+  da.outscale = 1.0;
+  TRY(dst_launch(c->dst, da, false, s));
+  da.X = c->guess_V;
+  da.ldx = c->guess_ldv;
+  da.Y = c->Vit[1];
+  da.scale = nullptr;
+  TRY(dst_launch(c->dst, da, false, s));
+  TsqrIO io{};
+  io.st = c->st;
+  io.nsides = 2;
+  io.X[0] = c->Uit[1];
+  io.X[1] = c->Vit[1];
+  io.x_f32 = 0;
+  io.ldx = n;
+  io.Q[0] = c->Q[0];
+  io.Q[1] = c->Q[1];
+  io.ldq = n;
+  TRY(tsqr_run(c->tsqr, io, s));
+  CoreArgs ca{};
+  ca.st = c->st;
+  ca.R0 = tsqr_R(c->tsqr, 0);
+  ca.R1 = tsqr_R(c->tsqr, 1);
+  ca.pmax = c->r_max;
+  ca.Uhat = c->Uhat;
+  ca.Vtil = c->Vtil;
+  ca.nb = 0;
+  ca.trace = c->trace;
+  ca.maxiter = c->maxiter;
+  ca.guess = 1;
+  TRY(core_launch(ca, true, s));
+  ProdArgs pa{};
+  pa.st = c->st;
+  pa.Q[0] = c->Q[0];
+  pa.Q[1] = c->Q[1];
+  pa.ldq = n;
+  pa.B[0] = c->Uhat;
+  pa.B[1] = c->Vtil;
+  pa.pmax = c->r_max;
+  pa.out[0] = c->Uit[0];
+  pa.out[1] = c->Vit[0];
+  pa.ldo = n;
+  pa.n = n;
+  pa.nb = 0;
+  pa.gate_guess = 1;
+  return prod_launch(pa, s);
+}
+
+// Stage 1 of a solve: state reset, input scan, DST of the factors, warm start (from the
+// right-hand side, then from the guess if one is set) and the candidates of the first selection.
+// Asynchronous on the context's stream.
 int enqueue_start(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const double* sigma_F,
                   const double* V_F, int64_t ldv) {
   const bool mixed = c->precision == LRP_MIXED;
@@ -378,7 +460,7 @@ int enqueue_start(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const doub
   const double eps = mixed ? std::max(c->tol, 1e-7) : c->tol;
   const double h = 1.0 / (double)(n + 1);
   if (hipEventRecord(c->ev0, s) != hipSuccess) return LRP_EDEVICE;
-  TRY(init_state_launch(c->st, rF, eps, c->tau, s));
+  TRY(init_state_launch(c->st, rF, eps, c->tau, c->replay_n, s));
   TRY(scan_inputs_launch(c->st, U_F, ldu, V_F, ldv, sigma_F, n, rF, s));
   // spectral factors U^ = DST(U_F) diag(h^2 sigma), V^ = DST(V_F)
   DstArgs da{};
@@ -443,6 +525,7 @@ int enqueue_start(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const doub
   pa.n = n;
   pa.nb = 0;
   TRY(prod_launch(pa, s));
+  if (c->guess_r0 > 0) TRY(enqueue_guess(c));
   const double* U[2] = {c->Uit[0], c->Vit[0]};
   int fslot = 0;
   TRY(select_candidates(c->sel, c->st, U, n, s, &fslot));
@@ -577,7 +660,8 @@ int64_t context_bytes(int64_t n, int pm, int maxiter, bool mixed) {
   b += mixed ? 4 * 4 * np : 4 * 8 * np;                            // U^, V^, C, R^T
   b += 6 * 8 * np;                                                 // Q, Z, two iterates per side
   b += 2 * 8 * (int64_t)pm * pm;                                   // U^, V~ coefficients
-  b += (int64_t)maxiter * (2 * kPMax * 4 + 5 * 4 + 2 * 8);         // trace
+  b += (int64_t)maxiter * (2 * kPMax * 4 + 7 * 4 + 2 * 8);         // trace
+  b += (int64_t)maxiter * (2 * kPMax * 4 + 2 * 4);                 // replay sets
   DstPlan dp{};
   if (dst_plan(&dp, n, 2 * pm) == LRP_OK) {
     b += 24 * (int64_t)(dp.t1_count + 2 * std::max(dp.t2_count, 1));
@@ -617,6 +701,10 @@ int solve_impl(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const double*
       LRP_LAUNCH(K_EMPTY, k_hold, dim3(1), dim3(64), 0, c->stream, 0);
     if (launch_status() != LRP_OK) return LRP_EDEVICE;
   }
+  struct GuessScope {  // the guess applies to this solve only
+    lrp_ctx* c;
+    ~GuessScope() { c->guess_r0 = 0; }
+  } gscope{c};
   TRY(enqueue_start(c, rF, U_F, ldu, sigma_F, V_F, ldv));
   // passes; the stop flag of pass k is copied right after its decision, and the host reads it
   // while the device runs pass k's candidate selection, so no pass is enqueued after the stop
@@ -745,7 +833,7 @@ int lrp_get_index_sets(const lrp_ctx* c, int64_t* I, int32_t* nI, int64_t* J, in
 
 int lrp_get_trace(const lrp_ctx* c, int32_t* count, int32_t* Ipre, int32_t* nIpre, int32_t* Jpre,
                   int32_t* nJpre, int32_t* nI, int32_t* nJ, int32_t* rank, double* indicator,
-                  double* rho) {
+                  double* rho, int32_t* branch, int32_t* route) {
   if (!c || !c->solved || !count || *count < 0) return LRP_EINVAL;
   const int avail = std::min(c->st_host->k, c->maxiter);
   const int m = std::min(*count, avail);
@@ -770,8 +858,62 @@ int lrp_get_trace(const lrp_ctx* c, int32_t* count, int32_t* Ipre, int32_t* nIpr
   if (cp(nIpre, t.nIpre, sizeof(int) * m) != hipSuccess || cp(nJpre, t.nJpre, sizeof(int) * m) != hipSuccess ||
       cp(nI, t.nI, sizeof(int) * m) != hipSuccess || cp(nJ, t.nJ, sizeof(int) * m) != hipSuccess ||
       cp(rank, t.rank, sizeof(int) * m) != hipSuccess || cp(indicator, t.ind, sizeof(double) * m) != hipSuccess ||
-      cp(rho, t.rho, sizeof(double) * m) != hipSuccess)
+      cp(rho, t.rho, sizeof(double) * m) != hipSuccess || cp(branch, t.branch, sizeof(int) * m) != hipSuccess ||
+      cp(route, t.route, sizeof(int) * m) != hipSuccess)
     return LRP_EDEVICE;
+  return LRP_OK;
+}
+
+int lrp_set_guess(lrp_ctx* c, int32_t r0, const double* U0, int64_t ldu0, const double* S0, const double* V0,
+                  int64_t ldv0) {
+  if (!c || r0 < 0 || r0 > c->r_max) return LRP_EINVAL;
+  if (r0 == 0) {
+    c->guess_r0 = 0;
+    return LRP_OK;
+  }
+  if (!U0 || !V0 || ldu0 < c->n || ldv0 < c->n) return LRP_EINVAL;
+  c->guess_r0 = r0;
+  c->guess_U = U0;
+  c->guess_ldu = ldu0;
+  c->guess_S = S0;
+  c->guess_V = V0;
+  c->guess_ldv = ldv0;
+  return LRP_OK;
+}
+
+int lrp_set_index_sets(lrp_ctx* c, int32_t npasses, const int64_t* I, const int32_t* nI, const int64_t* J,
+                       const int32_t* nJ) {
+  if (!c || npasses < 0 || npasses > c->maxiter) return LRP_EINVAL;
+  if (npasses == 0) {
+    c->replay_n = 0;
+    return LRP_OK;
+  }
+  if (!I || !nI || !J || !nJ) return LRP_EINVAL;
+  const int rm = c->r_max;
+  std::vector<int> hI((size_t)npasses * kPMax, -1), hJ((size_t)npasses * kPMax, -1);
+  std::vector<int> hnI(npasses), hnJ(npasses);
+  for (int k = 0; k < npasses; ++k) {
+    for (int side = 0; side < 2; ++side) {
+      const int cnt = side == 0 ? nI[k] : nJ[k];
+      const int64_t* src = (side == 0 ? I : J) + (size_t)k * rm;
+      int* dst = (side == 0 ? hI.data() : hJ.data()) + (size_t)k * kPMax;
+      if (cnt < 1 || cnt > rm) return LRP_EINVAL;
+      for (int q = 0; q < cnt; ++q) {
+        if (src[q] < 0 || src[q] >= c->n) return LRP_EINVAL;
+        for (int u = 0; u < q; ++u)
+          if (src[u] == src[q]) return LRP_EINVAL;
+        dst[q] = (int)src[q];
+      }
+      (side == 0 ? hnI : hnJ)[k] = cnt;
+    }
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return LRP_EDEVICE;
+  if (hipMemcpy(c->replay.I, hI.data(), sizeof(int) * hI.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->replay.J, hJ.data(), sizeof(int) * hJ.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->replay.nI, hnI.data(), sizeof(int) * npasses, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->replay.nJ, hnJ.data(), sizeof(int) * npasses, hipMemcpyHostToDevice) != hipSuccess)
+    return LRP_EDEVICE;
+  c->replay_n = npasses;
   return LRP_OK;
 }
 

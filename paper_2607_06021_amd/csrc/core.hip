@@ -713,7 +713,8 @@ __global__ __launch_bounds__(kCoreThreads) void k_core(CoreArgs a) {
   tri_norms(B0, B1, k0, red, nrm2);
   const double bound = nrm2[0] * nrm2[1] * cut_pinv * kEps * 4.0;
   double* M;
-  if (bound < 1.0) {
+  const bool qr_route = bound < 1.0;
+  if (qr_route) {
     // With A = Q(I,:) and R_m = R_R (|J| <= |I|) the core is M = A^+ R_m^T; with A = Z(J,:) and
     // R_m = R_C it is M = R_C (A^+)^T, i.e. M^T = A^+ R_m^T: the same product, stored
     // transposed. A^+ R_m^T = R^{-1} (H^T R_m^T)(0:k0, :), H the QR's reflectors.
@@ -861,6 +862,8 @@ __global__ __launch_bounds__(kCoreThreads) void k_core(CoreArgs a) {
       a.trace.nJ[kp] = nJp;
       a.trace.rank[kp] = r;
       a.trace.ind[kp] = INFINITY;
+      a.trace.branch[kp] = branch ? 1 : 0;
+      a.trace.route[kp] = qr_route ? 0 : 1;
     }
   }
 }
@@ -969,7 +972,8 @@ __global__ __launch_bounds__(kCoreThreads) void k_core_warm(CoreArgs a) {
   __shared__ double sig[kPMax], tau[kPMax], vbq[2 * kPMax];
   __shared__ int ord[kPMax], flags[2];
   const int t = threadIdx.x;
-  const int rF = st->rF;
+  // the width of the start: the right-hand side's rank, or the guess's columns
+  const int rF = a.guess ? st->ncols[0] : st->rF;
   const int pm = a.pmax;
   for (int e = t; e < rF * rF; e += blockDim.x) {
     const int i = e % rF, j = e / rF;
@@ -979,6 +983,11 @@ __global__ __launch_bounds__(kCoreThreads) void k_core_warm(CoreArgs a) {
   }
   __syncthreads();
   const int r = svd_qr(B3, rF, rF, (double)rF, B0, B1, B2, tau, vbq, sig, ord, flags);
+  // a zero guess leaves the start from the right-hand side in place
+  if (a.guess && r == 0) {
+    if (t == 0) st->guess_ok = 0;
+    return;
+  }
   for (int e = t; e < r * pm; e += blockDim.x) {
     const int i = e % pm, rr = e / pm;
     a.Uhat[i + (int64_t)rr * pm] = i < rF ? B2[i + rr * LDP] : 0.0;
@@ -986,6 +995,7 @@ __global__ __launch_bounds__(kCoreThreads) void k_core_warm(CoreArgs a) {
   }
   if (t < kPMax) st->S[0][t] = t < r ? sig[ord[t]] : 0.0;
   __syncthreads();
+  if (t == 0 && a.guess) st->guess_ok = 1;
   if (t == 0) {
     st->r[0] = r;
     st->nIb[0] = 0;
@@ -1017,8 +1027,10 @@ int core_launch(const CoreArgs& a, bool warm, hipStream_t s) {
 // ----------------------------------------------------------------------------------------
 // Set-up, input scan and final truncation
 // ----------------------------------------------------------------------------------------
-__global__ void k_init_state(DevState* st, int rF, double eps, double tau) {
+__global__ void k_init_state(DevState* st, int rF, double eps, double tau, int replay_n) {
   if (threadIdx.x != 0) return;
+  st->replay_n = replay_n;
+  st->guess_ok = 0;
   st->done = 0;
   st->status = LRP_NOT_CONVERGED;
   st->k = 0;
@@ -1045,8 +1057,20 @@ __global__ void k_init_state(DevState* st, int rF, double eps, double tau) {
   st->indb[0] = st->indb[1] = INFINITY;
 }
 
-int init_state_launch(DevState* st, int rF, double eps, double tau, hipStream_t s) {
-  LRP_LAUNCH(K_INIT, k_init_state, dim3(1), dim3(64), 0, s, st, rF, eps, tau);
+int init_state_launch(DevState* st, int rF, double eps, double tau, int replay_n, hipStream_t s) {
+  LRP_LAUNCH(K_INIT, k_init_state, dim3(1), dim3(64), 0, s, st, rF, eps, tau, replay_n);
+  return launch_status();
+}
+
+__global__ void k_guess_begin(DevState* st, int r0) {
+  if (threadIdx.x != 0 || st->done) return;
+  st->ncols[0] = r0;
+  st->ncols[1] = r0;
+  st->guess_ok = 0;
+}
+
+int guess_begin_launch(DevState* st, int r0, hipStream_t s) {
+  LRP_LAUNCH(K_INIT, k_guess_begin, dim3(1), dim3(64), 0, s, st, r0);
   return launch_status();
 }
 
@@ -1059,7 +1083,7 @@ __global__ void k_scan(DevState* st, const double* U, int64_t ldu, const double*
     const int64_t i = e % n, c = e / n;
     bad |= !isfinite(U[i + c * ldu]) || !isfinite(V[i + c * ldv]);
   }
-  if (blockIdx.x == 0 && threadIdx.x < rF) bad |= !isfinite(sig[threadIdx.x]);
+  if (sig && blockIdx.x == 0 && threadIdx.x < rF) bad |= !isfinite(sig[threadIdx.x]);
   if (bad) {
     st->status = LRP_ENUMERIC;
     st->done = 1;

@@ -38,6 +38,13 @@ struct lrp_ctx {
   double* Vit[2] = {nullptr, nullptr};
   double *Uhat = nullptr, *Vtil = nullptr;
   TraceBuf trace{};
+  // replay (lrp_set_index_sets): sets of passes 0 .. replay_n-1, device copies
+  lrp::ReplayBuf replay{};
+  int replay_n = 0;
+  // initial guess of the next solve (lrp_set_guess); r0 = 0: none
+  int guess_r0 = 0;
+  const double *guess_U = nullptr, *guess_S = nullptr, *guess_V = nullptr;
+  int64_t guess_ldu = 0, guess_ldv = 0;
   DstPlan dst{};
   TsqrPlan tsqr{};
   SelectPlan sel{};

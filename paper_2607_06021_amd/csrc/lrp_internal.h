@@ -34,6 +34,8 @@ struct DevState {
   int r_sig;    // leading singular vectors used by the next selection
   int r_final;  // rank of the returned solution
   int eta_need;  // 1: the last core passed the cheap bound on the indicator (a stop is possible)
+  int replay_n;  // passes 0 .. replay_n-1 take their index sets from the replay buffers
+  int guess_ok;  // 1: the initial guess was nonzero and replaced the start from the right-hand side
   double nrm, ind, rho, eta1, eta2;
   double eps;   // effective tolerance
   double tau;   // prune threshold
@@ -58,6 +60,16 @@ struct TraceBuf {
   int* rank;
   double* ind;
   double* rho;
+  int* branch;  // 1: |J| <= |I| (the core solves with Q(I,:)); 0: with Z(J,:)
+  int* route;   // pseudo-inverse of the core: 0 Householder QR (left inverse), 1 Jacobi SVD with cutoff
+};
+
+// Index sets given for the first passes of a solve (replay): maxiter x kPMax entries per side.
+struct ReplayBuf {
+  int* I;
+  int* J;
+  int* nI;  // maxiter
+  int* nJ;
 };
 
 // One level of the TSQR tree, two independent sides per launch.

@@ -129,6 +129,8 @@ struct CoreArgs {
   int nb;            // iterate buffer written by this pass
   TraceBuf trace;    // row = the device pass counter
   int maxiter;
+  int guess;         // warm start only: 1 = from the initial guess (width st->ncols[0]; a zero
+                     // guess leaves the start from the right-hand side in place)
 };
 int core_launch(const CoreArgs& a, bool warm, hipStream_t s);
 
@@ -143,6 +145,7 @@ struct ProdArgs {
   int64_t ldo;
   int64_t n;
   int nb;              // buffer index whose rank st->r[nb] gives the columns
+  int gate_guess;      // 1: run only if st->guess_ok (the product of a warm start from a guess)
 };
 int prod_launch(const ProdArgs& a, hipStream_t s);
 
@@ -182,6 +185,7 @@ struct SelectArgs {
   const int* ci[2];
   int pmax;
   TraceBuf trace;
+  ReplayBuf replay;     // sets of passes k < st->replay_n
 };
 int select_update(const SelectArgs& a, hipStream_t s);
 
@@ -209,7 +213,9 @@ int rho_launch(const RhoPlan& p, const RhoArgs& a, hipStream_t s);
 int scan_inputs_launch(DevState* st, const double* U, int64_t ldu, const double* V, int64_t ldv,
                        const double* sig, int64_t n, int rF, hipStream_t s);
 int finalize_launch(DevState* st, double* S_out, int r_max, hipStream_t s);
-int init_state_launch(DevState* st, int rF, double eps, double tau, hipStream_t s);
+int init_state_launch(DevState* st, int rF, double eps, double tau, int replay_n, hipStream_t s);
+// Warm start from a guess of r0 columns: QR widths r0, guess_ok cleared.
+int guess_begin_launch(DevState* st, int r0, hipStream_t s);
 int lambda_launch(double* lam, float* lam32, int64_t n, hipStream_t s);
 
 }  // namespace lrp

@@ -24,7 +24,7 @@ constexpr int kProdRowsPerBlock = 16 * kProdTilesPerWave * 4;  // 4 waves
 
 __global__ __launch_bounds__(256) void k_prod(ProdArgs a) {
   const DevState* st = a.st;
-  if (st->done) return;
+  if (st->done || (a.gate_guess && !st->guess_ok)) return;
   const int side = blockIdx.y;
   const int kin = st->ncols[side];
   const int r = st->r[a.nb];

@@ -218,20 +218,33 @@ __global__ __launch_bounds__(64) void k_select(SelectArgs a) {
     same = 1;
   }
   __syncthreads();
-  for (int side = 0; side < 2; ++side) {
-    const int nold = side == 0 ? nI : nJ;
-    const int take = max(0, min(min(rsig, a.pmax - nold), nv_s[side]));
-    // the new indices in ascending order: rank among the first `take` candidates
-    if (t < take) {
-      const int v = newv[side][t];
-      int rk = 0;
-      for (int q = 0; q < take; ++q) rk += newv[side][q] < v ? 1 : 0;
-      pre[side][nold + rk] = v;
+  const int kp = st->k;  // the pass being computed
+  if (kp < st->replay_n) {
+    // replay: the given sets are this pass's sets
+    const int rn[2] = {a.replay.nI[kp], a.replay.nJ[kp]};
+    for (int side = 0; side < 2; ++side) {
+      if (t < rn[side]) pre[side][t] = (side == 0 ? a.replay.I : a.replay.J)[kp * kPMax + t];
+      if (t == 0) {
+        take_s[side] = rn[side];
+        nold_s[side] = 0;
+      }
     }
-    if (t < nold) pre[side][t] = side == 0 ? oldI[t] : oldJ[t];
-    if (t == 0) {
-      take_s[side] = take;
-      nold_s[side] = nold;
+  } else {
+    for (int side = 0; side < 2; ++side) {
+      const int nold = side == 0 ? nI : nJ;
+      const int take = max(0, min(min(rsig, a.pmax - nold), nv_s[side]));
+      // the new indices in ascending order: rank among the first `take` candidates
+      if (t < take) {
+        const int v = newv[side][t];
+        int rk = 0;
+        for (int q = 0; q < take; ++q) rk += newv[side][q] < v ? 1 : 0;
+        pre[side][nold + rk] = v;
+      }
+      if (t < nold) pre[side][t] = side == 0 ? oldI[t] : oldJ[t];
+      if (t == 0) {
+        take_s[side] = take;
+        nold_s[side] = nold;
+      }
     }
   }
   __syncthreads();
@@ -258,7 +271,6 @@ __global__ __launch_bounds__(64) void k_select(SelectArgs a) {
     st->Jpre[t] = pre[1][t];
     st->Jprev[t] = pre[1][t];
   }
-  const int kp = st->k;  // the pass being computed
   a.trace.Ipre[kp * kPMax + t] = t < nIpre ? pre[0][t] : -1;
   a.trace.Jpre[kp * kPMax + t] = t < nJpre ? pre[1][t] : -1;
   if (t == 0) {

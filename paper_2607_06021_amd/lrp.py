@@ -105,8 +105,12 @@ def lib() -> ctypes.CDLL:
     L.lrp_get_index_sets.argtypes = [_c_vp, P(_c_i64), P(_c_i32), P(_c_i64), P(_c_i32)]
     L.lrp_get_index_sets.restype = ctypes.c_int
     L.lrp_get_trace.argtypes = [_c_vp, P(_c_i32), P(_c_i32), P(_c_i32), P(_c_i32), P(_c_i32), P(_c_i32),
-                                P(_c_i32), P(_c_i32), P(_c_dbl), P(_c_dbl)]
+                                P(_c_i32), P(_c_i32), P(_c_dbl), P(_c_dbl), P(_c_i32), P(_c_i32)]
     L.lrp_get_trace.restype = ctypes.c_int
+    L.lrp_set_guess.argtypes = [_c_vp, _c_i32, _c_vp, _c_i64, _c_vp, _c_vp, _c_i64]
+    L.lrp_set_guess.restype = ctypes.c_int
+    L.lrp_set_index_sets.argtypes = [_c_vp, _c_i32, P(_c_i64), P(_c_i32), P(_c_i64), P(_c_i32)]
+    L.lrp_set_index_sets.restype = ctypes.c_int
     L.lrp_destroy.argtypes = [_c_vp]
     L.lrp_destroy.restype = ctypes.c_int
     L.lrp_strerror.argtypes = [ctypes.c_int]
@@ -215,15 +219,30 @@ class Solver:
         return {arr[q].name.decode(): (int(arr[q].launches), float(arr[q].ms)) for q in range(min(cnt.value, cap))}
 
     # ------------------------------------------------------------------------------------
-    def solve(self, U_F, sigma, V_F, out=None):
+    def solve(self, U_F, sigma, V_F, out=None, guess=None):
         """Solve with F = U_F diag(sigma) V_F^T (FP64 CUDA tensors, factors column-major).
 
+        guess: optional (U0, S0, V0), the initial guess of Algorithm 4 in physical space
+        (column-major (n, r0) FP64 CUDA tensors; S0 a vector of r0 weights or None).
         Returns (U, S, V, rank, info): U, V are (n, r_max) column-major with zero columns
         beyond `rank`, S has r_max entries.
         """
         import torch
 
         n, rm = self.n, self.r_max
+        if guess is not None:
+            U0, S0, V0 = guess
+            p0, ld0 = _colmajor(U0, n)
+            q0, lq0 = _colmajor(V0, n)
+            if U0.shape[1] != V0.shape[1] or (S0 is not None and tuple(S0.shape) != (U0.shape[1],)):
+                raise ValueError("guess factors must have matching column counts")
+            for t in (U0, V0) + ((S0,) if S0 is not None else ()):
+                if t.dtype != torch.float64 or not t.is_cuda:
+                    raise ValueError("guess factors must be float64 CUDA tensors")
+            if S0 is not None and not S0.is_contiguous():
+                raise ValueError("S0 must be contiguous")
+            _check(lib().lrp_set_guess(self._h, U0.shape[1], p0, ld0, S0.data_ptr() if S0 is not None else None,
+                                       q0, lq0), "lrp_set_guess")
         rF = U_F.shape[1]
         pu, ldu = _colmajor(U_F, n)
         pv, ldv = _colmajor(V_F, n)
@@ -269,9 +288,9 @@ class Solver:
         cnt = _c_i32(m)
         Ip = (_c_i32 * (m * rm))()
         Jp = (_c_i32 * (m * rm))()
-        nIp, nJp, nI, nJ, rk = [(_c_i32 * m)() for _ in range(5)]
+        nIp, nJp, nI, nJ, rk, br, rt = [(_c_i32 * m)() for _ in range(7)]
         ind, rho = (_c_dbl * m)(), (_c_dbl * m)()
-        _check(lib().lrp_get_trace(self._h, ctypes.byref(cnt), Ip, nIp, Jp, nJp, nI, nJ, rk, ind, rho),
+        _check(lib().lrp_get_trace(self._h, ctypes.byref(cnt), Ip, nIp, Jp, nJp, nI, nJ, rk, ind, rho, br, rt),
                "lrp_get_trace")
         out = []
         for k in range(cnt.value):
@@ -284,8 +303,26 @@ class Solver:
                 "rank": rk[k],
                 "indicator": ind[k],
                 "rho": rho[k],
+                "branch": bool(br[k]),
+                "route": "qr" if rt[k] == 0 else "jacobi",
             })
         return out
+
+    def set_index_sets(self, sets):
+        """Replay: passes 0 .. len(sets)-1 of the following solves use sets[k] = (I, J) as their
+        index sets; an empty list switches replay off."""
+        m, rm = len(sets), self.r_max
+        I = (_c_i64 * max(1, m * rm))()
+        J = (_c_i64 * max(1, m * rm))()
+        nI = (_c_i32 * max(1, m))()
+        nJ = (_c_i32 * max(1, m))()
+        for k, (Ik, Jk) in enumerate(sets):
+            nI[k], nJ[k] = len(Ik), len(Jk)
+            for q, v in enumerate(Ik[:rm]):
+                I[k * rm + q] = int(v)
+            for q, v in enumerate(Jk[:rm]):
+                J[k * rm + q] = int(v)
+        _check(lib().lrp_set_index_sets(self._h, m, I, nI, J, nJ), "lrp_set_index_sets")
 
     def dst1(self, X, scale=None, mul: float = 1.0, precision: str = "fp64"):
         """Orthonormal DST-I of the columns of X (n x c, column-major FP64 CUDA tensor)."""

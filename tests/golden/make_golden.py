@@ -1,5 +1,7 @@
 """Write oracle results for the full-size n = 2^20 - 1 workload (the oracle needs minutes
-there). Calls only oracle/ and the seeded input generators.
+there): per-pass index sets, sizes, ranks, rho and indicator, the singular values, sampled
+rows of the factors and Gaussian sketches of the solution. Calls only oracle/ and the seeded
+input generators.
 
     python tests/golden/make_golden.py
 """
@@ -15,6 +17,10 @@ sys.path.insert(0, ROOT)
 
 import workloads  # noqa: E402
 from oracle import crossdeim as cd  # noqa: E402
+
+
+SKETCH_K = 64
+SKETCH_SEEDS = (777, 778)
 
 
 def main(name="n1048575_r30_fp64", seed=0, nrows=200):
@@ -39,11 +45,24 @@ def main(name="n1048575_r30_fp64", seed=0, nrows=200):
         "ranks": [t.rank for t in res.trace],
         "gapI": [t.gapI for t in res.trace],
         "gapJ": [t.gapJ for t in res.trace],
+        "rho": [t.rho for t in res.trace],
+        "indicator": [t.indicator for t in res.trace],
+        "eta1": [t.eta1 for t in res.trace],
+        "eta2": [t.eta2 for t in res.trace],
         "S": res.S.tolist(),
         "rows": rows.tolist(),
         "U_rows": res.U[rows].tolist(),
         "V_rows": res.V[rows].tolist(),
     }
+    # Gaussian sketches of the solution, A = Om^T U diag(S), B = Om'^T V: a solution W' is
+    # compared through ||Om^T (W' - W) Om'||_F / ||Om^T W Om'||_F (Om, Om' regenerated from
+    # the seeds by workloads.sketch_matrix)
+    for key, mat, sd in (("sketch_U", res.U * res.S[None, :], SKETCH_SEEDS[0]), ("sketch_V", res.V, SKETCH_SEEDS[1])):
+        Om = workloads.sketch_matrix(w.n, SKETCH_K, sd)
+        out[key] = (Om.T @ mat).tolist()
+        del Om
+    out["sketch_seeds"] = list(SKETCH_SEEDS)
+    out["sketch_k"] = SKETCH_K
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_seed{seed}.json")
     with open(path, "w") as f:
         json.dump(out, f)

@@ -13,7 +13,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(L.LIB_PATH), reason="liblrp.s
 def test_header_symbols_exported():
     names = L.header_functions()
     assert {"lrp_create", "lrp_solve", "lrp_destroy", "lrp_get_index_sets", "lrp_get_trace",
-            "lrp_strerror", "lrp_dst1", "lrp_tsqr"} <= set(names)
+            "lrp_strerror", "lrp_dst1", "lrp_tsqr", "lrp_set_guess", "lrp_set_index_sets"} <= set(names)
     lib = L.lib()
     for nm in names:
         assert hasattr(lib, nm), nm
@@ -48,7 +48,10 @@ def test_null_context_and_arguments():
     assert lib.lrp_solve(None, 2, None, 0, None, None, 0, None, 0, None, None, 0, ctypes.byref(r), None) == L.LRP_EINVAL
     assert lib.lrp_destroy(None) == L.LRP_OK
     cnt = ctypes.c_int32(4)
-    assert lib.lrp_get_trace(None, ctypes.byref(cnt), None, None, None, None, None, None, None, None, None) == L.LRP_EINVAL
+    assert lib.lrp_get_trace(None, ctypes.byref(cnt), None, None, None, None, None, None, None, None, None, None,
+                             None) == L.LRP_EINVAL
+    assert lib.lrp_set_guess(None, 1, None, 0, None, None, 0) == L.LRP_EINVAL
+    assert lib.lrp_set_index_sets(None, 1, None, None, None, None) == L.LRP_EINVAL
     assert lib.lrp_get_index_sets(None, None, None, None, None) == L.LRP_EINVAL
     assert lib.lrp_dst1(None, 1, None, 0, None, 0, None, 1.0, 0) == L.LRP_EINVAL
     assert lib.lrp_tsqr(None, 1, None, 0, None, 0, None, 0) == L.LRP_EINVAL

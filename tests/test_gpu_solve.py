@@ -35,11 +35,18 @@ def dev(a):
     return fortran(t) if a.ndim == 2 else t
 
 
-def gpu_solve(n, U, s, V, r_max, tol, maxiter, precision="fp64", prune_tau=0.0):
+def gpu_solve(n, U, s, V, r_max, tol, maxiter, precision="fp64", prune_tau=0.0, guess=None, replay=None):
+    """One solve through the C-ABI. guess: (U0, S0, V0) host arrays (S0 may be None);
+    replay: list of (I, J) sets for the first passes."""
     from paper_2607_06021_amd import Solver
 
     with Solver(n, r_max, tol, maxiter=maxiter, precision=precision, prune_tau=prune_tau) as sol:
-        Uo, So, Vo, r, info = sol.solve(dev(U), dev(s), dev(V))
+        if replay is not None:
+            sol.set_index_sets(replay)
+        g = None
+        if guess is not None:
+            g = (dev(guess[0]), None if guess[1] is None else dev(guess[1]), dev(guess[2]))
+        Uo, So, Vo, r, info = sol.solve(dev(U), dev(s), dev(V), guess=g)
         res = {
             "U": Uo[:, :r].cpu().numpy(),
             "S": So.cpu().numpy(),
@@ -54,7 +61,62 @@ def gpu_solve(n, U, s, V, r_max, tol, maxiter, precision="fp64", prune_tau=0.0):
     return res
 
 
-def compare_fp64(g, o, label):
+# rho = ||X_k - X_{k-1}||_F / ||S_k||_F: two iterates that each agree with the oracle's to the
+# FP64 result tolerance 1e-10 (relative Frobenius) move rho by at most 2e-10 (plus the
+# relative error of the norm, far below 1e-8).
+RHO_ABS, RHO_REL = 2e-10, 1e-8
+
+
+def oracle_spread(n, U, s, V, r_max, tol, maxiter, reps=2, **kw):
+    """Per-pass spread of the oracle's own rho and indicator when the right-hand side is
+    perturbed by 1e-15 relative (rounding of the inputs): max |change| over `reps` seeded
+    perturbations. Early passes of forced (replayed) index sets can be ill-conditioned, and
+    their rho then moves far more than the final result does."""
+    o = cd.solve(n, U, s, V, r_max, tol, maxiter, **kw)
+    spread = [[0.0, 0.0] for _ in o.trace]
+    for r in range(reps):
+        Up = U * (1.0 + 1e-15 * np.random.default_rng(r).standard_normal(U.shape))
+        p = cd.solve(n, Up, s, V, r_max, tol, maxiter, **kw)
+        for k, (a, b) in enumerate(zip(o.trace, p.trace)):
+            for q, (x, y) in enumerate(((a.rho, b.rho), (a.indicator, b.indicator))):
+                if math.isfinite(x) and math.isfinite(y):
+                    spread[k][q] = max(spread[k][q], abs(x - y))
+    return spread
+
+
+def compare_stop_values(g, o, label, spread=None):
+    """rho and the indicator of every pass where the GPU computed them (it skips them where the
+    stopping test cannot pass) against the oracle's values of the same pass.
+
+    The indicator is min(eta1 (1 + eta2), eta2 (1 + eta1)) S_min / ||S||_F with
+    eta = 1/sigma_min of the interpolation rows of the iterate's orthonormal basis. With both
+    iterates within 1e-10 ||S||_F of each other (the FP64 result tolerance): S_min moves by at
+    most 1e-10 ||S||_F (singular values are 1-Lipschitz in the Frobenius norm), a relative
+    change d = 1e-10 ||S||_F / S_min; the basis spans the iterate's column space, which moves
+    by an angle of about d, so sigma_min of its rows moves by about d and eta by a relative
+    d eta. The bound is twice the sum of these relative changes.
+
+    spread (optional, from oracle_spread): per pass, the oracle's own change under rounding of
+    its inputs; ten times it is added to each bound."""
+    for tg, to in zip(g["trace"], o.trace):
+        sp = spread[to.k] if spread is not None and to.k < len(spread) else (0.0, 0.0)
+        if math.isfinite(tg["rho"]):
+            d = abs(tg["rho"] - to.rho)
+            tol = RHO_ABS + RHO_REL * to.rho + 10.0 * sp[0]
+            print(f"  {label} pass {to.k}: rho gpu {tg['rho']:.6e} oracle {to.rho:.6e} diff {d:.1e} bound {tol:.1e}",
+                  flush=True)
+            assert d <= tol, f"pass {to.k} rho"
+        if math.isfinite(tg["indicator"]):
+            smin_rel = float(to.S[-1]) / float(np.linalg.norm(to.S))
+            d_rel = 1e-10 / smin_rel
+            tol = to.indicator * (2.0 * d_rel * (1.0 + to.eta1 + to.eta2) + 1e-8) + 10.0 * sp[1]
+            d = abs(tg["indicator"] - to.indicator)
+            print(f"  {label} pass {to.k}: indicator gpu {tg['indicator']:.6e} oracle {to.indicator:.6e} "
+                  f"diff {d:.1e} bound {tol:.1e}", flush=True)
+            assert d <= tol, f"pass {to.k} indicator"
+
+
+def compare_fp64(g, o, label, spread=None):
     info = g["info"]
     print(f"{label}: status {info['status']}/{o.status} iters {info['iters']}/{o.iters} rank {g['rank']}/{o.rank}",
           flush=True)
@@ -68,10 +130,12 @@ def compare_fp64(g, o, label):
         assert tg["I_pre"] == to.I_pre and tg["J_pre"] == to.J_pre, f"pass {to.k}"
         assert tg["nI"] == len(to.I) and tg["nJ"] == len(to.J), f"pass {to.k} pruning"
         assert tg["rank"] == to.rank, f"pass {to.k} rank"
+        assert tg["branch"] == to.branch, f"pass {to.k} branch of Algorithm 1"
     assert info["status"] == o.status
     assert info["iters"] == o.iters
     assert g["rank"] == o.rank
     assert g["sets"] == (o.I, o.J)
+    compare_stop_values(g, o, label, spread)
     e = cd.rel_err((g["U"], g["S"][: g["rank"]], g["V"]), (o.U, o.S, o.V))
     print(f"  rel err vs oracle {e:.3e}  gpu ms {info['ms']:.3f}")
     assert e <= 1e-10
@@ -111,15 +175,20 @@ def test_n65535_fp64_parity():
 
 
 def test_n65535_mixed_error():
+    """Mixed precision against the FP64 oracle and against the GPU's own FP64 path (both at the
+    1e-5 tolerance of the mixed path)."""
     w = workloads.CONFIGS["n65535_r20_mixed"]
     U, s, V = workloads.make(w, 0)
     print(f"solve {w.name} seed 0", flush=True)
     o = cd.solve(w.n, U, s, V, w.r_max, w.tol, w.maxiter)
     g = gpu_solve(w.n, U, s, V, w.r_max, w.tol, w.maxiter, precision="mixed")
+    g64 = gpu_solve(w.n, U, s, V, w.r_max, w.tol, w.maxiter, precision="fp64")
     e = cd.rel_err((g["U"], g["S"][: g["rank"]], g["V"]), (o.U, o.S, o.V))
+    e64 = cd.rel_err((g["U"], g["S"][: g["rank"]], g["V"]), (g64["U"], g64["S"][: g64["rank"]], g64["V"]))
     print(f"  mixed: status {g['info']['status']} iters {g['info']['iters']} rank {g['rank']} "
-          f"rel err vs FP64 oracle {e:.3e}")
+          f"rel err vs FP64 oracle {e:.3e}, vs GPU FP64 path {e64:.3e}")
     assert e <= 1e-5
+    assert e64 <= 1e-5
 
 
 @pytest.mark.parametrize("n", [255, 65535])
@@ -266,14 +335,36 @@ def test_profile_mode_same_result_and_kernel_times(precision):
     assert 0.5 * info.ms < total < 1.05 * info.ms
 
 
-def test_n1048575_fp64_against_golden():
-    """Full-size n = 2^20 - 1: the oracle takes minutes, so its index sets, ranks, singular
-    values and sampled rows were stored by tests/golden/make_golden.py (oracle only)."""
+def load_golden():
     path = os.path.join(GOLDEN, "n1048575_r30_fp64_seed0.json")
     if not os.path.exists(path):
         pytest.skip("golden file not generated")
     with open(path) as f:
-        gold = json.load(f)
+        return json.load(f)
+
+
+def sketched_rel_err(n, U, S, V, gold):
+    """||Om^T (W - W_o) Om'||_F / ||Om^T W_o Om'||_F with W = U diag(S) V^T and the oracle's
+    sketches A_o = Om^T U_o diag(S_o), B_o = Om'^T V_o. For Gaussian Om, Om' (k columns) the
+    squared sketched norm of a matrix is k^2 times its squared Frobenius norm in expectation,
+    so the ratio estimates the relative Frobenius error."""
+    k = gold["sketch_k"]
+    Om = workloads.sketch_matrix(n, k, gold["sketch_seeds"][0])
+    A = Om.T @ (U * S[None, :])
+    del Om
+    Om = workloads.sketch_matrix(n, k, gold["sketch_seeds"][1])
+    B = Om.T @ V
+    del Om
+    Ao, Bo = np.array(gold["sketch_U"]), np.array(gold["sketch_V"])
+    ref = Ao @ Bo.T
+    return float(np.linalg.norm(A @ B.T - ref) / np.linalg.norm(ref))
+
+
+def test_n1048575_fp64_against_golden():
+    """Full-size n = 2^20 - 1: the oracle takes minutes, so its per-pass index sets, ranks, rho
+    and indicator, its singular values, sampled rows and Gaussian sketches of its solution were
+    stored by tests/golden/make_golden.py (oracle only)."""
+    gold = load_golden()
     w = workloads.CONFIGS["n1048575_r30_fp64"]
     U, s, V = workloads.make(w, 0)
     print(f"solve {w.name} seed 0 (golden)", flush=True)
@@ -292,3 +383,27 @@ def test_n1048575_fp64_against_golden():
     err = np.max(np.abs(Wg - Wo)) / np.max(np.abs(Wo))
     print(f"  sampled entries max rel err {err:.2e}")
     assert err <= 1e-9
+    for k, tg in enumerate(g["trace"]):
+        if math.isfinite(tg["rho"]):
+            print(f"  pass {k}: rho gpu {tg['rho']:.6e} oracle {gold['rho'][k]:.6e}")
+            assert abs(tg["rho"] - gold["rho"][k]) <= RHO_ABS + RHO_REL * gold["rho"][k]
+    es = sketched_rel_err(w.n, g["U"], S, g["V"], gold)
+    print(f"  sketched relative Frobenius error {es:.2e}")
+    assert es <= 1e-10
+
+
+def test_n1048575_mixed_against_golden_and_fp64():
+    """The mixed path at n = 2^20 - 1: error against the oracle (through its stored sketches)
+    and against the GPU's FP64 path (exact, in factored form), both <= 1e-5."""
+    gold = load_golden()
+    w = workloads.CONFIGS["n1048575_r30_mixed"]
+    U, s, V = workloads.make(w, 0)
+    print(f"solve {w.name} seed 0 (golden)", flush=True)
+    gm = gpu_solve(w.n, U, s, V, w.r_max, w.tol, w.maxiter, precision="mixed")
+    g64 = gpu_solve(w.n, U, s, V, w.r_max, w.tol, w.maxiter, precision="fp64")
+    rm, r64 = gm["rank"], g64["rank"]
+    es = sketched_rel_err(w.n, gm["U"], gm["S"][:rm], gm["V"], gold)
+    e64 = cd.rel_err((gm["U"], gm["S"][:rm], gm["V"]), (g64["U"], g64["S"][:r64], g64["V"]))
+    print(f"  mixed: status {gm['info']['status']} iters {gm['info']['iters']} rank {rm}; "
+          f"sketched error vs oracle {es:.2e}, vs GPU FP64 {e64:.2e}; ms {gm['info']['ms']:.2f}")
+    assert es <= 1e-5 and e64 <= 1e-5

@@ -32,6 +32,7 @@ __all__ = [
     "sine_rhs",
     "make",
     "served_stream",
+    "sketch_matrix",
 ]
 
 
@@ -209,3 +210,10 @@ def served_stream(
         Request(i, float(t[i]), int(ns[i]), int(ranks[i]), "mixed" if mixed[i] else "fp64", 1000 + i)
         for i in range(count)
     ]
+
+
+def sketch_matrix(n: int, k: int = 64, seed: int = 777) -> np.ndarray:
+    """Seeded n x k standard Gaussian test matrix (C order), for comparing two low-rank
+    solutions at sizes where the n x n product cannot be formed: ||Om^T (A - B) Om'||_F
+    estimates ||A - B||_F up to the factor k."""
+    return np.random.default_rng(seed).standard_normal((n, k))
