@@ -44,7 +44,9 @@ enum lrp_status {
   LRP_EINVAL = -1,       /* bad argument: sizes, null or overlapping pointers, n+1 not a power of two */
   LRP_ENOMEM = -2,       /* device allocation failed in lrp_create */
   LRP_EDEVICE = -3,      /* a HIP call failed */
-  LRP_ENUMERIC = -4      /* NaN or Inf in the right-hand side factors */
+  LRP_ENUMERIC = -4,     /* NaN or Inf in the right-hand side factors */
+  LRP_ESIZE = -5         /* the problem needs more workspace than the fixed workspace of an
+                            entry point that allocates nothing (lrp_tsqr_noalloc) */
 };
 
 enum lrp_precision {
@@ -233,6 +235,31 @@ int lrp_dst1(lrp_ctx* ctx, int32_t ncols, const double* X, int64_t ldx, double* 
  */
 int lrp_tsqr(lrp_ctx* ctx, int32_t ncols, const double* A, int64_t lda, double* Q, int64_t ldq,
              double* R, int64_t ldr);
+
+/*
+ * lrp_tsqr_noalloc -- the thin QR of lrp_tsqr without a context and without any device or host
+ * allocation, for callers that cannot allocate: code under HIP graph capture, tight serving
+ * loops and harnesses that forbid hipMalloc. The tree's workspace (Householder vectors, their
+ * scalars and the stacked R factors of every level, and the intermediate Q pieces) is a fixed
+ * static device array of lrp_tsqr_noalloc_max_bytes() bytes (32 MiB) on each GPU the library
+ * runs on, held until the process ends. It holds about 1.7 n ncols doubles at 64 columns
+ * (largest n: 32661 at 64 columns, 91392 at 32, 217600 at 16, 4129344 at 1 column).
+ *   n      rows, 1 <= n; ncols columns, 1 <= ncols <= 64, ncols <= n.
+ *   A      device, n x ncols, ld lda >= n (read).
+ *   Q      device, n x ncols, ld ldq >= n (written; orthonormal columns); must not overlap A.
+ *   R      device, ncols x ncols, ld ldr >= ncols (written; upper triangular, zeros below).
+ *   stream hipStream_t the work is ordered on (NULL: the null stream).
+ * Asynchronous: enqueues the kernels on stream and returns. Every call on one GPU shares that
+ * GPU's workspace (each call writes every workspace element it reads, so nothing carries over
+ * from an earlier call), so calls whose work can overlap on one GPU race: order them on one
+ * stream or synchronize between them. Returns LRP_OK, LRP_EINVAL (arguments), LRP_ESIZE (the
+ * workspace for n x ncols exceeds the fixed size) or LRP_EDEVICE; nothing is enqueued on error.
+ */
+int lrp_tsqr_noalloc(int64_t n, int32_t ncols, const double* A, int64_t lda, double* Q, int64_t ldq,
+                     double* R, int64_t ldr, void* stream);
+
+/* lrp_tsqr_noalloc_max_bytes -- size in bytes of lrp_tsqr_noalloc's fixed per-GPU workspace. */
+int64_t lrp_tsqr_noalloc_max_bytes(void);
 
 /* ---------------------------------------------------------------------------------------
  * Serving: a solve queue with continuous admission.

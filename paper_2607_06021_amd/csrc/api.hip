@@ -736,6 +736,7 @@ const char* lrp_strerror(int code) {
     case LRP_ENOMEM: return "device allocation failed";
     case LRP_EDEVICE: return "HIP runtime error";
     case LRP_ENUMERIC: return "non-finite input or degenerate fibers";
+    case LRP_ESIZE: return "problem larger than the fixed workspace of the allocation-free entry point";
     default: return "unknown status";
   }
 }

@@ -8,6 +8,8 @@
 // piece of the parent level's Q.
 //
 // Two sides (e.g. C and R^T) are processed by the same launch (blockIdx.y).
+#include <mutex>
+
 #include "lrp_kernels.h"
 
 namespace lrp {
@@ -568,8 +570,14 @@ __global__ __launch_bounds__(kWyThreads) void k_tsqr_apply_wy(ApplyArgs a) {
 }
 
 // ----------------------------------------------------------------------------------------
-int tsqr_plan(TsqrPlan* p, int64_t n, int pmax) {
-  if (pmax < 1 || pmax > kPMax) return LRP_EINVAL;
+// Tree layout: level 0 factors n rows in blocks of kTsqrRows; each level above stacks the R
+// factors of g = kTsqrRows / pmax blocks. `get(bytes)` supplies each buffer (nullptr: failure);
+// buffers of sides >= nsides, and level 0's Y when Q is written to the caller's matrix
+// (level0_y false), are not requested.
+template <typename Get>
+static int tsqr_layout(TsqrPlan* p, int64_t n, int pmax, int nsides, bool level0_y, Get&& get) {
+  if (pmax < 1 || pmax > kPMax || n < 1) return LRP_EINVAL;
+  *p = TsqrPlan{};
   p->n = n;
   p->pmax = pmax;
   int64_t rows = n;
@@ -582,17 +590,15 @@ int tsqr_plan(TsqrPlan* p, int64_t n, int pmax) {
     lv.rows = rows;
     lv.block_rows = br;
     lv.nblocks = (int)((rows + br - 1) / br);
-    for (int s = 0; s < 2; ++s) {
-      size_t vb = sizeof(double) * (size_t)rows * pmax;
-      size_t tb = sizeof(double) * (size_t)lv.nblocks * pmax;
-      size_t rb = sizeof(double) * (size_t)lv.nblocks * pmax * pmax;
-      if (hipMalloc(&lv.V[s], vb) != hipSuccess) return LRP_ENOMEM;
-      if (hipMalloc(&lv.tau[s], tb) != hipSuccess) return LRP_ENOMEM;
-      if (hipMalloc(&lv.Rout[s], rb) != hipSuccess) return LRP_ENOMEM;
-      if (hipMalloc(&lv.Y[s], vb) != hipSuccess) return LRP_ENOMEM;
+    for (int s = 0; s < nsides; ++s) {
+      const size_t vb = sizeof(double) * (size_t)rows * pmax;
+      const size_t tb = sizeof(double) * (size_t)lv.nblocks * pmax;
+      const size_t rb = sizeof(double) * (size_t)lv.nblocks * pmax * pmax;
       // no initialisation: every element of R that is read (columns below the active width,
       // all pmax rows) is written by the factorization first. (A plain memset here would run
       // on the null stream, unordered with the context's non-blocking stream.)
+      if (!(lv.V[s] = get(vb)) || !(lv.tau[s] = get(tb)) || !(lv.Rout[s] = get(rb))) return LRP_ENOMEM;
+      if ((L > 0 || level0_y) && !(lv.Y[s] = get(vb))) return LRP_ENOMEM;
     }
     ++L;
     if (lv.nblocks == 1) break;
@@ -601,6 +607,13 @@ int tsqr_plan(TsqrPlan* p, int64_t n, int pmax) {
   }
   p->nlevels = L;
   return LRP_OK;
+}
+
+int tsqr_plan(TsqrPlan* p, int64_t n, int pmax) {
+  return tsqr_layout(p, n, pmax, 2, true, [](size_t bytes) -> double* {
+    void* q = nullptr;
+    return hipMalloc(&q, bytes) == hipSuccess ? (double*)q : nullptr;
+  });
 }
 
 int tsqr_run(const TsqrPlan& p, const TsqrIO& io, hipStream_t s) {
@@ -660,4 +673,93 @@ int tsqr_run(const TsqrPlan& p, const TsqrIO& io, hipStream_t s) {
   return launch_status();
 }
 
+// ----------------------------------------------------------------------------------------
+// The QR without allocation: the tree's workspace is a static device array (one copy per GPU,
+// held until the process ends), found once per device with hipGetSymbolAddress. The host never
+// uses the array's name as an address; kernels get the device pointer.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+static int scratch_ptr(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return LRP_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LRP_EDEVICE;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return LRP_OK;
+}
+
+// Workspace bytes of a one-sided tree for n rows and p columns (each buffer 256-byte aligned).
+static size_t tsqr_noalloc_bytes(int64_t n, int p, int* rc) {
+  size_t total = 0;
+  TsqrPlan plan;
+  *rc = tsqr_layout(&plan, n, p, 1, false, [&](size_t bytes) -> double* {
+    total += (bytes + 255) & ~size_t(255);
+    return reinterpret_cast<double*>(256);  // any non-null value: nothing is dereferenced
+  });
+  return total;
+}
+
+__global__ void k_copy_r(const double* __restrict__ src, int lds, int p, double* __restrict__ R, int64_t ldr) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= p * p) return;
+  const int i = e % p, j = e / p;
+  R[i + (int64_t)j * ldr] = i <= j ? src[i + (int64_t)j * lds] : 0.0;
+}
+
 }  // namespace lrp
+
+extern "C" {
+
+int64_t lrp_tsqr_noalloc_max_bytes(void) { return (int64_t)lrp::kScratchBytes; }
+
+int lrp_tsqr_noalloc(int64_t n, int32_t ncols, const double* A, int64_t lda, double* Q, int64_t ldq, double* R,
+                     int64_t ldr, void* stream) {
+  using namespace lrp;
+  if (!A || !Q || !R || n < 1 || ncols < 1 || ncols > kPMax || ncols > n) return LRP_EINVAL;
+  if (lda < n || ldq < n || ldr < ncols) return LRP_EINVAL;
+  const uintptr_t a0 = (uintptr_t)A, a1 = a0 + (uintptr_t)(((ncols - 1) * lda + n) * 8);
+  const uintptr_t q0 = (uintptr_t)Q, q1 = q0 + (uintptr_t)(((ncols - 1) * ldq + n) * 8);
+  if (a0 < q1 && q0 < a1) return LRP_EINVAL;
+  int rc = LRP_OK;
+  const size_t need = tsqr_noalloc_bytes(n, ncols, &rc);
+  if (rc != LRP_OK) return LRP_EINVAL;
+  if (need > kScratchBytes) return LRP_ESIZE;
+  void* base = nullptr;
+  rc = scratch_ptr(&base);
+  if (rc != LRP_OK) return rc;
+  unsigned char* cur = static_cast<unsigned char*>(base);
+  TsqrPlan plan;
+  rc = tsqr_layout(&plan, n, ncols, 1, false, [&](size_t bytes) -> double* {
+    double* q = reinterpret_cast<double*>(cur);
+    cur += (bytes + 255) & ~size_t(255);
+    return q;
+  });
+  if (rc != LRP_OK) return rc;
+  TsqrIO io{};
+  io.st = nullptr;
+  io.ncols[0] = ncols;
+  io.ncols[1] = 0;
+  io.nsides = 1;
+  io.X[0] = A;
+  io.x_f32 = 0;
+  io.ldx = lda;
+  io.Q[0] = Q;
+  io.ldq = ldq;
+  hipStream_t s = (hipStream_t)stream;
+  rc = tsqr_run(plan, io, s);
+  if (rc != LRP_OK) return rc;
+  const int pp = ncols * ncols;
+  hipLaunchKernelGGL(k_copy_r, dim3((pp + 255) / 256), dim3(256), 0, s, tsqr_R(plan, 0), ncols, ncols, R, ldr);
+  return launch_status();
+}
+
+}  // extern "C"

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "liblrp.so")
 HEADER = os.path.join(HERE, "..", "include", "lrp.h")
 
 LRP_OK, LRP_NOT_CONVERGED, LRP_STAGNATED = 0, 1, 2
-LRP_EINVAL, LRP_ENOMEM, LRP_EDEVICE, LRP_ENUMERIC = -1, -2, -3, -4
+LRP_EINVAL, LRP_ENOMEM, LRP_EDEVICE, LRP_ENUMERIC, LRP_ESIZE = -1, -2, -3, -4, -5
 LRP_FP64, LRP_MIXED = 0, 1
 
 _c_i32 = ctypes.c_int32
@@ -137,6 +137,10 @@ def lib() -> ctypes.CDLL:
     L.lrp_context_bytes.restype = ctypes.c_int64
     L.lrp_get_profile.argtypes = [_c_vp, P(_c_i32), P(KernelTime)]
     L.lrp_get_profile.restype = ctypes.c_int
+    L.lrp_tsqr_noalloc.argtypes = [_c_i64, _c_i32, _c_vp, _c_i64, _c_vp, _c_i64, _c_vp, _c_i64, _c_vp]
+    L.lrp_tsqr_noalloc.restype = ctypes.c_int
+    L.lrp_tsqr_noalloc_max_bytes.argtypes = []
+    L.lrp_tsqr_noalloc_max_bytes.restype = ctypes.c_int64
     _LIB = L
     return L
 
