@@ -139,13 +139,15 @@ int lrp_get_index_sets(const lrp_ctx* ctx, int64_t* I, int32_t* nI, int64_t* J, 
  *               solves with Z(J,:);
  *   route       host, count: how the core's pseudo-inverse was formed: 0 through a Householder
  *               QR (a bound showed that the cutoff drops no singular value, so the pseudo-inverse
- *               is the left inverse), 1 through a Jacobi SVD with the cutoff.
+ *               is the left inverse), 1 through a Jacobi SVD with the cutoff;
+ *   sweeps      host, count: one-sided Jacobi sweeps of the SVD of the pass's core (the last
+ *               sweep makes no rotation).
  *   count       host in/out: capacity in passes on input, passes recorded on output.
  * Any array pointer may be NULL. Returns LRP_OK or LRP_EINVAL.
  */
 int lrp_get_trace(const lrp_ctx* ctx, int32_t* count, int32_t* Ipre, int32_t* nIpre, int32_t* Jpre,
                   int32_t* nJpre, int32_t* nI, int32_t* nJ, int32_t* rank, double* indicator,
-                  double* rho, int32_t* branch, int32_t* route);
+                  double* rho, int32_t* branch, int32_t* route, int32_t* sweeps);
 
 /*
  * lrp_set_guess -- the initial guess U0, V0 of Algorithm 4 (its signature takes them as input;

@@ -86,6 +86,7 @@ void free_ctx(lrp_ctx* c) {
   dfree(c->trace.rho);
   dfree(c->trace.branch);
   dfree(c->trace.route);
+  dfree(c->trace.sweeps);
   dfree(c->replay.I);
   dfree(c->replay.J);
   dfree(c->replay.nI);
@@ -180,6 +181,7 @@ int create_impl(lrp_ctx* c) {
   TRY(dalloc(&c->trace.rho, mi));
   TRY(dalloc(&c->trace.branch, mi));
   TRY(dalloc(&c->trace.route, mi));
+  TRY(dalloc(&c->trace.sweeps, mi));
   TRY(dalloc(&c->replay.I, mi * kPMax));
   TRY(dalloc(&c->replay.J, mi * kPMax));
   TRY(dalloc(&c->replay.nI, mi));
@@ -660,7 +662,7 @@ int64_t context_bytes(int64_t n, int pm, int maxiter, bool mixed) {
   b += mixed ? 4 * 4 * np : 4 * 8 * np;                            // U^, V^, C, R^T
   b += 6 * 8 * np;                                                 // Q, Z, two iterates per side
   b += 2 * 8 * (int64_t)pm * pm;                                   // U^, V~ coefficients
-  b += (int64_t)maxiter * (2 * kPMax * 4 + 7 * 4 + 2 * 8);         // trace
+  b += (int64_t)maxiter * (2 * kPMax * 4 + 8 * 4 + 2 * 8);         // trace
   b += (int64_t)maxiter * (2 * kPMax * 4 + 2 * 4);                 // replay sets
   DstPlan dp{};
   if (dst_plan(&dp, n, 2 * pm) == LRP_OK) {
@@ -834,7 +836,7 @@ int lrp_get_index_sets(const lrp_ctx* c, int64_t* I, int32_t* nI, int64_t* J, in
 
 int lrp_get_trace(const lrp_ctx* c, int32_t* count, int32_t* Ipre, int32_t* nIpre, int32_t* Jpre,
                   int32_t* nJpre, int32_t* nI, int32_t* nJ, int32_t* rank, double* indicator,
-                  double* rho, int32_t* branch, int32_t* route) {
+                  double* rho, int32_t* branch, int32_t* route, int32_t* sweeps) {
   if (!c || !c->solved || !count || *count < 0) return LRP_EINVAL;
   const int avail = std::min(c->st_host->k, c->maxiter);
   const int m = std::min(*count, avail);
@@ -860,7 +862,7 @@ int lrp_get_trace(const lrp_ctx* c, int32_t* count, int32_t* Ipre, int32_t* nIpr
       cp(nI, t.nI, sizeof(int) * m) != hipSuccess || cp(nJ, t.nJ, sizeof(int) * m) != hipSuccess ||
       cp(rank, t.rank, sizeof(int) * m) != hipSuccess || cp(indicator, t.ind, sizeof(double) * m) != hipSuccess ||
       cp(rho, t.rho, sizeof(double) * m) != hipSuccess || cp(branch, t.branch, sizeof(int) * m) != hipSuccess ||
-      cp(route, t.route, sizeof(int) * m) != hipSuccess)
+      cp(route, t.route, sizeof(int) * m) != hipSuccess || cp(sweeps, t.sweeps, sizeof(int) * m) != hipSuccess)
     return LRP_EDEVICE;
   return LRP_OK;
 }

@@ -234,7 +234,7 @@ __device__ inline void jac_store(const JacProb& pr, int col, int li, const doubl
 // Every column pair is visited once per sweep, no two pairs of a round share a column, and no
 // barrier is needed inside a group round.
 template <bool WV>
-__device__ void jacobi_waves(JacProb* P, int nprob, int* flags) {
+__device__ int jacobi_waves(JacProb* P, int nprob, int* flags) {
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int q = (nprob == 2 && wv >= 8) ? 1 : 0;
   const int lw = wv - 8 * q;
@@ -247,7 +247,7 @@ __device__ void jacobi_waves(JacProb* P, int nprob, int* flags) {
   }
   if (kmax < 2) {
     __syncthreads();
-    return;
+    return 0;
   }
   const int ng = jac_groups(pr.k);
   const bool mine = pr.k >= 2 && lw < (ng >> 1) && (nprob == 2 || wv < 8);
@@ -255,7 +255,9 @@ __device__ void jacobi_waves(JacProb* P, int nprob, int* flags) {
   const double tol2 = tol * tol;
   double a[4], b[4], va[4], vb[4];
   bool active = true;
+  int sweeps = 0;
   for (int sweep = 0; sweep < 60; ++sweep) {
+    sweeps = sweep + 1;
     if (t < 2) flags[t] = 0;
     __syncthreads();
     bool rot = false;
@@ -312,15 +314,15 @@ __device__ void jacobi_waves(JacProb* P, int nprob, int* flags) {
     __syncthreads();
     if (!more) break;
   }
+  return sweeps;
 }
 
-__device__ void jacobi(JacProb* P, int nprob, int* flags) {
+// Returns the number of sweeps made (the last one made no rotation).
+__device__ int jacobi(JacProb* P, int nprob, int* flags) {
   bool wv = false;
   for (int x = 0; x < nprob; ++x) wv |= P[x].V != nullptr;
-  if (wv)
-    jacobi_waves<true>(P, nprob, flags);
-  else
-    jacobi_waves<false>(P, nprob, flags);
+  if (wv) return jacobi_waves<true>(P, nprob, flags);
+  return jacobi_waves<false>(P, nprob, flags);
 }
 
 // sig[c] = ||A(:, c)||, ord[r] = column of rank r (descending, ties to the smaller index).
@@ -642,10 +644,11 @@ __device__ void tri_norms(const double* QR, const double* Ri, int k, double* red
 // are Q V (reflectors applied to [V; 0]) and the right ones the normalized columns of W. Jacobi on
 // the triangular factor of a graded matrix needs far fewer sweeps than on the matrix itself.
 // Columns are sorted by singular value (ties to the smaller index) and truncated at
-// cut_mult eps sigma_1. Outputs: U^ (nJ x r) in Cb, V~ (nI x r) in Xb; returns r. Mb, Xb, Vq, Cb
-// are distinct 64 x 64 LDS buffers (Mb, Vq are overwritten); tau: kPMax, vbq: 2 kPMax doubles.
+// cut_mult eps sigma_1. Outputs: U^ (nJ x r) in Cb, V~ (nI x r) in Xb; returns r and the Jacobi
+// sweeps in *sweeps. Mb, Xb, Vq, Cb are distinct 64 x 64 LDS buffers (Mb, Vq are overwritten);
+// tau: kPMax, vbq: 2 kPMax doubles.
 __device__ __forceinline__ int svd_qr(double* Mb, int nJ, int nI, double cut_mult, double* Xb, double* Vq, double* Cb,
-                      double* tau, double* vbq, double* sig, int* ord, int* flags) {
+                      double* tau, double* vbq, double* sig, int* ord, int* flags, int* sweeps) {
   const int t = threadIdx.x;
   const bool tall = nJ >= nI;
   const int m = tall ? nJ : nI, k = tall ? nI : nJ;
@@ -662,7 +665,7 @@ __device__ __forceinline__ int svd_qr(double* Mb, int nJ, int nI, double cut_mul
   }
   __syncthreads();
   JacProb pr{Mb, k, k, Vq};
-  jacobi(&pr, 1, flags);
+  *sweeps = jacobi(&pr, 1, flags);
   norms_sorted(Mb, k, k, sig, ord);
   const double smax = k > 0 ? sig[ord[0]] : 0.0;
   int r = 0;
@@ -785,7 +788,8 @@ __global__ __launch_bounds__(kCoreThreads) void k_core(CoreArgs a) {
   // ---- truncated SVD of the core (M is B3): U^ -> B2, V~ -> B0
   double* Ub = B2;
   double* Vb = B0;
-  const int r = svd_qr(M, nJ, nI, cut_pinv, B0, B1, B2, tau, vbq, sig, ord, flags);
+  int sweeps = 0;
+  const int r = svd_qr(M, nJ, nI, cut_pinv, B0, B1, B2, tau, vbq, sig, ord, flags, &sweeps);
   // now Ub = U^ (nJ x r), Vb = V~ (nI x r), singular values sig[ord[0..r)]
   for (int e = t; e < r * pm; e += blockDim.x) {
     const int i = e % pm, rr = e / pm;
@@ -864,6 +868,7 @@ __global__ __launch_bounds__(kCoreThreads) void k_core(CoreArgs a) {
       a.trace.ind[kp] = INFINITY;
       a.trace.branch[kp] = branch ? 1 : 0;
       a.trace.route[kp] = qr_route ? 0 : 1;
+      a.trace.sweeps[kp] = sweeps;
     }
   }
 }
@@ -982,7 +987,8 @@ __global__ __launch_bounds__(kCoreThreads) void k_core_warm(CoreArgs a) {
     B3[i + j * LDP] = s;
   }
   __syncthreads();
-  const int r = svd_qr(B3, rF, rF, (double)rF, B0, B1, B2, tau, vbq, sig, ord, flags);
+  int sweeps = 0;
+  const int r = svd_qr(B3, rF, rF, (double)rF, B0, B1, B2, tau, vbq, sig, ord, flags, &sweeps);
   // a zero guess leaves the start from the right-hand side in place
   if (a.guess && r == 0) {
     if (t == 0) st->guess_ok = 0;

@@ -62,6 +62,7 @@ struct TraceBuf {
   double* rho;
   int* branch;  // 1: |J| <= |I| (the core solves with Q(I,:)); 0: with Z(J,:)
   int* route;   // pseudo-inverse of the core: 0 Householder QR (left inverse), 1 Jacobi SVD with cutoff
+  int* sweeps;  // one-sided Jacobi sweeps of the core's SVD
 };
 
 // Index sets given for the first passes of a solve (replay): maxiter x kPMax entries per side.

@@ -105,7 +105,7 @@ def lib() -> ctypes.CDLL:
     L.lrp_get_index_sets.argtypes = [_c_vp, P(_c_i64), P(_c_i32), P(_c_i64), P(_c_i32)]
     L.lrp_get_index_sets.restype = ctypes.c_int
     L.lrp_get_trace.argtypes = [_c_vp, P(_c_i32), P(_c_i32), P(_c_i32), P(_c_i32), P(_c_i32), P(_c_i32),
-                                P(_c_i32), P(_c_i32), P(_c_dbl), P(_c_dbl), P(_c_i32), P(_c_i32)]
+                                P(_c_i32), P(_c_i32), P(_c_dbl), P(_c_dbl), P(_c_i32), P(_c_i32), P(_c_i32)]
     L.lrp_get_trace.restype = ctypes.c_int
     L.lrp_set_guess.argtypes = [_c_vp, _c_i32, _c_vp, _c_i64, _c_vp, _c_vp, _c_i64]
     L.lrp_set_guess.restype = ctypes.c_int
@@ -292,9 +292,9 @@ class Solver:
         cnt = _c_i32(m)
         Ip = (_c_i32 * (m * rm))()
         Jp = (_c_i32 * (m * rm))()
-        nIp, nJp, nI, nJ, rk, br, rt = [(_c_i32 * m)() for _ in range(7)]
+        nIp, nJp, nI, nJ, rk, br, rt, sw = [(_c_i32 * m)() for _ in range(8)]
         ind, rho = (_c_dbl * m)(), (_c_dbl * m)()
-        _check(lib().lrp_get_trace(self._h, ctypes.byref(cnt), Ip, nIp, Jp, nJp, nI, nJ, rk, ind, rho, br, rt),
+        _check(lib().lrp_get_trace(self._h, ctypes.byref(cnt), Ip, nIp, Jp, nJp, nI, nJ, rk, ind, rho, br, rt, sw),
                "lrp_get_trace")
         out = []
         for k in range(cnt.value):
@@ -309,6 +309,7 @@ class Solver:
                 "rho": rho[k],
                 "branch": bool(br[k]),
                 "route": "qr" if rt[k] == 0 else "jacobi",
+                "sweeps": sw[k],
             })
         return out
 

@@ -49,7 +49,7 @@ def test_null_context_and_arguments():
     assert lib.lrp_destroy(None) == L.LRP_OK
     cnt = ctypes.c_int32(4)
     assert lib.lrp_get_trace(None, ctypes.byref(cnt), None, None, None, None, None, None, None, None, None, None,
-                             None) == L.LRP_EINVAL
+                             None, None) == L.LRP_EINVAL
     assert lib.lrp_set_guess(None, 1, None, 0, None, None, 0) == L.LRP_EINVAL
     assert lib.lrp_set_index_sets(None, 1, None, None, None, None) == L.LRP_EINVAL
     assert lib.lrp_get_index_sets(None, None, None, None, None) == L.LRP_EINVAL
