@@ -64,8 +64,21 @@ typedef struct lrp_opts {
                         (Algorithm 4); 0 -> 1e-12 (FP64) or 1e-7 (mixed) */
   void* stream;      /* hipStream_t to order all work on; NULL -> a stream owned by the context */
   int32_t flags;     /* bitwise OR of enum lrp_flags; other bits -> LRP_EINVAL */
-  int32_t reserved;  /* must be 0 */
+  int32_t selector;  /* enum lrp_selector: how each pass picks its new indices (Algorithm 4
+                        step 5); other values -> LRP_EINVAL */
 } lrp_opts;
+
+enum lrp_selector {
+  LRP_SEL_LEVERAGE = 0,  /* leverage scores (Algorithm 3): the r_sig largest scores outside the
+                            current set, appended in ascending index order */
+  LRP_SEL_QDEIM = 1      /* QDEIM (Algorithm 2): the first r_sig pivots of the column-pivoted
+                            Householder QR of U(:, :r_sig)^T (the largest remaining squared norm,
+                            near-ties within 1e-12 relative to the smaller index), those not yet
+                            in the set appended in pivot order; when none is new, and at the first
+                            pass, the index outside the set with the largest leverage score is
+                            appended as well (Algorithm 4's safeguard, taken deterministically).
+                            Costs one launch per possible pivot (r_max) per pass. */
+};
 
 enum lrp_flags {
   LRP_FLAG_PROFILE = 1  /* record the device time of every kernel launch of each solve with

@@ -117,6 +117,7 @@ void free_ctx(lrp_ctx* c) {
     }
   }
   dfree(c->sel.gmax);
+  qdeim_free(&c->qd);
   dfree(c->rho.part);
   dfree(c->rho.M);
   dfree(c->rho.G);
@@ -202,6 +203,7 @@ int create_impl(lrp_ctx* c) {
   }
   TRY(tsqr_plan(&c->tsqr, n, pm));
   TRY(select_plan(&c->sel, n));
+  if (c->selector == LRP_SEL_QDEIM) TRY(qdeim_plan(&c->qd, n, c->stream));
   TRY(rho_plan(&c->rho, n));
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
       hipEventCreateWithFlags(&c->evfin, hipEventDisableTiming) != hipSuccess ||
@@ -285,6 +287,8 @@ int enqueue_pass_update(lrp_ctx* c, int k) {
   sa.pmax = pm;
   sa.trace = c->trace;
   sa.replay = c->replay;
+  sa.n = n;
+  sa.qd = c->selector == LRP_SEL_QDEIM ? c->qd.ctl : nullptr;
   // the candidate slot depends only on the merge depth, which is fixed per context
   const int slot = c->sel.nlevels & 1;
   sa.cs[0] = c->sel.cand_s[slot][0];
@@ -369,13 +373,22 @@ int enqueue_pass_update(lrp_ctx* c, int k) {
   return LRP_OK;
 }
 
-// The tail of pass k: the leverage-score candidates of the new iterate, for the selection that
+// Candidates of the next selection from the iterate U[0], U[1]: the leverage-score lists, and
+// with QDEIM also the pivots of the column-pivoted QR (the leverage lists then give the
+// safeguard index).
+int enqueue_selection(lrp_ctx* c, const double* U[2]) {
+  int fslot = 0;
+  TRY(select_candidates(c->sel, c->st, U, c->n, c->stream, &fslot));
+  if (c->selector == LRP_SEL_QDEIM) TRY(qdeim_launch(c->qd, c->st, U, c->n, c->r_max, c->stream));
+  return LRP_OK;
+}
+
+// The tail of pass k: the selection candidates of the new iterate, for the selection that
 // opens pass k+1 (every kernel returns at once once the stop flag is set).
 int enqueue_pass_select(lrp_ctx* c, int k) {
   const int nb_new = (k + 1) & 1;
   const double* U[2] = {c->Uit[nb_new], c->Vit[nb_new]};
-  int fslot = 0;
-  return select_candidates(c->sel, c->st, U, c->n, c->stream, &fslot);
+  return enqueue_selection(c, U);
 }
 
 int enqueue_pass_kernels(lrp_ctx* c, int k) {
@@ -529,9 +542,7 @@ int enqueue_start(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const doub
   TRY(prod_launch(pa, s));
   if (c->guess_r0 > 0) TRY(enqueue_guess(c));
   const double* U[2] = {c->Uit[0], c->Vit[0]};
-  int fslot = 0;
-  TRY(select_candidates(c->sel, c->st, U, n, s, &fslot));
-  return LRP_OK;
+  return enqueue_selection(c, U);
 }
 
 // Pass k: the launch sequence depends only on the parity of k (which iterate buffer is
@@ -754,7 +765,8 @@ int lrp_create(lrp_ctx** ctx, int64_t n, int32_t r_max, double tol, const lrp_op
   if (o.maxiter < 0 || o.maxiter > 1000) return LRP_EINVAL;
   if (o.precision != LRP_FP64 && o.precision != LRP_MIXED) return LRP_EINVAL;
   if (!(o.prune_tau >= 0.0) || o.prune_tau >= 1.0) return LRP_EINVAL;
-  if ((o.flags & ~LRP_FLAG_PROFILE) || o.reserved != 0) return LRP_EINVAL;
+  if ((o.flags & ~LRP_FLAG_PROFILE) || (o.selector != LRP_SEL_LEVERAGE && o.selector != LRP_SEL_QDEIM))
+    return LRP_EINVAL;
   lrp_ctx* c = new (std::nothrow) lrp_ctx();
   if (!c) return LRP_ENOMEM;
   c->n = n;
@@ -764,6 +776,7 @@ int lrp_create(lrp_ctx** ctx, int64_t n, int32_t r_max, double tol, const lrp_op
   c->precision = o.precision;
   c->tau = o.prune_tau > 0.0 ? o.prune_tau : (o.precision == LRP_MIXED ? 1e-7 : 1e-12);
   c->profile = (o.flags & LRP_FLAG_PROFILE) != 0;
+  c->selector = o.selector;
   if (o.stream) {
     c->stream = (hipStream_t)o.stream;
   } else {
@@ -803,7 +816,7 @@ int lrp_get_profile(const lrp_ctx* c, int32_t* count, lrp_kernel_time* out) {
       "k_init_state", "k_scan", "k_dst_single", "k_dst_pass1", "k_dst_pass2", "k_fiber",
       "k_tsqr_factor", "k_tsqr_apply", "k_core_warm", "k_core", "k_prod", "k_pi", "k_gmax",
       "k_topk_block", "k_topk_merge", "k_select", "k_rho_a", "k_rho_b", "k_rho_reduce",
-      "k_rho_final", "k_eta", "k_finalize", "copy", "empty kernel"};
+      "k_rho_final", "k_eta", "k_finalize", "copy", "empty kernel", "k_qdeim_step"};
   if (!c || !count || *count < 0 || (*count > 0 && !out)) return LRP_EINVAL;
   if (!c->profile || !c->solved) {
     *count = 0;

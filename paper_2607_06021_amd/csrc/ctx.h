@@ -48,6 +48,8 @@ struct lrp_ctx {
   DstPlan dst{};
   TsqrPlan tsqr{};
   SelectPlan sel{};
+  lrp::QdeimPlan qd{};  // QDEIM selection only
+  int selector = LRP_SEL_LEVERAGE;
   RhoPlan rho{};
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evfin = nullptr, evit[2] = {nullptr, nullptr};
   hipGraphExec_t gexec[2] = {nullptr, nullptr};  // captured pass, per parity (serving loop)
@@ -74,6 +76,7 @@ int check_solve_args(int64_t n, int r_max, int32_t r_F, const double* U_F, int64
                      const double* V_F, int64_t ldv, const double* U_out, int64_t ldou, const double* S_out,
                      const double* V_out, int64_t ldov);
 // asynchronous stages on the context's stream
+int enqueue_selection(lrp_ctx* c, const double* U[2]);
 int enqueue_start(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const double* sigma_F,
                   const double* V_F, int64_t ldv);
 int enqueue_pass(lrp_ctx* c, int k);

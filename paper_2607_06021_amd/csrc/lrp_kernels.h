@@ -16,7 +16,7 @@ namespace lrp {
 enum KernelId {
   K_INIT, K_SCAN, K_DST_SINGLE, K_DST_PASS1, K_DST_PASS2, K_FIBER, K_TSQR_FACTOR, K_TSQR_APPLY,
   K_CORE_WARM, K_CORE, K_PROD, K_PI, K_GMAX, K_TOPK_BLOCK, K_TOPK_MERGE, K_SELECT, K_RHO_A,
-  K_RHO_B, K_RHO_REDUCE, K_RHO_FINAL, K_ETA, K_FINALIZE, K_COPY, K_EMPTY, K_COUNT
+  K_RHO_B, K_RHO_REDUCE, K_RHO_FINAL, K_ETA, K_FINALIZE, K_COPY, K_EMPTY, K_QDEIM, K_COUNT
 };
 // Called right before a launch (or copy) on stream s: when this thread is recording a
 // profile on s, records an event that ends the previous entry and starts this one.
@@ -179,13 +179,39 @@ int select_plan(SelectPlan* p, int64_t n);
 // Leverage scores of the iterate in buffers U0/U1 and top candidates outside the pruned sets.
 int select_candidates(const SelectPlan& p, const DevState* st, const double* U[2], int64_t ldu,
                       hipStream_t s, int* final_list_slot);
+// ---------------------------------------------------------------- QDEIM (select.hip)
+// Control block of the column-pivoted QR of U(:, :r_sig)^T, one per side (device memory).
+struct QdeimCtl {
+  double v[kPMax];  // reflector of the last step at its absolute positions (zero elsewhere), v_j = 1
+  double tau;
+  double floor;     // squared norms at or below it count as 0 (set by the first step)
+  int piv[kPMax];   // pivots in the order chosen
+  int count;        // blocks of the current step that have finished (0 between launches)
+  int pad;
+};
+struct QdeimPlan {
+  int64_t n;
+  int nblocks;
+  double* work[2];  // n x kPMax: the rows of U(:, :r_sig) as the reflectors transform them
+  double* nrm[2];   // n: trailing squared norm of each row (-1 once pivoted)
+  double* bmax[2];  // nblocks: block maxima of nrm
+  int* flag[2];     // n: 1 once the row is a pivot
+  QdeimCtl* ctl;    // 2
+};
+int qdeim_plan(QdeimPlan* p, int64_t n, hipStream_t s);
+void qdeim_free(QdeimPlan* p);
+// r_sig pivots per side of the iterate U[side] (ld ldu); pmax launches, those past r_sig return at once.
+int qdeim_launch(const QdeimPlan& p, const DevState* st, const double* U[2], int64_t ldu, int pmax, hipStream_t s);
+
 struct SelectArgs {
   DevState* st;
   const double* cs[2];  // final candidate list per side (kPMax entries, best first)
   const int* ci[2];
   int pmax;
+  int64_t n;
   TraceBuf trace;
   ReplayBuf replay;     // sets of passes k < st->replay_n
+  const QdeimCtl* qd;   // QDEIM pivots (null: leverage-score selection)
 };
 int select_update(const SelectArgs& a, hipStream_t s);
 

@@ -197,6 +197,7 @@ __global__ __launch_bounds__(64) void k_select(SelectArgs a) {
   if (st->done) return;
   const int t = threadIdx.x;
   __shared__ int oldI[kPMax], oldJ[kPMax], prevI[kPMax], prevJ[kPMax], newv[2][kPMax];
+  // (QDEIM reads oldI/oldJ and newv, all written before the first barrier below)
   __shared__ int pre[2][kPMax];
   __shared__ int take_s[2], nold_s[2], nv_s[2];
   __shared__ int same;
@@ -228,6 +229,35 @@ __global__ __launch_bounds__(64) void k_select(SelectArgs a) {
         take_s[side] = rn[side];
         nold_s[side] = 0;
       }
+    }
+  } else if (a.qd) {
+    // QDEIM (Algorithm 2 with Algorithm 4 steps 5-12): the pivots not in the old set are
+    // appended in pivot order (capped at pmax); when none is new, or at the first pass, the
+    // best leverage-score candidate outside the new set is appended as well (the safeguard)
+    for (int side = 0; side < 2; ++side) {
+      const int nold = side == 0 ? nI : nJ;
+      const int* old = side == 0 ? oldI : oldJ;
+      const int p = t < rsig ? a.qd[side].piv[t] : -1;
+      bool isnew = t < rsig;
+      for (int q = 0; q < nold; ++q) isnew &= old[q] != p;
+      const unsigned long long nb = __ballot(isnew);
+      const int pos = nold + __popcll(nb & ((1ull << t) - 1));
+      if (isnew && pos < a.pmax) pre[side][pos] = p;
+      const int cnt = min(a.pmax, nold + (int)__popcll(nb));
+      __syncthreads();
+      // candidate t of the leverage-score list (best first, old set excluded): usable when valid
+      // and not among the new pivots
+      const int cand = newv[side][t];
+      bool ok = (side == 0 ? s0 : s1) >= 0.0;
+      for (int q = nold; q < cnt; ++q) ok &= pre[side][q] != cand;
+      const unsigned long long okb = __ballot(ok);
+      const bool guard = (cnt == nold || kp == 0) && cnt < a.pmax && cnt < a.n && okb != 0ull;
+      if (guard && t == __ffsll((long long)okb) - 1) pre[side][cnt] = cand;
+      if (t == 0) {
+        take_s[side] = cnt + (guard ? 1 : 0) - nold;
+        nold_s[side] = nold;
+      }
+      if (t < nold) pre[side][t] = old[t];
     }
   } else {
     for (int side = 0; side < 2; ++side) {
@@ -283,6 +313,196 @@ __global__ __launch_bounds__(64) void k_select(SelectArgs a) {
     a.trace.nIpre[kp] = nIpre;
     a.trace.nJpre[kp] = nJpre;
   }
+}
+
+// ----------------------------------------------------------------------------------------
+// QDEIM: column-pivoted Householder QR of A = U(:, :r_sig)^T (r_sig x n), the first r_sig pivots
+// (Algorithm 2). Column i of A is row i of U, so a thread owns one grid row and its r_sig
+// entries. Step j (one launch, both sides): every row not yet pivoted applies reflector j - 1
+// to its entries j-1 .. r_sig-1 and computes the squared norm of entries j .. r_sig-1 (at or
+// below the noise floor: 0); the block maxima go to memory, and the block that finishes last
+// picks pivot j -- among the rows within a relative 1e-12 of the largest norm, the smallest
+// index, i.e. the first such row of the first block whose maximum reaches that threshold -- and
+// builds reflector j from the pivot row (LAPACK convention, as in the column-pivoted QR).
+constexpr int kQdRows = 256;
+constexpr double kPivotTieRel = 1e-12;
+
+struct QdeimArgs {
+  const DevState* st;
+  const double* U[2];
+  int64_t ldu;
+  int64_t n;
+  int j;
+  double* work[2];
+  double* nrm[2];
+  double* bmax[2];
+  int* flag[2];
+  QdeimCtl* ctl;
+};
+
+__device__ inline int block_min_int256(int x, int* scratch) {
+  for (int m = 32; m >= 1; m >>= 1) x = min(x, __shfl_xor(x, m, 64));
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) scratch[w] = x;
+  __syncthreads();
+  const int r = min(min(scratch[0], scratch[1]), min(scratch[2], scratch[3]));
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kQdRows) void k_qdeim_step(QdeimArgs a) {
+  const DevState* st = a.st;
+  if (st->done) return;
+  const int r = st->r_sig, j = a.j;
+  if (j >= r) return;
+  const int side = blockIdx.y;
+  QdeimCtl* ctl = a.ctl + side;
+  double* W = a.work[side];
+  const int64_t n = a.n;
+  __shared__ double vs[kPMax];
+  __shared__ double red[4];
+  __shared__ int redi[4];
+  __shared__ int last;
+  if (threadIdx.x < kPMax) vs[threadIdx.x] = j > 0 ? ctl->v[threadIdx.x] : 0.0;
+  const double tauv = j > 0 ? ctl->tau : 0.0;
+  const double floor_v = j > 0 ? ctl->floor : 0.0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * kQdRows + threadIdx.x;
+  double nrm2 = -1.0;
+  if (i < n) {
+    if (j == 0) {
+      const double* Ui = a.U[side] + i;
+      double x[kPMax];
+#pragma unroll
+      for (int e = 0; e < kPMax; ++e) x[e] = e < r ? Ui[(int64_t)e * a.ldu] : 0.0;
+      nrm2 = 0.0;
+#pragma unroll
+      for (int e = 0; e < kPMax; ++e)
+        if (e < r) {
+          W[i + (int64_t)e * n] = x[e];
+          nrm2 = fma(x[e], x[e], nrm2);
+        }
+      a.flag[side][i] = 0;
+    } else if (!a.flag[side][i]) {
+      double x[kPMax];
+#pragma unroll
+      for (int e = 0; e < kPMax; ++e) x[e] = (e >= j - 1 && e < r) ? W[i + (int64_t)e * n] : 0.0;
+      double d = 0.0;
+#pragma unroll
+      for (int e = 0; e < kPMax; ++e) d = fma(vs[e], x[e], d);
+      const double w = tauv * d;
+      nrm2 = 0.0;
+#pragma unroll
+      for (int e = 0; e < kPMax; ++e)
+        if (e >= j && e < r) {
+          x[e] = fma(-w, vs[e], x[e]);
+          W[i + (int64_t)e * n] = x[e];
+          nrm2 = fma(x[e], x[e], nrm2);
+        }
+      if (nrm2 <= floor_v) nrm2 = 0.0;
+    }
+    a.nrm[side][i] = nrm2;
+  }
+  const double bm = block_max256(nrm2, red);
+  if (threadIdx.x == 0) a.bmax[side][blockIdx.x] = bm;
+  // publish this block's results, then count it; the block that completes the count sees every
+  // other block's results
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(&ctl->count, 1) == (int)gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const volatile double* bmx = a.bmax[side];
+  const int nb = gridDim.x;
+  double best = -1.0;
+  for (int q = threadIdx.x; q < nb; q += kQdRows) best = fmax(best, bmx[q]);
+  best = block_max256(best, red);
+  const double fl = j == 0 ? kFloorRel * best : floor_v;
+  const double thr = best * (1.0 - kPivotTieRel);
+  int fb = 0x7fffffff;
+  for (int q = threadIdx.x; q < nb; q += kQdRows)
+    if (bmx[q] >= thr) {
+      fb = q;
+      break;
+    }
+  fb = block_min_int256(fb, redi);
+  const volatile double* nv = a.nrm[side];
+  const int64_t row = (int64_t)fb * kQdRows + threadIdx.x;
+  const int cand = (row < n && nv[row] >= thr) ? (int)threadIdx.x : 0x7fffffff;
+  const int pl = block_min_int256(cand, redi);
+  const int p = fb * kQdRows + pl;
+  // reflector j from entries j .. r-1 of row p (wave 0, one entry per lane)
+  if (threadIdx.x < 64) {
+    const int e = threadIdx.x;
+    const volatile double* Wp = W + p;
+    const double x = (j + e < r) ? Wp[(int64_t)(j + e) * n] : 0.0;
+    const double xn = sqrt(wave_sum(x * x));
+    const double alpha = __shfl(x, 0, 64);
+    double v = 0.0, tau = 0.0;
+    if (xn != 0.0) {
+      const double beta = -copysign(xn, alpha);
+      v = e == 0 ? 1.0 : x / (alpha - beta);
+      tau = (beta - alpha) / beta;
+    }
+    for (int q = e; q < kPMax; q += 64) ctl->v[q] = 0.0;
+    if (j + e < r) ctl->v[j + e] = v;
+    if (e == 0) {
+      ctl->tau = tau;
+      ctl->piv[j] = p;
+      if (j == 0) ctl->floor = fl;
+      a.flag[side][p] = 1;
+      a.nrm[side][p] = -1.0;
+      ctl->count = 0;
+    }
+  }
+}
+
+int qdeim_plan(QdeimPlan* p, int64_t n, hipStream_t s) {
+  *p = QdeimPlan{};
+  p->n = n;
+  p->nblocks = (int)((n + kQdRows - 1) / kQdRows);
+  for (int q = 0; q < 2; ++q) {
+    if (hipMalloc(&p->work[q], sizeof(double) * (size_t)n * kPMax) != hipSuccess) return LRP_ENOMEM;
+    if (hipMalloc(&p->nrm[q], sizeof(double) * (size_t)n) != hipSuccess) return LRP_ENOMEM;
+    if (hipMalloc(&p->bmax[q], sizeof(double) * (size_t)p->nblocks) != hipSuccess) return LRP_ENOMEM;
+    if (hipMalloc(&p->flag[q], sizeof(int) * (size_t)n) != hipSuccess) return LRP_ENOMEM;
+  }
+  if (hipMalloc(&p->ctl, sizeof(QdeimCtl) * 2) != hipSuccess) return LRP_ENOMEM;
+  // the block counters start at 0 (on the context's stream, which is synchronized after set-up)
+  return hipMemsetAsync(p->ctl, 0, sizeof(QdeimCtl) * 2, s) == hipSuccess ? LRP_OK : LRP_EDEVICE;
+}
+
+void qdeim_free(QdeimPlan* p) {
+  for (int q = 0; q < 2; ++q) {
+    if (p->work[q]) (void)hipFree(p->work[q]);
+    if (p->nrm[q]) (void)hipFree(p->nrm[q]);
+    if (p->bmax[q]) (void)hipFree(p->bmax[q]);
+    if (p->flag[q]) (void)hipFree(p->flag[q]);
+  }
+  if (p->ctl) (void)hipFree(p->ctl);
+  *p = QdeimPlan{};
+}
+
+int qdeim_launch(const QdeimPlan& p, const DevState* st, const double* U[2], int64_t ldu, int pmax, hipStream_t s) {
+  QdeimArgs a{};
+  a.st = st;
+  a.U[0] = U[0];
+  a.U[1] = U[1];
+  a.ldu = ldu;
+  a.n = p.n;
+  for (int q = 0; q < 2; ++q) {
+    a.work[q] = p.work[q];
+    a.nrm[q] = p.nrm[q];
+    a.bmax[q] = p.bmax[q];
+    a.flag[q] = p.flag[q];
+  }
+  a.ctl = p.ctl;
+  for (int j = 0; j < pmax; ++j) {
+    a.j = j;
+    LRP_LAUNCH(K_QDEIM, k_qdeim_step, dim3(p.nblocks, 2), dim3(kQdRows), 0, s, a);
+  }
+  return launch_status();
 }
 
 // ----------------------------------------------------------------------------------------

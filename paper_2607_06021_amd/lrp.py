@@ -29,10 +29,11 @@ _c_vp = ctypes.c_void_p
 
 class Opts(ctypes.Structure):
     _fields_ = [("maxiter", _c_i32), ("precision", _c_i32), ("prune_tau", _c_dbl), ("stream", _c_vp),
-                ("flags", _c_i32), ("reserved", _c_i32)]
+                ("flags", _c_i32), ("selector", _c_i32)]
 
 
 LRP_FLAG_PROFILE = 1
+LRP_SEL_LEVERAGE, LRP_SEL_QDEIM = 0, 1
 
 
 class KernelTime(ctypes.Structure):
@@ -179,7 +180,7 @@ class Solver:
     """A library context: grid size n (n+1 a power of two), rank cap r_max, tolerance tol."""
 
     def __init__(self, n: int, r_max: int, tol: float, maxiter: int = 20, precision: str = "fp64",
-                 prune_tau: float = 0.0, stream=None, profile: bool = False):
+                 prune_tau: float = 0.0, stream=None, profile: bool = False, selector: str = "ls"):
         import torch
 
         self.n, self.r_max, self.tol = int(n), int(r_max), float(tol)
@@ -190,8 +191,11 @@ class Solver:
             # self.stream bracket exactly the library's kernels
             stream = torch.cuda.Stream()
         self.stream = stream
+        if selector not in ("ls", "qdeim"):
+            raise ValueError(f"unknown selector {selector!r}")
         o = Opts(self.maxiter, LRP_MIXED if precision == "mixed" else LRP_FP64, float(prune_tau),
-                 _c_vp(stream.cuda_stream), LRP_FLAG_PROFILE if profile else 0, 0)
+                 _c_vp(stream.cuda_stream), LRP_FLAG_PROFILE if profile else 0,
+                 LRP_SEL_QDEIM if selector == "qdeim" else LRP_SEL_LEVERAGE)
         h = _c_vp()
         _check(lib().lrp_create(ctypes.byref(h), self.n, self.r_max, self.tol, ctypes.byref(o)), "lrp_create")
         self._h = h

@@ -38,7 +38,7 @@ def test_create_rejects_bad_sizes(n, rmax, tol):
 def test_create_rejects_bad_options():
     h = ctypes.c_void_p()
     for o in (L.Opts(-1, 0, 0.0, None), L.Opts(5, 7, 0.0, None), L.Opts(5, 0, 2.0, None),
-              L.Opts(5, 0, 0.0, None, 2, 0), L.Opts(5, 0, 0.0, None, 0, 1)):
+              L.Opts(5, 0, 0.0, None, 2, 0), L.Opts(5, 0, 0.0, None, 0, 2), L.Opts(5, 0, 0.0, None, 0, -1)):
         assert L.lib().lrp_create(ctypes.byref(h), 255, 8, 1e-10, ctypes.byref(o)) == L.LRP_EINVAL
 
 
