@@ -64,20 +64,33 @@ typedef struct lrp_opts {
                         (Algorithm 4); 0 -> 1e-12 (FP64) or 1e-7 (mixed) */
   void* stream;      /* hipStream_t to order all work on; NULL -> a stream owned by the context */
   int32_t flags;     /* bitwise OR of enum lrp_flags; other bits -> LRP_EINVAL */
-  int32_t selector;  /* enum lrp_selector: how each pass picks its new indices (Algorithm 4
-                        step 5); other values -> LRP_EINVAL */
+  int32_t selector;  /* enum lrp_selector: how each pass picks its new indices (Algorithm 4's
+                        index selection); other values -> LRP_EINVAL */
+  double ls_oversampling; /* LRP_SEL_LEVERAGE_SAMPLED: rho in p_i = min(1, rho pi_i), i.e. the
+                             oversampling c = rho r_sig of Algorithm 3; 0 -> 2; must be finite
+                             and >= 0 */
+  uint64_t seed;     /* LRP_SEL_LEVERAGE_SAMPLED: key of the Philox4x32-10 generator */
 } lrp_opts;
 
 enum lrp_selector {
   LRP_SEL_LEVERAGE = 0,  /* leverage scores (Algorithm 3): the r_sig largest scores outside the
                             current set, appended in ascending index order */
-  LRP_SEL_QDEIM = 1      /* QDEIM (Algorithm 2): the first r_sig pivots of the column-pivoted
+  LRP_SEL_QDEIM = 1,     /* QDEIM (Algorithm 2): the first r_sig pivots of the column-pivoted
                             Householder QR of U(:, :r_sig)^T (the largest remaining squared norm,
                             near-ties within 1e-12 relative to the smaller index), those not yet
                             in the set appended in pivot order; when none is new, and at the first
                             pass, the index outside the set with the largest leverage score is
                             appended as well (Algorithm 4's safeguard, taken deterministically).
                             Costs one launch per possible pivot (r_max) per pass. */
+  LRP_SEL_LEVERAGE_SAMPLED = 2 /* leverage scores as Algorithm 3 states them: row i (outside the
+                            set) is kept with probability p_i = min(1, rho pi_i), pi_i the
+                            squared norm of row i of U(:, :r_sig); the uniform u_i is the
+                            Philox4x32-10 output for counter (i mod 2^32, i / 2^32, pass, side)
+                            and key (seed mod 2^32, seed / 2^32), 53 bits / 2^53, and i is kept
+                            when u_i < p_i. The kept rows with the largest scores fill the set up
+                            to r_max (appended in ascending order); when none is kept, the row
+                            outside the set with the largest -1 - u_i is appended (the
+                            safeguard's random index). */
 };
 
 enum lrp_flags {
@@ -185,7 +198,7 @@ int lrp_set_guess(lrp_ctx* ctx, int32_t r0, const double* U0, int64_t ldu0, cons
 /*
  * lrp_set_index_sets -- replay (a diagnostic): passes 0 .. npasses-1 of every following
  * lrp_solve on this context take the given index sets as the sets handed to the cross
- * approximation (Algorithm 4 step 6) instead of selecting them; later passes select from the
+ * approximation (the union of Algorithm 4) instead of selecting them; later passes select from the
  * iterate these produce, as usual. Run a mixed-precision solve on the sets of an FP64 solve to
  * separate rounding from index-set divergence.
  *   npasses  0 <= npasses <= maxiter; 0 switches replay off.

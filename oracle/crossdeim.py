@@ -36,14 +36,24 @@ the design notes of the repository):
     truncation; the loop makes exactly maxiter passes; no stop at k = 0; when the
     pre-prune index sets repeat, the iteration has reached a fixed point and the
     previous iterate is returned.
-  * QDEIM selection (Algorithm 2, QDEIM branch, used in Algorithm 4 step 5): the
+  * QDEIM selection (Algorithm 2, QDEIM branch, as Algorithm 4's index selection): the
     first r_sig pivots of the column-pivoted QR of U_{k-1}(:, :r_sig)^T, pivoting on
     the largest remaining column norm (ties to the smaller index); the indices not
-    already in I_{k-1} are appended in pivot order (the union of step 6; QDEIM sets
-    are ordered). The safeguard of steps 7-12 appends one more index when nothing
+    already in I_{k-1} are appended in pivot order (Algorithm 4's union; QDEIM sets
+    are ordered). Algorithm 4's safeguard appends one more index when nothing
     was added or at k = 0; the paper draws it at random, here it is the index outside
     the set with the largest leverage score (ties and noise to the smaller index),
     and it is added to the current set rather than to I*_k alone.
+  * sampled leverage scores (Algorithm 3 as stated): row i is kept with probability
+    p_i = min(1, c pi_i / r_sig) with c = rho r_sig, i.e. p_i = min(1, rho pi_i) for the floored
+    score pi_i = sum_{eta < r_sig} U(i, eta)^2 (Algorithm 3's 1/k normalization with k = r_sig;
+    the paper fixes only the order of c); the uniform u_i comes from the counter-based generator
+    Philox4x32-10 with counter (i mod 2^32, i / 2^32, pass, side) and key (seed mod 2^32,
+    seed / 2^32), u_i = 53 bits of its first two outputs / 2^53, and i is kept when u_i < p_i.
+    The kept rows outside I_{k-1} are taken by (score descending, index ascending) up to the cap
+    and appended in ascending index order; when none was kept (and the cap allows), the
+    safeguard of Algorithm 4 appends a random index of the complement: the one with the
+    largest -1 - u_i (computed in FP64; ties to the smaller index).
   * the initial guess U0, V0 of Algorithm 4 is given in physical space (the space of
     the solver's output factors, e.g. a previous solution U_W, S, V_W) with optional
     weights S0: the warm start is then the truncated SVD of
@@ -276,7 +286,7 @@ def pivoted_qr_order(A: np.ndarray, count: int) -> tuple:
 
 
 def qdeim_select(U: np.ndarray, r_sig: int, I_prev: Sequence[int], p_max: int, first: bool) -> Selection:
-    """QDEIM index update (Algorithm 2 QDEIM branch, Algorithm 4 steps 5-12).
+    """QDEIM index update (Algorithm 2 QDEIM branch; Algorithm 4's selection, union and safeguard).
 
     I* = the first r_sig pivots of the column-pivoted QR of U(:, :r_sig)^T; the pivots not in
     I_prev are appended in pivot order. If that adds nothing, or at the first pass, the index
@@ -306,6 +316,61 @@ def qdeim_select(U: np.ndarray, r_sig: int, I_prev: Sequence[int], p_max: int, f
         new.append(extra)
     gap = min(gaps) if gaps else math.inf
     return Selection(out, new, gap)
+
+
+# Philox4x32-10 (Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as easy as 1, 2, 3",
+# SC 2011): ten rounds of two 32 x 32 -> 64-bit multiplications on a 4 x 32-bit counter, the
+# 2 x 32-bit key bumped by two Weyl constants between rounds.
+PHILOX_M = (0xD2511F53, 0xCD9E8D57)
+PHILOX_W = (0x9E3779B9, 0xBB67AE85)
+
+
+def philox4x32_10(c0, c1, c2, c3, k0, k1):
+    """The four 32-bit outputs for counters (c0, c1, c2, c3) (arrays) and key (k0, k1)."""
+    mask = np.uint64(0xFFFFFFFF)
+    c = [np.asarray(x, dtype=np.uint64) & mask for x in (c0, c1, c2, c3)]
+    k0 = np.uint64(k0) & mask
+    k1 = np.uint64(k1) & mask
+    for _ in range(10):
+        p0 = np.uint64(PHILOX_M[0]) * c[0]
+        p1 = np.uint64(PHILOX_M[1]) * c[2]
+        c = [(p1 >> np.uint64(32)) ^ c[1] ^ k0, p1 & mask, (p0 >> np.uint64(32)) ^ c[3] ^ k1, p0 & mask]
+        k0 = (k0 + np.uint64(PHILOX_W[0])) & mask
+        k1 = (k1 + np.uint64(PHILOX_W[1])) & mask
+    return c
+
+
+def sample_uniforms(n: int, k: int, side: int, seed: int) -> np.ndarray:
+    """u_i in [0, 1), i < n, for pass k and side (0: rows I, 1: columns J)."""
+    i = np.arange(n, dtype=np.uint64)
+    x = philox4x32_10(i & np.uint64(0xFFFFFFFF), i >> np.uint64(32), np.full(n, k, dtype=np.uint64),
+                      np.full(n, side, dtype=np.uint64), seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    r53 = ((x[1] << np.uint64(32)) | x[0]) >> np.uint64(11)
+    return r53.astype(np.float64) * 2.0 ** -53
+
+
+def sampled_select(U: np.ndarray, r_sig: int, I_prev: Sequence[int], p_max: int, rho: float, u: np.ndarray) -> Selection:
+    """Algorithm 3 as stated, with Algorithm 4's union and its safeguard:
+    rows outside I_prev are kept with probability min(1, rho pi_i) (u_i < p_i); the kept ones
+    with the highest scores fill the set up to p_max (appended in ascending index order); if none
+    was kept, the row of the complement with the largest -1 - u_i is appended."""
+    n = U.shape[0]
+    pi = leverage_scores(U, r_sig)
+    top = float(pi.max()) if n else 0.0
+    score = np.where(pi <= FLOOR_REL * top, 0.0, pi)
+    prob = np.minimum(1.0, rho * score)
+    free = np.ones(n, dtype=bool)
+    free[np.asarray(list(I_prev), dtype=np.int64)] = False
+    kept = np.nonzero(free & (u < prob))[0]
+    order = kept[np.lexsort((kept, -score[kept]))]
+    room = max(0, min(p_max, n) - len(I_prev))
+    s = min(room, order.size)
+    new = sorted(int(i) for i in order[:s])
+    if s == 0 and room > 0:
+        cand = np.nonzero(free)[0]
+        key = -1.0 - u[cand]
+        new = [int(cand[np.lexsort((cand, -key))][0])]
+    return Selection(list(I_prev) + new, new, math.inf)
 
 
 def prune(idx: Sequence[int], diag: np.ndarray, tau: float) -> List[int]:
@@ -452,6 +517,8 @@ def solve(
     warm=None,
     replay=None,
     selector: str = "ls",
+    ls_oversampling: float = 2.0,
+    seed: int = 0,
 ) -> Result:
     """Low-rank Poisson solve: -Lap u = f, u = 0 on the boundary of the unit square.
 
@@ -459,9 +526,11 @@ def solve(
     warm: optional (U0, S0, V0), the initial guess of Algorithm 4 in physical space (S0 may be
     None); default (and for a zero guess): the right-hand side itself. replay: optional list of (I, J) index sets
     used for passes 0, 1, ... instead of selecting them (a diagnostic). selector: "ls"
-    (leverage scores, Algorithm 3) or "qdeim" (Algorithm 2).
+    (leverage scores, Algorithm 3, the top r_sig), "ls_sampled" (Algorithm 3's random sampling,
+    p_i = min(1, ls_oversampling pi_i) drawn with Philox4x32-10 keyed by seed) or "qdeim"
+    (Algorithm 2).
     """
-    if selector not in ("ls", "qdeim"):
+    if selector not in ("ls", "qdeim", "ls_sampled"):
         raise ValueError(f"unknown selector {selector!r}")
     U_F = np.asarray(U_F, dtype=np.float64)
     V_F = np.asarray(V_F, dtype=np.float64)
@@ -494,6 +563,9 @@ def solve(
         elif selector == "qdeim":
             selI = qdeim_select(U_prev, r_sig, I, r_max, k == 0)
             selJ = qdeim_select(V_prev, r_sig, J, r_max, k == 0)
+        elif selector == "ls_sampled":
+            selI = sampled_select(U_prev, r_sig, I, r_max, ls_oversampling, sample_uniforms(n, k, 0, seed))
+            selJ = sampled_select(V_prev, r_sig, J, r_max, ls_oversampling, sample_uniforms(n, k, 1, seed))
         else:
             selI = select(U_prev, r_sig, I, r_max)
             selJ = select(V_prev, r_sig, J, r_max)

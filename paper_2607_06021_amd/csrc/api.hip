@@ -289,6 +289,7 @@ int enqueue_pass_update(lrp_ctx* c, int k) {
   sa.replay = c->replay;
   sa.n = n;
   sa.qd = c->selector == LRP_SEL_QDEIM ? c->qd.ctl : nullptr;
+  sa.sampled = c->selector == LRP_SEL_LEVERAGE_SAMPLED;
   // the candidate slot depends only on the merge depth, which is fixed per context
   const int slot = c->sel.nlevels & 1;
   sa.cs[0] = c->sel.cand_s[slot][0];
@@ -378,7 +379,11 @@ int enqueue_pass_update(lrp_ctx* c, int k) {
 // safeguard index).
 int enqueue_selection(lrp_ctx* c, const double* U[2]) {
   int fslot = 0;
-  TRY(select_candidates(c->sel, c->st, U, c->n, c->stream, &fslot));
+  SampleOpts so{};
+  so.sampled = c->selector == LRP_SEL_LEVERAGE_SAMPLED;
+  so.rho = c->ls_rho;
+  so.seed = c->seed;
+  TRY(select_candidates(c->sel, c->st, U, c->n, c->stream, &fslot, so));
   if (c->selector == LRP_SEL_QDEIM) TRY(qdeim_launch(c->qd, c->st, U, c->n, c->r_max, c->stream));
   return LRP_OK;
 }
@@ -765,8 +770,10 @@ int lrp_create(lrp_ctx** ctx, int64_t n, int32_t r_max, double tol, const lrp_op
   if (o.maxiter < 0 || o.maxiter > 1000) return LRP_EINVAL;
   if (o.precision != LRP_FP64 && o.precision != LRP_MIXED) return LRP_EINVAL;
   if (!(o.prune_tau >= 0.0) || o.prune_tau >= 1.0) return LRP_EINVAL;
-  if ((o.flags & ~LRP_FLAG_PROFILE) || (o.selector != LRP_SEL_LEVERAGE && o.selector != LRP_SEL_QDEIM))
+  if ((o.flags & ~LRP_FLAG_PROFILE) ||
+      (o.selector != LRP_SEL_LEVERAGE && o.selector != LRP_SEL_QDEIM && o.selector != LRP_SEL_LEVERAGE_SAMPLED))
     return LRP_EINVAL;
+  if (!(o.ls_oversampling >= 0.0) || !std::isfinite(o.ls_oversampling)) return LRP_EINVAL;
   lrp_ctx* c = new (std::nothrow) lrp_ctx();
   if (!c) return LRP_ENOMEM;
   c->n = n;
@@ -777,6 +784,8 @@ int lrp_create(lrp_ctx** ctx, int64_t n, int32_t r_max, double tol, const lrp_op
   c->tau = o.prune_tau > 0.0 ? o.prune_tau : (o.precision == LRP_MIXED ? 1e-7 : 1e-12);
   c->profile = (o.flags & LRP_FLAG_PROFILE) != 0;
   c->selector = o.selector;
+  c->ls_rho = o.ls_oversampling > 0.0 ? o.ls_oversampling : 2.0;
+  c->seed = o.seed;
   if (o.stream) {
     c->stream = (hipStream_t)o.stream;
   } else {

@@ -50,6 +50,8 @@ struct lrp_ctx {
   SelectPlan sel{};
   lrp::QdeimPlan qd{};  // QDEIM selection only
   int selector = LRP_SEL_LEVERAGE;
+  double ls_rho = 2.0;  // sampled leverage scores: p_i = min(1, ls_rho pi_i)
+  uint64_t seed = 0;
   RhoPlan rho{};
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evfin = nullptr, evit[2] = {nullptr, nullptr};
   hipGraphExec_t gexec[2] = {nullptr, nullptr};  // captured pass, per parity (serving loop)

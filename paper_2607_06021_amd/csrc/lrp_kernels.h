@@ -177,8 +177,14 @@ struct SelectPlan {
 };
 int select_plan(SelectPlan* p, int64_t n);
 // Leverage scores of the iterate in buffers U0/U1 and top candidates outside the pruned sets.
+// sampled: rows are drawn with probability min(1, rho score) first (Philox4x32-10, key seed).
+struct SampleOpts {
+  int sampled;
+  double rho;
+  uint64_t seed;
+};
 int select_candidates(const SelectPlan& p, const DevState* st, const double* U[2], int64_t ldu,
-                      hipStream_t s, int* final_list_slot);
+                      hipStream_t s, int* final_list_slot, SampleOpts so = SampleOpts{});
 // ---------------------------------------------------------------- QDEIM (select.hip)
 // Control block of the column-pivoted QR of U(:, :r_sig)^T, one per side (device memory).
 struct QdeimCtl {
@@ -212,6 +218,7 @@ struct SelectArgs {
   TraceBuf trace;
   ReplayBuf replay;     // sets of passes k < st->replay_n
   const QdeimCtl* qd;   // QDEIM pivots (null: leverage-score selection)
+  int sampled;          // sampled leverage scores: take every drawn candidate (up to the cap)
 };
 int select_update(const SelectArgs& a, hipStream_t s);
 

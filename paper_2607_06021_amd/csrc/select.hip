@@ -15,7 +15,34 @@
 
 namespace lrp {
 
-// Candidate order throughout: a higher score first, then the smaller index.
+// Candidate order throughout: a higher key first, then the smaller index. Keys: the floored
+// leverage score (>= 0) of a row that may enter the set; with sampling, -1 - u_i (in (-2, -1])
+// for a row that was not drawn (the safeguard's random pick is the largest of these); kExcl for
+// a row already in the set; kPad for the padding past n.
+constexpr double kExcl = -4.0;
+constexpr double kPad = -8.0;
+
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011): ten rounds of two 32 x 32 -> 64-bit
+// multiplications on the 4 x 32-bit counter, the key bumped by two Weyl constants per round.
+// Returns the uniform in [0, 1) made of 53 bits of the first two output words.
+__device__ inline double philox_uniform(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                        uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c0 = n0;
+    c1 = (uint32_t)p1;
+    c2 = n2;
+    c3 = (uint32_t)p0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  const uint64_t r53 = (((uint64_t)c1 << 32) | c0) >> 11;
+  return (double)r53 * 0x1.0p-53;
+}
 
 struct PiArgs {
   const DevState* st;
@@ -65,6 +92,9 @@ struct TopkArgs {
   int64_t n;
   double* cs[2];  // out: nblocks x kPMax scores
   int* ci[2];
+  int sampled;    // 1: keep row i with probability min(1, rho score_i) (Algorithm 3)
+  double rho;
+  uint64_t seed;
 };
 
 // Rank of each entry of a 256-row block in the (score desc, index asc) order by counting the
@@ -95,10 +125,17 @@ __global__ __launch_bounds__(256) void k_topk_block(TopkArgs a) {
       const int4 e = ex4[q];
       ex |= (e.x == (int)i) | (e.y == (int)i) | (e.z == (int)i) | (e.w == (int)i);
     }
-    cs = ex ? -1.0 : (p <= floor_v ? 0.0 : p);
+    const double sc = p <= floor_v ? 0.0 : p;
+    cs = ex ? kExcl : sc;
+    if (a.sampled && !ex) {
+      // uniform of row i for the pass this selection opens (st->k) and this side
+      const double u = philox_uniform((uint32_t)i, (uint32_t)((uint64_t)i >> 32), (uint32_t)st->k, (uint32_t)side,
+                                      (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+      cs = u < fmin(1.0, a.rho * sc) ? sc : -1.0 - u;
+    }
     ci = (int)i;
   } else {  // padding: below every real entry, distinct indices
-    cs = -2.0;
+    cs = kPad;
     ci = 0x40000000 + (int)threadIdx.x;
   }
   es[threadIdx.x] = cs;
@@ -145,12 +182,12 @@ __global__ __launch_bounds__(kMergeThreads) void k_topk_merge(MergeArgs a) {
   const int q = threadIdx.x;
   {
     const int l = first + q / kPMax;
-    double cs = -2.0;
+    double cs = kPad;
     int ci = 0x50000000 + q;  // padding entries: distinct indices, below every real entry
     if (l < a.nlists) {
       cs = a.in_s[side][(int64_t)first * kPMax + q];
       ci = a.in_i[side][(int64_t)first * kPMax + q];
-      if (cs == -2.0) ci = 0x50000000 + q;
+      if (cs == kPad) ci = 0x50000000 + q;
     }
     es[0][q] = cs;
     ei[0][q] = ci;
@@ -209,6 +246,7 @@ __global__ __launch_bounds__(64) void k_select(SelectArgs a) {
   prevI[t] = st->Iprev[t];
   prevJ[t] = st->Jprev[t];
   const double s0 = a.cs[0][t], s1 = a.cs[1][t];
+  const double s0h = a.cs[0][0], s1h = a.cs[1][0];  // heads of the lists
   newv[0][t] = a.ci[0][t];
   newv[1][t] = a.ci[1][t];
   // number of valid (score >= 0) candidates: the lists are sorted, so count them
@@ -231,7 +269,7 @@ __global__ __launch_bounds__(64) void k_select(SelectArgs a) {
       }
     }
   } else if (a.qd) {
-    // QDEIM (Algorithm 2 with Algorithm 4 steps 5-12): the pivots not in the old set are
+    // QDEIM (Algorithm 2 in Algorithm 4's selection and union): the pivots not in the old set are
     // appended in pivot order (capped at pmax); when none is new, or at the first pass, the
     // best leverage-score candidate outside the new set is appended as well (the safeguard)
     for (int side = 0; side < 2; ++side) {
@@ -262,7 +300,16 @@ __global__ __launch_bounds__(64) void k_select(SelectArgs a) {
   } else {
     for (int side = 0; side < 2; ++side) {
       const int nold = side == 0 ? nI : nJ;
-      const int take = max(0, min(min(rsig, a.pmax - nold), nv_s[side]));
+      int take;
+      if (a.sampled) {
+        // every drawn row up to the cap; if none was drawn, the safeguard's random row (the head
+        // of the list, when it is a row outside the set)
+        const int room = max(0, (int)min((int64_t)a.pmax, a.n) - nold);
+        take = min(room, nv_s[side]);
+        if (take == 0 && room > 0 && (side == 0 ? s0h : s1h) > -2.0) take = 1;
+      } else {
+        take = max(0, min(min(rsig, a.pmax - nold), nv_s[side]));
+      }
       // the new indices in ascending order: rank among the first `take` candidates
       if (t < take) {
         const int v = newv[side][t];
@@ -533,7 +580,7 @@ int select_plan(SelectPlan* p, int64_t n) {
 // Writes the final candidate lists (side 0 then 1) into cand_s/cand_i[*final_list_slot].
 // The final list of side s starts at element 0 of cand_*[slot][s].
 int select_candidates(const SelectPlan& p, const DevState* st, const double* U[2], int64_t ldu,
-                      hipStream_t s, int* final_list_slot) {
+                      hipStream_t s, int* final_list_slot, SampleOpts so) {
   PiArgs pa{};
   pa.st = st;
   pa.U[0] = U[0];
@@ -553,6 +600,9 @@ int select_candidates(const SelectPlan& p, const DevState* st, const double* U[2
   ta.pi[1] = p.pi[1];
   ta.gmax = p.gmax;
   ta.n = p.n;
+  ta.sampled = so.sampled;
+  ta.rho = so.rho;
+  ta.seed = so.seed;
   for (int q = 0; q < 2; ++q) {
     ta.cs[q] = p.cand_s[0][q];
     ta.ci[q] = p.cand_i[0][q];

@@ -29,11 +29,12 @@ _c_vp = ctypes.c_void_p
 
 class Opts(ctypes.Structure):
     _fields_ = [("maxiter", _c_i32), ("precision", _c_i32), ("prune_tau", _c_dbl), ("stream", _c_vp),
-                ("flags", _c_i32), ("selector", _c_i32)]
+                ("flags", _c_i32), ("selector", _c_i32), ("ls_oversampling", _c_dbl), ("seed", ctypes.c_uint64)]
 
 
 LRP_FLAG_PROFILE = 1
-LRP_SEL_LEVERAGE, LRP_SEL_QDEIM = 0, 1
+LRP_SEL_LEVERAGE, LRP_SEL_QDEIM, LRP_SEL_LEVERAGE_SAMPLED = 0, 1, 2
+_SELECTORS = {"ls": LRP_SEL_LEVERAGE, "qdeim": LRP_SEL_QDEIM, "ls_sampled": LRP_SEL_LEVERAGE_SAMPLED}
 
 
 class KernelTime(ctypes.Structure):
@@ -180,7 +181,8 @@ class Solver:
     """A library context: grid size n (n+1 a power of two), rank cap r_max, tolerance tol."""
 
     def __init__(self, n: int, r_max: int, tol: float, maxiter: int = 20, precision: str = "fp64",
-                 prune_tau: float = 0.0, stream=None, profile: bool = False, selector: str = "ls"):
+                 prune_tau: float = 0.0, stream=None, profile: bool = False, selector: str = "ls",
+                 ls_oversampling: float = 2.0, seed: int = 0):
         import torch
 
         self.n, self.r_max, self.tol = int(n), int(r_max), float(tol)
@@ -191,11 +193,11 @@ class Solver:
             # self.stream bracket exactly the library's kernels
             stream = torch.cuda.Stream()
         self.stream = stream
-        if selector not in ("ls", "qdeim"):
+        if selector not in _SELECTORS:
             raise ValueError(f"unknown selector {selector!r}")
         o = Opts(self.maxiter, LRP_MIXED if precision == "mixed" else LRP_FP64, float(prune_tau),
-                 _c_vp(stream.cuda_stream), LRP_FLAG_PROFILE if profile else 0,
-                 LRP_SEL_QDEIM if selector == "qdeim" else LRP_SEL_LEVERAGE)
+                 _c_vp(stream.cuda_stream), LRP_FLAG_PROFILE if profile else 0, _SELECTORS[selector],
+                 float(ls_oversampling), int(seed))
         h = _c_vp()
         _check(lib().lrp_create(ctypes.byref(h), self.n, self.r_max, self.tol, ctypes.byref(o)), "lrp_create")
         self._h = h

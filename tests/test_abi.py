@@ -38,7 +38,8 @@ def test_create_rejects_bad_sizes(n, rmax, tol):
 def test_create_rejects_bad_options():
     h = ctypes.c_void_p()
     for o in (L.Opts(-1, 0, 0.0, None), L.Opts(5, 7, 0.0, None), L.Opts(5, 0, 2.0, None),
-              L.Opts(5, 0, 0.0, None, 2, 0), L.Opts(5, 0, 0.0, None, 0, 2), L.Opts(5, 0, 0.0, None, 0, -1)):
+              L.Opts(5, 0, 0.0, None, 2, 0), L.Opts(5, 0, 0.0, None, 0, 3), L.Opts(5, 0, 0.0, None, 0, -1),
+              L.Opts(5, 0, 0.0, None, 0, 2, -1.0), L.Opts(5, 0, 0.0, None, 0, 2, float("inf"))):
         assert L.lib().lrp_create(ctypes.byref(h), 255, 8, 1e-10, ctypes.byref(o)) == L.LRP_EINVAL
 
 
@@ -59,7 +60,7 @@ def test_null_context_and_arguments():
 
 
 def test_struct_layouts_match_header():
-    assert ctypes.sizeof(L.Opts) == 32
+    assert ctypes.sizeof(L.Opts) == 48 and L.Opts.ls_oversampling.offset == 32 and L.Opts.seed.offset == 40
     assert L.Opts.prune_tau.offset == 8 and L.Opts.stream.offset == 16 and L.Opts.flags.offset == 24
     assert ctypes.sizeof(L.KernelTime) == 24 and L.KernelTime.ms.offset == 16
     assert ctypes.sizeof(L.Info) == 48
