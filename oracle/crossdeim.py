@@ -54,6 +54,11 @@ the design notes of the repository):
     and appended in ascending index order; when none was kept (and the cap allows), the
     safeguard of Algorithm 4 appends a random index of the complement: the one with the
     largest -1 - u_i (computed in FP64; ties to the smaller index).
+  * the test matrices of Section 4.2 are square (m = n) with 0-based indices: H(i, j) =
+    1/(1 + i + j) is then the Hilbert matrix, and K uses the grid x_i = -1 + 2 i/(n - 1) on
+    both sides. Cross-DEIM on them starts from the truncated SVD of a given guess U0 V0^T
+    (Algorithm 4's inputs; the tests draw seeded Gaussian guesses) and returns the cross
+    approximation itself, truncated as the Poisson solve.
   * the initial guess U0, V0 of Algorithm 4 is given in physical space (the space of
     the solver's output factors, e.g. a previous solution U_W, S, V_W) with optional
     weights S0: the warm start is then the truncated SVD of
@@ -186,10 +191,13 @@ def scross(Uh, Vh, lam, I: Sequence[int], J: Sequence[int]) -> Cross:
     SVD of M = U^ S V~^T gives U = Q U^, V = Z V~ (the SVD of the |J| x n matrix in the
     listing has the same singular values and left factor).
     """
+    return scross_fibers(columns(Uh, Vh, lam, J), rows(Uh, Vh, lam, I).T, I, J)
+
+
+def scross_fibers(C: np.ndarray, Rt: np.ndarray, I: Sequence[int], J: Sequence[int]) -> Cross:
+    """Algorithm 1 from the fibers C = G(:, J) (n x |J|) and R^T = G(I, :)^T (n x |I|) of any G."""
     I = list(I)
     J = list(J)
-    C = columns(Uh, Vh, lam, J)
-    Rt = rows(Uh, Vh, lam, I).T
     Q, RC = thin_qr(C)
     Zq, RR = thin_qr(Rt)
     if len(J) <= len(I):
@@ -504,6 +512,64 @@ def final_rank(S: np.ndarray, tol: float, r_max: int) -> int:
     return max(min(r_star, r_max), 1)
 
 
+def _cross_deim(n, fibers, ws, r_max, tol, maxiter, prune_tau, stop_at_fixed_point, replay, selector,
+                ls_oversampling, seed):
+    """Algorithm 4 from the starting iterate ws = (U_{-1}, S_{-1}, V_{-1}); fibers(I, J) returns
+    (G(:, J), G(I, :)^T). Returns the last iterate, status, passes and the trace."""
+    if selector not in ("ls", "qdeim", "ls_sampled"):
+        raise ValueError(f"unknown selector {selector!r}")
+    U_prev, S_prev, V_prev = ws
+    I: List[int] = []
+    J: List[int] = []
+    pre_prev = None
+    trace: List[IterRecord] = []
+    status = STATUS_NOT_CONVERGED
+    rho = math.inf
+    ind = math.inf
+    iters = 0
+    for k in range(maxiter):
+        r_sig = int(np.count_nonzero(S_prev > tol * S_prev[0]))
+        if replay is not None and k < len(replay):
+            rI = [int(i) for i in replay[k][0]]
+            rJ = [int(j) for j in replay[k][1]]
+            selI = Selection(rI, [i for i in rI if i not in I], math.inf)
+            selJ = Selection(rJ, [j for j in rJ if j not in J], math.inf)
+        elif selector == "qdeim":
+            selI = qdeim_select(U_prev, r_sig, I, r_max, k == 0)
+            selJ = qdeim_select(V_prev, r_sig, J, r_max, k == 0)
+        elif selector == "ls_sampled":
+            selI = sampled_select(U_prev, r_sig, I, r_max, ls_oversampling, sample_uniforms(n, k, 0, seed))
+            selJ = sampled_select(V_prev, r_sig, J, r_max, ls_oversampling, sample_uniforms(n, k, 1, seed))
+        else:
+            selI = select(U_prev, r_sig, I, r_max)
+            selJ = select(V_prev, r_sig, J, r_max)
+        pre = (selI.indices, selJ.indices)
+        if stop_at_fixed_point and pre_prev is not None and pre == pre_prev:
+            status = STATUS_STAGNATED
+            break
+        C, Rt = fibers(selI.indices, selJ.indices)
+        cr = scross_fibers(C, Rt, selI.indices, selJ.indices)
+        iters += 1
+        I = prune(selI.indices, cr.rR, prune_tau)
+        J = prune(selJ.indices, cr.rC, prune_tau)
+        ind, eta1, eta2 = indicator(cr.U, cr.S, cr.V, I, J)
+        nrm = float(np.linalg.norm(cr.S))
+        if k == 0:
+            rho = math.inf
+        else:
+            rho = lr_diff_norm(cr.U, cr.S, cr.V, U_prev, S_prev, V_prev) / nrm
+        trace.append(
+            IterRecord(k, selI.indices, selJ.indices, I, J, r_sig, cr.S.size, cr.S, rho, ind,
+                       eta1, eta2, selI.gap, selJ.gap, cr.branch)
+        )
+        U_prev, S_prev, V_prev = cr.U, cr.S, cr.V
+        pre_prev = pre
+        if max(rho, ind) < tol:
+            status = STATUS_OK
+            break
+    return U_prev, S_prev, V_prev, status, iters, I, J, rho, ind, trace
+
+
 def solve(
     n: int,
     U_F: np.ndarray,
@@ -544,56 +610,59 @@ def solve(
     if ws is None:  # F = 0: the solution is 0
         z = np.zeros((n, 1))
         return Result(z, np.zeros(1), z.copy(), 1, STATUS_OK, 0, [], [], 0.0, 0.0, [])
-    U_prev, S_prev, V_prev = ws
-    I: List[int] = []
-    J: List[int] = []
-    pre_prev = None
-    trace: List[IterRecord] = []
-    status = STATUS_NOT_CONVERGED
-    rho = math.inf
-    ind = math.inf
-    iters = 0
-    for k in range(maxiter):
-        r_sig = int(np.count_nonzero(S_prev > tol * S_prev[0]))
-        if replay is not None and k < len(replay):
-            rI = [int(i) for i in replay[k][0]]
-            rJ = [int(j) for j in replay[k][1]]
-            selI = Selection(rI, [i for i in rI if i not in I], math.inf)
-            selJ = Selection(rJ, [j for j in rJ if j not in J], math.inf)
-        elif selector == "qdeim":
-            selI = qdeim_select(U_prev, r_sig, I, r_max, k == 0)
-            selJ = qdeim_select(V_prev, r_sig, J, r_max, k == 0)
-        elif selector == "ls_sampled":
-            selI = sampled_select(U_prev, r_sig, I, r_max, ls_oversampling, sample_uniforms(n, k, 0, seed))
-            selJ = sampled_select(V_prev, r_sig, J, r_max, ls_oversampling, sample_uniforms(n, k, 1, seed))
-        else:
-            selI = select(U_prev, r_sig, I, r_max)
-            selJ = select(V_prev, r_sig, J, r_max)
-        pre = (selI.indices, selJ.indices)
-        if stop_at_fixed_point and pre_prev is not None and pre == pre_prev:
-            status = STATUS_STAGNATED
-            break
-        cr = scross(Uh, Vh, lam, selI.indices, selJ.indices)
-        iters += 1
-        I = prune(selI.indices, cr.rR, prune_tau)
-        J = prune(selJ.indices, cr.rC, prune_tau)
-        ind, eta1, eta2 = indicator(cr.U, cr.S, cr.V, I, J)
-        nrm = float(np.linalg.norm(cr.S))
-        if k == 0:
-            rho = math.inf
-        else:
-            rho = lr_diff_norm(cr.U, cr.S, cr.V, U_prev, S_prev, V_prev) / nrm
-        trace.append(
-            IterRecord(k, selI.indices, selJ.indices, I, J, r_sig, cr.S.size, cr.S, rho, ind,
-                       eta1, eta2, selI.gap, selJ.gap, cr.branch)
-        )
-        U_prev, S_prev, V_prev = cr.U, cr.S, cr.V
-        pre_prev = pre
-        if max(rho, ind) < tol:
-            status = STATUS_OK
-            break
+
+    def fibers(I, J):
+        return columns(Uh, Vh, lam, J), rows(Uh, Vh, lam, I).T
+
+    U_prev, S_prev, V_prev, status, iters, I, J, rho, ind, trace = _cross_deim(
+        n, fibers, ws, r_max, tol, maxiter, prune_tau, stop_at_fixed_point, replay, selector, ls_oversampling, seed)
     r = final_rank(S_prev, tol, r_max)
     U_out = dst1(U_prev[:, :r])
     V_out = dst1(V_prev[:, :r])
     return Result(U_out, S_prev[:r].copy(), V_out, r, status, iters, I, J, rho, ind, trace,
                   U_prev, S_prev, V_prev)
+
+
+# ----------------------------------------------------------------------------------------
+# Cross-DEIM on the paper's test matrices (Section 4.2): G given entrywise
+# ----------------------------------------------------------------------------------------
+def hilbert(n: int, I: Sequence[int], J: Sequence[int]) -> np.ndarray:
+    """H(i, j) = 1/(1 + i + j) with 0-based i, j (the Hilbert matrix 1/(i + j - 1), 1-based)."""
+    i = np.asarray(I, dtype=np.float64)[:, None]
+    j = np.asarray(J, dtype=np.float64)[None, :]
+    return 1.0 / (1.0 + i + j)
+
+
+def kmatrix(n: int, I: Sequence[int], J: Sequence[int]) -> np.ndarray:
+    """K(i, j) = (|x_i + y_j| / 2)^5 on the grid x_i = y_i = -1 + 2 i/(n - 1), i = 0..n-1
+    (Section 4.2, 1-based there); the fifth power is formed as ((t t)(t t)) t."""
+    x = -1.0 + 2.0 * np.asarray(I, dtype=np.float64) / (n - 1)
+    y = -1.0 + 2.0 * np.asarray(J, dtype=np.float64) / (n - 1)
+    t = np.abs(x[:, None] + y[None, :]) / 2.0
+    t2 = t * t
+    return (t2 * t2) * t
+
+
+MATRICES = {"hilbert": hilbert, "k": kmatrix}
+
+
+def solve_matrix(kind: str, n: int, U0: np.ndarray, V0: np.ndarray, r_max: int, tol: float, maxiter: int,
+                 prune_tau: float = 1e-12, selector: str = "ls", ls_oversampling: float = 2.0, seed: int = 0,
+                 replay=None) -> Result:
+    """Cross-DEIM (Algorithm 4 with Algorithm 1) on the n x n test matrix `kind` ("hilbert" or
+    "k"), started from the truncated SVD of the guess U0 V0^T (Algorithm 4's inputs U0, V0;
+    truncated at r0 eps sigma_1 as the Poisson warm start). Returns G ~= U diag(S) V^T."""
+    g = MATRICES[kind]
+    ws = warm_start(np.asarray(U0, dtype=np.float64), np.asarray(V0, dtype=np.float64))
+    if ws is None:
+        raise ValueError("the initial guess is zero")
+
+    def fibers(I, J):
+        all_rows = np.arange(n)
+        return g(n, all_rows, J), g(n, I, all_rows).T
+
+    U_prev, S_prev, V_prev, status, iters, I, J, rho, ind, trace = _cross_deim(
+        n, fibers, ws, r_max, tol, maxiter, prune_tau, True, replay, selector, ls_oversampling, seed)
+    r = final_rank(S_prev, tol, r_max)
+    return Result(U_prev[:, :r].copy(), S_prev[:r].copy(), V_prev[:, :r].copy(), r, status, iters, I, J, rho,
+                  ind, trace, U_prev, S_prev, V_prev)

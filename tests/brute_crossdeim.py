@@ -162,32 +162,8 @@ class Pass:
         self.__dict__.update(kw)
 
 
-def solve(n, U_F, sigma, V_F, r_max, tol, maxiter, prune_tau=1e-12, warm=None, replay=None,
-          selector="ls"):
-    """Algorithm 4 on the dense W^; returns a dict with the physical factors and the trace."""
-    Z = sine_matrix(n)
-    G = spectral_solution(n, U_F, sigma, V_F)
-    h = 1.0 / (n + 1)
-    Fh = Z @ ((np.asarray(U_F) * (h * h * np.asarray(sigma))[None, :]) @ np.asarray(V_F).T) @ Z
-    rF = np.asarray(U_F).shape[1]
-
-    def start(M, rank_cap):
-        Ua, s, Vt = np.linalg.svd(M)
-        if s[0] == 0.0:
-            return None
-        r = int(np.sum(s > rank_cap * EPS * s[0]))
-        return Ua[:, :r], s[:r], Vt[:r].T
-
-    it = start(Fh, rF)
-    if it is None:
-        z = np.zeros((n, 1))
-        return {"U": z, "S": np.zeros(1), "V": z, "rank": 1, "status": 0, "iters": 0, "passes": []}
-    if warm is not None:
-        U0, S0, V0 = warm
-        S0 = np.ones(np.asarray(U0).shape[1]) if S0 is None else np.asarray(S0)
-        g = start(Z @ ((np.asarray(U0) * S0[None, :]) @ np.asarray(V0).T) @ Z, np.asarray(U0).shape[1])
-        if g is not None:
-            it = g
+def cross_deim_dense(G, it, r_max, tol, maxiter, prune_tau=1e-12, replay=None, selector="ls"):
+    """Algorithm 4 on a dense G from the starting iterate it = (U, S, V)."""
     Up, Sp, Vp = it
     I: List[int] = []
     J: List[int] = []
@@ -233,10 +209,61 @@ def solve(n, U_F, sigma, V_F, r_max, tol, maxiter, prune_tau=1e-12, warm=None, r
         if max(rho, ind) < tol:
             status = 0
             break
+    return Up, Sp, Vp, status, iters, passes, I, J
+
+
+def final_rank_scan(Sp, tol, r_max):
+    """Smallest r whose tail of squared singular values is below (tol ||S||)^2, scanning upwards."""
     total = float(np.sum(Sp * Sp))
     r = 0
     while r < Sp.size and float(np.sum(Sp[r:] ** 2)) >= (tol * math.sqrt(total)) ** 2:
         r += 1
-    r = max(min(r, r_max), 1)
+    return max(min(r, r_max), 1)
+
+
+def solve(n, U_F, sigma, V_F, r_max, tol, maxiter, prune_tau=1e-12, warm=None, replay=None,
+          selector="ls"):
+    """Algorithm 4 on the dense W^; returns a dict with the physical factors and the trace."""
+    Z = sine_matrix(n)
+    G = spectral_solution(n, U_F, sigma, V_F)
+    h = 1.0 / (n + 1)
+    Fh = Z @ ((np.asarray(U_F) * (h * h * np.asarray(sigma))[None, :]) @ np.asarray(V_F).T) @ Z
+    rF = np.asarray(U_F).shape[1]
+
+    def start(M, rank_cap):
+        Ua, s, Vt = np.linalg.svd(M)
+        if s[0] == 0.0:
+            return None
+        r = int(np.sum(s > rank_cap * EPS * s[0]))
+        return Ua[:, :r], s[:r], Vt[:r].T
+
+    it = start(Fh, rF)
+    if it is None:
+        z = np.zeros((n, 1))
+        return {"U": z, "S": np.zeros(1), "V": z, "rank": 1, "status": 0, "iters": 0, "passes": []}
+    if warm is not None:
+        U0, S0, V0 = warm
+        S0 = np.ones(np.asarray(U0).shape[1]) if S0 is None else np.asarray(S0)
+        g = start(Z @ ((np.asarray(U0) * S0[None, :]) @ np.asarray(V0).T) @ Z, np.asarray(U0).shape[1])
+        if g is not None:
+            it = g
+    Up, Sp, Vp, status, iters, passes, I, J = cross_deim_dense(G, it, r_max, tol, maxiter, prune_tau, replay,
+                                                              selector)
+    r = final_rank_scan(Sp, tol, r_max)
     return {"U": Z @ Up[:, :r], "S": Sp[:r].copy(), "V": Z @ Vp[:, :r], "rank": r, "status": status,
+            "iters": iters, "passes": passes, "I": I, "J": J}
+
+
+def solve_matrix(G, U0, V0, r_max, tol, maxiter, prune_tau=1e-12, selector="ls"):
+    """Algorithm 4 on an explicit dense matrix G, started from the SVD of U0 V0^T (truncated at
+    r0 eps sigma_1); returns a dict as solve (no sine transforms)."""
+    M = np.asarray(U0) @ np.asarray(V0).T
+    Ua, s, Vt = np.linalg.svd(M)
+    r0 = np.asarray(U0).shape[1]
+    r = int(np.sum(s > r0 * EPS * s[0]))
+    it = (Ua[:, :r], s[:r], Vt[:r].T)
+    Up, Sp, Vp, status, iters, passes, I, J = cross_deim_dense(G, it, r_max, tol, maxiter, prune_tau, None,
+                                                              selector)
+    r = final_rank_scan(Sp, tol, r_max)
+    return {"U": Up[:, :r], "S": Sp[:r].copy(), "V": Vp[:, :r], "rank": r, "status": status,
             "iters": iters, "passes": passes, "I": I, "J": J}

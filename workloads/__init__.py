@@ -33,6 +33,8 @@ __all__ = [
     "make",
     "served_stream",
     "sketch_matrix",
+    "matrix_guess",
+    "MATRIX_CONFIGS",
 ]
 
 
@@ -217,3 +219,24 @@ def sketch_matrix(n: int, k: int = 64, seed: int = 777) -> np.ndarray:
     solutions at sizes where the n x n product cannot be formed: ||Om^T (A - B) Om'||_F
     estimates ||A - B||_F up to the factor k."""
     return np.random.default_rng(seed).standard_normal((n, k))
+
+
+def matrix_guess(n: int, r0: int, seed: int = 0):
+    """Seeded initial guess (U0, V0) for Cross-DEIM on a test matrix: two n x r0 standard
+    Gaussian matrices (column-major), drawn U0 first."""
+    rng = np.random.default_rng(seed)
+    U0 = np.asfortranarray(rng.standard_normal((n, r0)))
+    V0 = np.asfortranarray(rng.standard_normal((n, r0)))
+    return U0, V0
+
+
+# Cross-DEIM on the paper's test matrices (Section 4.2: the Hilbert matrix to 1e-9 and the K
+# matrix to 1e-6); three sizes each, rank cap 64, a seeded rank-8 Gaussian initial guess.
+MATRIX_CONFIGS = {
+    "hilbert_n1000": ("hilbert", 1000, 1e-9),
+    "hilbert_n16384": ("hilbert", 16384, 1e-9),
+    "hilbert_n262144": ("hilbert", 262144, 1e-9),
+    "k_n1000": ("k", 1000, 1e-6),
+    "k_n16384": ("k", 16384, 1e-6),
+    "k_n262144": ("k", 262144, 1e-6),
+}
