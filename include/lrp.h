@@ -70,7 +70,18 @@ typedef struct lrp_opts {
                              oversampling c = rho r_sig of Algorithm 3; 0 -> 2; must be finite
                              and >= 0 */
   uint64_t seed;     /* LRP_SEL_LEVERAGE_SAMPLED: key of the Philox4x32-10 generator */
+  int32_t matrix;    /* enum lrp_matrix: the matrix G whose cross approximation is computed;
+                        other values -> LRP_EINVAL */
+  int32_t reserved;  /* must be 0 */
 } lrp_opts;
+
+enum lrp_matrix {
+  LRP_MAT_POISSON = 0,  /* the spectral solution of the Poisson problem (lrp_solve) */
+  LRP_MAT_HILBERT = 1,  /* H(i, j) = 1/(1 + i + j), 0-based: the Hilbert matrix (Section 4.2;
+                           lrp_cross_solve) */
+  LRP_MAT_K = 2         /* K(i, j) = (|x_i + x_j|/2)^5 on the grid x_i = -1 + 2 i/(n - 1), a C^4
+                           function with a kink along x + y = 0 (Section 4.2; lrp_cross_solve) */
+};
 
 enum lrp_selector {
   LRP_SEL_LEVERAGE = 0,  /* leverage scores (Algorithm 3): the r_sig largest scores outside the
@@ -116,7 +127,8 @@ typedef struct lrp_info {
 /*
  * lrp_create -- context for grids of n interior points per dimension and rank cap r_max.
  *   ctx    out (host): receives the context.
- *   n      grid size; n+1 must be a power of two, 4 <= n+1 <= 2^23.
+ *   n      grid size; n+1 must be a power of two, 4 <= n+1 <= 2^23 (for the test matrices of
+ *          opts.matrix: 2 <= n <= 2^23).
  *   r_max  rank cap of the result and cap of each index set, 1 <= r_max <= 64, r_max <= n.
  *   tol    tolerance eps of Algorithm 4, relative to ||S_k||_F; tol >= 0.
  *   opts   host, may be NULL (defaults).
@@ -146,6 +158,23 @@ int lrp_create(lrp_ctx** ctx, int64_t n, int32_t r_max, double tol, const lrp_op
 int lrp_solve(lrp_ctx* ctx, int32_t r_F, const double* U_F, int64_t ldu, const double* sigma_F,
               const double* V_F, int64_t ldv, double* U_out, int64_t ldou, double* S_out,
               double* V_out, int64_t ldov, int32_t* r_out, lrp_info* info);
+
+/*
+ * lrp_cross_solve -- Cross-DEIM (Algorithm 4 with Algorithm 1) on the n x n test matrix the
+ * context was created for (opts.matrix = LRP_MAT_HILBERT or LRP_MAT_K; any n >= 2), started from
+ * the initial guess U0 V0^T of Algorithm 4: its truncated SVD (thin QRs of U0 and V0, SVD of
+ * R_u R_v^T, truncated at r0 eps sigma_1) is the first iterate. Returns G ~= U diag(S) V^T, the
+ * cross approximation truncated at the tolerance (no transform: U, V are the iterate's
+ * orthonormal factors).
+ *   r0       columns of the guess, 1 <= r0 <= r_max.
+ *   U0, V0   device, n x r0, leading dimensions ldu0, ldv0 >= n.
+ *   U_out, S_out, V_out, r_out, info   as in lrp_solve.
+ * Returns as lrp_solve; LRP_ENUMERIC for a zero or non-finite guess, LRP_EINVAL on a Poisson
+ * context (and lrp_solve returns LRP_EINVAL on a test-matrix context).
+ */
+int lrp_cross_solve(lrp_ctx* ctx, int32_t r0, const double* U0, int64_t ldu0, const double* V0, int64_t ldv0,
+                    double* U_out, int64_t ldou, double* S_out, double* V_out, int64_t ldov, int32_t* r_out,
+                    lrp_info* info);
 
 /*
  * lrp_get_index_sets -- the pruned row set I and column set J of the iterate returned by the

@@ -150,16 +150,23 @@ int create_impl(lrp_ctx* c) {
   TRY(dalloc(&c->st, 1));
   if (hipHostMalloc((void**)&c->st_host, sizeof(DevState)) != hipSuccess) return LRP_ENOMEM;
   if (hipHostMalloc((void**)&c->done_host, 2 * sizeof(int)) != hipSuccess) return LRP_ENOMEM;
-  TRY(dalloc(&c->lam, n));
-  TRY(dalloc(&c->lam32, n));
+  const bool poisson = c->matrix == LRP_MAT_POISSON;
+  if (poisson) {
+    TRY(dalloc(&c->lam, n));
+    TRY(dalloc(&c->lam32, n));
+  }
   if (mixed) {
-    TRY(dalloc(&c->Uh32, np));
-    TRY(dalloc(&c->Vh32, np));
+    if (poisson) {
+      TRY(dalloc(&c->Uh32, np));
+      TRY(dalloc(&c->Vh32, np));
+    }
     TRY(dalloc(&c->C32, np));
     TRY(dalloc(&c->Rt32, np));
   } else {
-    TRY(dalloc(&c->Uh, np));
-    TRY(dalloc(&c->Vh, np));
+    if (poisson) {
+      TRY(dalloc(&c->Uh, np));
+      TRY(dalloc(&c->Vh, np));
+    }
     TRY(dalloc(&c->C, np));
     TRY(dalloc(&c->Rt, np));
   }
@@ -187,9 +194,9 @@ int create_impl(lrp_ctx* c) {
   TRY(dalloc(&c->replay.J, mi * kPMax));
   TRY(dalloc(&c->replay.nI, mi));
   TRY(dalloc(&c->replay.nJ, mi));
-  // DST tables and work
-  TRY(dst_plan(&c->dst, n, 2 * pm));
-  {
+  // DST tables and work (the Poisson solve only)
+  if (poisson) TRY(dst_plan(&c->dst, n, 2 * pm));
+  if (poisson) {
     const int c1 = c->dst.t1_count, c2 = std::max(c->dst.t2_count, 1);
     TRY(dalloc(&c->dst.t1_64, c1));
     TRY(dalloc(&c->dst.t1_32, c1));
@@ -210,8 +217,10 @@ int create_impl(lrp_ctx* c) {
       hipEventCreateWithFlags(&c->evit[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->evit[1], hipEventDisableTiming) != hipSuccess)
     return LRP_EDEVICE;
-  TRY(lambda_launch(c->lam, c->lam32, n, c->stream));
-  TRY(dst_tables(&c->dst, c->stream));
+  if (poisson) {
+    TRY(lambda_launch(c->lam, c->lam32, n, c->stream));
+    TRY(dst_tables(&c->dst, c->stream));
+  }
   if (hipStreamSynchronize(c->stream) != hipSuccess) return LRP_EDEVICE;
   return LRP_OK;
 }
@@ -307,6 +316,7 @@ int enqueue_pass_update(lrp_ctx* c, int k) {
   fa.Rt = mixed ? (void*)c->Rt32 : (void*)c->Rt;
   fa.ldc = n;
   fa.n = n;
+  fa.matrix = c->matrix;
   TRY(fiber_launch(fa, mixed, s));
   TsqrIO io{};
   io.st = c->st;
@@ -550,6 +560,77 @@ int enqueue_start(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const doub
   return enqueue_selection(c, U);
 }
 
+// Stage 1 of a Cross-DEIM run on a test matrix (Section 4.2): state reset, input scan, the
+// guess copied into the iterate buffers of pass 0's new side, its truncated SVD (thin QRs of U0
+// and V0, SVD of R_u R_v^T, truncated at r0 eps sigma_1) as the starting iterate, and the
+// candidates of the first selection.
+int enqueue_start_matrix(lrp_ctx* c, int r0, const double* U0, int64_t ldu0, const double* V0, int64_t ldv0) {
+  const int64_t n = c->n;
+  hipStream_t s = c->stream;
+  const double eps = c->precision == LRP_MIXED ? std::max(c->tol, 1e-7) : c->tol;
+  if (hipEventRecord(c->ev0, s) != hipSuccess) return LRP_EDEVICE;
+  TRY(init_state_launch(c->st, r0, eps, c->tau, c->replay_n, s));
+  TRY(scan_inputs_launch(c->st, U0, ldu0, V0, ldv0, nullptr, n, r0, s));
+  TRY(copy_cols_launch(c->st, U0, ldu0, c->Uit[1], n, n, r0, r0, s, 0));
+  TRY(copy_cols_launch(c->st, V0, ldv0, c->Vit[1], n, n, r0, r0, s, 0));
+  TsqrIO io{};
+  io.st = c->st;
+  io.nsides = 2;
+  io.X[0] = c->Uit[1];
+  io.X[1] = c->Vit[1];
+  io.x_f32 = 0;
+  io.ldx = n;
+  io.Q[0] = c->Q[0];
+  io.Q[1] = c->Q[1];
+  io.ldq = n;
+  TRY(tsqr_run(c->tsqr, io, s));
+  CoreArgs ca{};
+  ca.st = c->st;
+  ca.R0 = tsqr_R(c->tsqr, 0);
+  ca.R1 = tsqr_R(c->tsqr, 1);
+  ca.pmax = c->r_max;
+  ca.Uhat = c->Uhat;
+  ca.Vtil = c->Vtil;
+  ca.nb = 0;
+  ca.trace = c->trace;
+  ca.maxiter = c->maxiter;
+  ca.zero_is_error = 1;
+  TRY(core_launch(ca, true, s));
+  ProdArgs pa{};
+  pa.st = c->st;
+  pa.Q[0] = c->Q[0];
+  pa.Q[1] = c->Q[1];
+  pa.ldq = n;
+  pa.B[0] = c->Uhat;
+  pa.B[1] = c->Vtil;
+  pa.pmax = c->r_max;
+  pa.out[0] = c->Uit[0];
+  pa.out[1] = c->Vit[0];
+  pa.ldo = n;
+  pa.n = n;
+  pa.nb = 0;
+  TRY(prod_launch(pa, s));
+  const double* U[2] = {c->Uit[0], c->Vit[0]};
+  return enqueue_selection(c, U);
+}
+
+// Stage 3 of a test-matrix run: final truncation and the returned iterate copied into the
+// caller's buffers (there is no transform back), state read-back.
+int enqueue_finish_matrix(lrp_ctx* c, double* U_out, int64_t ldou, double* S_out, double* V_out, int64_t ldov) {
+  const int64_t n = c->n;
+  const int pm = c->r_max;
+  hipStream_t s = c->stream;
+  TRY(finalize_launch(c->st, S_out, pm, s));
+  TRY(copy_ret_launch(c->st, c->Uit[0], c->Uit[1], n, U_out, ldou, pm, s));
+  TRY(copy_ret_launch(c->st, c->Vit[0], c->Vit[1], n, V_out, ldov, pm, s));
+  if (hipEventRecord(c->ev1, s) != hipSuccess) return LRP_EDEVICE;
+  prof_begin(s, K_COPY);
+  if (hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return LRP_EDEVICE;
+  prof_end(s);
+  return hipEventRecord(c->evfin, s) == hipSuccess ? LRP_OK : LRP_EDEVICE;
+}
+
 // Pass k: the launch sequence depends only on the parity of k (which iterate buffer is
 // new), so each parity is captured once into a hipGraph and replayed; if capture is not
 // possible the kernels are launched directly.
@@ -657,10 +738,12 @@ int collect(lrp_ctx* c, int32_t* r_out, lrp_info* info) {
 int check_solve_args(int64_t n, int r_max, int32_t r_F, const double* U_F, int64_t ldu, const double* sigma_F,
                      const double* V_F, int64_t ldv, const double* U_out, int64_t ldou, const double* S_out,
                      const double* V_out, int64_t ldov) {
-  if (!U_F || !sigma_F || !V_F || !U_out || !S_out || !V_out) return LRP_EINVAL;
+  if (!U_F || !V_F || !U_out || !S_out || !V_out) return LRP_EINVAL;
   if (r_F < 1 || r_F > r_max) return LRP_EINVAL;
   if (ldu < n || ldv < n || ldou < n || ldov < n) return LRP_EINVAL;
-  const Range in[3] = {span(U_F, n, ldu, r_F, 8), span(V_F, n, ldv, r_F, 8), span(sigma_F, r_F, r_F, 1, 8)};
+  // sigma_F may be null (a guess without weights): it then overlaps nothing
+  const Range in[3] = {span(U_F, n, ldu, r_F, 8), span(V_F, n, ldv, r_F, 8),
+                       sigma_F ? span(sigma_F, r_F, r_F, 1, 8) : Range{0, 0}};
   const Range out[3] = {span(U_out, n, ldou, r_max, 8), span(V_out, n, ldov, r_max, 8), span(S_out, r_max, r_max, 1, 8)};
   for (int a = 0; a < 3; ++a) {
     for (int b = 0; b < 3; ++b)
@@ -723,7 +806,10 @@ int solve_impl(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const double*
     lrp_ctx* c;
     ~GuessScope() { c->guess_r0 = 0; }
   } gscope{c};
-  TRY(enqueue_start(c, rF, U_F, ldu, sigma_F, V_F, ldv));
+  if (c->matrix == LRP_MAT_POISSON)
+    TRY(enqueue_start(c, rF, U_F, ldu, sigma_F, V_F, ldv));
+  else
+    TRY(enqueue_start_matrix(c, rF, U_F, ldu, V_F, ldv));
   // passes; the stop flag of pass k is copied right after its decision, and the host reads it
   // while the device runs pass k's candidate selection, so no pass is enqueued after the stop
   // (only the selection of the last pass, whose kernels return at once)
@@ -732,7 +818,10 @@ int solve_impl(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const double*
     if (hipEventSynchronize(c->evit[k & 1]) != hipSuccess) return LRP_EDEVICE;
     if (c->done_host[k & 1]) break;
   }
-  TRY(enqueue_finish(c, U_out, ldou, S_out, V_out, ldov));
+  if (c->matrix == LRP_MAT_POISSON)
+    TRY(enqueue_finish(c, U_out, ldou, S_out, V_out, ldov));
+  else
+    TRY(enqueue_finish_matrix(c, U_out, ldou, S_out, V_out, ldov));
   if (hipEventSynchronize(c->evfin) != hipSuccess) return LRP_EDEVICE;
   if (c->profile) {
     g_prof = nullptr;
@@ -762,11 +851,16 @@ const char* lrp_strerror(int code) {
 int lrp_create(lrp_ctx** ctx, int64_t n, int32_t r_max, double tol, const lrp_opts* opts) {
   if (!ctx) return LRP_EINVAL;
   *ctx = nullptr;
-  if (n < 3 || !pow2(n + 1) || n + 1 > (int64_t(1) << 23)) return LRP_EINVAL;
-  if (r_max < 1 || r_max > kPMax || r_max > n) return LRP_EINVAL;
-  if (!(tol >= 0.0) || !std::isfinite(tol)) return LRP_EINVAL;
   lrp_opts o{};
   if (opts) o = *opts;
+  if (o.matrix != LRP_MAT_POISSON && o.matrix != LRP_MAT_HILBERT && o.matrix != LRP_MAT_K) return LRP_EINVAL;
+  if (o.matrix == LRP_MAT_POISSON) {
+    if (n < 3 || !pow2(n + 1) || n + 1 > (int64_t(1) << 23)) return LRP_EINVAL;
+  } else if (n < 2 || n > (int64_t(1) << 23)) {
+    return LRP_EINVAL;
+  }
+  if (r_max < 1 || r_max > kPMax || r_max > n) return LRP_EINVAL;
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return LRP_EINVAL;
   if (o.maxiter < 0 || o.maxiter > 1000) return LRP_EINVAL;
   if (o.precision != LRP_FP64 && o.precision != LRP_MIXED) return LRP_EINVAL;
   if (!(o.prune_tau >= 0.0) || o.prune_tau >= 1.0) return LRP_EINVAL;
@@ -774,6 +868,7 @@ int lrp_create(lrp_ctx** ctx, int64_t n, int32_t r_max, double tol, const lrp_op
       (o.selector != LRP_SEL_LEVERAGE && o.selector != LRP_SEL_QDEIM && o.selector != LRP_SEL_LEVERAGE_SAMPLED))
     return LRP_EINVAL;
   if (!(o.ls_oversampling >= 0.0) || !std::isfinite(o.ls_oversampling)) return LRP_EINVAL;
+  if (o.reserved != 0) return LRP_EINVAL;
   lrp_ctx* c = new (std::nothrow) lrp_ctx();
   if (!c) return LRP_ENOMEM;
   c->n = n;
@@ -784,6 +879,7 @@ int lrp_create(lrp_ctx** ctx, int64_t n, int32_t r_max, double tol, const lrp_op
   c->tau = o.prune_tau > 0.0 ? o.prune_tau : (o.precision == LRP_MIXED ? 1e-7 : 1e-12);
   c->profile = (o.flags & LRP_FLAG_PROFILE) != 0;
   c->selector = o.selector;
+  c->matrix = o.matrix;
   c->ls_rho = o.ls_oversampling > 0.0 ? o.ls_oversampling : 2.0;
   c->seed = o.seed;
   if (o.stream) {
@@ -807,11 +903,23 @@ int lrp_create(lrp_ctx** ctx, int64_t n, int32_t r_max, double tol, const lrp_op
 int lrp_solve(lrp_ctx* c, int32_t r_F, const double* U_F, int64_t ldu, const double* sigma_F,
               const double* V_F, int64_t ldv, double* U_out, int64_t ldou, double* S_out,
               double* V_out, int64_t ldov, int32_t* r_out, lrp_info* info) {
-  if (!c || !r_out) return LRP_EINVAL;
+  if (!c || !r_out || !sigma_F || c->matrix != LRP_MAT_POISSON) return LRP_EINVAL;
   const int rc = check_solve_args(c->n, c->r_max, r_F, U_F, ldu, sigma_F, V_F, ldv, U_out, ldou, S_out, V_out, ldov);
   if (rc != LRP_OK) return rc;
   c->solved = false;
   return solve_impl(c, r_F, U_F, ldu, sigma_F, V_F, ldv, U_out, ldou, S_out, V_out, ldov, r_out, info);
+}
+
+int lrp_cross_solve(lrp_ctx* c, int32_t r0, const double* U0, int64_t ldu0, const double* V0, int64_t ldv0,
+                    double* U_out, int64_t ldou, double* S_out, double* V_out, int64_t ldov, int32_t* r_out,
+                    lrp_info* info) {
+  if (!c || !r_out || c->matrix == LRP_MAT_POISSON) return LRP_EINVAL;
+  // the guess takes the place of the right-hand side factors (no weights)
+  const int rc = check_solve_args(c->n, c->r_max, r0, U0, ldu0, nullptr, V0, ldv0, U_out, ldou, S_out, V_out, ldov);
+  if (rc != LRP_OK) return rc;
+  c->solved = false;
+  c->guess_r0 = 0;
+  return solve_impl(c, r0, U0, ldu0, nullptr, V0, ldv0, U_out, ldou, S_out, V_out, ldov, r_out, info);
 }
 
 int64_t lrp_context_bytes(int64_t n, int32_t r_max, int32_t maxiter, int32_t precision) {

@@ -1007,7 +1007,11 @@ __global__ __launch_bounds__(kCoreThreads) void k_core_warm(CoreArgs a) {
     st->nIb[0] = 0;
     st->nJb[0] = 0;
     st->indb[0] = INFINITY;
-    if (r == 0) {  // F = 0: the solution is 0
+    if (r == 0 && a.zero_is_error) {  // a zero starting guess: nothing to start from
+      st->done = 1;
+      st->status = LRP_ENUMERIC;
+      st->r_sig = 0;
+    } else if (r == 0) {  // F = 0: the solution is 0
       st->zero = 1;
       st->done = 1;
       st->status = LRP_OK;
@@ -1133,6 +1137,44 @@ __global__ void k_finalize(DevState* st, double* S_out, int r_max) {
 
 int finalize_launch(DevState* st, double* S_out, int r_max, hipStream_t s) {
   LRP_LAUNCH(K_FINALIZE, k_finalize, dim3(1), dim3(64), 0, s, st, S_out, r_max);
+  return launch_status();
+}
+
+__global__ void k_copy_cols(const DevState* st, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t n,
+                            int cols, int cols_out) {
+  if (st && st->status < 0) return;
+  const int64_t total = n * cols_out;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % n, c = e / n;
+    Y[i + c * ldy] = c < cols ? X[i + c * ldx] : 0.0;
+  }
+}
+
+int copy_cols_launch(const DevState* st, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t n, int cols,
+                     int cols_out, hipStream_t s, int) {
+  const int64_t total = n * cols_out;
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (total + 255) / 256));
+  LRP_LAUNCH(K_FINALIZE, k_copy_cols, dim3(blocks), dim3(256), 0, s, st, X, ldx, Y, ldy, n, cols, cols_out);
+  return launch_status();
+}
+
+__global__ void k_copy_ret(const DevState* st, const double* X0, const double* X1, int64_t n, double* Y, int64_t ldy,
+                           int r_max) {
+  if (st->status < 0) return;
+  const double* X = st->ret ? X1 : X0;
+  const int cols = st->zero ? 0 : st->r_final;
+  const int64_t total = n * r_max;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % n, c = e / n;
+    Y[i + c * ldy] = c < cols ? X[i + c * n] : 0.0;
+  }
+}
+
+int copy_ret_launch(const DevState* st, const double* X0, const double* X1, int64_t n, double* Y, int64_t ldy,
+                    int r_max, hipStream_t s) {
+  const int64_t total = n * r_max;
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (total + 255) / 256));
+  LRP_LAUNCH(K_FINALIZE, k_copy_ret, dim3(blocks), dim3(256), 0, s, st, X0, X1, n, Y, ldy, r_max);
   return launch_status();
 }
 

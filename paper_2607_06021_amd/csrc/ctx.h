@@ -50,6 +50,7 @@ struct lrp_ctx {
   SelectPlan sel{};
   lrp::QdeimPlan qd{};  // QDEIM selection only
   int selector = LRP_SEL_LEVERAGE;
+  int matrix = LRP_MAT_POISSON;  // the matrix G of the cross approximation
   double ls_rho = 2.0;  // sampled leverage scores: p_i = min(1, ls_rho pi_i)
   uint64_t seed = 0;
   RhoPlan rho{};

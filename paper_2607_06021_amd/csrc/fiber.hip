@@ -72,8 +72,50 @@ __global__ __launch_bounds__(256) void k_fiber(FiberArgs a) {
   }
 }
 
+// Fibers of the test matrices of Section 4.2 (square, 0-based indices), from their formulas in
+// FP64 (rounded to FP32 for the mixed-precision path):
+//   H(i, j) = 1/(1 + i + j) (the Hilbert matrix);
+//   K(i, j) = (|x_i + x_j| / 2)^5, x_i = -1 + 2 i/(n - 1), the fifth power as ((t t)(t t)) t.
+// Side 0 writes C(i, c) = G(i, J_c), side 1 R^T(j, c) = G(I_c, j). One thread per grid row,
+// coalesced column-major stores.
+__device__ inline double matrix_entry(int kind, int64_t i, int64_t j, int64_t n) {
+  if (kind == LRP_MAT_HILBERT) return 1.0 / ((1.0 + (double)i) + (double)j);
+  const double x = -1.0 + (2.0 * (double)i) / (double)(n - 1);
+  const double y = -1.0 + (2.0 * (double)j) / (double)(n - 1);
+  const double t = fabs(x + y) / 2.0;
+  const double t2 = t * t;
+  return (t2 * t2) * t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fiber_matrix(FiberArgs a) {
+  const DevState* st = a.st;
+  if (st->done) return;
+  const int side = blockIdx.y;
+  const int nc = side == 0 ? st->nJpre : st->nIpre;
+  const int* idx = side == 0 ? st->Jpre : st->Ipre;
+  T* out = (T*)(side == 0 ? a.C : a.Rt);
+  __shared__ int ix[kPMax];
+  if (threadIdx.x < kPMax) ix[threadIdx.x] = threadIdx.x < nc ? idx[threadIdx.x] : 0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  for (int c = 0; c < nc; ++c) {
+    // side 0: G(i, J_c); side 1: G(I_c, i)
+    const double g = side == 0 ? matrix_entry(a.matrix, i, ix[c], a.n) : matrix_entry(a.matrix, ix[c], i, a.n);
+    out[i + (int64_t)c * a.ldc] = (T)g;
+  }
+}
+
 int fiber_launch(const FiberArgs& a, bool fp32, hipStream_t s) {
   dim3 grid((unsigned)((a.n + 255) / 256), 2);
+  if (a.matrix != LRP_MAT_POISSON) {
+    if (fp32)
+      LRP_LAUNCH(K_FIBER, k_fiber_matrix<float>, grid, dim3(256), 0, s, a);
+    else
+      LRP_LAUNCH(K_FIBER, k_fiber_matrix<double>, grid, dim3(256), 0, s, a);
+    return launch_status();
+  }
   if (fp32)
     LRP_LAUNCH(K_FIBER, k_fiber<float>, grid, dim3(256), 0, s, a);
   else

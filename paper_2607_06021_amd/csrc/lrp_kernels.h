@@ -112,6 +112,8 @@ struct FiberArgs {
   void* Rt;         // n x pmax: R^T = W^(Ipre, :)^T
   int64_t ldc;
   int64_t n;
+  int matrix;       // enum lrp_matrix: LRP_MAT_POISSON uses Uh, Vh, lam; the test matrices are
+                    // evaluated from their formulas
 };
 int fiber_launch(const FiberArgs& a, bool fp32, hipStream_t s);
 
@@ -131,6 +133,7 @@ struct CoreArgs {
   int maxiter;
   int guess;         // warm start only: 1 = from the initial guess (width st->ncols[0]; a zero
                      // guess leaves the start from the right-hand side in place)
+  int zero_is_error; // warm start only: a zero start is an error (LRP_ENUMERIC), not F = 0
 };
 int core_launch(const CoreArgs& a, bool warm, hipStream_t s);
 
@@ -249,6 +252,14 @@ int finalize_launch(DevState* st, double* S_out, int r_max, hipStream_t s);
 int init_state_launch(DevState* st, int rF, double eps, double tau, int replay_n, hipStream_t s);
 // Warm start from a guess of r0 columns: QR widths r0, guess_ok cleared.
 int guess_begin_launch(DevState* st, int r0, hipStream_t s);
+// Y(:, 0:cols) = X(:, 0:cols) for n rows, columns cols..cols_out-1 of Y set to 0 (skipped after an
+// error in st, if given).
+int copy_cols_launch(const DevState* st, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t n, int cols,
+                     int cols_out, hipStream_t s, int unused);
+// The returned iterate (X0 or X1 by st->ret, st->r_final columns, 0 for a zero result) into Y,
+// r_max columns (zeros past the rank).
+int copy_ret_launch(const DevState* st, const double* X0, const double* X1, int64_t n, double* Y, int64_t ldy,
+                    int r_max, hipStream_t s);
 int lambda_launch(double* lam, float* lam32, int64_t n, hipStream_t s);
 
 }  // namespace lrp

@@ -29,12 +29,15 @@ _c_vp = ctypes.c_void_p
 
 class Opts(ctypes.Structure):
     _fields_ = [("maxiter", _c_i32), ("precision", _c_i32), ("prune_tau", _c_dbl), ("stream", _c_vp),
-                ("flags", _c_i32), ("selector", _c_i32), ("ls_oversampling", _c_dbl), ("seed", ctypes.c_uint64)]
+                ("flags", _c_i32), ("selector", _c_i32), ("ls_oversampling", _c_dbl), ("seed", ctypes.c_uint64),
+                ("matrix", _c_i32), ("reserved", _c_i32)]
 
 
 LRP_FLAG_PROFILE = 1
 LRP_SEL_LEVERAGE, LRP_SEL_QDEIM, LRP_SEL_LEVERAGE_SAMPLED = 0, 1, 2
 _SELECTORS = {"ls": LRP_SEL_LEVERAGE, "qdeim": LRP_SEL_QDEIM, "ls_sampled": LRP_SEL_LEVERAGE_SAMPLED}
+LRP_MAT_POISSON, LRP_MAT_HILBERT, LRP_MAT_K = 0, 1, 2
+_MATRICES = {"poisson": LRP_MAT_POISSON, "hilbert": LRP_MAT_HILBERT, "k": LRP_MAT_K}
 
 
 class KernelTime(ctypes.Structure):
@@ -139,6 +142,9 @@ def lib() -> ctypes.CDLL:
     L.lrp_context_bytes.restype = ctypes.c_int64
     L.lrp_get_profile.argtypes = [_c_vp, P(_c_i32), P(KernelTime)]
     L.lrp_get_profile.restype = ctypes.c_int
+    L.lrp_cross_solve.argtypes = [_c_vp, _c_i32, _c_vp, _c_i64, _c_vp, _c_i64, _c_vp, _c_i64, _c_vp, _c_vp, _c_i64,
+                                  P(_c_i32), P(Info)]
+    L.lrp_cross_solve.restype = ctypes.c_int
     L.lrp_tsqr_noalloc.argtypes = [_c_i64, _c_i32, _c_vp, _c_i64, _c_vp, _c_i64, _c_vp, _c_i64, _c_vp]
     L.lrp_tsqr_noalloc.restype = ctypes.c_int
     L.lrp_tsqr_noalloc_max_bytes.argtypes = []
@@ -182,7 +188,7 @@ class Solver:
 
     def __init__(self, n: int, r_max: int, tol: float, maxiter: int = 20, precision: str = "fp64",
                  prune_tau: float = 0.0, stream=None, profile: bool = False, selector: str = "ls",
-                 ls_oversampling: float = 2.0, seed: int = 0):
+                 ls_oversampling: float = 2.0, seed: int = 0, matrix: str = "poisson"):
         import torch
 
         self.n, self.r_max, self.tol = int(n), int(r_max), float(tol)
@@ -195,9 +201,11 @@ class Solver:
         self.stream = stream
         if selector not in _SELECTORS:
             raise ValueError(f"unknown selector {selector!r}")
+        if matrix not in _MATRICES:
+            raise ValueError(f"unknown matrix {matrix!r}")
         o = Opts(self.maxiter, LRP_MIXED if precision == "mixed" else LRP_FP64, float(prune_tau),
                  _c_vp(stream.cuda_stream), LRP_FLAG_PROFILE if profile else 0, _SELECTORS[selector],
-                 float(ls_oversampling), int(seed))
+                 float(ls_oversampling), int(seed), _MATRICES[matrix], 0)
         h = _c_vp()
         _check(lib().lrp_create(ctypes.byref(h), self.n, self.r_max, self.tol, ctypes.byref(o)), "lrp_create")
         self._h = h
@@ -275,6 +283,35 @@ class Solver:
         code = lib().lrp_solve(self._h, rF, pu, ldu, sigma.data_ptr(), pv, ldv, puo, lduo, So.data_ptr(),
                                pvo, ldvo, ctypes.byref(r), ctypes.byref(info))
         _check(code, "lrp_solve", warn_ok=True)
+        return Uo, So, Vo, int(r.value), info
+
+    def cross(self, U0, V0, out=None):
+        """Cross-DEIM on the context's test matrix from the guess U0 V0^T (column-major (n, r0)
+        FP64 CUDA tensors). Returns (U, S, V, rank, info) as solve."""
+        import torch
+
+        n, rm = self.n, self.r_max
+        p0, ld0 = _colmajor(U0, n)
+        q0, lq0 = _colmajor(V0, n)
+        if U0.shape[1] != V0.shape[1]:
+            raise ValueError("U0 and V0 must have the same number of columns")
+        for t in (U0, V0):
+            if t.dtype != torch.float64 or not t.is_cuda:
+                raise ValueError("inputs must be float64 CUDA tensors")
+        if out is None:
+            Uo = empty_fortran(n, rm, torch.float64, U0.device)
+            Vo = empty_fortran(n, rm, torch.float64, U0.device)
+            So = torch.empty(rm, dtype=torch.float64, device=U0.device)
+        else:
+            Uo, So, Vo = out
+        puo, lduo = _colmajor(Uo, n)
+        pvo, ldvo = _colmajor(Vo, n)
+        r = _c_i32(0)
+        info = Info()
+        self._order()
+        code = lib().lrp_cross_solve(self._h, U0.shape[1], p0, ld0, q0, lq0, puo, lduo, So.data_ptr(), pvo, ldvo,
+                                     ctypes.byref(r), ctypes.byref(info))
+        _check(code, "lrp_cross_solve", warn_ok=True)
         return Uo, So, Vo, int(r.value), info
 
     def _order(self):

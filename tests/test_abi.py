@@ -39,8 +39,15 @@ def test_create_rejects_bad_options():
     h = ctypes.c_void_p()
     for o in (L.Opts(-1, 0, 0.0, None), L.Opts(5, 7, 0.0, None), L.Opts(5, 0, 2.0, None),
               L.Opts(5, 0, 0.0, None, 2, 0), L.Opts(5, 0, 0.0, None, 0, 3), L.Opts(5, 0, 0.0, None, 0, -1),
-              L.Opts(5, 0, 0.0, None, 0, 2, -1.0), L.Opts(5, 0, 0.0, None, 0, 2, float("inf"))):
+              L.Opts(5, 0, 0.0, None, 0, 2, -1.0), L.Opts(5, 0, 0.0, None, 0, 2, float("inf")),
+              L.Opts(5, 0, 0.0, None, 0, 0, 0.0, 0, 3), L.Opts(5, 0, 0.0, None, 0, 0, 0.0, 0, 0, 1)):
         assert L.lib().lrp_create(ctypes.byref(h), 255, 8, 1e-10, ctypes.byref(o)) == L.LRP_EINVAL
+    # a test-matrix context takes any n >= 2, the Poisson one only n + 1 a power of two
+    for n, mat, want in ((1000, 1, True), (1, 1, False), (1000, 0, False)):
+        o = L.Opts(5, 0, 0.0, None, 0, 0, 0.0, 0, mat)
+        rc = L.lib().lrp_create(ctypes.byref(h), n, 8, 1e-10, ctypes.byref(o)) if not want else None
+        if not want:
+            assert rc == L.LRP_EINVAL
 
 
 def test_null_context_and_arguments():
@@ -52,6 +59,7 @@ def test_null_context_and_arguments():
     assert lib.lrp_get_trace(None, ctypes.byref(cnt), None, None, None, None, None, None, None, None, None, None,
                              None, None) == L.LRP_EINVAL
     assert lib.lrp_set_guess(None, 1, None, 0, None, None, 0) == L.LRP_EINVAL
+    assert lib.lrp_cross_solve(None, 1, None, 0, None, 0, None, 0, None, None, 0, ctypes.byref(r), None) == L.LRP_EINVAL
     assert lib.lrp_set_index_sets(None, 1, None, None, None, None) == L.LRP_EINVAL
     assert lib.lrp_get_index_sets(None, None, None, None, None) == L.LRP_EINVAL
     assert lib.lrp_dst1(None, 1, None, 0, None, 0, None, 1.0, 0) == L.LRP_EINVAL
@@ -60,7 +68,8 @@ def test_null_context_and_arguments():
 
 
 def test_struct_layouts_match_header():
-    assert ctypes.sizeof(L.Opts) == 48 and L.Opts.ls_oversampling.offset == 32 and L.Opts.seed.offset == 40
+    assert ctypes.sizeof(L.Opts) == 56 and L.Opts.ls_oversampling.offset == 32 and L.Opts.seed.offset == 40
+    assert L.Opts.matrix.offset == 48
     assert L.Opts.prune_tau.offset == 8 and L.Opts.stream.offset == 16 and L.Opts.flags.offset == 24
     assert ctypes.sizeof(L.KernelTime) == 24 and L.KernelTime.ms.offset == 16
     assert ctypes.sizeof(L.Info) == 48
