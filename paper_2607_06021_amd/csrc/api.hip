@@ -91,13 +91,7 @@ void free_ctx(lrp_ctx* c) {
   dfree(c->replay.J);
   dfree(c->replay.nI);
   dfree(c->replay.nJ);
-  dfree(c->dst.t1_64);
-  dfree(c->dst.t2_64);
-  dfree(c->dst.tl_64);
-  dfree(c->dst.t1_32);
-  dfree(c->dst.t2_32);
-  dfree(c->dst.tl_32);
-  dfree(c->dst.work);
+  dst_free(&c->dst);
   for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
   c->prof_ev.clear();
 
@@ -195,18 +189,9 @@ int create_impl(lrp_ctx* c) {
   TRY(dalloc(&c->replay.nI, mi));
   TRY(dalloc(&c->replay.nJ, mi));
   // DST tables and work (the Poisson solve only)
-  if (poisson) TRY(dst_plan(&c->dst, n, 2 * pm));
   if (poisson) {
-    const int c1 = c->dst.t1_count, c2 = std::max(c->dst.t2_count, 1);
-    TRY(dalloc(&c->dst.t1_64, c1));
-    TRY(dalloc(&c->dst.t1_32, c1));
-    TRY(dalloc(&c->dst.t2_64, c2));
-    TRY(dalloc(&c->dst.t2_32, c2));
-    TRY(dalloc(&c->dst.tl_64, c2));
-    TRY(dalloc(&c->dst.tl_32, c2));
-    if (c->dst.four_step) {
-      if (hipMalloc(&c->dst.work, (size_t)c->dst.work_bytes) != hipSuccess) return LRP_ENOMEM;
-    }
+    TRY(dst_plan(&c->dst, n, 2 * pm));
+    TRY(dst_alloc(&c->dst));
   }
   TRY(tsqr_plan(&c->tsqr, n, pm));
   TRY(select_plan(&c->sel, n));
@@ -764,10 +749,7 @@ int64_t context_bytes(int64_t n, int pm, int maxiter, bool mixed) {
   b += (int64_t)maxiter * (2 * kPMax * 4 + 8 * 4 + 2 * 8);         // trace
   b += (int64_t)maxiter * (2 * kPMax * 4 + 2 * 4);                 // replay sets
   DstPlan dp{};
-  if (dst_plan(&dp, n, 2 * pm) == LRP_OK) {
-    b += 24 * (int64_t)(dp.t1_count + 2 * std::max(dp.t2_count, 1));
-    b += dp.work_bytes;
-  }
+  if (dst_plan(&dp, n, 2 * pm) == LRP_OK) b += dst_bytes(dp);
   int64_t rows = n, br = kTsqrRows;                                // TSQR tree, two sides
   const int g = kTsqrRows / pm;
   for (int L = 0; L < kMaxLevels; ++L) {
@@ -855,7 +837,8 @@ int lrp_create(lrp_ctx** ctx, int64_t n, int32_t r_max, double tol, const lrp_op
   if (opts) o = *opts;
   if (o.matrix != LRP_MAT_POISSON && o.matrix != LRP_MAT_HILBERT && o.matrix != LRP_MAT_K) return LRP_EINVAL;
   if (o.matrix == LRP_MAT_POISSON) {
-    if (n < 3 || !pow2(n + 1) || n + 1 > (int64_t(1) << 23)) return LRP_EINVAL;
+    // n + 1 a power of two up to 2^23, or any other n up to 2^22 - 1 (Bluestein DST)
+    if (n < 2 || n + 1 > (int64_t(1) << 23) || (!pow2(n + 1) && n + 1 > (int64_t(1) << 22))) return LRP_EINVAL;
   } else if (n < 2 || n > (int64_t(1) << 23)) {
     return LRP_EINVAL;
   }
@@ -923,7 +906,8 @@ int lrp_cross_solve(lrp_ctx* c, int32_t r0, const double* U0, int64_t ldu0, cons
 }
 
 int64_t lrp_context_bytes(int64_t n, int32_t r_max, int32_t maxiter, int32_t precision) {
-  if (n < 3 || !pow2(n + 1) || n + 1 > (int64_t(1) << 23) || r_max < 1 || r_max > kPMax || r_max > n) return 0;
+  if (n < 2 || n + 1 > (int64_t(1) << 23) || (!pow2(n + 1) && n + 1 > (int64_t(1) << 22))) return 0;
+  if (r_max < 1 || r_max > kPMax || r_max > n) return 0;
   if (maxiter < 0 || (precision != LRP_FP64 && precision != LRP_MIXED)) return 0;
   return context_bytes(n, r_max, maxiter == 0 ? 20 : maxiter, precision == LRP_MIXED);
 }

@@ -26,7 +26,15 @@
 //   k2 are Z[k2 + L2 k1], outputs k1 >= L1/2 give Z[(L2-k2) + L2 (L1-1-k1)] of the mirror column.
 //   Each pass moves about n elements per column in and out.
 // Twiddles come from tables built on the device from sincospi (exact arguments 2k/P).
+#include <type_traits>
+
 #include "lrp_kernels.h"
+
+#define TRY_DST(expr)                 \
+  do {                                \
+    const int rc_ = (expr);           \
+    if (rc_ != LRP_OK) return rc_;    \
+  } while (0)
 
 namespace lrp {
 
@@ -473,6 +481,237 @@ __global__ __launch_bounds__(512) void k_dst_pass2(DstArgs a) {
 }
 
 // ----------------------------------------------------------------------------------------
+// n + 1 not a power of two: Bluestein's chirp-z method. With w = W_L (L = 2(n+1)) and
+// c_j = w^{j^2/2} = exp(-pi i (j^2 mod 2L)/L), jk = (j^2 + k^2 - (k-j)^2)/2 gives
+//   Z_k = sum_j z_j w^{jk} = c_k sum_j (z_j c_j) conj(c_{k-j}),
+// a circular convolution of a_j = z_j c_j (zero past L) with b_m = conj(c_|m|) (|m| < L) over
+// M >= 2L - 1 points: Z_k = c_k IDFT_M(DFT_M(a) DFT_M(b))_k, and IDFT(x) = conj(DFT(conj x))/M.
+// DFT_M(b) is a table built at set-up. Per column pair: a forward FFT of a (the chirp folded
+// into the loads), the product with the table (conjugated, folded into the FFT's stores), a
+// second forward FFT, and the outputs c_k conj(.)/M for k = 1..n (folded into its stores).
+// M <= 4096: one kernel; above, each FFT is four-step (M = M1 M2, input j = j1 + M1 j2, output
+// k = k2 + M2 k1: pass 1 transforms over j2 for each j1 and applies W_M^{j1 k2}, pass 2
+// transforms over j1 for each k2).
+struct BsArgs {
+  DstArgs d;           // columns, destination, scales (as the power-of-two path)
+  int64_t N;           // n + 1 (L = 2N)
+  int logM1;           // four-step: M1 = 2^logM1 (pass-2 length); M2 = 2^logM2 (pass-1 length)
+  int64_t s1;          // row stride of the pass-1 -> pass-2 intermediate (complex elements)
+  const void* chirp;   // L entries
+  const void* bhat;    // M entries
+  const void *t1, *t2, *tl;  // W_M1^j (or W_M^j for one pass), W_M2^j, W_M^b (b < M2)
+  void* S;             // intermediate, per pair M2 s1
+  void* B;             // between the FFTs, per pair M
+  int pair0;           // first column pair of this round
+  int npairs;          // column pairs in this round
+  int plain;           // set-up only: FFT of B into B (no chirp, table or DST stores)
+};
+
+// Element j of a = z c (zero past L) for the pair (xa, xb).
+template <typename T>
+__device__ __forceinline__ cx<T> bs_input(const double* xa, const double* xb, int64_t N, const cx<T>* chirp, int64_t j) {
+  if (j >= 2 * N) return {T(0), T(0)};
+  return cmul(load_z<T>(xa, xb, N, j), chirp[j]);
+}
+
+// Output k of the pair: Z_k = c_k conj(v)/M.
+template <typename T>
+__device__ __forceinline__ void bs_output(const BsArgs& a, int ca, int cb, int ncols, int64_t k, cx<T> v, T invM,
+                                          double sa, double sb) {
+  if (k < 1 || k >= a.N) return;
+  const cx<T> c = reinterpret_cast<const cx<T>*>(a.chirp)[k];
+  const cx<T> vc{v.x * invM, -v.y * invM};
+  put_pair<T>(a.d, ca, cb, ncols, k, cmul(c, vc), sa, sb);
+}
+
+template <typename T, int LOGM>
+__global__ __launch_bounds__(512) void k_dst_bs_single(BsArgs a) {
+  constexpr int M = 1 << LOGM, E = 16, TP = M / E;
+  constexpr int SEQS = single_seqs(LOGM), SEQ = seq_len(M);
+  __shared__ cx<T> lds[SEQS * SEQ];
+  const double* X;
+  int ncols;
+  if (!dst_resolve(a.d, X, ncols)) return;
+  const int tt = threadIdx.x % TP, sl = threadIdx.x / TP;
+  const int lp = blockIdx.x * SEQS + sl;  // pair within this round (the last block may run past)
+  const bool mine = lp < a.npairs;
+  const int pair = a.pair0 + lp;
+  const int ca = 2 * pair, cb = ca + 1;
+  const double* xa = mine && ca < ncols ? X + (int64_t)ca * a.d.ldx : nullptr;
+  const double* xb = mine && cb < ncols ? X + (int64_t)cb * a.d.ldx : nullptr;
+  const cx<T>* chirp = reinterpret_cast<const cx<T>*>(a.chirp);
+  const cx<T>* bhat = reinterpret_cast<const cx<T>*>(a.bhat);
+  const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.t1);
+  cx<T> x[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) x[e] = bs_input<T>(xa, xb, a.N, chirp, tt + TP * e);
+  fft_seq<T, LOGM, E>(x, lds + sl * SEQ, tt, tw);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const cx<T> v = cmul(x[e], bhat[tt + TP * e]);
+    x[e] = {v.x, -v.y};
+  }
+  fft_seq<T, LOGM, E>(x, lds + sl * SEQ, tt, tw);
+  if (!mine || ca >= a.d.ncols_out) return;
+  double sa, sb;
+  col_scales(a.d, ca, cb, ncols, sa, sb);
+  const T invM = T(1.0 / (double)M);
+#pragma unroll
+  for (int e = 0; e < E; ++e) bs_output<T>(a, ca, cb, ncols, tt + TP * e, x[e], invM, sa, sb);
+}
+
+// Pass 1: TJ consecutive j1 (lane-fastest, contiguous reads) x M2/16 threads; the transform over
+// j2, the twiddle W_M^{j1 k2}, the intermediate S[k2][j1]. FROM_X: the input is a = z c from the
+// columns; otherwise the buffer B.
+template <typename T, int LOG2, bool FROM_X>
+__global__ __launch_bounds__(512) void k_dst_bs_pass1(BsArgs a) {
+  constexpr int M2 = 1 << LOG2, E = 16, TP = M2 / E;
+  constexpr int TJ = tile1_of<T>(LOG2), SEQ = seq_len(M2);
+  __shared__ cx<T> lds[TJ * SEQ];
+  const double* X = nullptr;
+  int ncols = 0;
+  if (!a.plain && !dst_resolve(a.d, X, ncols)) return;
+  const int M1 = 1 << a.logM1;
+  const int64_t M = (int64_t)M1 * M2;
+  const int ntiles = M1 / TJ;
+  const int tile = blockIdx.x % ntiles;
+  const int pair = a.pair0 + blockIdx.x / ntiles;
+  const int ca = 2 * pair, cb = ca + 1;
+  if (!a.plain && ca >= ncols) return;  // a zero pair: the last pass writes its zeros
+  const int cl = threadIdx.x % TJ, tt = threadIdx.x / TJ;
+  const int j1 = tile * TJ + cl;
+  cx<T> x[E];
+  if (FROM_X) {
+    const double* xa = X + (int64_t)ca * a.d.ldx;
+    const double* xb = cb < ncols ? X + (int64_t)cb * a.d.ldx : nullptr;
+    const cx<T>* chirp = reinterpret_cast<const cx<T>*>(a.chirp);
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[e] = bs_input<T>(xa, xb, a.N, chirp, j1 + (int64_t)M1 * (tt + TP * e));
+  } else {
+    const cx<T>* Bp = reinterpret_cast<const cx<T>*>(a.B) + (int64_t)(pair - a.pair0) * M;
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[e] = Bp[j1 + (int64_t)M1 * (tt + TP * e)];
+  }
+  fft_seq<T, LOG2, E>(x, lds + cl * SEQ, tt, reinterpret_cast<const cx<T>*>(a.t2));
+  const cx<T>* thi = reinterpret_cast<const cx<T>*>(a.t1);  // W_M^{M2 h} = W_M1^h
+  const cx<T>* tlo = reinterpret_cast<const cx<T>*>(a.tl);  // W_M^b, b < M2
+  cx<T>* S = reinterpret_cast<cx<T>*>(a.S) + (int64_t)(pair - a.pair0) * M2 * a.s1;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k2 = tt + TP * e;
+    const int64_t m = (int64_t)j1 * k2;
+    S[(int64_t)k2 * a.s1 + j1] = cmul(x[e], cmul(thi[m >> LOG2], tlo[m & (M2 - 1)]));
+  }
+}
+
+// Pass 2: TK consecutive k2 x M1/16 threads (lane-fastest along the sequence, contiguous reads of
+// S); outputs staged in LDS so that each row k1 goes out as TK consecutive k2. TO_DST: the DST
+// outputs; otherwise conj(X_k bhat_k) into B (plain: X_k itself).
+template <typename T, int LOG1, bool TO_DST>
+__global__ __launch_bounds__(512) void k_dst_bs_pass2(BsArgs a) {
+  constexpr int M1 = 1 << LOG1, E = 16, TP = M1 / E;
+  constexpr int TK = tile2_of<T>(LOG1), SEQ = seq_len(M1);
+  constexpr int OST = TK + 1;
+  constexpr int NLDS = TK * SEQ > M1 * OST ? TK * SEQ : M1 * OST;
+  __shared__ cx<T> lds[NLDS];
+  const double* X = nullptr;
+  int ncols = 0;
+  if (!a.plain && !dst_resolve(a.d, X, ncols)) return;
+  const int64_t M2 = int64_t(1) << (a.d.logL2);  // M2 travels in d.logL2
+  const int64_t M = M1 * M2;
+  const int ntiles = (int)(M2 / TK);
+  const int tile = blockIdx.x % ntiles;
+  const int pair = a.pair0 + blockIdx.x / ntiles;
+  const int ca = 2 * pair, cb = ca + 1;
+  if (TO_DST && ca >= a.d.ncols_out) return;
+  const int k0 = tile * TK;
+  const int nthreads = TK * TP;
+  const bool zero = !a.plain && ca >= ncols;
+  if (!TO_DST && zero) return;
+  const int tt = threadIdx.x % TP, kl = threadIdx.x / TP;
+  if (!zero) {
+    const cx<T>* S = reinterpret_cast<const cx<T>*>(a.S) + (int64_t)(pair - a.pair0) * M2 * a.s1;
+    cx<T> x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[e] = S[(int64_t)(k0 + kl) * a.s1 + tt + TP * e];
+    fft_seq<T, LOG1, E>(x, lds + kl * SEQ, tt, reinterpret_cast<const cx<T>*>(a.t1));
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds[(tt + TP * e) * OST + kl] = x[e];  // row k1, column k2 - k0
+    __syncthreads();
+  }
+  if (TO_DST) {
+    double sa, sb;
+    col_scales(a.d, ca, cb, ncols, sa, sb);
+    const T invM = T(1.0 / (double)M);
+    for (int g = threadIdx.x; g < M1 * TK; g += nthreads) {
+      const int c = g % TK, k1 = g / TK;
+      const int64_t k = k0 + c + M2 * k1;
+      if (k < 1 || k >= a.N) continue;
+      if (zero)
+        put_pair<T>(a.d, ca, cb, ncols, k, cx<T>{T(0), T(0)}, sa, sb);
+      else
+        bs_output<T>(a, ca, cb, ncols, k, lds[k1 * OST + c], invM, sa, sb);
+    }
+  } else {
+    const cx<T>* bhat = reinterpret_cast<const cx<T>*>(a.bhat);
+    cx<T>* Bp = reinterpret_cast<cx<T>*>(a.B) + (int64_t)(pair - a.pair0) * M;
+    for (int g = threadIdx.x; g < M1 * TK; g += nthreads) {
+      const int c = g % TK, k1 = g / TK;
+      const int64_t k = k0 + c + M2 * k1;
+      cx<T> v = lds[k1 * OST + c];
+      if (!a.plain) {
+        v = cmul(v, bhat[k]);
+        v.y = -v.y;
+      }
+      Bp[k] = v;
+    }
+  }
+}
+
+// Set-up for M <= 4096: the forward FFT of one FP64 sequence B in place.
+template <int LOGM>
+__global__ __launch_bounds__(256) void k_fft_plain_single(double2* B, const double2* tw) {
+  constexpr int M = 1 << LOGM, E = 16, TP = M / E;
+  __shared__ cx<double> lds[seq_len(M)];
+  const int tt = threadIdx.x;
+  cx<double>* Bc = reinterpret_cast<cx<double>*>(B);
+  cx<double> x[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) x[e] = Bc[tt + TP * e];
+  fft_seq<double, LOGM, E>(x, lds, tt, reinterpret_cast<const cx<double>*>(tw));
+#pragma unroll
+  for (int e = 0; e < E; ++e) Bc[tt + TP * e] = x[e];
+}
+
+// Set-up: the circular chirp b (M entries, conj(c_|m|) for |m| < L, 0 between) into B, FP64.
+__global__ void k_bs_bvec(double2* B, const double2* chirp, int64_t L, int64_t M) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  double2 v = make_double2(0.0, 0.0);
+  if (m < L) v = make_double2(chirp[m].x, -chirp[m].y);
+  else if (M - m < L) v = make_double2(chirp[M - m].x, -chirp[M - m].y);
+  B[m] = v;
+}
+
+__global__ void k_bs_chirp(double2* c64, float2* c32, int64_t L) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= L) return;
+  const int64_t q = (j * j) % (2 * L);  // j < 2^23, so j^2 fits in 64 bits
+  double s, c;
+  sincospi((double)q / (double)L, &s, &c);
+  c64[j] = make_double2(c, -s);
+  c32[j] = make_float2((float)c, (float)-s);
+}
+
+__global__ void k_copy_c64_c32(const double2* a, double2* b64, float2* b32, int64_t M) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  b64[j] = a[j];
+  b32[j] = make_float2((float)a[j].x, (float)a[j].y);
+}
+
+// ----------------------------------------------------------------------------------------
 // Host side
 // ----------------------------------------------------------------------------------------
 static int ilog2(int64_t v) {
@@ -483,11 +722,29 @@ static int ilog2(int64_t v) {
 
 int dst_plan(DstPlan* p, int64_t n, int max_cols) {
   const int64_t M = n + 1;
+  *p = DstPlan{};
+  p->n = n;
+  p->max_pairs = (max_cols + 1) / 2;
+  if ((M & (M - 1)) != 0) {  // Bluestein
+    const int logM = ilog2(4 * M - 1);
+    if (M < 3 || logM > 24) return LRP_EINVAL;
+    p->bluestein = 1;
+    p->logM = logM;
+    p->logL = logM;
+    p->four_step = logM > 12;
+    p->logL2 = p->four_step ? logM / 2 : 0;
+    p->logL1 = logM - p->logL2;
+    const int64_t L1 = int64_t(1) << p->logL1, L2 = int64_t(1) << p->logL2;
+    p->t1_count = (int)L1;
+    p->t2_count = p->four_step ? (int)L2 : 0;
+    p->s1 = p->four_step ? L1 + 16 : 0;
+    p->batch_pairs = std::min(p->max_pairs, 8);
+    p->work_bytes = p->four_step ? (int64_t)p->batch_pairs * L2 * p->s1 * 16 : 0;
+    return LRP_OK;
+  }
   const int logL = ilog2(2 * M);
   if (logL < 3 || logL > 24) return LRP_EINVAL;
-  p->n = n;
   p->logL = logL;
-  p->max_pairs = (max_cols + 1) / 2;
   if (logL <= 12) {
     p->four_step = 0;
     p->logL1 = logL;
@@ -505,7 +762,77 @@ int dst_plan(DstPlan* p, int64_t n, int max_cols) {
   return LRP_OK;
 }
 
+int64_t dst_bytes(const DstPlan& p) {
+  int64_t b = 24 * (int64_t)(p.t1_count + 2 * std::max(p.t2_count, 1)) + p.work_bytes;
+  if (p.bluestein) {
+    const int64_t M = int64_t(1) << p.logM, L = 2 * (p.n + 1);
+    b += 24 * (L + M) + (int64_t)p.batch_pairs * M * 16;
+  }
+  return b;
+}
+
+template <typename T>
+static int dalloc_n(T** q, int64_t count) {
+  *q = nullptr;
+  return hipMalloc((void**)q, sizeof(T) * (size_t)std::max<int64_t>(count, 1)) == hipSuccess ? LRP_OK : LRP_ENOMEM;
+}
+
+int dst_alloc(DstPlan* p) {
+  const int c1 = p->t1_count, c2 = std::max(p->t2_count, 1);
+  if (dalloc_n(&p->t1_64, c1) || dalloc_n(&p->t1_32, c1) || dalloc_n(&p->t2_64, c2) || dalloc_n(&p->t2_32, c2) ||
+      dalloc_n(&p->tl_64, c2) || dalloc_n(&p->tl_32, c2))
+    return LRP_ENOMEM;
+  if (p->four_step && hipMalloc(&p->work, (size_t)p->work_bytes) != hipSuccess) return LRP_ENOMEM;
+  if (p->bluestein) {
+    const int64_t M = int64_t(1) << p->logM, L = 2 * (p->n + 1);
+    if (dalloc_n(&p->chirp_64, L) || dalloc_n(&p->chirp_32, L) || dalloc_n(&p->bhat_64, M) ||
+        dalloc_n(&p->bhat_32, M))
+      return LRP_ENOMEM;
+    if (hipMalloc(&p->work2, (size_t)p->batch_pairs * M * 16) != hipSuccess) return LRP_ENOMEM;
+  }
+  return LRP_OK;
+}
+
+void dst_free(DstPlan* p) {
+  void* bufs[] = {p->t1_64, p->t2_64, p->tl_64, p->t1_32, p->t2_32, p->tl_32, p->work,
+                  p->chirp_64, p->chirp_32, p->bhat_64, p->bhat_32, p->work2};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  p->t1_64 = p->t2_64 = p->tl_64 = p->chirp_64 = p->bhat_64 = nullptr;
+  p->t1_32 = p->t2_32 = p->tl_32 = p->chirp_32 = p->bhat_32 = nullptr;
+  p->work = p->work2 = nullptr;
+}
+
+template <typename T>
+static int bs_launch(const DstPlan& p, BsArgs b, hipStream_t s);
+
 int dst_tables(DstPlan* p, hipStream_t s) {
+  if (p->bluestein) {
+    const int64_t L1 = int64_t(1) << p->logL1, L2 = int64_t(1) << p->logL2;
+    const int64_t M = int64_t(1) << p->logM, L = 2 * (p->n + 1);
+    // W_M1^k (W_M^k for one pass), W_M2^k, W_M^b (b < M2)
+    hipLaunchKernelGGL(k_twiddle, dim3((unsigned)((L1 + 255) / 256)), dim3(256), 0, s, p->t1_64, p->t1_32, (int)L1,
+                       (int)L1);
+    if (p->four_step) {
+      hipLaunchKernelGGL(k_twiddle, dim3((unsigned)((L2 + 255) / 256)), dim3(256), 0, s, p->t2_64, p->t2_32, (int)L2,
+                         (int)L2);
+      hipLaunchKernelGGL(k_twiddle, dim3((unsigned)((L2 + 255) / 256)), dim3(256), 0, s, p->tl_64, p->tl_32, (int)M,
+                         (int)L2);
+    }
+    hipLaunchKernelGGL(k_bs_chirp, dim3((unsigned)((L + 255) / 256)), dim3(256), 0, s, p->chirp_64, p->chirp_32, L);
+    // bhat = DFT_M(b), FP64: b into the first pair's slot of work2, transformed in place
+    double2* B = static_cast<double2*>(p->work2);
+    hipLaunchKernelGGL(k_bs_bvec, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, B, p->chirp_64, L, M);
+    BsArgs b{};
+    b.plain = 1;
+    b.N = p->n + 1;
+    b.B = B;
+    b.npairs = 1;
+    TRY_DST(bs_launch<double>(*p, b, s));
+    hipLaunchKernelGGL(k_copy_c64_c32, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, B, p->bhat_64,
+                       p->bhat_32, M);
+    return launch_status();
+  }
   const int L1 = 1 << p->logL1, L2 = 1 << p->logL2;
   const int L = 1 << p->logL;
   // t1: W_{L1}^k, k < L1 ; t2: W_{L2}^k, k < L2 ; tl: W_L^b, b < L2
@@ -562,10 +889,108 @@ static void launch_four_step(int logL1, int logL2, int npairs, const DstArgs& a,
 #undef LRP_P2
 }
 
+template <typename T, bool FROM_X>
+static int bs_pass1(int logL2, int M1, int np, const BsArgs& b, hipStream_t s) {
+#define LRP_BSP1(LG)                                                                                \
+  case LG: {                                                                                        \
+    constexpr int tj = tile1_of<T>(LG);                                                             \
+    LRP_LAUNCH(K_DST_PASS1, (k_dst_bs_pass1<T, LG, FROM_X>), dim3((M1 / tj) * np),                 \
+               dim3(tj * ((1 << LG) / 16)), 0, s, b);                                              \
+    return launch_status();                                                                         \
+  }
+  switch (logL2) {
+    LRP_BSP1(6) LRP_BSP1(7) LRP_BSP1(8) LRP_BSP1(9) LRP_BSP1(10) LRP_BSP1(11) LRP_BSP1(12)
+    default: return LRP_EINVAL;
+  }
+#undef LRP_BSP1
+}
+
+template <typename T, bool TO_DST>
+static int bs_pass2(int logL1, int M2, int np, const BsArgs& b, hipStream_t s) {
+#define LRP_BSP2(LG)                                                                                \
+  case LG: {                                                                                        \
+    constexpr int tk = tile2_of<T>(LG);                                                             \
+    LRP_LAUNCH(K_DST_PASS2, (k_dst_bs_pass2<T, LG, TO_DST>), dim3((M2 / tk) * np),                 \
+               dim3(tk * ((1 << LG) / 16)), 0, s, b);                                              \
+    return launch_status();                                                                         \
+  }
+  switch (logL1) {
+    LRP_BSP2(7) LRP_BSP2(8) LRP_BSP2(9) LRP_BSP2(10) LRP_BSP2(11) LRP_BSP2(12)
+    default: return LRP_EINVAL;
+  }
+#undef LRP_BSP2
+}
+
+// The Bluestein transform of b.npairs pairs from b.pair0; plain (set-up): the forward FFT of
+// b.B (one FP64 sequence) in place.
+template <typename T>
+static int bs_launch(const DstPlan& p, BsArgs b, hipStream_t s) {
+  const bool f32 = std::is_same<T, float>::value;
+  b.t1 = f32 ? (const void*)p.t1_32 : (const void*)p.t1_64;
+  b.t2 = f32 ? (const void*)p.t2_32 : (const void*)p.t2_64;
+  b.tl = f32 ? (const void*)p.tl_32 : (const void*)p.tl_64;
+  b.chirp = f32 ? (const void*)p.chirp_32 : (const void*)p.chirp_64;
+  b.bhat = f32 ? (const void*)p.bhat_32 : (const void*)p.bhat_64;
+  b.S = p.work;
+  b.s1 = p.s1;
+  b.logM1 = p.logL1;
+  b.d.logL2 = p.logL2;
+  const int np = b.npairs;
+  if (!p.four_step) {
+    if (b.plain) {
+#define LRP_FPS(LG)                                                                                  \
+  case LG:                                                                                           \
+    hipLaunchKernelGGL((k_fft_plain_single<LG>), dim3(1), dim3((1 << LG) / 16), 0, s,               \
+                       static_cast<double2*>(b.B), p.t1_64);                                         \
+    return launch_status();
+      switch (p.logM) {
+        LRP_FPS(4) LRP_FPS(5) LRP_FPS(6) LRP_FPS(7) LRP_FPS(8) LRP_FPS(9) LRP_FPS(10) LRP_FPS(11) LRP_FPS(12)
+        default: return LRP_EINVAL;
+      }
+#undef LRP_FPS
+    }
+#define LRP_BS1(LG)                                                                                 \
+  case LG: {                                                                                        \
+    constexpr int seqs = single_seqs(LG);                                                           \
+    LRP_LAUNCH(K_DST_SINGLE, (k_dst_bs_single<T, LG>), dim3((np + seqs - 1) / seqs),               \
+               dim3(seqs * ((1 << LG) / 16)), 0, s, b);                                            \
+    return launch_status();                                                                         \
+  }
+    switch (p.logM) {
+      LRP_BS1(4) LRP_BS1(5) LRP_BS1(6) LRP_BS1(7) LRP_BS1(8) LRP_BS1(9) LRP_BS1(10) LRP_BS1(11) LRP_BS1(12)
+      default: return LRP_EINVAL;
+    }
+#undef LRP_BS1
+  }
+  const int M1 = 1 << p.logL1, M2 = 1 << p.logL2;
+  if (b.plain) {
+    TRY_DST((bs_pass1<T, false>(p.logL2, M1, np, b, s)));
+    return bs_pass2<T, false>(p.logL1, M2, np, b, s);
+  }
+  TRY_DST((bs_pass1<T, true>(p.logL2, M1, np, b, s)));    // DFT of a = z c
+  TRY_DST((bs_pass2<T, false>(p.logL1, M2, np, b, s)));   // conj(. bhat) into B
+  TRY_DST((bs_pass1<T, false>(p.logL2, M1, np, b, s)));   // DFT of B
+  return bs_pass2<T, true>(p.logL1, M2, np, b, s);         // c_k conj(.)/M: the DST outputs
+}
+
 int dst_launch(const DstPlan& p, DstArgs a, bool fp32, hipStream_t s) {
   const int npairs = (a.ncols_out + 1) / 2;
   if (npairs <= 0) return LRP_OK;
   if (npairs > p.max_pairs) return LRP_EINVAL;
+  if (p.bluestein) {
+    a.outscale *= 1.0 / std::sqrt(2.0 * (double)(p.n + 1));
+    BsArgs b{};
+    b.d = a;
+    b.N = p.n + 1;
+    b.B = p.work2;
+    for (int p0 = 0; p0 < npairs; p0 += p.batch_pairs) {
+      b.pair0 = p0;
+      b.npairs = std::min(p.batch_pairs, npairs - p0);
+      const int rc = fp32 ? bs_launch<float>(p, b, s) : bs_launch<double>(p, b, s);
+      if (rc != LRP_OK) return rc;
+    }
+    return LRP_OK;
+  }
   a.logL = p.logL;
   a.logL1 = p.logL1;
   a.logL2 = p.logL2;

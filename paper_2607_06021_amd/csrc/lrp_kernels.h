@@ -50,6 +50,16 @@ struct DstPlan {
   double2 *t1_64, *t2_64, *tl_64;
   float2 *t1_32, *t2_32, *tl_32;
   void* work;
+  // n + 1 not a power of two: the length-2(n+1) DFT by Bluestein's chirp-z method on
+  // power-of-two FFTs of length M = 2^logM >= 4(n+1) - 1 (M = M1 M2 above 4096 points)
+  int bluestein;
+  int logM;
+  int batch_pairs;         // column pairs per round of launches (bounds the work buffers)
+  double2* chirp_64;       // L entries exp(-pi i (j^2 mod 2L)/L)
+  float2* chirp_32;
+  double2* bhat_64;        // M entries: DFT_M of the circular chirp b_m = conj(chirp_|m|)
+  float2* bhat_32;
+  void* work2;             // batch_pairs x M complex: the data between the two FFTs (FP64 size)
 };
 
 struct DstArgs {
@@ -73,7 +83,11 @@ struct DstArgs {
 };
 
 int dst_plan(DstPlan* p, int64_t n, int max_cols);
+int dst_alloc(DstPlan* p);  // tables and work buffers of a plan
+void dst_free(DstPlan* p);
 int dst_tables(DstPlan* p, hipStream_t s);
+// device bytes dst_alloc takes for this plan
+int64_t dst_bytes(const DstPlan& p);
 int dst_launch(const DstPlan& p, DstArgs a, bool fp32, hipStream_t s);
 
 // ---------------------------------------------------------------- TSQR (tsqr.hip)

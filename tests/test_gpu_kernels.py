@@ -48,6 +48,36 @@ def test_dst_fp64_matches_oracle(n, ncols):
     assert err <= 1e-14 * math.log2(n + 1)
 
 
+# n + 1 not a power of two (Bluestein): tiny grids, the one-pass FFT (M <= 4096), the four-step
+# FFT, the paper's grid sizes n = 2^k, column counts that leave half a pair and that take two
+# rounds of column pairs
+@pytest.mark.parametrize("n,ncols", [(2, 1), (3, 2), (5, 3), (100, 5), (1000, 9), (1024, 4), (4096, 20),
+                                     (16384, 7), (65536, 3), (262144, 2)])
+def test_dst_general_n_matches_oracle(n, ncols):
+    from paper_2607_06021_amd import Solver
+
+    print(f"dst general n={n} ncols={ncols}", flush=True)
+    rng = np.random.default_rng(n + 7 * ncols)
+    X = rng.standard_normal((n, ncols))
+    scale = rng.standard_normal(ncols)
+    torch = _torch()
+    with Solver(n, min(32, n), 1e-10) as s:
+        Xd = to_dev(X)
+        Y = to_np(s.dst1(Xd, scale=torch.from_numpy(scale).cuda(), mul=0.5))
+        Y32 = to_np(s.dst1(Xd, precision="mixed"))
+        back = to_np(s.dst1(s.dst1(Xd)))
+        torch.cuda.synchronize()
+    ref = cd.dst1(X)
+    err = np.max(np.abs(Y - ref * scale[None, :] * 0.5)) / np.max(np.abs(ref * scale[None, :] * 0.5))
+    e32 = np.max(np.abs(Y32 - ref)) / np.max(np.abs(ref))
+    einv = np.max(np.abs(back - X)) / np.max(np.abs(X))
+    print(f"  max rel err fp64 {err:.2e} fp32 {e32:.2e} involution {einv:.2e}")
+    lg = math.log2(4 * (n + 1))
+    assert err <= 2e-15 * lg
+    assert e32 <= 2e-6 * lg
+    assert einv <= 4e-15 * lg
+
+
 @pytest.mark.parametrize("n", [255, 65535])
 def test_dst_fp32_and_involution(n):
     from paper_2607_06021_amd import Solver

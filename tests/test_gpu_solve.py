@@ -191,7 +191,33 @@ def test_n65535_mixed_error():
     assert e64 <= 1e-5
 
 
-@pytest.mark.parametrize("n", [255, 65535])
+# the paper's grid sizes n = 2^k (n + 1 not a power of two: the Bluestein DST), with the
+# recipes of the n = 255, 4095 and 65535 workloads
+@pytest.mark.parametrize("name,n,seed", [("n255_r5_fp64", 1024, 0), ("n4095_r10_fp64", 4096, 1),
+                                         ("n65535_r20_fp64", 65536, 0)])
+def test_paper_grid_sizes_fp64_parity(name, n, seed):
+    w = workloads.CONFIGS[name]
+    U, s, V = workloads.make(w, seed, n=n)
+    print(f"solve {name} recipe at n={n} seed {seed}", flush=True)
+    o = cd.solve(n, U, s, V, w.r_max, w.tol, w.maxiter)
+    g = gpu_solve(n, U, s, V, w.r_max, w.tol, w.maxiter)
+    compare_fp64(g, o, f"n={n}")
+
+
+def test_paper_grid_size_mixed_error():
+    w = workloads.CONFIGS["n65535_r20_mixed"]
+    n = 65536
+    U, s, V = workloads.make(w, 0, n=n)
+    print(f"mixed at n={n}", flush=True)
+    o = cd.solve(n, U, s, V, w.r_max, w.tol, w.maxiter)
+    g = gpu_solve(n, U, s, V, w.r_max, w.tol, w.maxiter, precision="mixed")
+    e = cd.rel_err((g["U"], g["S"][: g["rank"]], g["V"]), (o.U, o.S, o.V))
+    print(f"  mixed n={n}: status {g['info']['status']} iters {g['info']['iters']} rank {g['rank']} "
+          f"rel err vs FP64 oracle {e:.3e} ms {g['info']['ms']:.2f}", flush=True)
+    assert e <= 1e-5
+
+
+@pytest.mark.parametrize("n", [255, 1024, 65535])
 def test_manufactured_sine_rank_one(n):
     k, l, a = 5, 9, 2.0
     U, s, V = workloads.sine_rhs(n, [(k, l, a)])
