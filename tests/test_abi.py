@@ -26,7 +26,8 @@ def test_strerror_codes():
     assert L.strerror(99) == "unknown status"
 
 
-@pytest.mark.parametrize("n,rmax,tol", [(256, 8, 1e-10), (254, 8, 1e-10), (2, 1, 1e-10), (255, 0, 1e-10),
+# n + 1 need not be a power of two (up to 2^22; powers of two up to 2^23)
+@pytest.mark.parametrize("n,rmax,tol", [(1, 1, 1e-10), (5_000_000, 8, 1e-10), (255, 0, 1e-10),
                                         (255, 65, 1e-10), (255, 8, -1.0), (255, 8, float("nan")),
                                         ((1 << 24) - 1, 8, 1e-10), (7, 8, 1e-10)])
 def test_create_rejects_bad_sizes(n, rmax, tol):
