@@ -44,7 +44,7 @@ def test_create_rejects_bad_options():
               L.Opts(5, 0, 0.0, None, 0, 0, 0.0, 0, 3), L.Opts(5, 0, 0.0, None, 0, 0, 0.0, 0, 0, 1)):
         assert L.lib().lrp_create(ctypes.byref(h), 255, 8, 1e-10, ctypes.byref(o)) == L.LRP_EINVAL
     # a test-matrix context takes any n >= 2, the Poisson one only n + 1 a power of two
-    for n, mat, want in ((1000, 1, True), (1, 1, False), (1000, 0, False)):
+    for n, mat, want in ((1000, 1, True), (1, 1, False), (5_000_000, 0, False)):
         o = L.Opts(5, 0, 0.0, None, 0, 0, 0.0, 0, mat)
         rc = L.lib().lrp_create(ctypes.byref(h), n, 8, 1e-10, ctypes.byref(o)) if not want else None
         if not want:
@@ -95,7 +95,8 @@ def test_context_bytes_scale():
     small = L.lib().lrp_context_bytes(4095, 32, 20, 0)
     big = L.lib().lrp_context_bytes(65535, 32, 20, 0)
     assert 0 < small < big
-    assert L.lib().lrp_context_bytes(4094, 32, 20, 0) == 0
+    assert L.lib().lrp_context_bytes(5_000_000, 32, 20, 0) == 0
+    assert L.lib().lrp_context_bytes(4096, 32, 20, 0) > small  # general n (Bluestein work buffers)
     # the mixed path keeps the spectral factors and fibers in FP32
     assert L.lib().lrp_context_bytes(65535, 32, 20, 1) < big
 
