@@ -3,9 +3,13 @@
 One step = one whole solve (DST of the factors, warm start, every Cross-DEIM pass until the
 stopping test, final truncation and DST back) on seeded synthetic input already resident in
 HBM. The headline `value` is the mixed-precision path (FP32 DSTs and fibers, FP64 QR, core and
-stopping test); the FP64 path is timed beside it. Prints one JSON line.
+stopping test); the FP64 path is timed beside it. Also reported: a measured device copy rate,
+both precisions at n = 2^20 - 1 (rank-30 RHS) with the streaming kernels' rooflines and the
+error against the oracle's stored sketches, and a served stream of mixed sizes (p50/p99 from
+the scheduled arrival, by size, queue wait versus run). Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--large-steps L] [--served R]
+                    [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -36,6 +40,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
+    ap.add_argument("--large-steps", type=int, default=4,
+                    help="timed solves per precision at n = 2^20 - 1 (0: skip that leg)")
     ap.add_argument("--served", type=int, default=2000, help="requests in the served stream (0: skip)")
     ap.add_argument("--served-active", type=int, default=8)
     ap.add_argument("--served-budget-gb", type=float, default=64.0)
@@ -133,13 +139,14 @@ def profile_solve(w, prec, args_dev):
 def kernel_model(w, prec, trace, info, rF):
     """Algorithmic bytes and flops of each kernel class over one solve (what the method must
     move or compute; counted from the pass sizes of the trace)."""
-    n, pm = w.n, w.r_max
+    n = w.n
     wb = 4 if prec == "mixed" else 8           # width of the spectral factors and fibers
     r = info.rank
     passes = trace                              # passes actually computed
     out = {}
-    # DST: forward U_F, V_F (read FP64, write w); back: read rank columns, write all r_max
-    out["dst"] = {"bytes": 2 * n * rF * (8 + wb) + 2 * (n * r * 8 + n * pm * 8)}
+    # DST: forward U_F, V_F (read FP64, write w); back: read and write the rank live columns
+    # (the zero fill of the r_max - r unused output columns is not counted)
+    out["dst"] = {"bytes": 2 * n * rF * (8 + wb) + 2 * (2 * n * r * 8)}
     fb = 0
     pb = 0
     pf = 0
@@ -225,7 +232,11 @@ def rooflines(w, prec, prof, trace, info, rF):
 
 
 def served_leg(count, seed, budget_gb, max_active, rate=None):
-    """Served stream: saturated throughput, then Poisson arrivals at 70% of it (p50/p99)."""
+    """Served stream through one Server kept open throughout: first every shape of the stream
+    is warmed (max_active requests of each at once, so the contexts the measurement needs
+    exist), then the saturated rate is measured, then Poisson arrivals at 70% of it. Latency
+    runs from each request's scheduled arrival time to its completion; it is reported overall,
+    by grid size, and split into the wait for admission and the run after it."""
     import numpy as np
     import torch
 
@@ -238,40 +249,61 @@ def served_leg(count, seed, budget_gb, max_active, rate=None):
     inputs = [workloads.bump_rhs_device(r.n, r.seed, r.rank, 0.05, 0.2, dev) for r in probe]
     torch.cuda.synchronize()
 
-    def run(reqs, rate_s):
-        with Server(budget_bytes=int(budget_gb * (1 << 30)), max_active=max_active) as srv:
+    def pct(x, q):
+        return round(float(np.percentile(x, q)), 3) if len(x) else None
+
+    with Server(budget_bytes=int(budget_gb * (1 << 30)), max_active=max_active) as srv:
+        def run(reqs, rate_s):
             t0 = time.perf_counter()
-            tickets = []
+            tickets, late = [], []
             for r in reqs:
+                due = t0 + (r.arrival_s if rate_s is not None else 0.0)
                 if rate_s is not None:
-                    due = t0 + r.arrival_s
                     while time.perf_counter() < due:
                         pass
+                late.append(max(0.0, time.perf_counter() - due) * 1e3)
                 U, sg, V = inputs[r.idx]
                 tickets.append(srv.submit(r.n, U, sg, V, 48, 1e-10, 20, r.precision, sync=False))
             res = [srv.wait(t) for t in tickets]
             wall = time.perf_counter() - t0
-            st = srv.stats()
-        lat = np.array([x[6] for x in res])
-        bad = [(r.idx, r.n, r.rank, r.precision, int(x[4])) for r, x in zip(reqs, res) if x[4] < 0]
-        return wall, lat, bad, st
+            return wall, res, np.array(late)
 
-    # warm the contexts of every shape once, then measure the saturated rate
-    nsat = min(count, 400)
-    run(probe[: min(count, 40)], None)
-    wall, lat, bad, _ = run(probe[:nsat], None)
-    sat = nsat / wall
-    use_rate = rate if rate is not None else 0.7 * sat
-    reqs = workloads.served_stream(count=count, rate_per_s=use_rate, seed=seed)
-    log(f"served: saturated {sat:.1f} solves/s; Poisson arrivals at {use_rate:.1f}/s")
-    wall, lat, bad, st = run(reqs, use_rate)
+        # warm every (n, precision) shape: max_active requests of it in flight together
+        shapes = {}
+        for r in probe:
+            shapes.setdefault((r.n, r.precision), []).append(r)
+        for rs in shapes.values():
+            run((rs * max_active)[:max_active], None)
+        ctx0 = srv.stats()["contexts"]
+        nsat = min(count, 400)
+        wall, _, _ = run(probe[:nsat], None)
+        sat = nsat / wall
+        use_rate = rate if rate is not None else 0.7 * sat
+        reqs = workloads.served_stream(count=count, rate_per_s=use_rate, seed=seed)
+        log(f"served: {ctx0} contexts warm; saturated {sat:.1f} solves/s; Poisson arrivals at {use_rate:.1f}/s")
+        wall, res, late = run(reqs, use_rate)
+        st = srv.stats()
+    lat = late + np.array([x[6] for x in res])           # from the scheduled arrival
+    queue = late + np.array([x[7] for x in res])         # arrival to admission
+    runms = np.array([x[8] for x in res])                # admission to completion
+    bad = [(r.idx, r.n, r.rank, r.precision, int(x[4])) for r, x in zip(reqs, res) if x[4] < 0]
+    by_n = {}
+    for nn in sorted({r.n for r in reqs}):
+        sel = np.array([r.n == nn for r in reqs])
+        by_n[str(nn)] = {"requests": int(sel.sum()), "p50_ms": pct(lat[sel], 50), "p99_ms": pct(lat[sel], 99),
+                         "run_p50_ms": pct(runms[sel], 50), "run_p99_ms": pct(runms[sel], 99),
+                         "queue_p99_ms": pct(queue[sel], 99)}
     return {"requests": count, "arrival_rate_per_s": round(use_rate, 2), "saturated_solves_per_s": round(sat, 2),
-            "solves_per_s": round(count / wall, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
-            "p99_ms": round(float(np.percentile(lat, 99)), 3), "failed": len(bad),
+            "solves_per_s": round(count / wall, 2), "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+            "latency_from": "scheduled arrival",
+            "queue_p50_ms": pct(queue, 50), "queue_p99_ms": pct(queue, 99),
+            "run_p50_ms": pct(runms, 50), "run_p99_ms": pct(runms, 99),
+            "submit_lateness_p99_ms": pct(late, 99), "by_n": by_n, "failed": len(bad),
             "failures": [{"request": i, "n": nn, "rank": rk, "precision": pr, "status": stt}
                          for i, nn, rk, pr, stt in bad[:10]],
             "mix": "n in {1023,4095,16383,65535,262143} w.p. .3/.3/.2/.15/.05, rank U{2..20}, cap 48, "
-                   "FP64 or mixed w.p. 0.5", "max_active": max_active, "contexts": st["contexts"]}
+                   "FP64 or mixed w.p. 0.5", "max_active": max_active, "contexts_warm": ctx0,
+            "contexts_after": st["contexts"]}
 
 
 def cpu_baseline(w, U, s, V):
@@ -304,6 +336,121 @@ def dominant_roofline(res, workload):
     return r
 
 
+def copy_bandwidth():
+    """Measured device-to-device copy rate (read + write bytes per second) of a 2 GiB tensor:
+    the practical HBM ceiling the streaming kernels are compared with."""
+    import numpy as np
+    import torch
+
+    a = torch.ones(2 ** 28, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    times = []
+    for _ in range(10):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    gbs = 2 * a.numel() * 8 / (float(np.median(times)) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return round(gbs, 1)
+
+
+def run_leg(w, prec, args_dev, steps, warmup, rF):
+    """Time `steps` solves of workload `w` (after `warmup`), then profile one solve."""
+    import numpy as np
+
+    from paper_2607_06021_amd import Solver
+
+    log(f"timing {w.name} {prec}: n={w.n} r_max={w.r_max} steps={steps} warmup={warmup}")
+    sol = Solver(w.n, w.r_max, w.tol, maxiter=w.maxiter, precision=prec)
+    ms, infos = time_solves(sol, args_dev, steps, warmup)
+    Uo, So, Vo, r, info = sol.solve(*args_dev)
+    out = (Uo[:, :r].cpu().numpy(), So[:r].cpu().numpy(), Vo[:, :r].cpu().numpy())
+    res = {"ms": ms, "info": info.as_dict(), "dev_ms": float(np.median([i["ms"] for i in infos]))}
+    sol.close()
+    del Uo, So, Vo
+    prof, trace, pinfo = profile_solve(w, prec, args_dev)
+    total = sum(v for _, v in prof.values())
+    res["profile"] = {k: {"launches": v[0], "ms": round(v[1], 4), "share": round(v[1] / total, 4)}
+                      for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
+    res["rooflines"] = rooflines(w, prec, prof, trace, pinfo, rF)
+    res["dominant"] = max(prof.items(), key=lambda kv: kv[1][1])[0]
+    log(f"  {prec}: {ms:.3f} ms/solve (device {res['dev_ms']:.3f} ms) "
+        f"iters {info.iters} rank {info.rank} status {info.status}")
+    return res, out
+
+
+def device_inputs(w, seed):
+    import torch
+
+    import workloads
+    from paper_2607_06021_amd import fortran
+
+    U, s, V = workloads.make(w, seed)
+    dev = torch.device("cuda:0")
+    return (U, s, V), (fortran(torch.from_numpy(U).to(dev)), torch.from_numpy(s).to(dev),
+                       fortran(torch.from_numpy(V).to(dev)))
+
+
+def large_leg(args):
+    """n = 2^20 - 1, rank-30 RHS, both precisions: time per solve, the streaming kernels'
+    rooflines, and the error against the oracle through its stored Gaussian sketches."""
+    import numpy as np
+    import torch
+
+    import workloads
+
+    gold_path = os.path.join(ROOT, "tests", "golden", "n1048575_r30_fp64_seed0.json")
+    gold = json.load(open(gold_path)) if os.path.exists(gold_path) else None
+    w64 = workloads.CONFIGS["n1048575_r30_fp64"]
+    wmx = workloads.CONFIGS["n1048575_r30_mixed"]
+    (U, s, V), args_dev = device_inputs(w64, 0)
+    rF = U.shape[1]
+    del U, s, V
+    out = {}
+    outs = {}
+    for prec, w in (("fp64", w64), ("mixed", wmx)):
+        res, o = run_leg(w, prec, args_dev, args.large_steps, 1, rF)
+        outs[prec] = o
+        e = None
+        if gold is not None:
+            e = sketched_rel_err(w.n, o[0], o[1], o[2], gold)
+        out[prec] = {"ms_per_solve": round(res["ms"], 3), "device_ms": round(res["dev_ms"], 3),
+                     "passes": res["info"]["iters"], "rank": res["info"]["rank"], "status": res["info"]["status"],
+                     "sketched_rel_err_vs_oracle": float(f"{e:.3e}") if e is not None else None,
+                     "dominant": res["dominant"],
+                     "rooflines": {k: res["rooflines"][k] for k in ("dst", "fiber", "prod")},
+                     "profile": dict(list(res["profile"].items())[:8])}
+    del args_dev
+    torch.cuda.empty_cache()
+    out["workload"] = ("Poisson n=1048575 (h=2^-20), rank-30 Gaussian-bump RHS (seed 0), rank cap 64, tol 1e-10")
+    out["mixed_speedup"] = round(out["fp64"]["ms_per_solve"] / out["mixed"]["ms_per_solve"], 3)
+    return out
+
+
+def sketched_rel_err(n, U, S, V, gold):
+    """Relative Frobenius error of U diag(S) V^T against the oracle's solution, estimated through
+    the Gaussian sketches stored with it (Om^T U_o diag(S_o), Om'^T V_o; the seeds give Om, Om')."""
+    import numpy as np
+
+    import workloads
+
+    k = gold["sketch_k"]
+    Om = workloads.sketch_matrix(n, k, gold["sketch_seeds"][0])
+    A = Om.T @ (U * S[None, :])
+    del Om
+    Om = workloads.sketch_matrix(n, k, gold["sketch_seeds"][1])
+    B = Om.T @ V
+    del Om
+    ref = np.array(gold["sketch_U"]) @ np.array(gold["sketch_V"]).T
+    return float(np.linalg.norm(A @ B.T - ref) / np.linalg.norm(ref))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -312,39 +459,22 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
-    import numpy as np
-    import torch
-
     import workloads
-    from paper_2607_06021_amd import Solver, fortran
 
     w64 = workloads.CONFIGS["n65535_r20_fp64"]
     wmx = workloads.CONFIGS["n65535_r20_mixed"]
-    U, s, V = workloads.make(w64, args.seed)
-    dev = torch.device("cuda:0")
-    args_dev = (fortran(torch.from_numpy(U).to(dev)), torch.from_numpy(s).to(dev),
-                fortran(torch.from_numpy(V).to(dev)))
+    (U, s, V), args_dev = device_inputs(w64, args.seed)
     results = {}
     outs = {}
     for prec, w in (("mixed", wmx), ("fp64", w64)):
         if args.precision not in ("both", prec):
             continue
-        log(f"timing {prec}: n={w.n} r_max={w.r_max} steps={args.steps} warmup={args.warmup}")
-        sol = Solver(w.n, w.r_max, w.tol, maxiter=w.maxiter, precision=prec)
-        ms, infos = time_solves(sol, args_dev, args.steps, args.warmup)
-        Uo, So, Vo, r, info = sol.solve(*args_dev)
-        outs[prec] = (Uo[:, :r].cpu().numpy(), So[:r].cpu().numpy(), Vo[:, :r].cpu().numpy())
-        results[prec] = {"ms": ms, "info": info.as_dict(), "dev_ms": float(np.median([i["ms"] for i in infos]))}
-        sol.close()
-        prof, trace, pinfo = profile_solve(w, prec, args_dev)
-        total = sum(ms for _, ms in prof.values())
-        results[prec]["profile"] = {k: {"launches": v[0], "ms": round(v[1], 4), "share": round(v[1] / total, 4)}
-                                    for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
-        results[prec]["rooflines"] = rooflines(w, prec, prof, trace, pinfo, U.shape[1])
-        dom = max(prof.items(), key=lambda kv: kv[1][1])[0]
-        results[prec]["dominant"] = dom
-        log(f"  {prec}: {ms:.3f} ms/solve (device {results[prec]['dev_ms']:.3f} ms) "
-            f"iters {info.iters} rank {info.rank} status {info.status}")
+        results[prec], outs[prec] = run_leg(w, prec, args_dev, args.steps, args.warmup, U.shape[1])
+    copy_gbs = copy_bandwidth()
+    log(f"  device copy: {copy_gbs} GB/s")
+    large = None
+    if args.large_steps > 0:
+        large = large_leg(args)
     served = None
     if args.served > 0:
         served = served_leg(args.served, 2026, args.served_budget_gb, args.served_active)
@@ -386,12 +516,14 @@ def main():
         "passes": {p: results[p]["info"]["iters"] for p in ("mixed", "fp64") if p in results},
         "rank": {p: results[p]["info"]["rank"] for p in ("mixed", "fp64") if p in results},
         "rel_err_vs_oracle": {k: float(f"{v:.3e}") for k, v in err.items()},
+        "copy_gbs": copy_gbs,
         "served_p50_ms": served["p50_ms"] if served else None,
         "served_p99_ms": served["p99_ms"] if served else None,
         "served": served,
         "roofline": dominant_roofline(results[head], (wmx if head == "mixed" else w64).name),
         "kernels": {p: {"rooflines": results[p]["rooflines"], "profile": results[p]["profile"]}
                     for p in ("mixed", "fp64") if p in results},
+        "n1048575": large,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

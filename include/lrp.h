@@ -335,7 +335,7 @@ typedef struct lrp_server lrp_server;
  * V_out are device pointers; inputs must stay valid and unchanged, and outputs untouched,
  * until the request completes. */
 typedef struct lrp_request {
-  int64_t n;          /* grid size, n+1 a power of two */
+  int64_t n;          /* grid size, as for lrp_create with the Poisson matrix */
   int32_t r_F;        /* 1 <= r_F <= r_max */
   int32_t r_max;      /* 1 <= r_max <= 64 */
   double tol;
@@ -387,6 +387,16 @@ int lrp_server_poll(lrp_server* srv, int64_t ticket, int32_t* done, int32_t* sta
 /* lrp_server_wait -- as lrp_server_poll, blocking until the request has finished. */
 int lrp_server_wait(lrp_server* srv, int64_t ticket, int32_t* status, int32_t* rank, lrp_info* info,
                     double* latency_ms);
+
+/*
+ * lrp_server_times -- where a finished request's latency went (host clock, milliseconds):
+ * *queue_ms from submission to admission into a context (waiting for a free context or for
+ * memory, including the creation of a new context), *run_ms from admission to completion
+ * (its stages on the device and the scheduler's polling). A request that failed before
+ * admission has *run_ms = 0. Either pointer may be NULL. Returns LRP_OK, or LRP_EINVAL for an
+ * unknown or unfinished ticket.
+ */
+int lrp_server_times(lrp_server* srv, int64_t ticket, double* queue_ms, double* run_ms);
 
 /* lrp_server_release -- forget a finished ticket. Returns LRP_OK or LRP_EINVAL. */
 int lrp_server_release(lrp_server* srv, int64_t ticket);

@@ -43,7 +43,8 @@ struct Job {
   lrp_request req{};
   Key key{};
   int64_t bytes = 0;
-  Clock::time_point t_submit, t_done;
+  Clock::time_point t_submit, t_admit, t_done;
+  bool admitted = false;
   bool done = false;
   int status = 0;
   int rank = 0;
@@ -250,6 +251,8 @@ bool admit(lrp_server* s) {
       }
     }
     s->queue.pop_front();
+    j->t_admit = Clock::now();
+    j->admitted = true;
     use->job = j;
     use->phase = 0;
     use->k = use->checked = 0;
@@ -329,8 +332,10 @@ int lrp_server_create(lrp_server** out, int64_t budget_bytes, int32_t max_active
 
 int lrp_server_submit(lrp_server* s, const lrp_request* r, int64_t* ticket) {
   if (!s || !r || !ticket) return LRP_EINVAL;
+  // stamped before anything else, so time spent waiting for the scheduler's lock counts
+  const Clock::time_point t_call = Clock::now();
   const int64_t n = r->n;
-  if (n < 3 || (n & (n + 1)) != 0 || n + 1 > (int64_t(1) << 23)) return LRP_EINVAL;
+  if (lrp_context_bytes(n, r->r_max, r->maxiter, r->precision) <= 0) return LRP_EINVAL;
   if (r->r_max < 1 || r->r_max > kPMax || r->r_max > n) return LRP_EINVAL;
   if (!(r->tol >= 0.0) || r->maxiter < 0 || r->maxiter > 1000) return LRP_EINVAL;
   if (r->precision != LRP_FP64 && r->precision != LRP_MIXED) return LRP_EINVAL;
@@ -353,7 +358,7 @@ int lrp_server_submit(lrp_server* s, const lrp_request* r, int64_t* ticket) {
       return LRP_EINVAL;
     }
     j->ticket = s->next_ticket++;
-    j->t_submit = Clock::now();
+    j->t_submit = t_call;
     s->jobs[j->ticket] = j;
     s->queue.push_back(j);
     ++s->submitted;
@@ -382,6 +387,18 @@ int lrp_server_wait(lrp_server* s, int64_t ticket, int32_t* status, int32_t* ran
   if (!j) return LRP_EINVAL;
   s->cv_done.wait(g, [&] { return j->done; });
   report(j, status, rank, info, latency_ms);
+  return LRP_OK;
+}
+
+int lrp_server_times(lrp_server* s, int64_t ticket, double* queue_ms, double* run_ms) {
+  if (!s) return LRP_EINVAL;
+  std::lock_guard<std::mutex> g(s->mu);
+  Job* j = find_job(s, ticket);
+  if (!j || !j->done) return LRP_EINVAL;
+  using ms = std::chrono::duration<double, std::milli>;
+  const Clock::time_point a = j->admitted ? j->t_admit : j->t_done;
+  if (queue_ms) *queue_ms = ms(a - j->t_submit).count();
+  if (run_ms) *run_ms = ms(j->t_done - a).count();
   return LRP_OK;
 }
 

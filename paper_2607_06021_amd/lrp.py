@@ -132,6 +132,8 @@ def lib() -> ctypes.CDLL:
     L.lrp_server_poll.restype = ctypes.c_int
     L.lrp_server_wait.argtypes = [_c_vp, _c_i64, P(_c_i32), P(_c_i32), P(Info), P(_c_dbl)]
     L.lrp_server_wait.restype = ctypes.c_int
+    L.lrp_server_times.argtypes = [_c_vp, _c_i64, P(_c_dbl), P(_c_dbl)]
+    L.lrp_server_times.restype = ctypes.c_int
     L.lrp_server_release.argtypes = [_c_vp, _c_i64]
     L.lrp_server_release.restype = ctypes.c_int
     L.lrp_server_get_stats.argtypes = [_c_vp, P(ServerStats)]
@@ -456,7 +458,8 @@ class Server:
         return t.value
 
     def poll(self, ticket: int):
-        """None while running; else (U, S, V, rank, status, info, latency_ms)."""
+        """None while running; else (U, S, V, rank, status, info, latency_ms, queue_ms, run_ms):
+        latency from submission, split into the wait for admission and the run after it."""
         done, st, rk, lat = _c_i32(), _c_i32(), _c_i32(), _c_dbl()
         info = Info()
         _check(lib().lrp_server_poll(self._h, ticket, ctypes.byref(done), ctypes.byref(st), ctypes.byref(rk),
@@ -473,9 +476,11 @@ class Server:
         return self._result(ticket, st.value, rk.value, info, lat.value)
 
     def _result(self, ticket, status, rank, info, lat):
+        qms, rms = _c_dbl(), _c_dbl()
+        _check(lib().lrp_server_times(self._h, ticket, ctypes.byref(qms), ctypes.byref(rms)), "lrp_server_times")
         bufs = self._keep.pop(ticket)
         lib().lrp_server_release(self._h, ticket)
-        return bufs[3], bufs[4], bufs[5], rank, status, info, lat
+        return bufs[3], bufs[4], bufs[5], rank, status, info, lat, qms.value, rms.value
 
     def stats(self) -> Dict:
         st = ServerStats()

@@ -24,7 +24,8 @@ def test_served_results_equal_solo_results():
     from paper_2607_06021_amd.lrp import Server
 
     reqs = []
-    sizes = [1023, 4095, 16383, 1023, 65535, 4095, 255, 16383, 1023, 4095, 65535, 255]
+    # general sizes (n + 1 not a power of two) are served as well
+    sizes = [1023, 4095, 16383, 1023, 65535, 4095, 255, 16383, 1000, 4095, 65535, 3000]
     for i, n in enumerate(sizes):
         U, s, V, _ = workloads.bump_rhs(n, 1000 + i, 2 + (i * 7) % 19, 0.05, 0.2)
         prec = "mixed" if i % 2 else "fp64"
@@ -40,7 +41,9 @@ def test_served_results_equal_solo_results():
     assert stats["bytes_in_use"] <= 8 << 30
     lat = [r[6] for r in served]
     print(f"  latency ms: median {np.median(lat):.2f} max {np.max(lat):.2f}")
-    for (n, U, s, V, prec), (Us, Ss, Vs, rank, status, info, _) in zip(reqs, served):
+    for r in served:  # latency = wait for admission + run after it
+        assert r[7] >= 0.0 and r[8] > 0.0 and abs(r[7] + r[8] - r[6]) <= 1e-6 * max(1.0, r[6])
+    for (n, U, s, V, prec), (Us, Ss, Vs, rank, status, info, *_) in zip(reqs, served):
         with Solver(n, 48, 1e-10, maxiter=20, precision=prec) as sol:
             Uo, So, Vo, r, inf = sol.solve(U, s, V)
         assert status == inf.status and rank == r and info.iters == inf.iters
@@ -72,7 +75,7 @@ def test_contexts_created_under_load_all_succeed():
             tickets = [srv.submit(n, U, s, V, 48, 1e-10, 20, prec) for (n, U, s, V, prec) in part]
             served += [srv.wait(t) for t in tickets]
     assert all(r[4] >= 0 for r in served), [r[4] for r in served]
-    for (n, U, s, V, prec), (Us, Ss, Vs, rank, status, info, _) in zip(reqs, served):
+    for (n, U, s, V, prec), (Us, Ss, Vs, rank, status, info, *_) in zip(reqs, served):
         with Solver(n, 48, 1e-10, maxiter=20, precision=prec) as sol:
             Uo, So, Vo, r, inf = sol.solve(U, s, V)
         assert status == inf.status and rank == r
