@@ -347,6 +347,16 @@ __global__ __launch_bounds__(512) void k_dst_single(DstArgs a) {
   }
 }
 
+// XCD-aware order of the full tiles: the hardware hands consecutive workgroups to the 8 XCDs in
+// turn, so workgroup b runs on XCD b mod 8. Giving the workgroups of one XCD consecutive tiles
+// (b = 8 q + x takes tile x per + q) lets the neighbouring pieces of a cache line that adjacent
+// tiles read or write meet in that XCD's L2 instead of going to memory separately. The tail
+// past 8 per stays in place.
+__device__ __forceinline__ int xcd_order(int b, int nb) {
+  const int per = nb >> 3;
+  return b < 8 * per ? (b & 7) * per + (b >> 3) : b;
+}
+
 // ---------------------------------------------------------------- four-step pass 1
 // Block: TJ columns j1 (lane-fastest, so global reads and writes are coalesced) x L2/16 threads;
 // TJ = 16 (FP64) or 32 (FP32) columns, so each row of the input is read in 128- or 256-byte pieces.
@@ -363,10 +373,10 @@ __global__ __launch_bounds__(512) void k_dst_pass1(DstArgs a) {
   // single column j1 = L1/2 of every pair, so that the light tiles form the tail of the grid
   const int nfull = (L1 / 2) / TJ;
   const int npairs = gridDim.x / (nfull + 1);
-  const int b = blockIdx.x;
+  const int b = blockIdx.x < nfull * npairs ? xcd_order(blockIdx.x, nfull * npairs) : blockIdx.x;
   const int tile = b < nfull * npairs ? b % nfull : nfull;
-  const int pair = b < nfull * npairs ? b / nfull : b - nfull * npairs;
-  const int ca = 2 * pair, cb = ca + 1;
+  const int pair = b < nfull * npairs ? b / nfull : b - nfull * npairs;  // within this batch
+  const int ca = 2 * (a.pair0 + pair), cb = ca + 1;
   if (ca >= a.ncols_out || ca >= ncols) return;  // all-zero pairs are written by pass 2 alone
   const int cl = threadIdx.x % TJ, tt = threadIdx.x / TJ;
   const int64_t M = (int64_t)L1 * L2 / 2;
@@ -409,10 +419,10 @@ __global__ __launch_bounds__(512) void k_dst_pass2(DstArgs a) {
   // blocks ordered as in pass 1: full tiles of k2 < L2/2 first, the k2 = L2/2 tiles last
   const int nfull = (L2 / 2) / TK;
   const int npairs = gridDim.x / (nfull + 1);
-  const int b = blockIdx.x;
+  const int b = blockIdx.x < nfull * npairs ? xcd_order(blockIdx.x, nfull * npairs) : blockIdx.x;
   const int tile = b < nfull * npairs ? b % nfull : nfull;
-  const int pair = b < nfull * npairs ? b / nfull : b - nfull * npairs;
-  const int ca = 2 * pair, cb = ca + 1;
+  const int pair = b < nfull * npairs ? b / nfull : b - nfull * npairs;  // within this batch
+  const int ca = 2 * (a.pair0 + pair), cb = ca + 1;
   if (ca >= a.ncols_out) return;
   const int k0 = tile * TK;
   const int nthreads = TK * TP;
@@ -720,6 +730,10 @@ static int ilog2(int64_t v) {
   return l;
 }
 
+// Intermediate bytes of one pass-1/pass-2 round of the four-step DST (the memory-side cache
+// holds 256 MB; the round's input and output stream through it as well).
+constexpr int64_t kDstBatchBytes = int64_t(96) << 20;
+
 int dst_plan(DstPlan* p, int64_t n, int max_cols) {
   const int64_t M = n + 1;
   *p = DstPlan{};
@@ -758,7 +772,12 @@ int dst_plan(DstPlan* p, int64_t n, int max_cols) {
   p->t1_count = L1;
   p->t2_count = p->four_step ? L2 : 0;
   p->s1 = p->four_step ? L1 / 2 + 16 : 0;
-  p->work_bytes = p->four_step ? (int64_t)p->max_pairs * L2 * p->s1 * 16 : 0;
+  // column pairs per pass-1/pass-2 round: their intermediate (up to kDstBatchBytes) is written
+  // by pass 1 and read back by pass 2 at once, so it can stay in the memory-side cache (MALL)
+  const int64_t per_pair = p->four_step ? (int64_t)L2 * p->s1 * 16 : 0;
+  p->batch_pairs = p->four_step ? (int)std::max<int64_t>(1, std::min<int64_t>(p->max_pairs, kDstBatchBytes / per_pair))
+                                : p->max_pairs;
+  p->work_bytes = (int64_t)p->batch_pairs * per_pair;
   return LRP_OK;
 }
 
@@ -1006,10 +1025,16 @@ int dst_launch(const DstPlan& p, DstArgs a, bool fp32, hipStream_t s) {
       launch_single<double>(p.logL, npairs, a, s);
   } else {
     a.work = p.work;
-    if (fp32)
-      launch_four_step<float>(p.logL1, p.logL2, npairs, a, s);
-    else
-      launch_four_step<double>(p.logL1, p.logL2, npairs, a, s);
+    // FP32 intermediates take half the bytes, so twice the pairs fit the work buffer
+    const int bp = fp32 ? std::min(p.max_pairs, 2 * p.batch_pairs) : p.batch_pairs;
+    for (int p0 = 0; p0 < npairs; p0 += bp) {
+      a.pair0 = p0;
+      const int nb = std::min(bp, npairs - p0);
+      if (fp32)
+        launch_four_step<float>(p.logL1, p.logL2, nb, a, s);
+      else
+        launch_four_step<double>(p.logL1, p.logL2, nb, a, s);
+    }
   }
   return launch_status();
 }

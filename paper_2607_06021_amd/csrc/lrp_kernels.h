@@ -76,6 +76,7 @@ struct DstArgs {
   const DevState* st;   // optional: skip after an error; pick_ret selects source/rank
   int pick_ret;
   // filled by the launcher
+  int pair0;  // first column pair of this launch (pairs are transformed in batches)
   int logL, logL1, logL2;
   int64_t s1;
   const void *t1, *t2, *tl;
