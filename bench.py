@@ -418,6 +418,8 @@ def large_leg(args):
     out = {}
     outs = {}
     for prec, w in (("fp64", w64), ("mixed", wmx)):
+        if args.precision not in ("both", prec):
+            continue
         res, o = run_leg(w, prec, args_dev, args.large_steps, 1, rF)
         outs[prec] = o
         e = None
@@ -432,7 +434,8 @@ def large_leg(args):
     del args_dev
     torch.cuda.empty_cache()
     out["workload"] = ("Poisson n=1048575 (h=2^-20), rank-30 Gaussian-bump RHS (seed 0), rank cap 64, tol 1e-10")
-    out["mixed_speedup"] = round(out["fp64"]["ms_per_solve"] / out["mixed"]["ms_per_solve"], 3)
+    out["mixed_speedup"] = (round(out["fp64"]["ms_per_solve"] / out["mixed"]["ms_per_solve"], 3)
+                            if "fp64" in out and "mixed" in out else None)
     return out
 
 
