@@ -10,9 +10,11 @@
 //                       (16 consecutive rows of 4 columns per instruction);
 //   result (16 x 16):   lane l, item v holds out(i0 + l%16, c0 + l/16 + 4 v).
 // Columns of Q at or beyond p and rows of B at or beyond p read as 0, so stale memory never
-// enters the sums (the MFMAs always run over the padded 64 x 64 B). Each wave keeps B in
-// registers and streams 8 row tiles, loading the next tile's Q while the current one is on
-// the matrix cores.
+// enters the sums. The MFMAs run only over the live part of the padded 64 x 64 B: KS 4-row steps
+// (p rounded up to 16) by NT 16-column tiles (r rounded up to 16), compile-time counts chosen
+// once per launch by a uniform switch, so that every variant stays straight-line code (uniform
+// branches inside the unrolled loop break its schedule). Each wave keeps B in registers and
+// streams 8 row tiles, loading the next tile's Q while the current one is on the matrix cores.
 #include "lrp_kernels.h"
 
 namespace lrp {
@@ -22,69 +24,91 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kProdTilesPerWave = 8;
 constexpr int kProdRowsPerBlock = 16 * kProdTilesPerWave * 4;  // 4 waves
 
-__global__ __launch_bounds__(256) void k_prod(ProdArgs a) {
-  const DevState* st = a.st;
-  if (st->done || (a.gate_guess && !st->guess_ok)) return;
-  const int side = blockIdx.y;
-  const int kin = st->ncols[side];
-  const int r = st->r[a.nb];
+template <int KS, int NT>
+__device__ __forceinline__ void prod_body(const ProdArgs& a, int side, int kin, int r, double* Bs) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  // B zero-padded to 64 x 64 in LDS (row-major, padded rows), then held in registers by
-  // every wave for all of its row tiles
-  __shared__ double Bs[kPMax * (kPMax + 1)];
+  // B zero-padded to 64 x 64 in LDS (Bs: row-major, padded rows), then its live part held in
+  // registers by every wave for all of its row tiles
   const double* Bg = a.B[side];
   for (int e = threadIdx.x; e < kPMax * kPMax; e += blockDim.x) {
     const int m = e % kPMax, c = e / kPMax;
     Bs[m * (kPMax + 1) + c] = (m < kin && c < r) ? Bg[m + (int64_t)c * a.pmax] : 0.0;
   }
   __syncthreads();
-  double bt[16][4];
+  double bt[KS][NT];
 #pragma unroll
-  for (int ks = 0; ks < 16; ++ks)
+  for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) bt[ks][nt] = Bs[(4 * ks + lk) * (kPMax + 1) + 16 * nt + lr];
+    for (int nt = 0; nt < NT; ++nt) bt[ks][nt] = Bs[(4 * ks + lk) * (kPMax + 1) + 16 * nt + lr];
   const double* Q = a.Q[side];
   double* out = a.out[side];
   const int64_t base = (int64_t)blockIdx.x * kProdRowsPerBlock + (int64_t)wave * 16 * kProdTilesPerWave;
-  auto load_tile = [&](int tile, double (&q)[16]) {
+  auto load_tile = [&](int tile, double (&q)[KS]) {
     const int64_t i = base + 16 * tile + lr;
     const bool row_ok = i < a.n;
 #pragma unroll
-    for (int ks = 0; ks < 16; ++ks) {
+    for (int ks = 0; ks < KS; ++ks) {
       const int m = 4 * ks + lk;
       q[ks] = (row_ok && m < kin) ? Q[i + (int64_t)m * a.ldq] : 0.0;
     }
   };
-  double qa[16], qb[16];
+  double qa[KS], qb[KS];
   load_tile(0, qa);
 #pragma unroll 1
   for (int tile = 0; tile < kProdTilesPerWave; tile += 2) {
     // even tile from qa while qb is loading, then odd tile from qb while qa is loading
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      double(&qc)[16] = h == 0 ? qa : qb;
-      double(&qn)[16] = h == 0 ? qb : qa;
+      double(&qc)[KS] = h == 0 ? qa : qb;
+      double(&qn)[KS] = h == 0 ? qb : qa;
       const int tcur = tile + h;
       if (tcur + 1 < kProdTilesPerWave) load_tile(tcur + 1, qn);
-      d4 acc[4];
+      d4 acc[NT];
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) acc[nt] = d4{0.0, 0.0, 0.0, 0.0};
+      for (int nt = 0; nt < NT; ++nt) acc[nt] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int ks = 0; ks < 16; ++ks)
+      for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
+        for (int nt = 0; nt < NT; ++nt)
           acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(bt[ks][nt], qc[ks], acc[nt], 0, 0, 0);
       const int64_t i = base + 16 * tcur + lr;
       const bool row_ok = i < a.n;
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt)
+      for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int c = 16 * nt + lk + 4 * v;
           if (row_ok && c < r) out[i + (int64_t)c * a.ldo] = acc[nt][v];
         }
     }
+  }
+}
+
+template <int KS>
+__device__ __forceinline__ void prod_nt(const ProdArgs& a, int side, int kin, int r, double* Bs) {
+  switch ((r + 15) >> 4) {  // uniform
+    case 0:
+    case 1: prod_body<KS, 1>(a, side, kin, r, Bs); break;
+    case 2: prod_body<KS, 2>(a, side, kin, r, Bs); break;
+    case 3: prod_body<KS, 3>(a, side, kin, r, Bs); break;
+    default: prod_body<KS, 4>(a, side, kin, r, Bs); break;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_prod(ProdArgs a) {
+  const DevState* st = a.st;
+  if (st->done || (a.gate_guess && !st->guess_ok)) return;
+  const int side = blockIdx.y;
+  const int kin = st->ncols[side];
+  const int r = st->r[a.nb];
+  __shared__ double Bs[kPMax * (kPMax + 1)];
+  switch ((kin + 15) >> 4) {  // uniform: 4-row steps of B in groups of four
+    case 0:
+    case 1: prod_nt<4>(a, side, kin, r, Bs); break;
+    case 2: prod_nt<8>(a, side, kin, r, Bs); break;
+    case 3: prod_nt<12>(a, side, kin, r, Bs); break;
+    default: prod_nt<16>(a, side, kin, r, Bs); break;
   }
 }
 

@@ -68,13 +68,16 @@ __device__ inline void stage2(double* SA, const double* XA, int ca, double* SB, 
 // output columns (FP64 MFMA 16x16x4; the chunk rows are the contraction index).
 // A operand: X^T(16 w + l%16, k0 + l/16) = X[k0 + l/16][16 w + l%16]; B operand:
 // Y[k0 + l/16][16 nt + l%16]; result item v of lane l: row 16 w + l/16 + 4 v, column 16 nt + l%16.
+// Only the NT live output column tiles run (Y is zero beyond them); a wave whose output rows
+// are all beyond X's live columns skips the chunk (its output stays zero).
+template <int NT>
 __device__ inline void gram_chunk(const double* X, const double* Y, int w, int lr, int lk, d4 (&acc)[4]) {
 #pragma unroll
   for (int ks = 0; ks < kRhoChunk / 4; ++ks) {
     const int row = 4 * ks + lk;
     const double xa = X[row * kRS + 16 * w + lr];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+    for (int nt = 0; nt < NT; ++nt)
       acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, Y[row * kRS + 16 * nt + lr], acc[nt], 0, 0, 0);
   }
 }
@@ -86,13 +89,10 @@ __device__ inline void store_partial(double* out, int w, int lr, int lk, const d
     for (int v = 0; v < 4; ++v) out[(16 * w + lk + 4 * v) * kPMax + 16 * nt + lr] = acc[nt][v];
 }
 
-// Pass A: partial M = A^T B over the block's rows.
-__global__ __launch_bounds__(kRhoThreads) void k_rho_a(RhoKArgs a) {
-  DevState* st = a.st;
-  if (!rho_needed(st)) return;
-  const int side = blockIdx.y;
-  const int r = st->r[a.nb_new], ro = st->r[a.nb_old];
-  __shared__ double As[kRhoChunk * kRS], Bs[kRhoChunk * kRS];
+// Pass A: partial M = A^T B over the block's rows (output tiles: NT = ceil(ro/16) columns,
+// rows below r).
+template <int NT>
+__device__ __forceinline__ void rho_a_body(const RhoKArgs& a, int side, int r, int ro, double* As, double* Bs) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
   d4 acc[4];
 #pragma unroll
@@ -102,21 +102,33 @@ __global__ __launch_bounds__(kRhoThreads) void k_rho_a(RhoKArgs a) {
   for (int64_t r0 = row0; r0 < rend; r0 += kRhoChunk) {
     stage2(As, a.A[side], r, Bs, a.B[side], ro, a.ldu, rend, r0);
     __syncthreads();
-    gram_chunk(As, Bs, w, lr, lk, acc);
+    if (16 * w < r) gram_chunk<NT>(As, Bs, w, lr, lk, acc);  // uniform per wave
     __syncthreads();
   }
   store_partial(a.part + ((int64_t)blockIdx.x * 2 + side) * kPMax * kPMax, w, lr, lk, acc);
 }
 
-// Pass B: Y = B - A M (rows of the chunk, MFMA with M as the second operand), then partial
-// G = Y^T Y.
-__global__ __launch_bounds__(kRhoThreads) void k_rho_b(RhoKArgs a) {
+__global__ __launch_bounds__(kRhoThreads) void k_rho_a(RhoKArgs a) {
   DevState* st = a.st;
   if (!rho_needed(st)) return;
   const int side = blockIdx.y;
   const int r = st->r[a.nb_new], ro = st->r[a.nb_old];
   __shared__ double As[kRhoChunk * kRS], Bs[kRhoChunk * kRS];
-  __shared__ double Ms[kPMax * kRS];
+  switch ((ro + 15) >> 4) {  // uniform
+    case 0:
+    case 1: rho_a_body<1>(a, side, r, ro, As, Bs); break;
+    case 2: rho_a_body<2>(a, side, r, ro, As, Bs); break;
+    case 3: rho_a_body<3>(a, side, r, ro, As, Bs); break;
+    default: rho_a_body<4>(a, side, r, ro, As, Bs); break;
+  }
+}
+
+// Pass B: Y = B - A M (rows of the chunk, MFMA with M as the second operand), then partial
+// G = Y^T Y. Live tiles only: KS 4-column steps of A (r rounded up to 16), NT output column
+// tiles (ceil(ro/16)); the waves whose G rows lie beyond ro skip the Gram product.
+template <int KS, int NT>
+__device__ __forceinline__ void rho_b_body(const RhoKArgs& a, int side, int r, int ro, double* As, double* Bs,
+                                           double* Ms) {
   const double* Mg = a.M + (int64_t)side * kPMax * kPMax;
   for (int e = threadIdx.x; e < kPMax * kPMax; e += blockDim.x) Ms[(e / kPMax) * kRS + e % kPMax] = Mg[e];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
@@ -134,25 +146,53 @@ __global__ __launch_bounds__(kRhoThreads) void k_rho_b(RhoKArgs a) {
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) tm[nt] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int ks = 0; ks < kPMax / 4; ++ks) {
+    for (int ks = 0; ks < KS; ++ks) {
       const double xa = As[(16 * w + lr) * kRS + 4 * ks + lk];
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt)
+      for (int nt = 0; nt < NT; ++nt)
         tm[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, Ms[(4 * ks + lk) * kRS + 16 * nt + lr], tm[nt], 0, 0, 0);
     }
     // Y = B - T in place of B (each element is read and written by its own lane)
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+    for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         double* y = &Bs[(16 * w + lk + 4 * v) * kRS + 16 * nt + lr];
         *y = *y - tm[nt][v];
       }
     __syncthreads();
-    gram_chunk(Bs, Bs, w, lr, lk, acc);
+    if (16 * w < ro) gram_chunk<NT>(Bs, Bs, w, lr, lk, acc);  // uniform per wave
     __syncthreads();
   }
   store_partial(a.part + ((int64_t)blockIdx.x * 2 + side) * kPMax * kPMax, w, lr, lk, acc);
+}
+
+template <int KS>
+__device__ __forceinline__ void rho_b_nt(const RhoKArgs& a, int side, int r, int ro, double* As, double* Bs,
+                                         double* Ms) {
+  switch ((ro + 15) >> 4) {  // uniform
+    case 0:
+    case 1: rho_b_body<KS, 1>(a, side, r, ro, As, Bs, Ms); break;
+    case 2: rho_b_body<KS, 2>(a, side, r, ro, As, Bs, Ms); break;
+    case 3: rho_b_body<KS, 3>(a, side, r, ro, As, Bs, Ms); break;
+    default: rho_b_body<KS, 4>(a, side, r, ro, As, Bs, Ms); break;
+  }
+}
+
+__global__ __launch_bounds__(kRhoThreads) void k_rho_b(RhoKArgs a) {
+  DevState* st = a.st;
+  if (!rho_needed(st)) return;
+  const int side = blockIdx.y;
+  const int r = st->r[a.nb_new], ro = st->r[a.nb_old];
+  __shared__ double As[kRhoChunk * kRS], Bs[kRhoChunk * kRS];
+  __shared__ double Ms[kPMax * kRS];
+  switch ((r + 15) >> 4) {  // uniform: 4-column steps of A in groups of four
+    case 0:
+    case 1: rho_b_nt<4>(a, side, r, ro, As, Bs, Ms); break;
+    case 2: rho_b_nt<8>(a, side, r, ro, As, Bs, Ms); break;
+    case 3: rho_b_nt<12>(a, side, r, ro, As, Bs, Ms); break;
+    default: rho_b_nt<16>(a, side, r, ro, As, Bs, Ms); break;
+  }
 }
 
 // Sum the per-block partials in block order: out[side][e] = sum_b part[b][side][e].
