@@ -14,6 +14,8 @@
 
 namespace lrp {
 
+constexpr int kCUs = 256;  // compute units of the MI355X
+
 struct FactorArgs {
   const DevState* st;
   int ncols[2];
@@ -197,7 +199,7 @@ __device__ inline void householder_column(const double (&col)[4], int c, int l, 
 // applies it to its four columns (four dot products reduced together), and the wave of column
 // j+1 goes on at once to build v_{j+1}: one barrier per reflector. Nothing is written to global
 // memory inside the loop, so the per-step barrier waits on LDS only.
-__global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) {
+__device__ __forceinline__ void factor_block(const FactorArgs& a) {
   const int side = blockIdx.y;
   if (a.st && a.st->done) return;
   const int p = side_cols(a.st, a.ncols, side);
@@ -206,7 +208,9 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) {
   if (p <= 0 || nr <= 0) return;
   const int t = threadIdx.x, l = t & 63, c0 = 4 * (t >> 6), m = slot_perm(l);
   __shared__ double vbuf[2][kTsqrRows];
-  __shared__ double tsh[kPMax];
+  __shared__ double tsh[kPMax];   // tau, R(c, c) and the reflector scale of column c
+  __shared__ double rdsh[kPMax];
+  __shared__ double vssh[kPMax];
 
   // Every load reads a valid element (row and column clamped into the block) and the unused ones
   // are replaced by zeros afterwards, so that all 16 loads are in flight together.
@@ -248,20 +252,17 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) {
     }
   }
   // After its reflector is built, column c is final: its registers keep R(0..c-1, c) above the
-  // diagonal and the unscaled tail below it (the reflector is the tail times vscale), and
-  // rdiag = R(c, c).
-  double rdiag[4] = {0.0, 0.0, 0.0, 0.0}, vscale[4] = {0.0, 0.0, 0.0, 0.0};
+  // diagonal and the unscaled tail below it (the reflector is the tail times vssh[c]), and
+  // rdsh[c] = R(c, c).
   if (c0 == 0) {
     double col[4], beta, tau, sc;
     pick_slot(x, m, col);  // column 0 is slot m
     householder_column(col, 0, l, vbuf[0], beta, tau, sc);
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (q == m) {
-        rdiag[q] = beta;
-        vscale[q] = sc;
-      }
-    if (l == 0) tsh[0] = tau;
+    if (l == 0) {
+      tsh[0] = tau;
+      rdsh[0] = beta;
+      vssh[0] = sc;
+    }
   }
   __syncthreads();
   for (int j = 0; j < p; ++j) {
@@ -287,13 +288,11 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) {
         double col[4], beta, tn, sc;
         pick_slot(x, sl, col);
         householder_column(col, cn, l, vbuf[cn & 1], beta, tn, sc);
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (q == sl) {
-            rdiag[q] = beta;
-            vscale[q] = sc;
-          }
-        if (l == 0) tsh[cn] = tn;
+        if (l == 0) {
+          tsh[cn] = tn;
+          rdsh[cn] = beta;
+          vssh[cn] = sc;
+        }
       }
     }
     __syncthreads();
@@ -305,15 +304,26 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) {
   for (int q = 0; q < 4; ++q) {
     const int c = c0 + (q ^ m);
     if (c < p) {
+      const double rd = rdsh[c], vsc = vssh[c];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int r = 64 * k + l;
-        if (r < nr) V[row0 + r + (int64_t)c * a.ldv] = (r > c) ? x[k][q] * vscale[q] : (r == c ? 1.0 : 0.0);
-        if (r < a.pmax) Rb[r + (int64_t)c * a.ldr] = (r < c) ? x[k][q] : (r == c ? rdiag[q] : 0.0);
+        if (r < nr) V[row0 + r + (int64_t)c * a.ldv] = (r > c) ? x[k][q] * vsc : (r == c ? 1.0 : 0.0);
+        if (r < a.pmax) Rb[r + (int64_t)c * a.ldr] = (r < c) ? x[k][q] : (r == c ? rd : 0.0);
       }
     }
   }
   if (t < p) a.tau[side][(int64_t)blockIdx.x * a.pmax + t] = tsh[t];
+}
+
+// Two builds of the same body: one register-lean enough (64 VGPRs, a few loop-invariant values
+// spilled) for two 16-wave workgroups per CU, for the levels with more workgroups than CUs, where
+// the second workgroup's steps fill the first one's latency; and one without that limit for the
+// upper levels, where each CU runs a single block and the spills would only lengthen its chain.
+__global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) { factor_block(a); }
+__global__ __launch_bounds__(kTsqrThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_tsqr_factor_w8(
+    FactorArgs a) {
+  factor_block(a);
 }
 
 // Q formation in compact WY form on the FP64 matrix cores. The block's reflectors give
@@ -647,7 +657,10 @@ int tsqr_run(const TsqrPlan& p, const TsqrIO& io, hipStream_t s) {
       f.tau[q] = lv.tau[q];
       f.Rout[q] = lv.Rout[q];
     }
-    LRP_LAUNCH(K_TSQR_FACTOR, k_tsqr_factor, dim3(lv.nblocks, ns), dim3(kTsqrThreads), 0, s, f);
+    if ((int64_t)lv.nblocks * ns > kCUs)
+      LRP_LAUNCH(K_TSQR_FACTOR, k_tsqr_factor_w8, dim3(lv.nblocks, ns), dim3(kTsqrThreads), 0, s, f);
+    else
+      LRP_LAUNCH(K_TSQR_FACTOR, k_tsqr_factor, dim3(lv.nblocks, ns), dim3(kTsqrThreads), 0, s, f);
   }
   // top-down formation of Q
   for (int L = p.nlevels - 1; L >= 0; --L) {
