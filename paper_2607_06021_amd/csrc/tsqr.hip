@@ -579,6 +579,223 @@ __global__ __launch_bounds__(kWyThreads) void k_tsqr_apply_wy(ApplyArgs a) {
   }
 }
 
+// The same Q formation in a build lean enough for two workgroups per CU (at most 80 KB of LDS
+// and 128 VGPRs), for the tree levels with more workgroups than CUs: V is staged by 64-row
+// quarters into one 64 x kWyLd buffer, which holds S once V is consumed; the parent piece T_par
+// and the final product's V operands are read from memory where they are used (the block read
+// them moments before, so they come from L2) instead of waiting in registers. Every sum is formed
+// in the same order as in k_tsqr_apply_wy, so the two builds give the same result.
+__global__ __launch_bounds__(kWyThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_tsqr_apply_lean(
+    ApplyArgs a) {
+  const int side = blockIdx.y;
+  if (a.st && a.st->done) return;
+  const int p = side_cols(a.st, a.ncols, side);
+  const int64_t row0 = (int64_t)blockIdx.x * a.block_rows;
+  const int nr = (int)min((int64_t)a.block_rows, a.rows - row0);
+  if (p <= 0 || nr <= 0) return;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  constexpr int kQuarter = kPMax;         // rows of V staged at a time (= the rows of S)
+  constexpr int kWaves = kWyThreads / 64;
+  __shared__ double QS[kQuarter * kWyLd];  // V(r, c) of one quarter, zero past p / nr; then S
+  __shared__ double XZ[kPMax * kWyLd];     // X, then Z in place; zero outside p x p
+  __shared__ double tsh[kPMax];
+  const double* V = a.V[side] + row0;  // V(r, c) = V[r + c ldv], r < nr, c < p
+  const int64_t ldv = a.ldv;
+  const double* T = a.T[side];
+  const int64_t toff = (int64_t)blockIdx.x * a.pmax;
+  const int pt = (p + 15) >> 4;
+  const int pk = (p + 3) >> 2;
+  const int ntiles = pt * (pt + 1) / 2;
+
+  for (int e = t; e < kPMax * kWyLd; e += kWyThreads) XZ[e] = 0.0;
+  if (t < kPMax) tsh[t] = t < p ? a.tau[side][toff + t] : 0.0;
+
+  int tI[2], tJ[2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    int q = wave + kWaves * m, I = 0;
+    while (q >= pt - I && I < pt) {
+      q -= pt - I;
+      ++I;
+    }
+    tI[m] = I;
+    tJ[m] = I + q;
+  }
+  wy4 sacc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+  wy4 xacc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+  constexpr int kPer = kQuarter * kPMax / kWyThreads;  // 8
+
+  for (int qr0 = 0; qr0 < nr; qr0 += kQuarter) {  // uniform
+    double raw[kPer];
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+      const int e = t + kWyThreads * m, r = e % kQuarter, c = e / kQuarter;
+      raw[m] = V[min(qr0 + r, nr - 1) + (int64_t)min(c, p - 1) * ldv];
+    }
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+      const int e = t + kWyThreads * m, r = e % kQuarter, c = e / kQuarter;
+      keep_loaded(raw[m]);
+      QS[r * kWyLd + c] = (qr0 + r < nr && c < p) ? raw[m] : 0.0;
+    }
+    __syncthreads();
+    const int nks = (min(nr - qr0, kQuarter) + 3) >> 2;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      if (wave + kWaves * m >= ntiles) continue;
+      const int I = tI[m], J = tJ[m];
+      for (int ks = max(0, (16 * I - qr0) >> 2); ks < nks; ++ks) {
+        const double* row = QS + (4 * ks + lk) * kWyLd;
+        sacc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(row[16 * I + lr], row[16 * J + lr], sacc[m], 0, 0, 0);
+      }
+    }
+    if (qr0 == 0 && T) {  // X = V(0:p, :)^T T_par (p <= 64 rows: the first quarter)
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const int q = wave + kWaves * m;
+        if (q >= pt * pt) continue;
+        const int I = q / pt, J = q % pt;
+        for (int k0 = 4 * I; k0 < pk; k0 += 4) {
+          double tv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int r = 4 * (k0 + u) + lk;
+            tv[u] = T[toff + min(r, p - 1) + (int64_t)min(16 * J + lr, p - 1) * a.ldt];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int r = 4 * (k0 + u) + lk;
+            keep_loaded(tv[u]);
+            const double b = (r < p && 16 * J + lr < p) ? tv[u] : 0.0;
+            xacc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(QS[r * kWyLd + 16 * I + lr], b, xacc[m], 0, 0, 0);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // the staging buffer becomes S: zero, then the upper tiles
+  for (int e = t; e < kPMax * kWyLd; e += kWyThreads) QS[e] = 0.0;
+  __syncthreads();
+  double* S = QS;
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    if (wave + kWaves * m >= ntiles) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S[(16 * tI[m] + lk + 4 * v) * kWyLd + 16 * tJ[m] + lr] = sacc[m][v];
+  }
+  if (T) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int q = wave + kWaves * m;
+      if (q >= pt * pt) continue;
+      const int I = q / pt, J = q % pt;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) XZ[(16 * I + lk + 4 * v) * kWyLd + 16 * J + lr] = xacc[m][v];
+    }
+  } else {
+    for (int e = t; e < p * p; e += kWyThreads) {
+      const int i = e / p, j = e % p;
+      XZ[i * kWyLd + j] = V[j + (int64_t)i * ldv];  // X = V(0:p, 0:p)^T; j, i < p <= nr
+    }
+  }
+  __syncthreads();
+
+  // back substitution by 16-row blocks from the bottom (as in k_tsqr_apply_wy)
+  for (int b = pt - 1; b >= 0; --b) {  // uniform
+    const int r0 = 16 * b;
+    if (wave == 0) {
+      double x[16];
+#pragma unroll
+      for (int w = 0; w < 16; ++w) x[w] = XZ[(r0 + w) * kWyLd + lane];
+#pragma unroll
+      for (int w = 15; w >= 0; --w) {
+        const double z = tsh[r0 + w] * x[w];
+        XZ[(r0 + w) * kWyLd + lane] = z;
+#pragma unroll
+        for (int w2 = 0; w2 < w; ++w2) x[w2] = fma(-S[(r0 + w2) * kWyLd + r0 + w], z, x[w2]);
+      }
+    }
+    __syncthreads();
+    if (b == 0) break;
+    for (int q = wave; q < b * pt; q += kWaves) {
+      const int I = q / pt, J = q % pt;
+      wy4 acc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] = XZ[(16 * I + lk + 4 * v) * kWyLd + 16 * J + lr];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-S[(16 * I + lr) * kWyLd + r0 + 4 * kk + lk],
+                                                   XZ[(r0 + 4 * kk + lk) * kWyLd + 16 * J + lr], acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) XZ[(16 * I + lk + 4 * v) * kWyLd + 16 * J + lr] = acc[v];
+    }
+    __syncthreads();
+  }
+
+  // Y^T = Y0^T - Z^T V^T for this wave's row tiles; T_par and V from memory
+  double* Y = a.Y[side] + row0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int R = wave + kWaves * h;
+    const int row = 16 * R + lr;
+    if (16 * R >= nr) continue;  // uniform
+    double vb[16];
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+      const int c = 4 * ks + lk;
+      vb[ks] = V[min(row, nr - 1) + (int64_t)min(c, p - 1) * ldv];
+    }
+    wy4 acc[4];
+    if (T) {
+      double tp[4][4];
+#pragma unroll
+      for (int J = 0; J < 4; ++J)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int c = 16 * J + lk + 4 * v;
+          tp[J][v] = T[toff + min(row, p - 1) + (int64_t)min(c, p - 1) * a.ldt];
+        }
+#pragma unroll
+      for (int J = 0; J < 4; ++J)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int c = 16 * J + lk + 4 * v;
+          keep_loaded(tp[J][v]);
+          acc[J][v] = (row < p && c < p) ? tp[J][v] : 0.0;
+        }
+    } else {
+#pragma unroll
+      for (int J = 0; J < 4; ++J)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[J][v] = (row < p && row == 16 * J + lk + 4 * v) ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+      keep_loaded(vb[ks]);
+      vb[ks] = (row < nr && 4 * ks + lk < p) ? -vb[ks] : 0.0;
+    }
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+      if (ks >= pk) break;
+      const double* Zk = XZ + (4 * ks + lk) * kWyLd + lr;
+#pragma unroll
+      for (int J = 0; J < 4; ++J)
+        if (J < pt) acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(Zk[16 * J], vb[ks], acc[J], 0, 0, 0);
+    }
+    if (row < nr) {
+#pragma unroll
+      for (int J = 0; J < 4; ++J)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int col = 16 * J + lk + 4 * v;
+          if (col < p) Y[row + (int64_t)col * a.ldy] = acc[J][v];
+        }
+    }
+  }
+}
+
 // ----------------------------------------------------------------------------------------
 // Tree layout: level 0 factors n rows in blocks of kTsqrRows; each level above stacks the R
 // factors of g = kTsqrRows / pmax blocks. `get(bytes)` supplies each buffer (nullptr: failure);
@@ -681,7 +898,10 @@ int tsqr_run(const TsqrPlan& p, const TsqrIO& io, hipStream_t s) {
     }
     a.ldt = (L == p.nlevels - 1) ? 0 : p.lev[L + 1].rows;
     a.ldy = (L == 0 && io.Q[0]) ? io.ldq : lv.rows;
-    LRP_LAUNCH(K_TSQR_APPLY, k_tsqr_apply_wy, dim3(lv.nblocks, ns), dim3(kWyThreads), 0, s, a);
+    if ((int64_t)lv.nblocks * ns > kCUs)
+      LRP_LAUNCH(K_TSQR_APPLY, k_tsqr_apply_lean, dim3(lv.nblocks, ns), dim3(kWyThreads), 0, s, a);
+    else
+      LRP_LAUNCH(K_TSQR_APPLY, k_tsqr_apply_wy, dim3(lv.nblocks, ns), dim3(kWyThreads), 0, s, a);
   }
   return launch_status();
 }
