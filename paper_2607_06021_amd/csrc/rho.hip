@@ -14,7 +14,8 @@
 
 namespace lrp {
 
-constexpr int kRhoChunk = 64;
+constexpr int kRhoChunk = 64;   // rows per staged chunk (pass A)
+constexpr int kRhoChunkB = 32;  // (pass B)
 
 struct RhoKArgs {
   DevState* st;
@@ -42,20 +43,21 @@ constexpr int kRhoThreads = 256;
 // XB into SB (row-major, stride 65), zero beyond the columns and beyond n. Every load reads a
 // valid element (clamped row and column); all 32 loads of a thread are issued before any is
 // used, so they are in flight together.
+template <int CH = kRhoChunk>
 __device__ inline void stage2(double* SA, const double* XA, int ca, double* SB, const double* XB, int cb,
                               int64_t ldu, int64_t n, int64_t r0) {
-  constexpr int kPer = kRhoChunk * kPMax / kRhoThreads;  // 16
+  constexpr int kPer = CH * kPMax / kRhoThreads;  // 16 for 64-row chunks
   double va[kPer], vb[kPer];
 #pragma unroll
   for (int m = 0; m < kPer; ++m) {
-    const int e = threadIdx.x + kRhoThreads * m, row = e % kRhoChunk, c = e / kRhoChunk;
+    const int e = threadIdx.x + kRhoThreads * m, row = e % CH, c = e / CH;
     const int64_t i = min(r0 + row, n - 1);
     va[m] = XA[i + (int64_t)min(c, max(ca - 1, 0)) * ldu];
     vb[m] = XB[i + (int64_t)min(c, max(cb - 1, 0)) * ldu];
   }
 #pragma unroll
   for (int m = 0; m < kPer; ++m) {
-    const int e = threadIdx.x + kRhoThreads * m, row = e % kRhoChunk, c = e / kRhoChunk;
+    const int e = threadIdx.x + kRhoThreads * m, row = e % CH, c = e / CH;
     const bool rok = r0 + row < n;
     asm volatile("" : "+v"(va[m]));
     asm volatile("" : "+v"(vb[m]));
@@ -70,10 +72,10 @@ __device__ inline void stage2(double* SA, const double* XA, int ca, double* SB, 
 // Y[k0 + l/16][16 nt + l%16]; result item v of lane l: row 16 w + l/16 + 4 v, column 16 nt + l%16.
 // Only the NT live output column tiles run (Y is zero beyond them); a wave whose output rows
 // are all beyond X's live columns skips the chunk (its output stays zero).
-template <int NT>
+template <int NT, int CH = kRhoChunk>
 __device__ inline void gram_chunk(const double* X, const double* Y, int w, int lr, int lk, d4 (&acc)[4]) {
 #pragma unroll
-  for (int ks = 0; ks < kRhoChunk / 4; ++ks) {
+  for (int ks = 0; ks < CH / 4; ++ks) {
     const int row = 4 * ks + lk;
     const double xa = X[row * kRS + 16 * w + lr];
 #pragma unroll
@@ -125,43 +127,56 @@ __global__ __launch_bounds__(kRhoThreads) void k_rho_a(RhoKArgs a) {
 
 // Pass B: Y = B - A M (rows of the chunk, MFMA with M as the second operand), then partial
 // G = Y^T Y. Live tiles only: KS 4-column steps of A (r rounded up to 16), NT output column
-// tiles (ceil(ro/16)); the waves whose G rows lie beyond ro skip the Gram product.
+// tiles (ceil(ro/16)); the waves whose G rows lie beyond ro skip the Gram product. Chunks of 32
+// rows keep the LDS at 66 KB, so that two workgroups share a CU; the T product's tiles (2 row
+// tiles x NT column tiles) are spread over the four waves. Every element is summed in the same
+// order as with 64-row chunks.
 template <int KS, int NT>
 __device__ __forceinline__ void rho_b_body(const RhoKArgs& a, int side, int r, int ro, double* As, double* Bs,
                                            double* Ms) {
+  constexpr int CH = kRhoChunkB;
   const double* Mg = a.M + (int64_t)side * kPMax * kPMax;
   for (int e = threadIdx.x; e < kPMax * kPMax; e += blockDim.x) Ms[(e / kPMax) * kRS + e % kPMax] = Mg[e];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
+  const int rt = w & 1, nt0 = w >> 1;  // T tiles of this wave: row tile rt, column tiles nt0, nt0 + 2
   d4 acc[4];
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) acc[nt] = d4{0.0, 0.0, 0.0, 0.0};
   const int64_t row0 = (int64_t)blockIdx.x * a.rows_per_block;
   const int64_t rend = min(a.n, row0 + a.rows_per_block);
-  for (int64_t r0 = row0; r0 < rend; r0 += kRhoChunk) {
-    stage2(As, a.A[side], r, Bs, a.B[side], ro, a.ldu, rend, r0);
+  for (int64_t r0 = row0; r0 < rend; r0 += CH) {
+    stage2<CH>(As, a.A[side], r, Bs, a.B[side], ro, a.ldu, rend, r0);
     __syncthreads();
-    // T = A M for chunk rows 16 w .. 16 w + 15: A operand A[16 w + l%16][k0 + l/16], B operand
-    // M[k0 + l/16][16 nt + l%16]; result item v: row 16 w + l/16 + 4 v, column 16 nt + l%16
-    d4 tm[4];
+    // T = A M for chunk rows 16 rt .. 16 rt + 15, column tiles nt0 + 2 j: A operand
+    // A[16 rt + l%16][k0 + l/16], B operand M[k0 + l/16][16 nt + l%16]; result item v: row
+    // 16 rt + l/16 + 4 v, column 16 nt + l%16
+    d4 tm[2];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) tm[nt] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < 2; ++j) tm[j] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      const double xa = As[(16 * w + lr) * kRS + 4 * ks + lk];
+      const double xa = As[(16 * rt + lr) * kRS + 4 * ks + lk];
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt)
-        tm[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, Ms[(4 * ks + lk) * kRS + 16 * nt + lr], tm[nt], 0, 0, 0);
+      for (int j = 0; j < 2; ++j) {
+        const int nt = nt0 + 2 * j;
+        if (nt < NT)  // uniform per wave
+          tm[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, Ms[(4 * ks + lk) * kRS + 16 * nt + lr], tm[j], 0, 0, 0);
+      }
     }
     // Y = B - T in place of B (each element is read and written by its own lane)
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt)
+    for (int j = 0; j < 2; ++j) {
+      const int nt = nt0 + 2 * j;
+      if (nt < NT) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        double* y = &Bs[(16 * w + lk + 4 * v) * kRS + 16 * nt + lr];
-        *y = *y - tm[nt][v];
+        for (int v = 0; v < 4; ++v) {
+          double* y = &Bs[(16 * rt + lk + 4 * v) * kRS + 16 * nt + lr];
+          *y = *y - tm[j][v];
+        }
       }
+    }
     __syncthreads();
-    if (16 * w < ro) gram_chunk<NT>(Bs, Bs, w, lr, lk, acc);  // uniform per wave
+    if (16 * w < ro) gram_chunk<NT, CH>(Bs, Bs, w, lr, lk, acc);  // uniform per wave
     __syncthreads();
   }
   store_partial(a.part + ((int64_t)blockIdx.x * 2 + side) * kPMax * kPMax, w, lr, lk, acc);
@@ -184,7 +199,7 @@ __global__ __launch_bounds__(kRhoThreads) void k_rho_b(RhoKArgs a) {
   if (!rho_needed(st)) return;
   const int side = blockIdx.y;
   const int r = st->r[a.nb_new], ro = st->r[a.nb_old];
-  __shared__ double As[kRhoChunk * kRS], Bs[kRhoChunk * kRS];
+  __shared__ double As[kRhoChunkB * kRS], Bs[kRhoChunkB * kRS];
   __shared__ double Ms[kPMax * kRS];
   switch ((r + 15) >> 4) {  // uniform: 4-column steps of A in groups of four
     case 0:
