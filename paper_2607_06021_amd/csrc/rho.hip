@@ -210,13 +210,19 @@ __global__ __launch_bounds__(kRhoThreads) void k_rho_b(RhoKArgs a) {
   }
 }
 
-// Sum the per-block partials in block order: out[side][e] = sum_b part[b][side][e].
+// Sum the per-block partials in block order: out[side][e] = sum_b part[b][side][e]. Only the
+// live rows x cols block is read (rows: r_new for M, r_old for G; cols: r_old); every partial
+// outside it is an exact zero, and so is the sum written there.
 __global__ __launch_bounds__(256) void k_rho_reduce(const DevState* st, const double* part, int nblocks,
-                                                    double* out) {
+                                                    double* out, int nb_rows, int nb_cols) {
   if (!rho_needed(st)) return;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;  // 0 .. 2*4096
   if (e >= 2 * kPMax * kPMax) return;
   const int side = e / (kPMax * kPMax), q = e % (kPMax * kPMax);
+  if (q / kPMax >= st->r[nb_rows] || q % kPMax >= st->r[nb_cols]) {
+    out[e] = 0.0;
+    return;
+  }
   // 16 loads in flight per step, added into four partial sums in a fixed order
   double sm[4] = {0.0, 0.0, 0.0, 0.0};
   const double* src = part + (int64_t)side * kPMax * kPMax + q;
@@ -247,42 +253,67 @@ __global__ __launch_bounds__(256) void k_rho_final(RhoFinalArgs a) {
   if (st->done) return;
   const bool need = rho_needed(st);
   __shared__ double red[4];
-  __shared__ double Am[kPMax][kPMax + 1], Bm[kPMax][kPMax + 1];
+  // M_u S' and the small matrices N_v, G_u, G_v in LDS (the loops below read them at a
+  // data-dependent length, so from memory every read would wait on its own latency)
+  __shared__ double Am[kPMax][kPMax + 1], Nvs[kPMax][kPMax + 1], Gus[kPMax][kPMax + 1], Gvs[kPMax][kPMax + 1];
+  __shared__ double Sos[kPMax];
   double rho = INFINITY;
   if (need) {
     const int r = st->r[a.nb_new], ro = st->r[a.nb_old];
     const double* S = st->S[a.nb_new];
-    const double* So = st->S[a.nb_old];
+    const double* So = Sos;
     const double* Mu = a.M;
-    const double* Nv = a.M + kPMax * kPMax;
-    const double* Gu = a.G;
-    const double* Gv = a.G + kPMax * kPMax;
-    for (int e = threadIdx.x; e < kPMax * kPMax; e += blockDim.x) {
-      const int aa = e / kPMax, m = e % kPMax;
-      Am[aa][m] = (aa < r && m < ro) ? Mu[aa * kPMax + m] * So[m] : 0.0;  // M_u S'
-      Bm[aa][m] = (aa < r && m < ro) ? Nv[aa * kPMax + m] * So[m] : 0.0;  // N_v S'
+    // every thread's loads are issued together (unrolled, fixed count), not one wait each
+    constexpr int kPer = kPMax * kPMax / 256;  // 16 (the kernel runs 256 threads)
+    if (threadIdx.x < kPMax) Sos[threadIdx.x] = st->S[a.nb_old][threadIdx.x];
+    {
+      double vn[kPer], vu[kPer], vv[kPer], vm[kPer];
+#pragma unroll
+      for (int m = 0; m < kPer; ++m) {
+        const int e = threadIdx.x + 256 * m;
+        vn[m] = a.M[kPMax * kPMax + e];
+        vu[m] = a.G[e];
+        vv[m] = a.G[kPMax * kPMax + e];
+        vm[m] = Mu[e];
+      }
+#pragma unroll
+      for (int m = 0; m < kPer; ++m) {
+        const int e = threadIdx.x + 256 * m, aa = e / kPMax, c = e % kPMax;
+        Nvs[aa][c] = vn[m];
+        Gus[aa][c] = vu[m];
+        Gvs[aa][c] = vv[m];
+        Am[aa][c] = vm[m];  // M_u for now; times S' below
+      }
     }
     __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+      const int e = threadIdx.x + 256 * m, aa = e / kPMax, c = e % kPMax;
+      Am[aa][c] = (aa < r && c < ro) ? Am[aa][c] * So[c] : 0.0;  // M_u S'
+    }
+    __syncthreads();
+    // N_v S' (Bm) is formed where it is used, with the same rounding as a stored product
+    auto Bm = [&](int aa, int m) { return (aa < r && m < ro) ? Nvs[aa][m] * So[m] : 0.0; };
     double part = 0.0;
     for (int e = threadIdx.x; e < r * r; e += blockDim.x) {  // T1
       const int aa = e / r, b = e % r;
       double s = (aa == b) ? S[aa] : 0.0;
-      for (int m = 0; m < ro; ++m) s = fma(-Am[aa][m], Nv[b * kPMax + m], s);
+      for (int m = 0; m < ro; ++m) s = fma(-Am[aa][m], Nvs[b][m], s);
       part = fma(s, s, part);
     }
     for (int e = threadIdx.x; e < r * ro; e += blockDim.x) {  // T2 and T3
       const int aa = e / ro, m2 = e % ro;
       double p2 = 0.0, p3 = 0.0;
       for (int m = 0; m < ro; ++m) {
-        p2 = fma(Am[aa][m], Gv[m * kPMax + m2], p2);
-        p3 = fma(Bm[aa][m], Gu[m * kPMax + m2], p3);
+        p2 = fma(Am[aa][m], Gvs[m][m2], p2);
+        p3 = fma(Bm(aa, m), Gus[m][m2], p3);
       }
       part = fma(p2, Am[aa][m2], part);
-      part = fma(p3, Bm[aa][m2], part);
+      part = fma(p3, Bm(aa, m2), part);
     }
     for (int e = threadIdx.x; e < ro * ro; e += blockDim.x) {  // T4
       const int m = e / ro, m2 = e % ro;
-      part += So[m] * Gu[m * kPMax + m2] * So[m2] * Gv[m2 * kPMax + m];
+      part += So[m] * Gus[m][m2] * So[m2] * Gvs[m2][m];
     }
     const double tot = block_sum256(part, red);
     rho = sqrt(fmax(tot, 0.0)) / st->nrm;
@@ -324,10 +355,12 @@ int rho_launch(const RhoPlan& p, const RhoArgs& ra, hipStream_t s) {
   a.part = p.part;
   const int red_blocks = (2 * kPMax * kPMax + 255) / 256;
   LRP_LAUNCH(K_RHO_A, k_rho_a, dim3(p.nblocks, 2), dim3(kRhoThreads), 0, s, a);
-  LRP_LAUNCH(K_RHO_REDUCE, k_rho_reduce, dim3(red_blocks), dim3(256), 0, s, ra.st, p.part, p.nblocks, p.M);
+  LRP_LAUNCH(K_RHO_REDUCE, k_rho_reduce, dim3(red_blocks), dim3(256), 0, s, ra.st, p.part, p.nblocks, p.M,
+             ra.nb_new, ra.nb_old);
   a.M = p.M;
   LRP_LAUNCH(K_RHO_B, k_rho_b, dim3(p.nblocks, 2), dim3(kRhoThreads), 0, s, a);
-  LRP_LAUNCH(K_RHO_REDUCE, k_rho_reduce, dim3(red_blocks), dim3(256), 0, s, ra.st, p.part, p.nblocks, p.G);
+  LRP_LAUNCH(K_RHO_REDUCE, k_rho_reduce, dim3(red_blocks), dim3(256), 0, s, ra.st, p.part, p.nblocks, p.G,
+             ra.nb_old, ra.nb_old);
   RhoFinalArgs f{};
   f.st = ra.st;
   f.M = p.M;
