@@ -281,8 +281,20 @@ def served_leg(count, seed, budget_gb, max_active, rate=None):
         use_rate = rate if rate is not None else 0.7 * sat
         reqs = workloads.served_stream(count=count, rate_per_s=use_rate, seed=seed)
         log(f"served: {ctx0} contexts warm; saturated {sat:.1f} solves/s; Poisson arrivals at {use_rate:.1f}/s")
+        st0 = srv.stats()
         wall, res, late = run(reqs, use_rate)
         st = srv.stats()
+        # the same saturated measurement with same-stage grouping off (passes on per-request streams)
+        srv.set_grouping(False)
+        for rs in shapes.values():
+            run((rs * max_active)[:max_active], None)
+        wall_u, _, _ = run(probe[:nsat], None)
+        sat_u = nsat / wall_u
+        srv.set_grouping(True)
+        log(f"served: saturated {sat_u:.1f} solves/s with grouping off")
+    grouping = {"mean_group_size_poisson": round((st["passes"] - st0["passes"]) /
+                                                 max(1, st["pass_launches"] - st0["pass_launches"]), 2),
+                "saturated_solves_per_s_grouping_off": round(sat_u, 2)}
     lat = late + np.array([x[6] for x in res])           # from the scheduled arrival
     queue = late + np.array([x[7] for x in res])         # arrival to admission
     runms = np.array([x[8] for x in res])                # admission to completion
@@ -303,7 +315,7 @@ def served_leg(count, seed, budget_gb, max_active, rate=None):
                          for i, nn, rk, pr, stt in bad[:10]],
             "mix": "n in {1023,4095,16383,65535,262143} w.p. .3/.3/.2/.15/.05, rank U{2..20}, cap 48, "
                    "FP64 or mixed w.p. 0.5", "max_active": max_active, "contexts_warm": ctx0,
-            "contexts_after": st["contexts"]}
+            "contexts_after": st["contexts"], "grouping": grouping}
 
 
 def cpu_baseline(w, U, s, V):

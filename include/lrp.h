@@ -324,10 +324,12 @@ int64_t lrp_tsqr_noalloc_max_bytes(void);
  * Requests (each one Poisson solve of the kind lrp_solve performs) are admitted in arrival
  * order as soon as a context of their shape (n, r_max, tol, maxiter, precision) is free or
  * can be created inside the device-memory budget; idle contexts of other shapes are freed to
- * make room. Every admitted request advances pass by pass on its own HIP stream, so passes
- * of different requests overlap on the device and a finished request frees its context
- * immediately for the next one. A request computes exactly what lrp_solve computes for it,
- * bit for bit, whatever else is in flight. The scheduler runs on a thread of its own.
+ * make room. Every admitted request advances pass by pass; the requests of one shape that
+ * are ready for their next pass run it together as one launch per stage (same-stage grouping,
+ * lrp_server_set_grouping), and groups of different shapes overlap on the device. A finished
+ * request frees its context immediately for the next one. A request computes exactly what
+ * lrp_solve computes for it, bit for bit, whatever else is in flight or in its group. The
+ * scheduler runs on a thread of its own.
  * --------------------------------------------------------------------------------------- */
 typedef struct lrp_server lrp_server;
 
@@ -358,6 +360,11 @@ typedef struct lrp_server_stats {
   int64_t queued, active;               /* waiting for admission / being solved now */
   int64_t bytes_in_use, bytes_budget;   /* device memory held by contexts / allowed */
   int32_t contexts;                     /* contexts currently held */
+  int32_t grouping;                     /* 1: same-stage grouping on (lrp_server_set_grouping) */
+  int64_t passes;                       /* Cross-DEIM passes run, over all requests */
+  int64_t pass_launches;                /* pass launch sequences: a grouped pass of m requests
+                                           counts once, so passes / pass_launches is the mean
+                                           group size */
 } lrp_server_stats;
 
 /*
@@ -403,6 +410,15 @@ int lrp_server_release(lrp_server* srv, int64_t ticket);
 
 /* lrp_server_get_stats -- counters of the server (host struct). */
 int lrp_server_get_stats(lrp_server* srv, lrp_server_stats* out);
+
+/*
+ * lrp_server_set_grouping -- same-stage grouping on (enabled != 0, the default) or off.
+ * With grouping on, the requests of one shape that are ready for their next Cross-DEIM pass
+ * (Alg. 4, one iteration) run it together, as one launch per stage of the pass (one graph per
+ * group size); off, each request's passes run on its own stream. Results are bitwise the same
+ * either way. Allowed only while no request is queued or active: LRP_EINVAL otherwise.
+ */
+int lrp_server_set_grouping(lrp_server* srv, int32_t enabled);
 
 /* lrp_server_destroy -- finish every admitted request, drop queued ones, free everything. */
 int lrp_server_destroy(lrp_server* srv);

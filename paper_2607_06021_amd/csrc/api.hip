@@ -210,6 +210,33 @@ int create_impl(lrp_ctx* c) {
   return LRP_OK;
 }
 
+// ---------------------------------------------------------------- pass records
+static thread_local PassRecord* g_rec = nullptr;  // record being filled on this thread
+
+PassRecord*& pass_recorder() { return g_rec; }
+
+void record_launch(PassRecord* r, const void* fn, dim3 grid, dim3 block, size_t shm, const void* args, size_t size) {
+  if (grid.z != 1 || block.y != 1 || block.z != 1 || shm > UINT32_MAX || size > 65536) {
+    r->bad = true;
+    return;
+  }
+  const size_t off = (r->blob.size() + 15) & ~(size_t)15;
+  r->blob.resize(off + size);
+  memcpy(r->blob.data() + off, args, size);
+  r->recs.push_back(LaunchRec{fn, grid.x, grid.y, block.x, (uint32_t)shm, (uint32_t)off, (uint32_t)size});
+}
+
+int enqueue_pass_kernels(lrp_ctx* c, int k);
+
+int record_pass(lrp_ctx* c, int k, PassRecord* out) {
+  *out = PassRecord{};
+  if (c->profile) return LRP_EINVAL;
+  g_rec = out;
+  const int rc = enqueue_pass_kernels(c, k);
+  g_rec = nullptr;
+  return (rc == LRP_OK && !out->bad && !out->recs.empty()) ? LRP_OK : LRP_EINVAL;
+}
+
 // ---------------------------------------------------------------- launch profile
 static thread_local lrp_ctx* g_prof = nullptr;  // context recording a profile on this thread
 

@@ -566,7 +566,7 @@ __device__ void explicit_reflectors(double* QR, int m, int k) {
 // row on the dependent chain); then the waves update the rows above the block,
 // X(0:16b, :) -= R(0:16b, block) X(block, :), as 16 x 16 MFMA tiles. Only the strict upper
 // triangle of QR is read (the reflector tails below it are not), and QR is zero past column k.
-__device__ void tri_inverse(const double* QR, int k, double* Ri, double* dinv) {
+__device__ __forceinline__ void tri_inverse(const double* QR, int k, double* Ri, double* dinv) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = blockDim.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   if (t < kPMax) dinv[t] = t < k ? 1.0 / QR[t + t * LDP] : 0.0;
@@ -688,7 +688,9 @@ __device__ __forceinline__ int svd_qr(double* Mb, int nJ, int nI, double cut_mul
   return r;
 }
 
-__global__ __launch_bounds__(kCoreThreads) void k_core(CoreArgs a) {
+template <class Src>
+__global__ __launch_bounds__(kCoreThreads) void k_core(Src in) {
+  const CoreArgs& a = kernel_args<CoreArgs>(in);
   DevState* st = a.st;
   if (st->done) return;
   __shared__ double B0[kBuf], B1[kBuf], B2[kBuf], B3[kBuf];
@@ -879,7 +881,9 @@ __global__ __launch_bounds__(kCoreThreads) void k_core(CoreArgs a) {
 // each stored tall (rows >= cols) so that Jacobi gives its min(rows, cols) singular values;
 // the two problems are solved side by side. Then the pass is accepted as the new iterate and
 // the solve stops when max(rho, indicator) < eps, or after maxiter passes.
-__global__ __launch_bounds__(kEtaThreads) void k_eta(EtaArgs a) {
+template <class Src>
+__global__ __launch_bounds__(kEtaThreads) void k_eta(Src in) {
+  const EtaArgs& a = kernel_args<EtaArgs>(in);
   DevState* st = a.st;
   if (st->done) return;
   __shared__ double E1[kBuf], E2[kBuf], Qs[kBuf], Us[kBuf];
@@ -965,7 +969,7 @@ __global__ __launch_bounds__(kEtaThreads) void k_eta(EtaArgs a) {
 }
 
 int eta_launch(const EtaArgs& a, hipStream_t s) {
-  LRP_LAUNCH(K_ETA, k_eta, dim3(1), dim3(kEtaThreads), 0, s, a);
+  LRP_LAUNCH_G(K_ETA, k_eta<EtaArgs>, k_eta<GroupRef>, dim3(1), dim3(kEtaThreads), 0, s, a);
   return launch_status();
 }
 
@@ -1028,7 +1032,7 @@ int core_launch(const CoreArgs& a, bool warm, hipStream_t s) {
   if (warm) {
     LRP_LAUNCH(K_CORE_WARM, k_core_warm, dim3(1), dim3(kCoreThreads), 0, s, a);
   } else {
-    LRP_LAUNCH(K_CORE, k_core, dim3(1), dim3(kCoreThreads), 0, s, a);
+    LRP_LAUNCH_G(K_CORE, k_core<CoreArgs>, k_core<GroupRef>, dim3(1), dim3(kCoreThreads), 0, s, a);
   }
   return launch_status();
 }

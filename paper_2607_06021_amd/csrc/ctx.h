@@ -83,6 +83,9 @@ int enqueue_selection(lrp_ctx* c, const double* U[2]);
 int enqueue_start(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const double* sigma_F,
                   const double* V_F, int64_t ldv);
 int enqueue_pass(lrp_ctx* c, int k);
+// The launches of pass k (they depend on its parity only) recorded, not made: for passes of
+// several requests run as one launch per stage. LRP_EINVAL if a launch has no grouped form.
+int record_pass(lrp_ctx* c, int k, PassRecord* out);
 int enqueue_poll(lrp_ctx* c, int k);
 int enqueue_finish(lrp_ctx* c, double* U_out, int64_t ldou, double* S_out, double* V_out, int64_t ldov);
 int collect(lrp_ctx* c, int32_t* r_out, lrp_info* info);

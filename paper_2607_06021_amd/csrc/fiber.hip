@@ -23,8 +23,9 @@ __device__ inline float div_pos(float q, float d) { return q / d; }
 // to kPMax with a uniform bound test, so the row never leaves registers); the outputs of 8
 // columns are accumulated at once (two partial sums each, so 16 independent FMA chains hide
 // the FP latency), with b_c(t) read from LDS as broadcasts.
-template <typename T>
-__global__ __launch_bounds__(256) void k_fiber(FiberArgs a) {
+template <typename T, class Src>
+__global__ __launch_bounds__(256) void k_fiber(Src in) {
+  const FiberArgs& a = kernel_args<FiberArgs>(in);
   const DevState* st = a.st;
   if (st->done) return;
   const int side = blockIdx.y;
@@ -87,8 +88,9 @@ __device__ inline double matrix_entry(int kind, int64_t i, int64_t j, int64_t n)
   return (t2 * t2) * t;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_fiber_matrix(FiberArgs a) {
+template <typename T, class Src>
+__global__ __launch_bounds__(256) void k_fiber_matrix(Src in) {
+  const FiberArgs& a = kernel_args<FiberArgs>(in);
   const DevState* st = a.st;
   if (st->done) return;
   const int side = blockIdx.y;
@@ -111,15 +113,15 @@ int fiber_launch(const FiberArgs& a, bool fp32, hipStream_t s) {
   dim3 grid((unsigned)((a.n + 255) / 256), 2);
   if (a.matrix != LRP_MAT_POISSON) {
     if (fp32)
-      LRP_LAUNCH(K_FIBER, k_fiber_matrix<float>, grid, dim3(256), 0, s, a);
+      LRP_LAUNCH_G(K_FIBER, (k_fiber_matrix<float, FiberArgs>), (k_fiber_matrix<float, GroupRef>), grid, dim3(256), 0, s, a);
     else
-      LRP_LAUNCH(K_FIBER, k_fiber_matrix<double>, grid, dim3(256), 0, s, a);
+      LRP_LAUNCH_G(K_FIBER, (k_fiber_matrix<double, FiberArgs>), (k_fiber_matrix<double, GroupRef>), grid, dim3(256), 0, s, a);
     return launch_status();
   }
   if (fp32)
-    LRP_LAUNCH(K_FIBER, k_fiber<float>, grid, dim3(256), 0, s, a);
+    LRP_LAUNCH_G(K_FIBER, (k_fiber<float, FiberArgs>), (k_fiber<float, GroupRef>), grid, dim3(256), 0, s, a);
   else
-    LRP_LAUNCH(K_FIBER, k_fiber<double>, grid, dim3(256), 0, s, a);
+    LRP_LAUNCH_G(K_FIBER, (k_fiber<double, FiberArgs>), (k_fiber<double, GroupRef>), grid, dim3(256), 0, s, a);
   return launch_status();
 }
 

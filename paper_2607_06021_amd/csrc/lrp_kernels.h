@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "lrp_internal.h"
 
@@ -30,8 +31,74 @@ ProfEvents prof_launch(hipStream_t s, int id);
 void prof_begin(hipStream_t s, int id);
 void prof_end(hipStream_t s);
 
+// ---------------------------------------------------------------- grouped launches
+// A pass of several requests of one shape runs as one launch per stage (the serving loop):
+// each request keeps the argument blocks of its pass's launches in device memory, at the same
+// offsets as every other request of that shape, and workgroup z of a grouped launch runs the
+// stage's kernel body on request z's block. The grid's x and y and the body are those of the
+// solo launch, so a request's result does not depend on the group it ran in.
+struct GroupRef {
+  const char* const* bases;  // per request z: its argument area (device)
+  uint32_t off;              // offset of this launch's block in every area
+};
+// The blocks are read through the constant address space: they do not change while a launch
+// runs, so uniform reads of them (dynamic indexing included) become scalar loads, as reads of
+// the kernel argument segment are.
+typedef const __attribute__((address_space(4))) char* lrp_const_ptr;
+template <class A>
+__device__ __forceinline__ const A& group_args(const GroupRef& g) {
+  const lrp_const_ptr* tab = (const lrp_const_ptr*)(const __attribute__((address_space(4))) void*)g.bases;
+  return *(const A*)(const __attribute__((address_space(4))) A*)(tab[blockIdx.z] + g.off);
+}
+// A stage kernel is a template over where its argument block comes from: the block itself (a
+// solo launch) or a GroupRef (a grouped launch); the kernel body binds `const Args& a` to
+// kernel_args<Args>(src) and is otherwise the same code for both.
+template <class A>
+__device__ __forceinline__ const A& kernel_args(const A& a) {
+  return a;
+}
+template <class A>
+__device__ __forceinline__ const A& kernel_args(const GroupRef& g) {
+  return group_args<A>(g);
+}
+
+// One launch of a recorded pass: the grouped kernel, the solo grid and block, and where the
+// argument block sits in the request's argument area.
+struct LaunchRec {
+  const void* fn;
+  unsigned gx, gy, bx;
+  uint32_t shm, off, size;
+  bool operator==(const LaunchRec& o) const {
+    return fn == o.fn && gx == o.gx && gy == o.gy && bx == o.bx && shm == o.shm && off == o.off && size == o.size;
+  }
+};
+// While a recorder is set on this thread, the launchers of a pass record instead of launching;
+// a launch without a grouped form marks the record unusable.
+struct PassRecord {
+  std::vector<LaunchRec> recs;
+  std::vector<unsigned char> blob;  // the argument blocks, 16-byte aligned
+  bool bad = false;
+};
+PassRecord*& pass_recorder();
+void record_launch(PassRecord* r, const void* fn, dim3 grid, dim3 block, size_t shm, const void* args, size_t size);
+
+// Launch of a stage with a grouped form KERNEL_G (one argument block ARGS).
+#define LRP_LAUNCH_G(ID, KERNEL, KERNEL_G, GRID, BLOCK, SHM, STREAM, ARGS)                             \
+  do {                                                                                                \
+    if (::lrp::PassRecord* rec_ = ::lrp::pass_recorder()) {                                           \
+      ::lrp::record_launch(rec_, reinterpret_cast<const void*>(KERNEL_G), GRID, BLOCK, SHM, &(ARGS),     \
+                           sizeof(ARGS));                                                             \
+      break;                                                                                          \
+    }                                                                                                 \
+    LRP_LAUNCH(ID, KERNEL, GRID, BLOCK, SHM, STREAM, ARGS);                                           \
+  } while (0)
+
 #define LRP_LAUNCH(ID, KERNEL, GRID, BLOCK, SHM, STREAM, ...)                                        \
   do {                                                                                              \
+    if (::lrp::PassRecord* rec_any_ = ::lrp::pass_recorder()) {                                     \
+      rec_any_->bad = true;                                                                         \
+      break;                                                                                        \
+    }                                                                                               \
     const ::lrp::ProfEvents pe_ = ::lrp::prof_launch((STREAM), (ID));                               \
     if (pe_.start)                                                                                  \
       hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHM, STREAM, pe_.start, pe_.stop, 0, __VA_ARGS__);  \

@@ -96,7 +96,9 @@ __device__ __forceinline__ void prod_nt(const ProdArgs& a, int side, int kin, in
   }
 }
 
-__global__ __launch_bounds__(256) void k_prod(ProdArgs a) {
+template <class Src>
+__global__ __launch_bounds__(256) void k_prod(Src in) {
+  const ProdArgs& a = kernel_args<ProdArgs>(in);
   const DevState* st = a.st;
   if (st->done || (a.gate_guess && !st->guess_ok)) return;
   const int side = blockIdx.y;
@@ -114,7 +116,7 @@ __global__ __launch_bounds__(256) void k_prod(ProdArgs a) {
 
 int prod_launch(const ProdArgs& a, hipStream_t s) {
   dim3 grid((unsigned)((a.n + kProdRowsPerBlock - 1) / kProdRowsPerBlock), 2);
-  LRP_LAUNCH(K_PROD, k_prod, grid, dim3(256), 0, s, a);
+  LRP_LAUNCH_G(K_PROD, k_prod<ProdArgs>, k_prod<GroupRef>, grid, dim3(256), 0, s, a);
   return launch_status();
 }
 

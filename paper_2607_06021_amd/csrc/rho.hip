@@ -110,7 +110,9 @@ __device__ __forceinline__ void rho_a_body(const RhoKArgs& a, int side, int r, i
   store_partial(a.part + ((int64_t)blockIdx.x * 2 + side) * kPMax * kPMax, w, lr, lk, acc);
 }
 
-__global__ __launch_bounds__(kRhoThreads) void k_rho_a(RhoKArgs a) {
+template <class Src>
+__global__ __launch_bounds__(kRhoThreads) void k_rho_a(Src in) {
+  const RhoKArgs& a = kernel_args<RhoKArgs>(in);
   DevState* st = a.st;
   if (!rho_needed(st)) return;
   const int side = blockIdx.y;
@@ -194,7 +196,9 @@ __device__ __forceinline__ void rho_b_nt(const RhoKArgs& a, int side, int r, int
   }
 }
 
-__global__ __launch_bounds__(kRhoThreads) void k_rho_b(RhoKArgs a) {
+template <class Src>
+__global__ __launch_bounds__(kRhoThreads) void k_rho_b(Src in) {
+  const RhoKArgs& a = kernel_args<RhoKArgs>(in);
   DevState* st = a.st;
   if (!rho_needed(st)) return;
   const int side = blockIdx.y;
@@ -213,8 +217,22 @@ __global__ __launch_bounds__(kRhoThreads) void k_rho_b(RhoKArgs a) {
 // Sum the per-block partials in block order: out[side][e] = sum_b part[b][side][e]. Only the
 // live rows x cols block is read (rows: r_new for M, r_old for G; cols: r_old); every partial
 // outside it is an exact zero, and so is the sum written there.
-__global__ __launch_bounds__(256) void k_rho_reduce(const DevState* st, const double* part, int nblocks,
-                                                    double* out, int nb_rows, int nb_cols) {
+struct RhoReduceArgs {
+  const DevState* st;
+  const double* part;  // nblocks x 2 x kPMax x kPMax
+  int nblocks;
+  double* out;         // 2 x kPMax x kPMax
+  int nb_rows, nb_cols;
+};
+
+template <class Src>
+__global__ __launch_bounds__(256) void k_rho_reduce(Src in) {
+  const RhoReduceArgs& a = kernel_args<RhoReduceArgs>(in);
+  const DevState* st = a.st;
+  const double* part = a.part;
+  const int nblocks = a.nblocks;
+  double* out = a.out;
+  const int nb_rows = a.nb_rows, nb_cols = a.nb_cols;
   if (!rho_needed(st)) return;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;  // 0 .. 2*4096
   if (e >= 2 * kPMax * kPMax) return;
@@ -248,7 +266,9 @@ struct RhoFinalArgs {
   TraceBuf trace;
 };
 
-__global__ __launch_bounds__(256) void k_rho_final(RhoFinalArgs a) {
+template <class Src>
+__global__ __launch_bounds__(256) void k_rho_final(Src in) {
+  const RhoFinalArgs& a = kernel_args<RhoFinalArgs>(in);
   DevState* st = a.st;
   if (st->done) return;
   const bool need = rho_needed(st);
@@ -354,13 +374,15 @@ int rho_launch(const RhoPlan& p, const RhoArgs& ra, hipStream_t s) {
   a.nb_old = ra.nb_old;
   a.part = p.part;
   const int red_blocks = (2 * kPMax * kPMax + 255) / 256;
-  LRP_LAUNCH(K_RHO_A, k_rho_a, dim3(p.nblocks, 2), dim3(kRhoThreads), 0, s, a);
-  LRP_LAUNCH(K_RHO_REDUCE, k_rho_reduce, dim3(red_blocks), dim3(256), 0, s, ra.st, p.part, p.nblocks, p.M,
-             ra.nb_new, ra.nb_old);
+  LRP_LAUNCH_G(K_RHO_A, k_rho_a<RhoKArgs>, k_rho_a<GroupRef>, dim3(p.nblocks, 2), dim3(kRhoThreads), 0, s, a);
+  const RhoReduceArgs rd{ra.st, p.part, p.nblocks, p.M, ra.nb_new, ra.nb_old};
+  LRP_LAUNCH_G(K_RHO_REDUCE, k_rho_reduce<RhoReduceArgs>, k_rho_reduce<GroupRef>, dim3(red_blocks), dim3(256), 0, s,
+               rd);
   a.M = p.M;
-  LRP_LAUNCH(K_RHO_B, k_rho_b, dim3(p.nblocks, 2), dim3(kRhoThreads), 0, s, a);
-  LRP_LAUNCH(K_RHO_REDUCE, k_rho_reduce, dim3(red_blocks), dim3(256), 0, s, ra.st, p.part, p.nblocks, p.G,
-             ra.nb_old, ra.nb_old);
+  LRP_LAUNCH_G(K_RHO_B, k_rho_b<RhoKArgs>, k_rho_b<GroupRef>, dim3(p.nblocks, 2), dim3(kRhoThreads), 0, s, a);
+  const RhoReduceArgs rg{ra.st, p.part, p.nblocks, p.G, ra.nb_old, ra.nb_old};
+  LRP_LAUNCH_G(K_RHO_REDUCE, k_rho_reduce<RhoReduceArgs>, k_rho_reduce<GroupRef>, dim3(red_blocks), dim3(256), 0, s,
+               rg);
   RhoFinalArgs f{};
   f.st = ra.st;
   f.M = p.M;
@@ -369,7 +391,7 @@ int rho_launch(const RhoPlan& p, const RhoArgs& ra, hipStream_t s) {
   f.nb_old = ra.nb_old;
   f.maxiter = ra.maxiter;
   f.trace = ra.trace;
-  LRP_LAUNCH(K_RHO_FINAL, k_rho_final, dim3(1), dim3(256), 0, s, f);
+  LRP_LAUNCH_G(K_RHO_FINAL, k_rho_final<RhoFinalArgs>, k_rho_final<GroupRef>, dim3(1), dim3(256), 0, s, f);
   return launch_status();
 }
 

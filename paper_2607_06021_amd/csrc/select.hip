@@ -53,7 +53,9 @@ struct PiArgs {
   double* bmax[2];
 };
 
-__global__ __launch_bounds__(256) void k_pi(PiArgs a) {
+template <class Src>
+__global__ __launch_bounds__(256) void k_pi(Src in) {
+  const PiArgs& a = kernel_args<PiArgs>(in);
   const DevState* st = a.st;
   if (st->done) return;
   const int side = blockIdx.y;
@@ -73,16 +75,23 @@ __global__ __launch_bounds__(256) void k_pi(PiArgs a) {
   if (threadIdx.x == 0) a.bmax[side][blockIdx.x] = m;
 }
 
-__global__ __launch_bounds__(256) void k_gmax(const DevState* st, double* const* bmax_unused,
-                                              const double* b0, const double* b1, int nb,
-                                              double* gmax) {
-  if (st->done) return;
-  const double* b = blockIdx.x == 0 ? b0 : b1;
+struct GmaxArgs {
+  const DevState* st;
+  const double* b[2];  // per side: nb block maxima
+  int nb;
+  double* gmax;        // out: 2
+};
+
+template <class Src>
+__global__ __launch_bounds__(256) void k_gmax(Src in) {
+  const GmaxArgs& a = kernel_args<GmaxArgs>(in);
+  if (a.st->done) return;
+  const double* b = a.b[blockIdx.x];
   double m = 0.0;
-  for (int e = threadIdx.x; e < nb; e += blockDim.x) m = fmax(m, b[e]);
+  for (int e = threadIdx.x; e < a.nb; e += blockDim.x) m = fmax(m, b[e]);
   __shared__ double red[4];
   m = block_max256(m, red);
-  if (threadIdx.x == 0) gmax[blockIdx.x] = m;
+  if (threadIdx.x == 0) a.gmax[blockIdx.x] = m;
 }
 
 struct TopkArgs {
@@ -100,7 +109,9 @@ struct TopkArgs {
 // Rank of each entry of a 256-row block in the (score desc, index asc) order by counting the
 // entries before it; scores sit in their own LDS array and are read two per load (the same
 // address on every lane, a broadcast), indices only for a tied score.
-__global__ __launch_bounds__(256) void k_topk_block(TopkArgs a) {
+template <class Src>
+__global__ __launch_bounds__(256) void k_topk_block(Src in) {
+  const TopkArgs& a = kernel_args<TopkArgs>(in);
   const DevState* st = a.st;
   if (st->done) return;
   const int side = blockIdx.y;
@@ -172,7 +183,9 @@ struct MergeArgs {
 // are each written once. One thread per entry; scores and indices are kept in separate LDS
 // arrays, double-buffered between rounds, and an index is read only on a tied score.
 constexpr int kMergeThreads = kMergeFan * kPMax;  // 1024
-__global__ __launch_bounds__(kMergeThreads) void k_topk_merge(MergeArgs a) {
+template <class Src>
+__global__ __launch_bounds__(kMergeThreads) void k_topk_merge(Src in) {
+  const MergeArgs& a = kernel_args<MergeArgs>(in);
   if (a.st->done) return;
   const int side = blockIdx.y;
   constexpr int NE = kMergeFan * kPMax;
@@ -229,7 +242,9 @@ __global__ __launch_bounds__(kMergeThreads) void k_topk_merge(MergeArgs a) {
   }
 }
 
-__global__ __launch_bounds__(64) void k_select(SelectArgs a) {
+template <class Src>
+__global__ __launch_bounds__(64) void k_select(Src in) {
+  const SelectArgs& a = kernel_args<SelectArgs>(in);
   DevState* st = a.st;
   if (st->done) return;
   const int t = threadIdx.x;
@@ -397,7 +412,9 @@ __device__ inline int block_min_int256(int x, int* scratch) {
   return r;
 }
 
-__global__ __launch_bounds__(kQdRows) void k_qdeim_step(QdeimArgs a) {
+template <class Src>
+__global__ __launch_bounds__(kQdRows) void k_qdeim_step(Src in) {
+  const QdeimArgs& a = kernel_args<QdeimArgs>(in);
   const DevState* st = a.st;
   if (st->done) return;
   const int r = st->r_sig, j = a.j;
@@ -547,7 +564,7 @@ int qdeim_launch(const QdeimPlan& p, const DevState* st, const double* U[2], int
   a.ctl = p.ctl;
   for (int j = 0; j < pmax; ++j) {
     a.j = j;
-    LRP_LAUNCH(K_QDEIM, k_qdeim_step, dim3(p.nblocks, 2), dim3(kQdRows), 0, s, a);
+    LRP_LAUNCH_G(K_QDEIM, k_qdeim_step<QdeimArgs>, k_qdeim_step<GroupRef>, dim3(p.nblocks, 2), dim3(kQdRows), 0, s, a);
   }
   return launch_status();
 }
@@ -591,9 +608,14 @@ int select_candidates(const SelectPlan& p, const DevState* st, const double* U[2
     pa.pi[q] = p.pi[q];
     pa.bmax[q] = p.bmax[q];
   }
-  LRP_LAUNCH(K_PI, k_pi, dim3(p.nblocks, 2), dim3(256), 0, s, pa);
-  LRP_LAUNCH(K_GMAX, k_gmax, dim3(2), dim3(256), 0, s, st, nullptr, p.bmax[0], p.bmax[1], p.nblocks,
-                     p.gmax);
+  LRP_LAUNCH_G(K_PI, k_pi<PiArgs>, k_pi<GroupRef>, dim3(p.nblocks, 2), dim3(256), 0, s, pa);
+  GmaxArgs ga{};
+  ga.st = st;
+  ga.b[0] = p.bmax[0];
+  ga.b[1] = p.bmax[1];
+  ga.nb = p.nblocks;
+  ga.gmax = p.gmax;
+  LRP_LAUNCH_G(K_GMAX, k_gmax<GmaxArgs>, k_gmax<GroupRef>, dim3(2), dim3(256), 0, s, ga);
   TopkArgs ta{};
   ta.st = st;
   ta.pi[0] = p.pi[0];
@@ -607,7 +629,7 @@ int select_candidates(const SelectPlan& p, const DevState* st, const double* U[2
     ta.cs[q] = p.cand_s[0][q];
     ta.ci[q] = p.cand_i[0][q];
   }
-  LRP_LAUNCH(K_TOPK_BLOCK, k_topk_block, dim3(p.nblocks, 2), dim3(256), 0, s, ta);
+  LRP_LAUNCH_G(K_TOPK_BLOCK, k_topk_block<TopkArgs>, k_topk_block<GroupRef>, dim3(p.nblocks, 2), dim3(256), 0, s, ta);
   int slot = 0;
   for (int L = 0; L < p.nlevels; ++L) {
     const int lists = p.lists[L];
@@ -621,7 +643,7 @@ int select_candidates(const SelectPlan& p, const DevState* st, const double* U[2
       ma.out_s[q] = p.cand_s[slot ^ 1][q];
       ma.out_i[q] = p.cand_i[slot ^ 1][q];
     }
-    LRP_LAUNCH(K_TOPK_MERGE, k_topk_merge, dim3(outl, 2), dim3(kMergeThreads), 0, s, ma);
+    LRP_LAUNCH_G(K_TOPK_MERGE, k_topk_merge<MergeArgs>, k_topk_merge<GroupRef>, dim3(outl, 2), dim3(kMergeThreads), 0, s, ma);
     slot ^= 1;
   }
   *final_list_slot = slot;
@@ -629,7 +651,7 @@ int select_candidates(const SelectPlan& p, const DevState* st, const double* U[2
 }
 
 int select_update(const SelectArgs& a, hipStream_t s) {
-  LRP_LAUNCH(K_SELECT, k_select, dim3(1), dim3(kPMax), 0, s, a);
+  LRP_LAUNCH_G(K_SELECT, k_select<SelectArgs>, k_select<GroupRef>, dim3(1), dim3(kPMax), 0, s, a);
   return launch_status();
 }
 

@@ -7,10 +7,17 @@
 // -- start, passes, finish -- but the scheduler advances all active requests together: it
 // enqueues the next pass of a request while at most two of its passes are unchecked, reads
 // each pass's stop flag through an event query (never blocking), and enqueues the finish
-// stage once the flag is set or maxiter passes were made. Passes of different requests thus
-// overlap on the device, and a finished request frees its slot at once for the next one.
-// A request's kernels and their arguments are exactly those of a solo lrp_solve, so its
-// result does not depend on what else is in flight.
+// stage once the flag is set or maxiter passes were made. A finished request frees its slot
+// at once for the next one.
+//
+// Same-stage grouping: requests whose passes make the same launches (one shape) form a group
+// with a stream of its own. At every scheduler tick the group's requests that may take their
+// next pass run it together, as one launch per stage: a captured graph per group size whose
+// kernels take a table of the requests' argument areas and run request z's arguments in
+// workgroup z (the grouped kernels of lrp_kernels.h). Start and finish stages stay on the
+// slots' streams, ordered against the group's stream by events. Groups of different shapes
+// run concurrently. A request's kernels, arguments, grids and reductions are exactly those of
+// a solo lrp_solve, so its result does not depend on what else is in flight or in its group.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -62,7 +69,47 @@ struct Slot {
   int checked = 0;     // passes whose stop flag has been read
   bool stop = false;
   uint64_t last_used = 0;
+  // grouped passes
+  int group = -1;            // index of the slot's group; -1: passes on the slot's stream
+  char* area = nullptr;      // device: the pass's argument blocks, parity 0 then parity 1
+  hipEvent_t ev_start = nullptr;
+  bool started = false;      // the start stage has completed (seen by the host)
+  bool moved = false;        // a pass of the current request ran on the group's stream
 };
+
+// Largest group: the largest number of active requests.
+constexpr int kMaxGroup = 64;
+
+// Requests whose passes make the same launches (grids, kernels, argument offsets).
+struct Group {
+  std::vector<LaunchRec> recs;
+  size_t area = 0;                    // bytes of one parity's argument blocks
+  hipStream_t stream = nullptr;
+  const char** table = nullptr;       // device: kMaxGroup argument-area bases
+  hipGraphExec_t exec[kMaxGroup] = {};  // by group size - 1, captured on first use
+  bool broken = false;                // a graph could not be built: passes run per slot
+};
+
+struct GroupBases {
+  const char* b[kMaxGroup];
+};
+struct GroupPoll {
+  const int* src[kMaxGroup];  // device: each request's stop flag
+  int* dst[kMaxGroup];        // pinned host: where the scheduler reads it
+};
+
+// The table of the group's next launch (written on the group's stream before its graph).
+__global__ void k_group_table(const char** table, GroupBases g, int count) {
+  const int t = threadIdx.x;
+  if (t < count) table[t] = g.b[t];
+}
+
+// After a grouped pass: each request's stop flag into its pinned host slot.
+__global__ void k_group_poll(GroupPoll p, int count) {
+  const int t = threadIdx.x;
+  if (t < count) *p.dst[t] = *p.src[t];
+  __threadfence_system();
+}
 
 }  // namespace
 
@@ -75,6 +122,10 @@ struct lrp_server {
   std::deque<Job*> queue;
   std::map<int64_t, Job*> jobs;
   std::vector<Slot> slots;  // touched only by the scheduler thread (sizes read under mu)
+  std::vector<Group> groups;  // scheduler thread only
+  bool grouping = true;       // set under mu while nothing is queued or active
+  bool grouping_tick = true;  // the scheduler's copy for the current tick
+  int64_t passes = 0, pass_launches = 0;  // under mu
   int64_t bytes_in_use = 0;
   int64_t next_ticket = 1;
   int64_t submitted = 0, completed = 0, failed = 0, active = 0;
@@ -106,7 +157,117 @@ void release_slot_job(Slot& sl, uint64_t tick) {
   sl.phase = 0;
   sl.k = sl.checked = 0;
   sl.stop = false;
+  sl.started = sl.moved = false;
   sl.last_used = tick;
+}
+
+// Passes of this slot run grouped (on its group's stream).
+bool grouped(const lrp_server* s, const Slot& sl) {
+  return s->grouping_tick && sl.group >= 0 && !s->groups[sl.group].broken;
+}
+
+// Records the slot's pass launches (both parities), uploads its argument blocks and joins the
+// group of its launch sequence (created if new). On any failure the slot stays ungrouped.
+void setup_group(lrp_server* s, Slot& sl) {
+  PassRecord r0, r1;
+  if (record_pass(sl.ctx, 0, &r0) != LRP_OK || record_pass(sl.ctx, 1, &r1) != LRP_OK) return;
+  if (!(r0.recs == r1.recs) || r0.blob.size() != r1.blob.size()) return;
+  const size_t half = (r0.blob.size() + 255) & ~(size_t)255;
+  if (hipEventCreateWithFlags(&sl.ev_start, hipEventDisableTiming) != hipSuccess) {
+    sl.ev_start = nullptr;
+    return;
+  }
+  bool ok = hipMalloc(&sl.area, 2 * half) == hipSuccess;
+  if (ok) ok = hipMemcpyAsync(sl.area, r0.blob.data(), r0.blob.size(), hipMemcpyHostToDevice, sl.stream) == hipSuccess;
+  if (ok)
+    ok = hipMemcpyAsync(sl.area + half, r1.blob.data(), r1.blob.size(), hipMemcpyHostToDevice, sl.stream) ==
+         hipSuccess;
+  if (ok) ok = hipStreamSynchronize(sl.stream) == hipSuccess;
+  int idx = -1;
+  for (size_t g = 0; ok && idx < 0 && g < s->groups.size(); ++g)
+    if (s->groups[g].area == half && s->groups[g].recs == r0.recs) idx = (int)g;
+  if (ok && idx < 0) {
+    Group G;
+    G.recs = r0.recs;
+    G.area = half;
+    ok = hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking) == hipSuccess;
+    if (ok && hipMalloc((void**)&G.table, sizeof(char*) * kMaxGroup) != hipSuccess) {
+      (void)hipStreamDestroy(G.stream);
+      ok = false;
+    }
+    if (ok) {
+      s->groups.push_back(G);
+      idx = (int)s->groups.size() - 1;
+    }
+  }
+  if (!ok) {
+    (void)hipGetLastError();
+    if (sl.area) (void)hipFree(sl.area);
+    (void)hipEventDestroy(sl.ev_start);
+    sl.area = nullptr;
+    sl.ev_start = nullptr;
+    return;
+  }
+  sl.group = idx;
+}
+
+// The graph of one grouped pass of m requests: the recorded launches with grid z = m, each
+// kernel reading its argument block through the group's table.
+int build_group_graph(Group& G, int m, hipGraphExec_t* out) {
+  hipGraph_t gr = nullptr;
+  if (hipStreamBeginCapture(G.stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    (void)hipGetLastError();
+    return LRP_EINVAL;
+  }
+  bool ok = true;
+  for (const LaunchRec& r : G.recs) {
+    GroupRef ref{G.table, r.off};
+    void* args[] = {&ref};
+    if (hipLaunchKernel(r.fn, dim3(r.gx, r.gy, (unsigned)m), dim3(r.bx), args, r.shm, G.stream) != hipSuccess) {
+      ok = false;
+      break;
+    }
+  }
+  ok = (hipStreamEndCapture(G.stream, &gr) == hipSuccess) && ok;
+  if (ok) ok = hipGraphInstantiate(out, gr, nullptr, nullptr, 0) == hipSuccess;
+  if (gr) (void)hipGraphDestroy(gr);
+  if (!ok) {
+    *out = nullptr;
+    (void)hipGetLastError();
+    return LRP_EINVAL;
+  }
+  return LRP_OK;
+}
+
+// One grouped pass of the m slots in mem (each at its own pass index): the table, the graph,
+// the stop flags to the host and each slot's pass event. LRP_EINVAL: no graph (nothing
+// enqueued); LRP_EDEVICE: a launch failed.
+int launch_group(lrp_server* s, Group& G, Slot* const* mem, int m) {
+  hipGraphExec_t& ex = G.exec[m - 1];
+  if (!ex && build_group_graph(G, m, &ex) != LRP_OK) return LRP_EINVAL;
+  GroupBases gb{};
+  GroupPoll gp{};
+  for (int i = 0; i < m; ++i) {
+    const Slot& sl = *mem[i];
+    gb.b[i] = sl.area + (size_t)(sl.k & 1) * G.area;
+    gp.src[i] = &sl.ctx->st->done;
+    gp.dst[i] = &sl.ctx->done_host[sl.k & 1];
+  }
+  hipLaunchKernelGGL(k_group_table, dim3(1), dim3(kMaxGroup), 0, G.stream, G.table, gb, m);
+  if (hipGetLastError() != hipSuccess) return LRP_EDEVICE;
+  if (hipGraphLaunch(ex, G.stream) != hipSuccess) return LRP_EDEVICE;
+  hipLaunchKernelGGL(k_group_poll, dim3(1), dim3(kMaxGroup), 0, G.stream, gp, m);
+  if (hipGetLastError() != hipSuccess) return LRP_EDEVICE;
+  for (int i = 0; i < m; ++i) {
+    Slot& sl = *mem[i];
+    if (hipEventRecord(sl.ctx->evit[sl.k & 1], G.stream) != hipSuccess) return LRP_EDEVICE;
+    ++sl.k;
+    sl.moved = true;
+  }
+  std::lock_guard<std::mutex> g(s->mu);
+  s->passes += m;
+  ++s->pass_launches;
+  return LRP_OK;
 }
 
 // Advance one active slot without blocking; true if anything was enqueued or completed.
@@ -115,7 +276,8 @@ bool advance(lrp_server* s, Slot& sl) {
   Job* j = sl.job;
   const lrp_request& q = j->req;
   if (sl.phase == 0) {
-    const int rc = enqueue_start(c, q.r_F, q.U_F, q.ldu, q.sigma_F, q.V_F, q.ldv);
+    int rc = enqueue_start(c, q.r_F, q.U_F, q.ldu, q.sigma_F, q.V_F, q.ldv);
+    if (rc == LRP_OK && grouped(s, sl) && hipEventRecord(sl.ev_start, sl.stream) != hipSuccess) rc = LRP_EDEVICE;
     if (rc != LRP_OK) {
       (void)hipStreamSynchronize(sl.stream);
       finish_job(s, j, rc, 0, nullptr);
@@ -127,6 +289,22 @@ bool advance(lrp_server* s, Slot& sl) {
   }
   if (sl.phase == 1) {
     bool progress = false;
+    if (grouped(s, sl) && !sl.started) {
+      // a grouped request joins its group once its start stage has completed
+      const hipError_t e = hipEventQuery(sl.ev_start);
+      if (e == hipErrorNotReady) {
+        (void)hipGetLastError();
+        return false;
+      }
+      if (e != hipSuccess) {
+        (void)hipStreamSynchronize(sl.stream);
+        finish_job(s, j, LRP_EDEVICE, 0, nullptr);
+        release_slot_job(sl, ++s->tick);
+        return true;
+      }
+      sl.started = true;
+      progress = true;
+    }
     if (sl.checked < sl.k) {
       const hipError_t e = hipEventQuery(c->evit[sl.checked & 1]);
       if (e == hipSuccess) {
@@ -142,8 +320,13 @@ bool advance(lrp_server* s, Slot& sl) {
         (void)hipGetLastError();  // not ready is not an error; leave no error state behind
       }
     }
-    if (!sl.stop && sl.k < c->maxiter && sl.k - sl.checked < 2) {
-      int rc = enqueue_pass(c, sl.k);
+    if (!grouped(s, sl) && !sl.stop && sl.k < c->maxiter && sl.k - sl.checked < 2) {
+      int rc = LRP_OK;
+      if (sl.moved) {  // earlier passes ran on the group's stream
+        if (hipStreamWaitEvent(sl.stream, c->evit[(sl.k - 1) & 1], 0) != hipSuccess) rc = LRP_EDEVICE;
+        sl.moved = false;
+      }
+      if (rc == LRP_OK) rc = enqueue_pass(c, sl.k);
       if (rc == LRP_OK) rc = enqueue_poll(c, sl.k);
       if (rc != LRP_OK) {
         (void)hipStreamSynchronize(sl.stream);
@@ -153,9 +336,15 @@ bool advance(lrp_server* s, Slot& sl) {
       }
       ++sl.k;
       progress = true;
+      std::lock_guard<std::mutex> g(s->mu);
+      ++s->passes;
+      ++s->pass_launches;
     }
     if (sl.stop || (sl.k == c->maxiter && sl.checked == sl.k)) {
-      const int rc = enqueue_finish(c, q.U_out, q.ldou, q.S_out, q.V_out, q.ldov);
+      int rc = LRP_OK;
+      // the finish follows the last pass enqueued, wherever it ran
+      if (sl.moved && hipStreamWaitEvent(sl.stream, c->evit[(sl.k - 1) & 1], 0) != hipSuccess) rc = LRP_EDEVICE;
+      if (rc == LRP_OK) rc = enqueue_finish(c, q.U_out, q.ldou, q.S_out, q.V_out, q.ldov);
       if (rc != LRP_OK) {
         (void)hipStreamSynchronize(sl.stream);
         finish_job(s, j, rc, 0, nullptr);
@@ -186,6 +375,8 @@ void destroy_slot(lrp_server* s, Slot& sl) {
     (void)hipStreamSynchronize(sl.stream);
     lrp_destroy(sl.ctx);
   }
+  if (sl.area) (void)hipFree(sl.area);
+  if (sl.ev_start) (void)hipEventDestroy(sl.ev_start);
   if (sl.stream) (void)hipStreamDestroy(sl.stream);
   s->bytes_in_use -= sl.bytes;
   sl = Slot{};
@@ -236,6 +427,7 @@ bool admit(lrp_server* s) {
         continue;
       }
       s->bytes_in_use += sl.bytes;
+      if (s->grouping) setup_group(s, sl);
       // reuse an empty entry if there is one
       bool placed = false;
       for (Slot& e : s->slots)
@@ -263,6 +455,38 @@ bool admit(lrp_server* s) {
   return progress;
 }
 
+// One grouped pass per group whose requests may take their next pass.
+bool launch_groups(lrp_server* s) {
+  bool progress = false;
+  for (size_t g = 0; g < s->groups.size(); ++g) {
+    Group& G = s->groups[g];
+    if (G.broken || !s->grouping_tick) continue;
+    Slot* mem[kMaxGroup];
+    int m = 0;
+    for (Slot& sl : s->slots)
+      if (m < kMaxGroup && sl.job && sl.group == (int)g && sl.phase == 1 && sl.started && !sl.stop &&
+          sl.k < sl.ctx->maxiter && sl.k - sl.checked < 2)
+        mem[m++] = &sl;
+    if (m == 0) continue;
+    const int rc = launch_group(s, G, mem, m);
+    if (rc == LRP_EINVAL) {  // no graph: the members go on with passes on their own streams
+      G.broken = true;
+      progress = true;
+    } else if (rc != LRP_OK) {
+      (void)hipStreamSynchronize(G.stream);
+      for (int i = 0; i < m; ++i) {
+        (void)hipStreamSynchronize(mem[i]->stream);
+        finish_job(s, mem[i]->job, LRP_EDEVICE, 0, nullptr);
+        release_slot_job(*mem[i], ++s->tick);
+      }
+      progress = true;
+    } else {
+      progress = true;
+    }
+  }
+  return progress;
+}
+
 void scheduler(lrp_server* s) {
   (void)hipSetDevice(s->device);
   for (;;) {
@@ -284,17 +508,27 @@ void scheduler(lrp_server* s) {
         if (s->active == 0) break;
       }
       progress = admit(s);
+      s->grouping_tick = s->grouping;
     }
     for (Slot& sl : s->slots)
       if (sl.job) progress |= advance(s, sl);
+    progress |= launch_groups(s);
     if (!progress) {
       std::unique_lock<std::mutex> g(s->mu);
       if (s->queue.empty() || s->active >= s->max_active)
         s->cv_work.wait_for(g, std::chrono::microseconds(20));
     }
   }
+  for (Group& G : s->groups) (void)hipStreamSynchronize(G.stream);
   for (Slot& sl : s->slots) destroy_slot(s, sl);
   s->slots.clear();
+  for (Group& G : s->groups) {
+    for (hipGraphExec_t& e : G.exec)
+      if (e) (void)hipGraphExecDestroy(e);
+    if (G.table) (void)hipFree(G.table);
+    if (G.stream) (void)hipStreamDestroy(G.stream);
+  }
+  s->groups.clear();
 }
 
 Job* find_job(lrp_server* s, int64_t ticket) {
@@ -425,6 +659,17 @@ int lrp_server_get_stats(lrp_server* s, lrp_server_stats* out) {
   int nc = 0;
   for (const Slot& sl : s->slots) nc += sl.ctx ? 1 : 0;
   out->contexts = nc;
+  out->grouping = s->grouping ? 1 : 0;
+  out->passes = s->passes;
+  out->pass_launches = s->pass_launches;
+  return LRP_OK;
+}
+
+int lrp_server_set_grouping(lrp_server* s, int32_t enabled) {
+  if (!s) return LRP_EINVAL;
+  std::lock_guard<std::mutex> g(s->mu);
+  if (!s->queue.empty() || s->active > 0) return LRP_EINVAL;
+  s->grouping = enabled != 0;
   return LRP_OK;
 }
 

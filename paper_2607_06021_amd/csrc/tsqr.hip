@@ -320,10 +320,14 @@ __device__ __forceinline__ void factor_block(const FactorArgs& a) {
 // spilled) for two 16-wave workgroups per CU, for the levels with more workgroups than CUs, where
 // the second workgroup's steps fill the first one's latency; and one without that limit for the
 // upper levels, where each CU runs a single block and the spills would only lengthen its chain.
-__global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(FactorArgs a) { factor_block(a); }
+template <class Src>
+__global__ __launch_bounds__(kTsqrThreads) void k_tsqr_factor(Src in) {
+  factor_block(kernel_args<FactorArgs>(in));
+}
+template <class Src>
 __global__ __launch_bounds__(kTsqrThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_tsqr_factor_w8(
-    FactorArgs a) {
-  factor_block(a);
+    Src in) {
+  factor_block(kernel_args<FactorArgs>(in));
 }
 
 // Q formation in compact WY form on the FP64 matrix cores. The block's reflectors give
@@ -341,7 +345,9 @@ typedef double wy4 __attribute__((ext_vector_type(4)));
 constexpr int kWyThreads = 512;  // 8 waves
 constexpr int kWyLd = kPMax + 1;
 
-__global__ __launch_bounds__(kWyThreads) void k_tsqr_apply_wy(ApplyArgs a) {
+template <class Src>
+__global__ __launch_bounds__(kWyThreads) void k_tsqr_apply_wy(Src in) {
+  const ApplyArgs& a = kernel_args<ApplyArgs>(in);
   const int side = blockIdx.y;
   if (a.st && a.st->done) return;
   const int p = side_cols(a.st, a.ncols, side);
@@ -585,8 +591,9 @@ __global__ __launch_bounds__(kWyThreads) void k_tsqr_apply_wy(ApplyArgs a) {
 // and the final product's V operands are read from memory where they are used (the block read
 // them moments before, so they come from L2) instead of waiting in registers. Every sum is formed
 // in the same order as in k_tsqr_apply_wy, so the two builds give the same result.
-__global__ __launch_bounds__(kWyThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_tsqr_apply_lean(
-    ApplyArgs a) {
+template <class Src>
+__global__ __launch_bounds__(kWyThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_tsqr_apply_lean(Src in) {
+  const ApplyArgs& a = kernel_args<ApplyArgs>(in);
   const int side = blockIdx.y;
   if (a.st && a.st->done) return;
   const int p = side_cols(a.st, a.ncols, side);
@@ -875,9 +882,9 @@ int tsqr_run(const TsqrPlan& p, const TsqrIO& io, hipStream_t s) {
       f.Rout[q] = lv.Rout[q];
     }
     if ((int64_t)lv.nblocks * ns > kCUs)
-      LRP_LAUNCH(K_TSQR_FACTOR, k_tsqr_factor_w8, dim3(lv.nblocks, ns), dim3(kTsqrThreads), 0, s, f);
+      LRP_LAUNCH_G(K_TSQR_FACTOR, k_tsqr_factor_w8<FactorArgs>, k_tsqr_factor_w8<GroupRef>, dim3(lv.nblocks, ns), dim3(kTsqrThreads), 0, s, f);
     else
-      LRP_LAUNCH(K_TSQR_FACTOR, k_tsqr_factor, dim3(lv.nblocks, ns), dim3(kTsqrThreads), 0, s, f);
+      LRP_LAUNCH_G(K_TSQR_FACTOR, k_tsqr_factor<FactorArgs>, k_tsqr_factor<GroupRef>, dim3(lv.nblocks, ns), dim3(kTsqrThreads), 0, s, f);
   }
   // top-down formation of Q
   for (int L = p.nlevels - 1; L >= 0; --L) {
@@ -899,9 +906,9 @@ int tsqr_run(const TsqrPlan& p, const TsqrIO& io, hipStream_t s) {
     a.ldt = (L == p.nlevels - 1) ? 0 : p.lev[L + 1].rows;
     a.ldy = (L == 0 && io.Q[0]) ? io.ldq : lv.rows;
     if ((int64_t)lv.nblocks * ns > kCUs)
-      LRP_LAUNCH(K_TSQR_APPLY, k_tsqr_apply_lean, dim3(lv.nblocks, ns), dim3(kWyThreads), 0, s, a);
+      LRP_LAUNCH_G(K_TSQR_APPLY, k_tsqr_apply_lean<ApplyArgs>, k_tsqr_apply_lean<GroupRef>, dim3(lv.nblocks, ns), dim3(kWyThreads), 0, s, a);
     else
-      LRP_LAUNCH(K_TSQR_APPLY, k_tsqr_apply_wy, dim3(lv.nblocks, ns), dim3(kWyThreads), 0, s, a);
+      LRP_LAUNCH_G(K_TSQR_APPLY, k_tsqr_apply_wy<ApplyArgs>, k_tsqr_apply_wy<GroupRef>, dim3(lv.nblocks, ns), dim3(kWyThreads), 0, s, a);
   }
   return launch_status();
 }

@@ -71,7 +71,8 @@ class Request(ctypes.Structure):
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", _c_i64), ("completed", _c_i64), ("failed", _c_i64), ("queued", _c_i64),
-                ("active", _c_i64), ("bytes_in_use", _c_i64), ("bytes_budget", _c_i64), ("contexts", _c_i32)]
+                ("active", _c_i64), ("bytes_in_use", _c_i64), ("bytes_budget", _c_i64), ("contexts", _c_i32),
+                ("grouping", _c_i32), ("passes", _c_i64), ("pass_launches", _c_i64)]
 
     def as_dict(self) -> Dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -138,6 +139,8 @@ def lib() -> ctypes.CDLL:
     L.lrp_server_release.restype = ctypes.c_int
     L.lrp_server_get_stats.argtypes = [_c_vp, P(ServerStats)]
     L.lrp_server_get_stats.restype = ctypes.c_int
+    L.lrp_server_set_grouping.argtypes = [_c_vp, _c_i32]
+    L.lrp_server_set_grouping.restype = ctypes.c_int
     L.lrp_server_destroy.argtypes = [_c_vp]
     L.lrp_server_destroy.restype = ctypes.c_int
     L.lrp_context_bytes.argtypes = [_c_i64, _c_i32, _c_i32, _c_i32]
@@ -405,11 +408,17 @@ class Solver:
 class Server:
     """A solve queue with continuous admission (lrp_server_*): submit requests, poll them."""
 
-    def __init__(self, budget_bytes: int, max_active: int = 8):
+    def __init__(self, budget_bytes: int, max_active: int = 8, grouping: bool = True):
         h = _c_vp()
         _check(lib().lrp_server_create(ctypes.byref(h), int(budget_bytes), int(max_active)), "lrp_server_create")
         self._h = h
         self._keep: Dict[int, tuple] = {}
+        if not grouping:
+            self.set_grouping(False)
+
+    def set_grouping(self, enabled: bool):
+        """Same-stage grouping of ready passes on or off (only while nothing is queued or active)."""
+        _check(lib().lrp_server_set_grouping(self._h, 1 if enabled else 0), "lrp_server_set_grouping")
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

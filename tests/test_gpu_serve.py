@@ -50,6 +50,74 @@ def test_served_results_equal_solo_results():
         assert torch.equal(Uo, Us) and torch.equal(So, Ss) and torch.equal(Vo, Vs), (n, prec)
 
 
+def test_grouped_passes_equal_ungrouped_and_solo():
+    """Same-stage grouping: a burst of requests of a few shapes runs its passes as grouped
+    launches (more request passes than pass launches), and every result is bitwise the one
+    of the same server with grouping off and of a solo lrp_solve."""
+    import torch
+
+    from paper_2607_06021_amd import Solver
+    from paper_2607_06021_amd.lrp import Server
+
+    reqs = []
+    for i in range(16):
+        n = (1023, 4095, 16383)[i % 3]
+        U, s, V, _ = workloads.bump_rhs(n, 2000 + i, 2 + (i * 5) % 17, 0.05, 0.2)
+        prec = "mixed" if (i // 3) % 2 else "fp64"
+        reqs.append((n, _dev(U), _dev(s), _dev(V), prec))
+    torch.cuda.synchronize()
+    results = {}
+    for grouping in (True, False):
+        print(f"serving {len(reqs)} requests, grouping {grouping}", flush=True)
+        with Server(budget_bytes=8 << 30, max_active=8, grouping=grouping) as srv:
+            tickets = [srv.submit(n, U, s, V, 48, 1e-10, 20, prec) for (n, U, s, V, prec) in reqs]
+            results[grouping] = [srv.wait(t) for t in tickets]
+            stats = srv.stats()
+        print("  stats", stats, flush=True)
+        assert stats["completed"] == len(reqs) and stats["failed"] == 0
+        assert stats["grouping"] == (1 if grouping else 0)
+        assert stats["passes"] >= len(reqs)
+        if grouping:  # passes of several requests shared launches
+            assert stats["pass_launches"] < stats["passes"]
+        else:
+            assert stats["pass_launches"] == stats["passes"]
+    for i, (n, U, s, V, prec) in enumerate(reqs):
+        a, b = results[True][i], results[False][i]
+        assert a[3:5] == b[3:5] and a[5].iters == b[5].iters, (i, n, prec)
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[2], b[2]), (i, n, prec)
+        if i % 4 == 0:
+            with Solver(n, 48, 1e-10, maxiter=20, precision=prec) as sol:
+                Uo, So, Vo, r, inf = sol.solve(U, s, V)
+            assert a[4] == inf.status and a[3] == r
+            assert torch.equal(Uo, a[0]) and torch.equal(So, a[1]) and torch.equal(Vo, a[2]), (i, n, prec)
+
+
+def test_grouping_switch_only_when_idle():
+    import torch
+
+    from paper_2607_06021_amd.lrp import LrpError, Server
+
+    n = 1023
+    U, s, V, _ = workloads.bump_rhs(n, 7, 4, 0.05, 0.2)
+    U, s, V = _dev(U), _dev(s), _dev(V)
+    torch.cuda.synchronize()
+    with Server(budget_bytes=2 << 30, max_active=2) as srv:
+        srv.set_grouping(False)
+        srv.set_grouping(True)
+        t = srv.submit(n, U, s, V, 48, 1e-10, 20, "fp64")
+        try:
+            srv.set_grouping(False)  # refused while the request is queued or active,
+            switched = True
+        except LrpError:
+            switched = False
+        r = srv.wait(t)
+        assert r[4] >= 0
+        st = srv.stats()
+        # unless it already finished before the call
+        assert st["grouping"] == (0 if switched else 1)
+        srv.set_grouping(True)
+
+
 def test_contexts_created_under_load_all_succeed():
     """Many shapes submitted at once: contexts are created while other requests run on the
     device (a set-up step that is not ordered with the contexts' own streams would race with
