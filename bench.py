@@ -43,8 +43,11 @@ def parse():
     ap.add_argument("--large-steps", type=int, default=4,
                     help="timed solves per precision at n = 2^20 - 1 (0: skip that leg)")
     ap.add_argument("--served", type=int, default=2000, help="requests in the served stream (0: skip)")
-    ap.add_argument("--served-active", type=int, default=8)
-    ap.add_argument("--served-budget-gb", type=float, default=64.0)
+    ap.add_argument("--served-active", type=int, default=32)
+    ap.add_argument("--served-budget-gb", type=float, default=192.0)
+    ap.add_argument("--served-compare-active", type=int, default=8,
+                    help="also measure the saturated rate at this many active requests, grouping on and off "
+                         "(0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="copy one 256 MiB device tensor and exit (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -231,12 +234,53 @@ def rooflines(w, prec, prof, trace, info, rF):
     return res
 
 
-def served_leg(count, seed, budget_gb, max_active, rate=None):
+def saturated_rates(inputs, probe, budget_gb, max_active):
+    """Saturated solve rate of the first 400 requests of the stream (all submitted at once) with
+    same-stage grouping on, off, and on again, every shape warmed first in each setting; the
+    mean group size is request passes per pass launch."""
+    import numpy as np
+
+    from paper_2607_06021_amd.lrp import Server
+
+    nsat = min(len(probe), 400)
+    out = {}
+    with Server(budget_bytes=int(budget_gb * (1 << 30)), max_active=max_active) as srv:
+        def run(reqs):
+            t0 = time.perf_counter()
+            ts = [srv.submit(r.n, *inputs[r.idx], 48, 1e-10, 20, r.precision, sync=False) for r in reqs]
+            res = [srv.wait(t) for t in ts]
+            return time.perf_counter() - t0, res
+
+        shapes = {}
+        for r in probe:
+            shapes.setdefault((r.n, r.precision), []).append(r)
+        rates = {True: [], False: []}
+        for grouping in (True, False, True):
+            srv.set_grouping(grouping)
+            for rs in shapes.values():
+                run((rs * max_active)[:max_active])
+            st0 = srv.stats()
+            wall, res = run(probe[:nsat])
+            st = srv.stats()
+            rates[grouping].append(nsat / wall)
+            if grouping:
+                out["mean_group_size"] = round((st["passes"] - st0["passes"]) /
+                                               max(1, st["pass_launches"] - st0["pass_launches"]), 2)
+            out["run_p50_ms_grouping_" + ("on" if grouping else "off")] = round(
+                float(np.median([x[8] for x in res])), 3)
+    out["solves_per_s_grouping_on"] = round(float(np.mean(rates[True])), 1)
+    out["solves_per_s_grouping_off"] = round(float(np.mean(rates[False])), 1)
+    out["max_active"] = max_active
+    return out
+
+
+def served_leg(count, seed, budget_gb, max_active, rate=None, compare_active=0):
     """Served stream through one Server kept open throughout: first every shape of the stream
     is warmed (max_active requests of each at once, so the contexts the measurement needs
     exist), then the saturated rate is measured, then Poisson arrivals at 70% of it. Latency
     runs from each request's scheduled arrival time to its completion; it is reported overall,
-    by grid size, and split into the wait for admission and the run after it."""
+    by grid size, and split into the wait for admission and the run after it. Then the saturated
+    rate with same-stage grouping on and off, at max_active and at compare_active requests."""
     import numpy as np
     import torch
 
@@ -244,6 +288,7 @@ def served_leg(count, seed, budget_gb, max_active, rate=None):
     from paper_2607_06021_amd.lrp import Server
 
     dev = torch.device("cuda:0")
+    torch.cuda.empty_cache()  # the contexts are device allocations of their own
     probe = workloads.served_stream(count=count, rate_per_s=1.0, seed=seed)
     log(f"served: generating {count} right-hand sides on the device")
     inputs = [workloads.bump_rhs_device(r.n, r.seed, r.rank, 0.05, 0.2, dev) for r in probe]
@@ -284,17 +329,14 @@ def served_leg(count, seed, budget_gb, max_active, rate=None):
         st0 = srv.stats()
         wall, res, late = run(reqs, use_rate)
         st = srv.stats()
-        # the same saturated measurement with same-stage grouping off (passes on per-request streams)
-        srv.set_grouping(False)
-        for rs in shapes.values():
-            run((rs * max_active)[:max_active], None)
-        wall_u, _, _ = run(probe[:nsat], None)
-        sat_u = nsat / wall_u
-        srv.set_grouping(True)
-        log(f"served: saturated {sat_u:.1f} solves/s with grouping off")
     grouping = {"mean_group_size_poisson": round((st["passes"] - st0["passes"]) /
                                                  max(1, st["pass_launches"] - st0["pass_launches"]), 2),
-                "saturated_solves_per_s_grouping_off": round(sat_u, 2)}
+                "saturated": [saturated_rates(inputs, probe, budget_gb, max_active)]}
+    if compare_active:
+        grouping["saturated"].append(saturated_rates(inputs, probe, budget_gb, compare_active))
+    for g in grouping["saturated"]:
+        log(f"served: saturated at {g['max_active']} active: {g['solves_per_s_grouping_on']} solves/s grouped "
+            f"(mean group {g['mean_group_size']}), {g['solves_per_s_grouping_off']} ungrouped")
     lat = late + np.array([x[6] for x in res])           # from the scheduled arrival
     queue = late + np.array([x[7] for x in res])         # arrival to admission
     runms = np.array([x[8] for x in res])                # admission to completion
@@ -495,7 +537,8 @@ def main():
         large = large_leg(args)
     served = None
     if args.served > 0:
-        served = served_leg(args.served, 2026, args.served_budget_gb, args.served_active)
+        served = served_leg(args.served, 2026, args.served_budget_gb, args.served_active,
+                            compare_active=args.served_compare_active)
         log(f"  served: p50 {served['p50_ms']} ms, p99 {served['p99_ms']} ms, {served['solves_per_s']} solves/s")
     cpu = None
     err = {}

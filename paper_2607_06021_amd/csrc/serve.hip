@@ -11,13 +11,16 @@
 // at once for the next one.
 //
 // Same-stage grouping: requests whose passes make the same launches (one shape) form a group
-// with a stream of its own. At every scheduler tick the group's requests that may take their
-// next pass run it together, as one launch per stage: a captured graph per group size whose
-// kernels take a table of the requests' argument areas and run request z's arguments in
-// workgroup z (the grouped kernels of lrp_kernels.h). Start and finish stages stay on the
-// slots' streams, ordered against the group's stream by events. Groups of different shapes
-// run concurrently. A request's kernels, arguments, grids and reductions are exactly those of
-// a solo lrp_solve, so its result does not depend on what else is in flight or in its group.
+// with a stream of its own. Two or more of its requests that take their next pass together run
+// it as one launch per stage: a captured graph per group size whose kernels take a table of the
+// requests' argument areas and run request z's arguments in workgroup z (the grouped kernels of
+// lrp_kernels.h). The scheduler aligns a group's requests: while several are running, a pass is
+// launched when one of them has nothing in flight, and then for every one that may take a pass,
+// so requests that started apart end up in the same launches; a request alone in its group (and
+// every first pass) runs on its own stream, two passes deep. Start and finish stages stay on
+// the slots' streams; a pass that follows one on another stream waits for it by an event.
+// A request's kernels, arguments, grids and reductions are exactly those of a solo lrp_solve,
+// so its result does not depend on what else is in flight or in its group.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -72,9 +75,9 @@ struct Slot {
   // grouped passes
   int group = -1;            // index of the slot's group; -1: passes on the slot's stream
   char* area = nullptr;      // device: the pass's argument blocks, parity 0 then parity 1
-  hipEvent_t ev_start = nullptr;
-  bool started = false;      // the start stage has completed (seen by the host)
-  bool moved = false;        // a pass of the current request ran on the group's stream
+  bool moved = false;        // the request's last pass ran on the group's stream
+  uint64_t last_launch = 0;  // the group launch of that pass (0: its own stream)
+  hipEvent_t ev_start = nullptr;  // end of the start stage (a first pass may run grouped)
 };
 
 // Largest group: the largest number of active requests.
@@ -85,29 +88,38 @@ struct Group {
   std::vector<LaunchRec> recs;
   size_t area = 0;                    // bytes of one parity's argument blocks
   hipStream_t stream = nullptr;
-  const char** table = nullptr;       // device: kMaxGroup argument-area bases
+  const char** table = nullptr;       // device: kTable entries (see GroupTable)
   hipGraphExec_t exec[kMaxGroup] = {};  // by group size - 1, captured on first use
   bool broken = false;                // a graph could not be built: passes run per slot
 };
 
-struct GroupBases {
-  const char* b[kMaxGroup];
+// The table of one grouped launch, per request z of the group: the base of its argument blocks
+// (the GroupRef bases), its device stop flag and the pinned host slot the flag is copied to.
+struct GroupTable {
+  const char* base[kMaxGroup];
+  const int* src[kMaxGroup];
+  int* dst[kMaxGroup];
 };
-struct GroupPoll {
-  const int* src[kMaxGroup];  // device: each request's stop flag
-  int* dst[kMaxGroup];        // pinned host: where the scheduler reads it
-};
+constexpr int kTable = 3 * kMaxGroup;
 
 // The table of the group's next launch (written on the group's stream before its graph).
-__global__ void k_group_table(const char** table, GroupBases g, int count) {
+__global__ void k_group_table(const char** table, GroupTable g, int count) {
   const int t = threadIdx.x;
-  if (t < count) table[t] = g.b[t];
+  if (t < count) {
+    table[t] = g.base[t];
+    table[kMaxGroup + t] = reinterpret_cast<const char*>(g.src[t]);
+    table[2 * kMaxGroup + t] = reinterpret_cast<const char*>(g.dst[t]);
+  }
 }
 
-// After a grouped pass: each request's stop flag into its pinned host slot.
-__global__ void k_group_poll(GroupPoll p, int count) {
+// The last node of a grouped pass: each request's stop flag into its pinned host slot.
+__global__ void k_group_poll(const char* const* table, int count) {
   const int t = threadIdx.x;
-  if (t < count) *p.dst[t] = *p.src[t];
+  if (t < count) {
+    const int* src = reinterpret_cast<const int*>(table[kMaxGroup + t]);
+    int* dst = reinterpret_cast<int*>(const_cast<char*>(table[2 * kMaxGroup + t]));
+    *dst = *src;
+  }
   __threadfence_system();
 }
 
@@ -126,6 +138,7 @@ struct lrp_server {
   bool grouping = true;       // set under mu while nothing is queued or active
   bool grouping_tick = true;  // the scheduler's copy for the current tick
   int64_t passes = 0, pass_launches = 0;  // under mu
+  uint64_t launch_seq = 0;                // group launches made (scheduler thread)
   int64_t bytes_in_use = 0;
   int64_t next_ticket = 1;
   int64_t submitted = 0, completed = 0, failed = 0, active = 0;
@@ -157,7 +170,8 @@ void release_slot_job(Slot& sl, uint64_t tick) {
   sl.phase = 0;
   sl.k = sl.checked = 0;
   sl.stop = false;
-  sl.started = sl.moved = false;
+  sl.moved = false;
+  sl.last_launch = 0;
   sl.last_used = tick;
 }
 
@@ -175,6 +189,7 @@ void setup_group(lrp_server* s, Slot& sl) {
   const size_t half = (r0.blob.size() + 255) & ~(size_t)255;
   if (hipEventCreateWithFlags(&sl.ev_start, hipEventDisableTiming) != hipSuccess) {
     sl.ev_start = nullptr;
+    (void)hipGetLastError();
     return;
   }
   bool ok = hipMalloc(&sl.area, 2 * half) == hipSuccess;
@@ -191,7 +206,7 @@ void setup_group(lrp_server* s, Slot& sl) {
     G.recs = r0.recs;
     G.area = half;
     ok = hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking) == hipSuccess;
-    if (ok && hipMalloc((void**)&G.table, sizeof(char*) * kMaxGroup) != hipSuccess) {
+    if (ok && hipMalloc((void**)&G.table, sizeof(char*) * kTable) != hipSuccess) {
       (void)hipStreamDestroy(G.stream);
       ok = false;
     }
@@ -212,7 +227,7 @@ void setup_group(lrp_server* s, Slot& sl) {
 }
 
 // The graph of one grouped pass of m requests: the recorded launches with grid z = m, each
-// kernel reading its argument block through the group's table.
+// kernel reading its argument block through the group's table, then the stop-flag copies.
 int build_group_graph(Group& G, int m, hipGraphExec_t* out) {
   hipGraph_t gr = nullptr;
   if (hipStreamBeginCapture(G.stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
@@ -228,6 +243,10 @@ int build_group_graph(Group& G, int m, hipGraphExec_t* out) {
       break;
     }
   }
+  if (ok) {
+    hipLaunchKernelGGL(k_group_poll, dim3(1), dim3(kMaxGroup), 0, G.stream, G.table, m);
+    ok = hipGetLastError() == hipSuccess;
+  }
   ok = (hipStreamEndCapture(G.stream, &gr) == hipSuccess) && ok;
   if (ok) ok = hipGraphInstantiate(out, gr, nullptr, nullptr, 0) == hipSuccess;
   if (gr) (void)hipGraphDestroy(gr);
@@ -239,33 +258,57 @@ int build_group_graph(Group& G, int m, hipGraphExec_t* out) {
   return LRP_OK;
 }
 
-// One grouped pass of the m slots in mem (each at its own pass index): the table, the graph,
-// the stop flags to the host and each slot's pass event. LRP_EINVAL: no graph (nothing
+// One grouped pass of the m slots in mem (each at its own pass index): the table, the graph
+// (whose last node copies the stop flags to the host) and each slot's pass event. LRP_EINVAL: no graph (nothing
 // enqueued); LRP_EDEVICE: a launch failed.
 int launch_group(lrp_server* s, Group& G, Slot* const* mem, int m) {
   hipGraphExec_t& ex = G.exec[m - 1];
   if (!ex && build_group_graph(G, m, &ex) != LRP_OK) return LRP_EINVAL;
-  GroupBases gb{};
-  GroupPoll gp{};
+  for (int i = 0; i < m; ++i) {  // work enqueued on a slot's own stream comes first
+    const Slot& sl = *mem[i];
+    if (sl.moved) continue;
+    const hipEvent_t e = sl.k > 0 ? sl.ctx->evit[(sl.k - 1) & 1] : sl.ev_start;
+    if (hipStreamWaitEvent(G.stream, e, 0) != hipSuccess) return LRP_EDEVICE;
+  }
+  const uint64_t id = ++s->launch_seq;
+  GroupTable gt{};
   for (int i = 0; i < m; ++i) {
     const Slot& sl = *mem[i];
-    gb.b[i] = sl.area + (size_t)(sl.k & 1) * G.area;
-    gp.src[i] = &sl.ctx->st->done;
-    gp.dst[i] = &sl.ctx->done_host[sl.k & 1];
+    gt.base[i] = sl.area + (size_t)(sl.k & 1) * G.area;
+    gt.src[i] = &sl.ctx->st->done;
+    gt.dst[i] = &sl.ctx->done_host[sl.k & 1];
   }
-  hipLaunchKernelGGL(k_group_table, dim3(1), dim3(kMaxGroup), 0, G.stream, G.table, gb, m);
+  hipLaunchKernelGGL(k_group_table, dim3(1), dim3(kMaxGroup), 0, G.stream, G.table, gt, m);
   if (hipGetLastError() != hipSuccess) return LRP_EDEVICE;
   if (hipGraphLaunch(ex, G.stream) != hipSuccess) return LRP_EDEVICE;
-  hipLaunchKernelGGL(k_group_poll, dim3(1), dim3(kMaxGroup), 0, G.stream, gp, m);
-  if (hipGetLastError() != hipSuccess) return LRP_EDEVICE;
   for (int i = 0; i < m; ++i) {
     Slot& sl = *mem[i];
     if (hipEventRecord(sl.ctx->evit[sl.k & 1], G.stream) != hipSuccess) return LRP_EDEVICE;
     ++sl.k;
     sl.moved = true;
+    sl.last_launch = id;
   }
   std::lock_guard<std::mutex> g(s->mu);
   s->passes += m;
+  ++s->pass_launches;
+  return LRP_OK;
+}
+
+// The slot's next pass on its own stream (after its previous pass if that ran on the group's
+// stream), with the stop-flag copy and its event.
+int solo_pass(lrp_server* s, Slot& sl) {
+  lrp_ctx* c = sl.ctx;
+  if (sl.moved) {
+    if (hipStreamWaitEvent(sl.stream, c->evit[(sl.k - 1) & 1], 0) != hipSuccess) return LRP_EDEVICE;
+    sl.moved = false;
+  }
+  int rc = enqueue_pass(c, sl.k);
+  if (rc == LRP_OK) rc = enqueue_poll(c, sl.k);
+  if (rc != LRP_OK) return rc;
+  ++sl.k;
+  sl.last_launch = 0;
+  std::lock_guard<std::mutex> g(s->mu);
+  ++s->passes;
   ++s->pass_launches;
   return LRP_OK;
 }
@@ -277,7 +320,7 @@ bool advance(lrp_server* s, Slot& sl) {
   const lrp_request& q = j->req;
   if (sl.phase == 0) {
     int rc = enqueue_start(c, q.r_F, q.U_F, q.ldu, q.sigma_F, q.V_F, q.ldv);
-    if (rc == LRP_OK && grouped(s, sl) && hipEventRecord(sl.ev_start, sl.stream) != hipSuccess) rc = LRP_EDEVICE;
+    if (rc == LRP_OK && sl.ev_start && hipEventRecord(sl.ev_start, sl.stream) != hipSuccess) rc = LRP_EDEVICE;
     if (rc != LRP_OK) {
       (void)hipStreamSynchronize(sl.stream);
       finish_job(s, j, rc, 0, nullptr);
@@ -289,22 +332,6 @@ bool advance(lrp_server* s, Slot& sl) {
   }
   if (sl.phase == 1) {
     bool progress = false;
-    if (grouped(s, sl) && !sl.started) {
-      // a grouped request joins its group once its start stage has completed
-      const hipError_t e = hipEventQuery(sl.ev_start);
-      if (e == hipErrorNotReady) {
-        (void)hipGetLastError();
-        return false;
-      }
-      if (e != hipSuccess) {
-        (void)hipStreamSynchronize(sl.stream);
-        finish_job(s, j, LRP_EDEVICE, 0, nullptr);
-        release_slot_job(sl, ++s->tick);
-        return true;
-      }
-      sl.started = true;
-      progress = true;
-    }
     if (sl.checked < sl.k) {
       const hipError_t e = hipEventQuery(c->evit[sl.checked & 1]);
       if (e == hipSuccess) {
@@ -321,24 +348,14 @@ bool advance(lrp_server* s, Slot& sl) {
       }
     }
     if (!grouped(s, sl) && !sl.stop && sl.k < c->maxiter && sl.k - sl.checked < 2) {
-      int rc = LRP_OK;
-      if (sl.moved) {  // earlier passes ran on the group's stream
-        if (hipStreamWaitEvent(sl.stream, c->evit[(sl.k - 1) & 1], 0) != hipSuccess) rc = LRP_EDEVICE;
-        sl.moved = false;
-      }
-      if (rc == LRP_OK) rc = enqueue_pass(c, sl.k);
-      if (rc == LRP_OK) rc = enqueue_poll(c, sl.k);
+      const int rc = solo_pass(s, sl);
       if (rc != LRP_OK) {
         (void)hipStreamSynchronize(sl.stream);
         finish_job(s, j, rc, 0, nullptr);
         release_slot_job(sl, ++s->tick);
         return true;
       }
-      ++sl.k;
       progress = true;
-      std::lock_guard<std::mutex> g(s->mu);
-      ++s->passes;
-      ++s->pass_launches;
     }
     if (sl.stop || (sl.k == c->maxiter && sl.checked == sl.k)) {
       int rc = LRP_OK;
@@ -455,33 +472,68 @@ bool admit(lrp_server* s) {
   return progress;
 }
 
-// One grouped pass per group whose requests may take their next pass.
+void fail_slot(lrp_server* s, Slot& sl, int rc) {
+  (void)hipStreamSynchronize(sl.stream);
+  finish_job(s, sl.job, rc, 0, nullptr);
+  release_slot_job(sl, ++s->tick);
+}
+
+// Running requests of one group below which each takes its passes on its own stream, two deep,
+// as without grouping: aligning them would hold a pass back for the others (up to one pass of
+// latency) to save launches that a few concurrent streams overlap anyway.
+constexpr int kAlignMin = 3;
+
+// The passes of the grouped slots. Per group: the running requests (act) and those that may take
+// a pass now (cand: fewer than two unchecked). With fewer than kAlignMin running, each takes its
+// passes on its own stream. With more, passes are launched when one of them has nothing in
+// flight (every candidate joins: a new request after its start stage, the others after their
+// pass in flight), or when all of them sit in flight in one group launch (the next pass of all
+// of them, keeping them aligned two passes deep). A launch of one request runs on its own stream.
 bool launch_groups(lrp_server* s) {
   bool progress = false;
+  if (!s->grouping_tick) return false;
   for (size_t g = 0; g < s->groups.size(); ++g) {
     Group& G = s->groups[g];
-    if (G.broken || !s->grouping_tick) continue;
-    Slot* mem[kMaxGroup];
-    int m = 0;
-    for (Slot& sl : s->slots)
-      if (m < kMaxGroup && sl.job && sl.group == (int)g && sl.phase == 1 && sl.started && !sl.stop &&
-          sl.k < sl.ctx->maxiter && sl.k - sl.checked < 2)
-        mem[m++] = &sl;
-    if (m == 0) continue;
+    if (G.broken) continue;
+    Slot* cand[kMaxGroup];
+    int nact = 0, ncand = 0;
+    bool idle = false, aligned = true;
+    uint64_t lid = 0;
+    for (Slot& sl : s->slots) {
+      if (!sl.job || sl.group != (int)g || sl.phase != 1 || sl.stop || sl.k >= sl.ctx->maxiter) continue;
+      ++nact;
+      if (sl.k - sl.checked >= 2 || ncand == kMaxGroup) {
+        aligned = false;
+        continue;
+      }
+      cand[ncand++] = &sl;
+      if (sl.k == sl.checked) idle = true;
+      if (sl.last_launch == 0 || (lid && sl.last_launch != lid)) aligned = false;
+      lid = sl.last_launch;
+    }
+    if (ncand == 0) continue;
+    if (nact >= kAlignMin && !idle && !(aligned && ncand == nact)) continue;  // wait to align
+    progress = true;
+    if (nact < kAlignMin) {
+      for (int i = 0; i < ncand; ++i) {
+        const int rc = solo_pass(s, *cand[i]);
+        if (rc != LRP_OK) fail_slot(s, *cand[i], rc);
+      }
+      continue;
+    }
+    if (ncand == 1) {
+      const int rc = solo_pass(s, *cand[0]);
+      if (rc != LRP_OK) fail_slot(s, *cand[0], rc);
+      continue;
+    }
+    const int m = ncand;
+    Slot* const* mem = cand;
     const int rc = launch_group(s, G, mem, m);
     if (rc == LRP_EINVAL) {  // no graph: the members go on with passes on their own streams
       G.broken = true;
-      progress = true;
     } else if (rc != LRP_OK) {
       (void)hipStreamSynchronize(G.stream);
-      for (int i = 0; i < m; ++i) {
-        (void)hipStreamSynchronize(mem[i]->stream);
-        finish_job(s, mem[i]->job, LRP_EDEVICE, 0, nullptr);
-        release_slot_job(*mem[i], ++s->tick);
-      }
-      progress = true;
-    } else {
-      progress = true;
+      for (int i = 0; i < m; ++i) fail_slot(s, *mem[i], LRP_EDEVICE);
     }
   }
   return progress;

@@ -51,25 +51,25 @@ def test_served_results_equal_solo_results():
 
 
 def test_grouped_passes_equal_ungrouped_and_solo():
-    """Same-stage grouping: a burst of requests of a few shapes runs its passes as grouped
-    launches (more request passes than pass launches), and every result is bitwise the one
-    of the same server with grouping off and of a solo lrp_solve."""
+    """Same-stage grouping: a burst with several requests of one shape runs their passes as
+    grouped launches (more request passes than pass launches), and every result is bitwise the
+    one of the same server with grouping off and of a solo lrp_solve."""
     import torch
 
     from paper_2607_06021_amd import Solver
     from paper_2607_06021_amd.lrp import Server
 
     reqs = []
-    for i in range(16):
-        n = (1023, 4095, 16383)[i % 3]
+    # two crowded shapes (grouped once three or more of a shape run) and a few others
+    shapes = [(4095, "mixed")] * 6 + [(1023, "fp64")] * 5 + [(16383, "mixed"), (1023, "mixed"), (3000, "fp64")]
+    for i, (n, prec) in enumerate(shapes):
         U, s, V, _ = workloads.bump_rhs(n, 2000 + i, 2 + (i * 5) % 17, 0.05, 0.2)
-        prec = "mixed" if (i // 3) % 2 else "fp64"
         reqs.append((n, _dev(U), _dev(s), _dev(V), prec))
     torch.cuda.synchronize()
     results = {}
     for grouping in (True, False):
         print(f"serving {len(reqs)} requests, grouping {grouping}", flush=True)
-        with Server(budget_bytes=8 << 30, max_active=8, grouping=grouping) as srv:
+        with Server(budget_bytes=8 << 30, max_active=len(reqs), grouping=grouping) as srv:
             tickets = [srv.submit(n, U, s, V, 48, 1e-10, 20, prec) for (n, U, s, V, prec) in reqs]
             results[grouping] = [srv.wait(t) for t in tickets]
             stats = srv.stats()
@@ -85,7 +85,7 @@ def test_grouped_passes_equal_ungrouped_and_solo():
         a, b = results[True][i], results[False][i]
         assert a[3:5] == b[3:5] and a[5].iters == b[5].iters, (i, n, prec)
         assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[2], b[2]), (i, n, prec)
-        if i % 4 == 0:
+        if i % 3 == 0:
             with Solver(n, 48, 1e-10, maxiter=20, precision=prec) as sol:
                 Uo, So, Vo, r, inf = sol.solve(U, s, V)
             assert a[4] == inf.status and a[3] == r
