@@ -120,11 +120,12 @@ void free_ctx(lrp_ctx* c) {
   if (c->evfin) (void)hipEventDestroy(c->evfin);
   for (int s = 0; s < 2; ++s)
     if (c->evit[s]) (void)hipEventDestroy(c->evit[s]);
-  for (int s = 0; s < 2; ++s) {
+  for (int s = 0; s < 4; ++s) {
     if (c->gexec[s]) (void)hipGraphExecDestroy(c->gexec[s]);
     if (c->gexec_upd[s]) (void)hipGraphExecDestroy(c->gexec_upd[s]);
-    if (c->gexec_sel[s]) (void)hipGraphExecDestroy(c->gexec_sel[s]);
   }
+  for (int s = 0; s < 2; ++s)
+    if (c->gexec_sel[s]) (void)hipGraphExecDestroy(c->gexec_sel[s]);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -231,9 +232,13 @@ int enqueue_pass_kernels(lrp_ctx* c, int k);
 int record_pass(lrp_ctx* c, int k, PassRecord* out) {
   *out = PassRecord{};
   if (c->profile) return LRP_EINVAL;
+  // the general fiber build, valid for every rank (its results equal the narrow build's)
+  const bool narrow = c->fiber_narrow;
+  c->fiber_narrow = false;
   g_rec = out;
   const int rc = enqueue_pass_kernels(c, k);
   g_rec = nullptr;
+  c->fiber_narrow = narrow;
   return (rc == LRP_OK && !out->bad && !out->recs.empty()) ? LRP_OK : LRP_EINVAL;
 }
 
@@ -329,6 +334,7 @@ int enqueue_pass_update(lrp_ctx* c, int k) {
   fa.ldc = n;
   fa.n = n;
   fa.matrix = c->matrix;
+  fa.narrow = c->fiber_narrow ? 1 : 0;
   TRY(fiber_launch(fa, mixed, s));
   TsqrIO io{};
   io.st = c->st;
@@ -501,6 +507,7 @@ int enqueue_start(lrp_ctx* c, int rF, const double* U_F, int64_t ldu, const doub
   hipStream_t s = c->stream;
   const double eps = mixed ? std::max(c->tol, 1e-7) : c->tol;
   const double h = 1.0 / (double)(n + 1);
+  c->fiber_narrow = rF <= 32;  // this solve's passes use the fiber build for its rank
   if (hipEventRecord(c->ev0, s) != hipSuccess) return LRP_EDEVICE;
   TRY(init_state_launch(c->st, rF, eps, c->tau, c->replay_n, s));
   TRY(scan_inputs_launch(c->st, U_F, ldu, V_F, ldv, sigma_F, n, rF, s));
@@ -665,12 +672,17 @@ static int enqueue_captured(lrp_ctx* c, int k, hipGraphExec_t* slot, int (*fn)(l
   return fn(c, k);
 }
 
-int enqueue_pass(lrp_ctx* c, int k) { return enqueue_captured(c, k, &c->gexec[k & 1], enqueue_pass_kernels); }
+// The captured pass for the fiber build of the current solve and the parity of k.
+static int graph_slot(const lrp_ctx* c, int k) { return (c->fiber_narrow ? 2 : 0) | (k & 1); }
+
+int enqueue_pass(lrp_ctx* c, int k) {
+  return enqueue_captured(c, k, &c->gexec[graph_slot(c, k)], enqueue_pass_kernels);
+}
 
 // Pass k with the stop flag read between its two parts: the update part (captured per parity),
 // the flag copy and its event, then the candidate selection (captured per parity).
 int enqueue_pass_polled(lrp_ctx* c, int k) {
-  TRY(enqueue_captured(c, k, &c->gexec_upd[k & 1], enqueue_pass_update));
+  TRY(enqueue_captured(c, k, &c->gexec_upd[graph_slot(c, k)], enqueue_pass_update));
   TRY(enqueue_poll(c, k));
   return enqueue_captured(c, k, &c->gexec_sel[k & 1], enqueue_pass_select);
 }

@@ -55,8 +55,11 @@ struct lrp_ctx {
   uint64_t seed = 0;
   RhoPlan rho{};
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evfin = nullptr, evit[2] = {nullptr, nullptr};
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};  // captured pass, per parity (serving loop)
-  hipGraphExec_t gexec_upd[2] = {nullptr, nullptr}, gexec_sel[2] = {nullptr, nullptr};  // split pass (solve)
+  // captured passes, per fiber build (narrow: rank <= 32) and parity: index 2 narrow + parity
+  hipGraphExec_t gexec[4] = {};      // the whole pass (serving loop)
+  hipGraphExec_t gexec_upd[4] = {};  // the split pass (solve): update part
+  hipGraphExec_t gexec_sel[2] = {};  // selection part, per parity
+  bool fiber_narrow = false;         // the right-hand side of the current solve has rank <= 32
   bool use_graphs = true;
   bool solved = false;
   // optional per-kernel timing (LRP_FLAG_PROFILE): events recorded before every launch

@@ -196,6 +196,7 @@ struct FiberArgs {
   int64_t n;
   int matrix;       // enum lrp_matrix: LRP_MAT_POISSON uses Uh, Vh, lam; the test matrices are
                     // evaluated from their formulas
+  int narrow;       // 1: the right-hand side's rank is at most 32 (a build with half the registers)
 };
 int fiber_launch(const FiberArgs& a, bool fp32, hipStream_t s);
 

@@ -326,6 +326,48 @@ def test_one_context_serves_different_ranks_and_pass_counts(precision):
             assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("seed", [0, 2])
+def test_rank_above_32_fp64_parity(seed):
+    """Right-hand sides of rank 40 (the fiber build for ranks above 32), cap 64: identical sets
+    and <= 1e-10 against the oracle (cases whose oracle sets are stable under 1e-15 noise)."""
+    n = 4095
+    U, s, V, _ = workloads.bump_rhs(n, 300 + seed, 40, 0.01, 0.1)
+    print(f"solve n {n} rank 40 seed {seed}", flush=True)
+    o = cd.solve(n, U, s, V, 64, 1e-10, 20)
+    g = gpu_solve(n, U, s, V, 64, 1e-10, 20)
+    compare_fp64(g, o, f"rank-40 seed {seed}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_one_context_switches_fiber_builds(precision):
+    """Ranks above and below 32 alternate on one context (two fiber builds, each with its own
+    captured passes): every solve bitwise equal to the same solve on a fresh context."""
+    from paper_2607_06021_amd import Solver
+
+    n = 4095
+    cases = []
+    for seed, rk in ((300, 40), (301, 12), (302, 40), (303, 32)):
+        U, s, V, _ = workloads.bump_rhs(n, seed, rk, 0.01, 0.1)
+        cases.append((dev(U), dev(s), dev(V)))
+    print(f"fiber builds on one context, {precision}", flush=True)
+    fresh = []
+    for U, s, V in cases:
+        with Solver(n, 64, 1e-10, maxiter=20, precision=precision) as sol:
+            Uo, So, Vo, r, info = sol.solve(U, s, V)
+            fresh.append((Uo.clone(), So.clone(), Vo.clone(), r, info.iters))
+    with Solver(n, 64, 1e-10, maxiter=20, precision=precision) as sol:
+        for (U, s, V), (Uf, Sf, Vf, rf, itf) in zip(cases, fresh):
+            Uo, So, Vo, r, info = sol.solve(U, s, V)
+            assert r == rf and info.iters == itf
+            assert torch_equal(Uo, Uf) and torch_equal(So, Sf) and torch_equal(Vo, Vf)
+
+
+def torch_equal(a, b):
+    import torch
+
+    return bool(torch.equal(a, b))
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_profile_mode_same_result_and_kernel_times(precision):
     """A context with the profile flag launches the passes kernel by kernel (no graphs) with
