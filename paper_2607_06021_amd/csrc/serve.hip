@@ -14,11 +14,12 @@
 // with a stream of its own. Two or more of its requests that take their next pass together run
 // it as one launch per stage: a captured graph per group size whose kernels take a table of the
 // requests' argument areas and run request z's arguments in workgroup z (the grouped kernels of
-// lrp_kernels.h). The scheduler aligns a group's requests: while several are running, a pass is
-// launched when one of them has nothing in flight, and then for every one that may take a pass,
-// so requests that started apart end up in the same launches; a request alone in its group (and
-// every first pass) runs on its own stream, two passes deep. Start and finish stages stay on
-// the slots' streams; a pass that follows one on another stream waits for it by an event.
+// lrp_kernels.h). Once three or more of a group's requests run, the scheduler aligns them: a
+// pass is launched when one of them has nothing in flight, and then for every one that may take
+// a pass (a new request after its start stage), so requests that started apart end up in the
+// same launches. With fewer running, each request takes its passes on its own stream, two
+// passes deep, as without grouping. Start and finish stages stay on the slots' streams; work
+// that follows work on another stream waits for it by an event.
 // A request's kernels, arguments, grids and reductions are exactly those of a solo lrp_solve,
 // so its result does not depend on what else is in flight or in its group.
 #include <chrono>
