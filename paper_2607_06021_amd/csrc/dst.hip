@@ -314,10 +314,18 @@ __host__ __device__ constexpr int tile2_for(int log1, int esz, int cap) {
   while (t > 1 && (lds_pass2(log1, t, esz) > kLdsMax || t * ((1 << log1) / 16) > 512)) t >>= 1;
   return t;
 }
-template <typename T>
-__host__ __device__ constexpr int tile1_of(int log2) { return tile1_for(log2, (int)sizeof(cx<T>), 32); }
-template <typename T>
-__host__ __device__ constexpr int tile2_of(int log1) { return tile2_for(log1, (int)sizeof(cx<T>), 16); }
+// Column tiles of the four-step passes: the widest that fit (CAP = 0), or at most CAP columns --
+// narrow tiles for launches that would otherwise leave CUs idle (few column pairs). A column's
+// transform is the same whatever tile it sits in.
+constexpr int kNarrow1 = 8, kNarrow2 = 4;
+template <typename T, int CAP = 0>
+__host__ __device__ constexpr int tile1_of(int log2) {
+  return tile1_for(log2, (int)sizeof(cx<T>), CAP ? CAP : 32);
+}
+template <typename T, int CAP = 0>
+__host__ __device__ constexpr int tile2_of(int log1) {
+  return tile2_for(log1, (int)sizeof(cx<T>), CAP ? CAP : 16);
+}
 
 // ---------------------------------------------------------------- L <= 4096: one pass
 template <typename T, int LOGL>
@@ -360,10 +368,10 @@ __device__ __forceinline__ int xcd_order(int b, int nb) {
 // ---------------------------------------------------------------- four-step pass 1
 // Block: TJ columns j1 (lane-fastest, so global reads and writes are coalesced) x L2/16 threads;
 // TJ = 16 (FP64) or 32 (FP32) columns, so each row of the input is read in 128- or 256-byte pieces.
-template <typename T, int LOG2>
+template <typename T, int LOG2, int CAP = 0>
 __global__ __launch_bounds__(512) void k_dst_pass1(DstArgs a) {
   constexpr int L2 = 1 << LOG2, E = 16, TP = L2 / E;
-  constexpr int TJ = tile1_of<T>(LOG2), SEQ = seq_len(L2);
+  constexpr int TJ = tile1_of<T, CAP>(LOG2), SEQ = seq_len(L2);
   __shared__ cx<T> lds[TJ * SEQ];
   const double* X;
   int ncols;
@@ -405,10 +413,10 @@ __global__ __launch_bounds__(512) void k_dst_pass1(DstArgs a) {
 // ---------------------------------------------------------------- four-step pass 2
 // Block: TK columns k2 (k2 = 0..L2/2) x L1/16 threads (lane-fastest along the sequence, so rows
 // of the intermediate are read contiguously); outputs are staged in LDS and written TK at a time.
-template <typename T, int LOG1>
+template <typename T, int LOG1, int CAP = 0>
 __global__ __launch_bounds__(512) void k_dst_pass2(DstArgs a) {
   constexpr int L1 = 1 << LOG1, E = 16, TP = L1 / E;
-  constexpr int TK = tile2_of<T>(LOG1), SEQ = seq_len(L1);
+  constexpr int TK = tile2_of<T, CAP>(LOG1), SEQ = seq_len(L1);
   constexpr int OST = TK + 1;  // staging row stride
   constexpr int NLDS = TK * SEQ > L1 * OST ? TK * SEQ : L1 * OST;
   __shared__ cx<T> lds[NLDS];
@@ -879,22 +887,33 @@ static void launch_single(int logL, int npairs, const DstArgs& a, hipStream_t s)
 #undef LRP_SINGLE
 }
 
+// A pass launch of fewer workgroups than this runs the narrow-tile build.
+constexpr int kDstMinBlocks = 2 * 256;
+
 template <typename T>
 static void launch_four_step(int logL1, int logL2, int npairs, const DstArgs& a, hipStream_t s) {
   const int L1 = 1 << logL1, L2 = 1 << logL2;
-#define LRP_P1(LG)                                                                          \
-  case LG: {                                                                                \
-    constexpr int tj = tile1_of<T>(LG);                                                     \
-    LRP_LAUNCH(K_DST_PASS1, (k_dst_pass1<T, LG>), dim3((L1 / 2 / tj + 1) * npairs),              \
-                       dim3(tj * ((1 << LG) / 16)), 0, s, a);                               \
-    break;                                                                                  \
+#define LRP_P1(LG)                                                                                    \
+  case LG: {                                                                                          \
+    constexpr int tj = tile1_of<T>(LG), tn = tile1_of<T, kNarrow1>(LG);                               \
+    if ((L1 / 2 / tj + 1) * npairs < kDstMinBlocks && tn < tj)                                        \
+      LRP_LAUNCH(K_DST_PASS1, (k_dst_pass1<T, LG, kNarrow1>), dim3((L1 / 2 / tn + 1) * npairs),         \
+                 dim3(tn * ((1 << LG) / 16)), 0, s, a);                                               \
+    else                                                                                              \
+      LRP_LAUNCH(K_DST_PASS1, (k_dst_pass1<T, LG>), dim3((L1 / 2 / tj + 1) * npairs),                   \
+                 dim3(tj * ((1 << LG) / 16)), 0, s, a);                                               \
+    break;                                                                                            \
   }
-#define LRP_P2(LG)                                                                          \
-  case LG: {                                                                                \
-    constexpr int tk = tile2_of<T>(LG);                                                     \
-    LRP_LAUNCH(K_DST_PASS2, (k_dst_pass2<T, LG>), dim3((L2 / 2 / tk + 1) * npairs),              \
-                       dim3(tk * ((1 << LG) / 16)), 0, s, a);                               \
-    break;                                                                                  \
+#define LRP_P2(LG)                                                                                    \
+  case LG: {                                                                                          \
+    constexpr int tk = tile2_of<T>(LG), tn = tile2_of<T, kNarrow2>(LG);                               \
+    if ((L2 / 2 / tk + 1) * npairs < kDstMinBlocks && tn < tk)                                        \
+      LRP_LAUNCH(K_DST_PASS2, (k_dst_pass2<T, LG, kNarrow2>), dim3((L2 / 2 / tn + 1) * npairs),         \
+                 dim3(tn * ((1 << LG) / 16)), 0, s, a);                                               \
+    else                                                                                              \
+      LRP_LAUNCH(K_DST_PASS2, (k_dst_pass2<T, LG>), dim3((L2 / 2 / tk + 1) * npairs),                   \
+                 dim3(tk * ((1 << LG) / 16)), 0, s, a);                                               \
+    break;                                                                                            \
   }
   switch (logL2) {
     LRP_P1(6) LRP_P1(7) LRP_P1(8) LRP_P1(9) LRP_P1(10) LRP_P1(11) LRP_P1(12)
