@@ -13,6 +13,7 @@ constexpr int kTsqrRows = 256;     // rows of one block QR
 constexpr int kTsqrThreads = 1024;  // 16 waves, four columns each
 constexpr int kSelRows = 256;      // rows per leverage-score block
 constexpr int kMergeFan = 16;      // candidate lists merged per block
+constexpr int kCUs = 256;          // compute units of the MI355X
 constexpr int kMaxLevels = 12;     // TSQR tree levels (n <= 2^23 needs 7 at p_max = 64)
 constexpr double kEps = 2.220446049250313e-16;
 // leverage scores at or below (64 eps)^2 * max(pi) are rounding noise and count as 0

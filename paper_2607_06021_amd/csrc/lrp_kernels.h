@@ -232,6 +232,7 @@ struct ProdArgs {
   int64_t n;
   int nb;              // buffer index whose rank st->r[nb] gives the columns
   int gate_guess;      // 1: run only if st->guess_ok (the product of a warm start from a guess)
+  int tiles;           // set by prod_launch: 16-row tiles per wave (even)
 };
 int prod_launch(const ProdArgs& a, hipStream_t s);
 

@@ -13,7 +13,7 @@
 // enters the sums. The MFMAs run only over the live part of the padded 64 x 64 B: KS 4-row steps
 // (p rounded up to 16) by NT 16-column tiles (r rounded up to 16), compile-time counts chosen
 // once per launch by a uniform switch, so that every variant stays straight-line code (uniform
-// branches inside the unrolled loop break its schedule). Each wave streams 8 row tiles, loading
+// branches inside the unrolled loop break its schedule). Each wave streams its row tiles (8; fewer at small n), loading
 // the next tile's Q while the current one is on the matrix cores, and reads B's operands from
 // LDS at every tile (216 registers, two waves per SIMD; B held in registers for the whole loop
 // took 334 and left one wave per SIMD: 0.58 -> 0.53 ms per FP64 launch at n = 2^20 - 1).
@@ -23,8 +23,9 @@ namespace lrp {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int kProdTilesPerWave = 8;
-constexpr int kProdRowsPerBlock = 16 * kProdTilesPerWave * 4;  // 4 waves
+// 16-row tiles per wave: 8, or fewer (4, 2) where a launch of 8 would make fewer workgroups
+// than twice the CU count. A tile's products are the same whatever wave computes them.
+constexpr int kProdTilesMax = 8;
 
 template <int KS, int NT>
 __device__ __forceinline__ void prod_body(const ProdArgs& a, int side, int kin, int r, double* Bs) {
@@ -40,7 +41,8 @@ __device__ __forceinline__ void prod_body(const ProdArgs& a, int side, int kin, 
   __syncthreads();
   const double* Q = a.Q[side];
   double* out = a.out[side];
-  const int64_t base = (int64_t)blockIdx.x * kProdRowsPerBlock + (int64_t)wave * 16 * kProdTilesPerWave;
+  const int tiles = a.tiles;
+  const int64_t base = (int64_t)blockIdx.x * 64 * tiles + (int64_t)wave * 16 * tiles;
   auto load_tile = [&](int tile, double (&q)[KS]) {
     const int64_t i = base + 16 * tile + lr;
     const bool row_ok = i < a.n;
@@ -53,14 +55,14 @@ __device__ __forceinline__ void prod_body(const ProdArgs& a, int side, int kin, 
   double qa[KS], qb[KS];
   load_tile(0, qa);
 #pragma unroll 1
-  for (int tile = 0; tile < kProdTilesPerWave; tile += 2) {
+  for (int tile = 0; tile < tiles; tile += 2) {
     // even tile from qa while qb is loading, then odd tile from qb while qa is loading
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       double(&qc)[KS] = h == 0 ? qa : qb;
       double(&qn)[KS] = h == 0 ? qb : qa;
       const int tcur = tile + h;
-      if (tcur + 1 < kProdTilesPerWave) load_tile(tcur + 1, qn);
+      if (tcur + 1 < tiles) load_tile(tcur + 1, qn);
       d4 acc[NT];
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) acc[nt] = d4{0.0, 0.0, 0.0, 0.0};
@@ -117,8 +119,12 @@ __global__ __launch_bounds__(256) void k_prod(Src in) {
   }
 }
 
-int prod_launch(const ProdArgs& a, hipStream_t s) {
-  dim3 grid((unsigned)((a.n + kProdRowsPerBlock - 1) / kProdRowsPerBlock), 2);
+int prod_launch(const ProdArgs& args, hipStream_t s) {
+  ProdArgs a = args;
+  a.tiles = kProdTilesMax;
+  while (a.tiles > 2 && 2 * (a.n + 64 * a.tiles - 1) / (64 * a.tiles) < 2 * kCUs) a.tiles >>= 1;
+  const int64_t rows = 64 * a.tiles;  // 4 waves
+  dim3 grid((unsigned)((a.n + rows - 1) / rows), 2);
   LRP_LAUNCH_G(K_PROD, k_prod<ProdArgs>, k_prod<GroupRef>, grid, dim3(256), 0, s, a);
   return launch_status();
 }

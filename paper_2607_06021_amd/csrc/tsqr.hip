@@ -14,7 +14,6 @@
 
 namespace lrp {
 
-constexpr int kCUs = 256;  // compute units of the MI355X
 
 struct FactorArgs {
   const DevState* st;
