@@ -181,6 +181,14 @@ bool grouped(const lrp_server* s, const Slot& sl) {
   return s->grouping_tick && sl.group >= 0 && !s->groups[sl.group].broken;
 }
 
+// A request that failed: its work on every stream it used has ended before its slot is reused.
+void fail_slot(lrp_server* s, Slot& sl, int rc) {
+  (void)hipStreamSynchronize(sl.stream);
+  if (sl.group >= 0) (void)hipStreamSynchronize(s->groups[sl.group].stream);
+  finish_job(s, sl.job, rc, 0, nullptr);
+  release_slot_job(sl, ++s->tick);
+}
+
 // Records the slot's pass launches (both parities), uploads its argument blocks and joins the
 // group of its launch sequence (created if new). On any failure the slot stays ungrouped.
 void setup_group(lrp_server* s, Slot& sl) {
@@ -323,9 +331,7 @@ bool advance(lrp_server* s, Slot& sl) {
     int rc = enqueue_start(c, q.r_F, q.U_F, q.ldu, q.sigma_F, q.V_F, q.ldv);
     if (rc == LRP_OK && sl.ev_start && hipEventRecord(sl.ev_start, sl.stream) != hipSuccess) rc = LRP_EDEVICE;
     if (rc != LRP_OK) {
-      (void)hipStreamSynchronize(sl.stream);
-      finish_job(s, j, rc, 0, nullptr);
-      release_slot_job(sl, ++s->tick);
+      fail_slot(s, sl, rc);
       return true;
     }
     sl.phase = 1;
@@ -340,9 +346,7 @@ bool advance(lrp_server* s, Slot& sl) {
         ++sl.checked;
         progress = true;
       } else if (e != hipErrorNotReady) {
-        (void)hipStreamSynchronize(sl.stream);
-        finish_job(s, j, LRP_EDEVICE, 0, nullptr);
-        release_slot_job(sl, ++s->tick);
+        fail_slot(s, sl, LRP_EDEVICE);
         return true;
       } else {
         (void)hipGetLastError();  // not ready is not an error; leave no error state behind
@@ -351,9 +355,7 @@ bool advance(lrp_server* s, Slot& sl) {
     if (!grouped(s, sl) && !sl.stop && sl.k < c->maxiter && sl.k - sl.checked < 2) {
       const int rc = solo_pass(s, sl);
       if (rc != LRP_OK) {
-        (void)hipStreamSynchronize(sl.stream);
-        finish_job(s, j, rc, 0, nullptr);
-        release_slot_job(sl, ++s->tick);
+        fail_slot(s, sl, rc);
         return true;
       }
       progress = true;
@@ -364,9 +366,7 @@ bool advance(lrp_server* s, Slot& sl) {
       if (sl.moved && hipStreamWaitEvent(sl.stream, c->evit[(sl.k - 1) & 1], 0) != hipSuccess) rc = LRP_EDEVICE;
       if (rc == LRP_OK) rc = enqueue_finish(c, q.U_out, q.ldou, q.S_out, q.V_out, q.ldov);
       if (rc != LRP_OK) {
-        (void)hipStreamSynchronize(sl.stream);
-        finish_job(s, j, rc, 0, nullptr);
-        release_slot_job(sl, ++s->tick);
+        fail_slot(s, sl, rc);
         return true;
       }
       sl.phase = 2;
@@ -471,12 +471,6 @@ bool admit(lrp_server* s) {
     progress = true;
   }
   return progress;
-}
-
-void fail_slot(lrp_server* s, Slot& sl, int rc) {
-  (void)hipStreamSynchronize(sl.stream);
-  finish_job(s, sl.job, rc, 0, nullptr);
-  release_slot_job(sl, ++s->tick);
 }
 
 // Running requests of one group below which each takes its passes on its own stream, two deep,
