@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "ctx.h"
+#include "serve_policy.h"
 
 using namespace lrp;
 
@@ -166,16 +167,6 @@ void finish_job(lrp_server* s, Job* j, int status, int rank, const lrp_info* inf
   s->cv_done.notify_all();
 }
 
-void release_slot_job(Slot& sl, uint64_t tick) {
-  sl.job = nullptr;
-  sl.phase = 0;
-  sl.k = sl.checked = 0;
-  sl.stop = false;
-  sl.moved = false;
-  sl.last_launch = 0;
-  sl.last_used = tick;
-}
-
 // Passes of this slot run grouped (on its group's stream).
 bool grouped(const lrp_server* s, const Slot& sl) {
   return s->grouping_tick && sl.group >= 0 && !s->groups[sl.group].broken;
@@ -186,7 +177,7 @@ void fail_slot(lrp_server* s, Slot& sl, int rc) {
   (void)hipStreamSynchronize(sl.stream);
   if (sl.group >= 0) (void)hipStreamSynchronize(s->groups[sl.group].stream);
   finish_job(s, sl.job, rc, 0, nullptr);
-  release_slot_job(sl, ++s->tick);
+  sched::release(sl, ++s->tick);
 }
 
 // Records the slot's pass launches (both parities), uploads its argument blocks and joins the
@@ -384,7 +375,7 @@ bool advance(lrp_server* s, Slot& sl) {
   lrp_info info{};
   const int status = (e == hipSuccess) ? collect(c, &rank, &info) : LRP_EDEVICE;
   finish_job(s, j, status, rank, &info);
-  release_slot_job(sl, ++s->tick);
+  sched::release(sl, ++s->tick);
   return true;
 }
 
@@ -400,90 +391,78 @@ void destroy_slot(lrp_server* s, Slot& sl) {
   sl = Slot{};
 }
 
-// Admit queued requests in order while slots and memory allow. Called with mu held.
-bool admit(lrp_server* s) {
-  bool progress = false;
-  while (!s->queue.empty() && s->active < s->max_active) {
-    Job* j = s->queue.front();
-    Slot* use = nullptr;
-    for (Slot& sl : s->slots)
-      if (sl.ctx && !sl.job && sl.key == j->key) {
-        use = &sl;
-        break;
-      }
-    if (!use && s->bytes_in_use + j->bytes > s->budget) {
-      // free the least recently used idle slot of another shape, then try again
-      Slot* victim = nullptr;
-      for (Slot& sl : s->slots)
-        if (sl.ctx && !sl.job && (!victim || sl.last_used < victim->last_used)) victim = &sl;
-      if (!victim) break;  // wait for a running request to finish
-      destroy_slot(s, *victim);
-      continue;
+// The server side of admission (sched::admit): slots, budget and context creation. Used with
+// mu held.
+struct AdmitHost {
+  lrp_server* s;
+  std::deque<Job*>& queue() { return s->queue; }
+  const std::vector<Slot>& slots() const { return s->slots; }
+  const Key& key(const Job* j) const { return j->key; }
+  int64_t bytes(const Job* j) const { return j->bytes; }
+  int64_t in_use() const { return s->bytes_in_use; }
+  int64_t budget() const { return s->budget; }
+  int64_t active() const { return s->active; }
+  int64_t max_active() const { return s->max_active; }
+  void evict(int i) { destroy_slot(s, s->slots[i]); }
+
+  // A context of j's shape on a new stream, in the first empty entry (or a new one).
+  int create(Job* j) {
+    Slot sl;
+    sl.key = j->key;
+    sl.bytes = j->bytes;
+    int rc = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess ? LRP_OK : LRP_EDEVICE;
+    if (rc == LRP_OK) {
+      lrp_opts o{};
+      o.maxiter = j->key.maxiter;
+      o.precision = j->key.precision;
+      o.stream = sl.stream;
+      rc = lrp_create(&sl.ctx, j->key.n, j->key.r_max, j->key.tol, &o);
     }
-    if (!use) {
-      Slot sl;
-      sl.key = j->key;
-      sl.bytes = j->bytes;
-      int rc = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess ? LRP_OK : LRP_EDEVICE;
-      if (rc == LRP_OK) {
-        lrp_opts o{};
-        o.maxiter = j->key.maxiter;
-        o.precision = j->key.precision;
-        o.stream = sl.stream;
-        rc = lrp_create(&sl.ctx, j->key.n, j->key.r_max, j->key.tol, &o);
-      }
-      if (rc != LRP_OK) {
-        if (sl.stream) (void)hipStreamDestroy(sl.stream);
-        s->queue.pop_front();
-        j->status = rc;
-        j->info.status = rc;
-        j->t_done = Clock::now();
-        j->done = true;
-        ++s->failed;
-        s->cv_done.notify_all();
-        progress = true;
-        continue;
-      }
-      s->bytes_in_use += sl.bytes;
-      if (s->grouping) setup_group(s, sl);
-      // reuse an empty entry if there is one
-      bool placed = false;
-      for (Slot& e : s->slots)
-        if (!e.ctx) {
-          e = sl;
-          use = &e;
-          placed = true;
-          break;
-        }
-      if (!placed) {
-        s->slots.push_back(sl);
-        use = &s->slots.back();
-      }
+    if (rc != LRP_OK) {
+      if (sl.stream) (void)hipStreamDestroy(sl.stream);
+      return rc;
     }
-    s->queue.pop_front();
+    s->bytes_in_use += sl.bytes;
+    if (s->grouping) setup_group(s, sl);
+    for (size_t i = 0; i < s->slots.size(); ++i)
+      if (!s->slots[i].ctx) {
+        s->slots[i] = sl;
+        return (int)i;
+      }
+    s->slots.push_back(sl);
+    return (int)s->slots.size() - 1;
+  }
+
+  void fail(Job* j, int rc) {
+    j->status = rc;
+    j->info.status = rc;
+    j->t_done = Clock::now();
+    j->done = true;
+    ++s->failed;
+    s->cv_done.notify_all();
+  }
+
+  void start(Job* j, int i) {
+    Slot& sl = s->slots[i];
     j->t_admit = Clock::now();
     j->admitted = true;
-    use->job = j;
-    use->phase = 0;
-    use->k = use->checked = 0;
-    use->stop = false;
+    sl.job = j;
+    sl.phase = 0;
+    sl.k = sl.checked = 0;
+    sl.stop = false;
     ++s->active;
-    progress = true;
   }
-  return progress;
-}
+};
 
 // Running requests of one group below which each takes its passes on its own stream, two deep,
 // as without grouping: aligning them would hold a pass back for the others (up to one pass of
 // latency) to save launches that a few concurrent streams overlap anyway.
 constexpr int kAlignMin = 3;
 
-// The passes of the grouped slots. Per group: the running requests (act) and those that may take
-// a pass now (cand: fewer than two unchecked). With fewer than kAlignMin running, each takes its
-// passes on its own stream. With more, passes are launched when one of them has nothing in
-// flight (every candidate joins: a new request after its start stage, the others after their
-// pass in flight), or when all of them sit in flight in one group launch (the next pass of all
-// of them, keeping them aligned two passes deep). A launch of one request runs on its own stream.
+// The passes of the grouped slots, per group as sched::plan_group decides: each on its own
+// stream while fewer than kAlignMin of the group's requests run, else one launch for every
+// request that may take a pass once one of them has nothing in flight (or all of them sit in
+// flight in one launch), keeping them aligned two passes deep.
 bool launch_groups(lrp_server* s) {
   bool progress = false;
   if (!s->grouping_tick) return false;
@@ -491,34 +470,18 @@ bool launch_groups(lrp_server* s) {
     Group& G = s->groups[g];
     if (G.broken) continue;
     Slot* cand[kMaxGroup];
-    int nact = 0, ncand = 0;
-    bool idle = false, aligned = true;
-    uint64_t lid = 0;
-    for (Slot& sl : s->slots) {
-      if (!sl.job || sl.group != (int)g || sl.phase != 1 || sl.stop || sl.k >= sl.ctx->maxiter) continue;
-      ++nact;
-      if (sl.k - sl.checked >= 2 || ncand == kMaxGroup) {
-        aligned = false;
-        continue;
-      }
-      cand[ncand++] = &sl;
-      if (sl.k == sl.checked) idle = true;
-      if (sl.last_launch == 0 || (lid && sl.last_launch != lid)) aligned = false;
-      lid = sl.last_launch;
-    }
-    if (ncand == 0) continue;
-    if (nact >= kAlignMin && !idle && !(aligned && ncand == nact)) continue;  // wait to align
+    int ncand = 0;
+    const auto member = [g](const Slot& sl) {
+      return sl.job && sl.group == (int)g && sl.phase == 1 && !sl.stop && sl.k < sl.ctx->maxiter;
+    };
+    const sched::Plan plan = sched::plan_group(s->slots, member, cand, kMaxGroup, kAlignMin, ncand);
+    if (plan == sched::Plan::None) continue;
     progress = true;
-    if (nact < kAlignMin) {
+    if (plan == sched::Plan::Solo) {
       for (int i = 0; i < ncand; ++i) {
         const int rc = solo_pass(s, *cand[i]);
         if (rc != LRP_OK) fail_slot(s, *cand[i], rc);
       }
-      continue;
-    }
-    if (ncand == 1) {
-      const int rc = solo_pass(s, *cand[0]);
-      if (rc != LRP_OK) fail_slot(s, *cand[0], rc);
       continue;
     }
     const int m = ncand;
@@ -554,7 +517,8 @@ void scheduler(lrp_server* s) {
         s->cv_done.notify_all();
         if (s->active == 0) break;
       }
-      progress = admit(s);
+      AdmitHost h{s};
+      progress = sched::admit(h);
       s->grouping_tick = s->grouping;
     }
     for (Slot& sl : s->slots)
