@@ -298,20 +298,21 @@ __host__ __device__ constexpr int single_seqs(int logL) {
   return (1 << logL) / 16 >= 64 ? 1 : 64 / ((1 << logL) >= 16 ? (1 << logL) / 16 : 1);
 }
 // Largest power-of-two tile (columns per workgroup) with at most `cap` columns, at most 512
-// threads (16 elements each) and at most kLdsMax bytes of LDS.
-constexpr int kLdsMax = 80 * 1024;  // two workgroups per CU
+// threads (16 elements each) and at most lds_max bytes of LDS: the whole 160 KB of a CU for the
+// wide tiles (longer row pieces), half of it for the narrow ones (two workgroups per CU).
+constexpr int kLdsWide = 160 * 1024, kLdsNarrow = 80 * 1024;
 __host__ __device__ constexpr int lds_pass1(int log2, int tj, int esz) { return tj * seq_len(1 << log2) * esz; }
 __host__ __device__ constexpr int lds_pass2(int log1, int tk, int esz) {
   return (tk * seq_len(1 << log1) > (1 << log1) * (tk + 1) ? tk * seq_len(1 << log1) : (1 << log1) * (tk + 1)) * esz;
 }
-__host__ __device__ constexpr int tile1_for(int log2, int esz, int cap) {
+__host__ __device__ constexpr int tile1_for(int log2, int esz, int cap, int lds_max) {
   int t = cap;
-  while (t > 1 && (lds_pass1(log2, t, esz) > kLdsMax || t * ((1 << log2) / 16) > 512)) t >>= 1;
+  while (t > 1 && (lds_pass1(log2, t, esz) > lds_max || t * ((1 << log2) / 16) > 512)) t >>= 1;
   return t;
 }
-__host__ __device__ constexpr int tile2_for(int log1, int esz, int cap) {
+__host__ __device__ constexpr int tile2_for(int log1, int esz, int cap, int lds_max) {
   int t = cap;
-  while (t > 1 && (lds_pass2(log1, t, esz) > kLdsMax || t * ((1 << log1) / 16) > 512)) t >>= 1;
+  while (t > 1 && (lds_pass2(log1, t, esz) > lds_max || t * ((1 << log1) / 16) > 512)) t >>= 1;
   return t;
 }
 // Column tiles of the four-step passes: the widest that fit (CAP = 0), or at most CAP columns --
@@ -320,11 +321,11 @@ __host__ __device__ constexpr int tile2_for(int log1, int esz, int cap) {
 constexpr int kNarrow1 = 8, kNarrow2 = 4;
 template <typename T, int CAP = 0>
 __host__ __device__ constexpr int tile1_of(int log2) {
-  return tile1_for(log2, (int)sizeof(cx<T>), CAP ? CAP : 32);
+  return tile1_for(log2, (int)sizeof(cx<T>), CAP ? CAP : 32, CAP ? kLdsNarrow : kLdsWide);
 }
 template <typename T, int CAP = 0>
 __host__ __device__ constexpr int tile2_of(int log1) {
-  return tile2_for(log1, (int)sizeof(cx<T>), CAP ? CAP : 16);
+  return tile2_for(log1, (int)sizeof(cx<T>), CAP ? CAP : 16, CAP ? kLdsNarrow : kLdsWide);
 }
 
 // ---------------------------------------------------------------- L <= 4096: one pass
