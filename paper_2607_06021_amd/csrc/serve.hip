@@ -137,6 +137,7 @@ struct lrp_server {
   std::map<int64_t, Job*> jobs;
   std::vector<Slot> slots;  // touched only by the scheduler thread (sizes read under mu)
   std::vector<Group> groups;  // scheduler thread only
+  std::vector<std::vector<Slot*>> members;  // per group, rebuilt each tick (scheduler thread)
   bool grouping = true;       // set under mu while nothing is queued or active
   bool grouping_tick = true;  // the scheduler's copy for the current tick
   int64_t passes = 0, pass_launches = 0;  // under mu
@@ -466,15 +467,20 @@ constexpr int kAlignMin = 3;
 bool launch_groups(lrp_server* s) {
   bool progress = false;
   if (!s->grouping_tick) return false;
+  // the running requests of each group, in slot order (one scan of the slots per tick)
+  std::vector<std::vector<Slot*>>& by = s->members;
+  by.resize(s->groups.size());
+  for (std::vector<Slot*>& v : by) v.clear();
+  for (Slot& sl : s->slots)
+    if (sl.job && sl.group >= 0 && sl.phase == 1 && !sl.stop && sl.k < sl.ctx->maxiter)
+      by[sl.group].push_back(&sl);
   for (size_t g = 0; g < s->groups.size(); ++g) {
     Group& G = s->groups[g];
-    if (G.broken) continue;
+    if (G.broken || by[g].empty()) continue;
     Slot* cand[kMaxGroup];
     int ncand = 0;
-    const auto member = [g](const Slot& sl) {
-      return sl.job && sl.group == (int)g && sl.phase == 1 && !sl.stop && sl.k < sl.ctx->maxiter;
-    };
-    const sched::Plan plan = sched::plan_group(s->slots, member, cand, kMaxGroup, kAlignMin, ncand);
+    const sched::Plan plan =
+        sched::plan_group(by[g].data(), (int)by[g].size(), cand, kMaxGroup, kAlignMin, ncand);
     if (plan == sched::Plan::None) continue;
     progress = true;
     if (plan == sched::Plan::Solo) {

@@ -99,22 +99,20 @@ void release(SlotT& sl, uint64_t tick) {
 
 enum class Plan { None, Solo, Launch };
 
-// The next passes of one group. Members are the group's running requests (member(slot) true);
-// a candidate is a member that may take a pass now (fewer than two passes unchecked). With
+// The next passes of one group, given its running requests (members, in slot order); a
+// candidate is a member that may take a pass now (fewer than two passes unchecked). With
 // fewer than align_min members, each candidate takes its pass on its own stream (Solo). With
 // more, passes start when some candidate has nothing in flight -- then every candidate joins
 // one launch -- or when all members sit in flight in the same launch (the next pass of all of
 // them, two deep); otherwise the group waits (None) so that the members line up. A launch of a
 // single candidate is Solo as well. The candidates are written to cand[0 .. ncand).
-template <class SlotT, class Member>
-Plan plan_group(std::vector<SlotT>& slots, Member member, SlotT** cand, int max_cand, int align_min, int& ncand) {
-  int nact = 0;
+template <class SlotT>
+Plan plan_group(SlotT* const* members, int nmem, SlotT** cand, int max_cand, int align_min, int& ncand) {
   ncand = 0;
   bool idle = false, aligned = true;
   uint64_t lid = 0;
-  for (SlotT& sl : slots) {
-    if (!member(sl)) continue;
-    ++nact;
+  for (int i = 0; i < nmem; ++i) {
+    SlotT& sl = *members[i];
     if (sl.k - sl.checked >= 2 || ncand == max_cand) {
       aligned = false;
       continue;
@@ -125,8 +123,8 @@ Plan plan_group(std::vector<SlotT>& slots, Member member, SlotT** cand, int max_
     lid = sl.last_launch;
   }
   if (ncand == 0) return Plan::None;
-  if (nact >= align_min && !idle && !(aligned && ncand == nact)) return Plan::None;
-  return nact < align_min || ncand == 1 ? Plan::Solo : Plan::Launch;
+  if (nmem >= align_min && !idle && !(aligned && ncand == nmem)) return Plan::None;
+  return nmem < align_min || ncand == 1 ? Plan::Solo : Plan::Launch;
 }
 
 }  // namespace sched

@@ -383,10 +383,14 @@ struct GroupSlot : Slot {
   bool member = true;
 };
 
+// The plan for the members among v (the server passes a group's running requests in slot order).
 Plan plan(std::vector<GroupSlot>& v, std::vector<int>& cand_idx) {
+  std::vector<GroupSlot*> mem;
+  for (GroupSlot& s : v)
+    if (s.member) mem.push_back(&s);
   GroupSlot* cand[64];
   int ncand = -1;
-  const Plan p = plan_group(v, [](const GroupSlot& s) { return s.member; }, cand, 64, 3, ncand);
+  const Plan p = plan_group(mem.data(), (int)mem.size(), cand, 64, 3, ncand);
   CHECK(ncand >= 0 && ncand <= (int)v.size());
   cand_idx.clear();
   for (int i = 0; i < ncand; ++i) cand_idx.push_back((int)(cand[i] - v.data()));
