@@ -314,22 +314,66 @@ __global__ __launch_bounds__(256) void k_rho_final(Src in) {
     __syncthreads();
     // N_v S' (Bm) is formed where it is used, with the same rounding as a stored product
     auto Bm = [&](int aa, int m) { return (aa < r && m < ro) ? Nvs[aa][m] * So[m] : 0.0; };
+    // T1 to T3 over 4 x 4 blocks of entries, thread t taking rows a0 .. a0+3 and columns
+    // c0 .. c0+3 (the 256 threads tile 64 x 64), so that every operand read from LDS serves four
+    // entries; each entry sums over m in increasing order.
     double part = 0.0;
-    for (int e = threadIdx.x; e < r * r; e += blockDim.x) {  // T1
-      const int aa = e / r, b = e % r;
-      double s = (aa == b) ? S[aa] : 0.0;
-      for (int m = 0; m < ro; ++m) s = fma(-Am[aa][m], Nvs[b][m], s);
-      part = fma(s, s, part);
-    }
-    for (int e = threadIdx.x; e < r * ro; e += blockDim.x) {  // T2 and T3
-      const int aa = e / ro, m2 = e % ro;
-      double p2 = 0.0, p3 = 0.0;
+    const int a0 = 4 * (threadIdx.x >> 4), c0 = 4 * (threadIdx.x & 15);
+    if (a0 < r && c0 < r) {  // T1: ||S_k - M_u S' N_v^T||^2
+      double sq[4][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sq[i][j] = (a0 + i == c0 + j && a0 + i < r) ? S[a0 + i] : 0.0;
       for (int m = 0; m < ro; ++m) {
-        p2 = fma(Am[aa][m], Gvs[m][m2], p2);
-        p3 = fma(Bm(aa, m), Gus[m][m2], p3);
+        double am[4], nv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          am[i] = Am[a0 + i][m];
+          nv[i] = Nvs[c0 + i][m];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) sq[i][j] = fma(-am[i], nv[j], sq[i][j]);
       }
-      part = fma(p2, Am[aa][m2], part);
-      part = fma(p3, Bm(aa, m2), part);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (a0 + i < r && c0 + j < r) part = fma(sq[i][j], sq[i][j], part);
+    }
+    if (a0 < r && c0 < ro) {  // T2 and T3
+      double p2[4][4], p3[4][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) p2[i][j] = p3[i][j] = 0.0;
+      for (int m = 0; m < ro; ++m) {
+        double am[4], bm[4], gv[4], gu[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          am[i] = Am[a0 + i][m];
+          bm[i] = Bm(a0 + i, m);
+          gv[i] = Gvs[m][c0 + i];
+          gu[i] = Gus[m][c0 + i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            p2[i][j] = fma(am[i], gv[j], p2[i][j]);
+            p3[i][j] = fma(bm[i], gu[j], p3[i][j]);
+          }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (a0 + i < r && c0 + j < ro) {
+            part = fma(p2[i][j], Am[a0 + i][c0 + j], part);
+            part = fma(p3[i][j], Bm(a0 + i, c0 + j), part);
+          }
     }
     for (int e = threadIdx.x; e < ro * ro; e += blockDim.x) {  // T4
       const int m = e / ro, m2 = e % ro;
