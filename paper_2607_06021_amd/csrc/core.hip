@@ -984,10 +984,15 @@ __global__ __launch_bounds__(kCoreThreads) void k_core_warm(CoreArgs a) {
   // the width of the start: the right-hand side's rank, or the guess's columns
   const int rF = a.guess ? st->ncols[0] : st->rF;
   const int pm = a.pmax;
+  // M = R_u R_v^T from the two triangular factors, staged in LDS first (B0 and B1 are free
+  // until the SVD), so that no thread waits on a chain of memory loads
+  load_block(a.R0, pm, rF, rF, B0);
+  load_block(a.R1, pm, rF, rF, B1);
+  __syncthreads();
   for (int e = t; e < rF * rF; e += blockDim.x) {
     const int i = e % rF, j = e / rF;
     double s = 0.0;
-    for (int m = max(i, j); m < rF; ++m) s = fma(a.R0[i + (int64_t)m * pm], a.R1[j + (int64_t)m * pm], s);
+    for (int m = max(i, j); m < rF; ++m) s = fma(B0[i + m * LDP], B1[j + m * LDP], s);
     B3[i + j * LDP] = s;
   }
   __syncthreads();
