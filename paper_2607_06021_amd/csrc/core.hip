@@ -29,7 +29,7 @@ namespace lrp {
 
 constexpr int LDP = kPMax + 1;        // padded leading dimension of the LDS matrices
 constexpr int kCoreThreads = 512;
-constexpr int kEtaThreads = 1024;  // two Jacobi problems of up to 8 waves each
+constexpr int kEtaThreads = 512;  // one Jacobi problem of up to 8 waves per workgroup
 constexpr int kBuf = kPMax * LDP;
 
 // ---------------------------------------------------------------- lane-group sums (DPP)
@@ -878,72 +878,60 @@ __global__ __launch_bounds__(kCoreThreads) void k_core(Src in) {
 // Indicator and stop decision of a pass (Algorithm 4, after rho): when a stop is possible
 // (cheap bound passed, rho < eps), eta_1 = 1/sigma_min(U_k(I,:)) and eta_2 =
 // 1/sigma_min(V_k(J,:)) on the pruned sets, with U_k(I,:) = Q(I,:) U^ and V_k(J,:) = Z(J,:) V~
-// each stored tall (rows >= cols) so that Jacobi gives its min(rows, cols) singular values;
-// the two problems are solved side by side. Then the pass is accepted as the new iterate and
+// each stored tall (rows >= cols) so that Jacobi gives its min(rows, cols) singular values.
+// Workgroup q solves problem q (two CUs; a problem's sweeps do not depend on the other's), and
+// the second workgroup to finish makes the decision: the pass is accepted as the new iterate and
 // the solve stops when max(rho, indicator) < eps, or after maxiter passes.
 template <class Src>
 __global__ __launch_bounds__(kEtaThreads) void k_eta(Src in) {
   const EtaArgs& a = kernel_args<EtaArgs>(in);
   DevState* st = a.st;
   if (st->done) return;
-  __shared__ double E1[kBuf], E2[kBuf], Qs[kBuf], Us[kBuf];
-  __shared__ double red[2];
-  __shared__ int flags[2], idx[2 * kPMax];
-  const int t = threadIdx.x;
+  __shared__ double E[kBuf], Qs[kBuf], Us[kBuf];
+  __shared__ double red[1];
+  __shared__ int flags[2], idx[kPMax], last;
+  const int t = threadIdx.x, q = blockIdx.x;
   const int nb = a.nb;
   const int r = st->r[nb];
   const bool need = st->k >= 1 && st->eta_need && st->rho < st->eps;
-  double smin1 = 0.0, smin2 = 0.0;
   if (need) {
-    const int nI = st->nI, nJ = st->nJ;      // pruned sets
-    const int kJ = st->ncols[0], kI = st->ncols[1];  // columns of Q and Z
-    const int pm = a.pmax;
-    const bool t1 = nI >= r, t2 = nJ >= r;
-    // E1 = Q(I,:) U^ and E2 = Z(J,:) V~ on the matrix cores, from rows and factors staged in
-    // LDS (each stored tall: transposed when the set is smaller than r)
-    if (t < kPMax) {
-      idx[t] = t < nI ? st->I[t] : 0;
-      idx[kPMax + t] = t < nJ ? st->J[t] : 0;
-    }
+    // side 0: rows I of Q (ncols[0] columns) times U^; side 1: rows J of Z (ncols[1]) times V~
+    const int ns = q == 0 ? st->nI : st->nJ;
+    const int kc = st->ncols[q];
+    const bool tall = ns >= r;
+    if (t < kPMax) idx[t] = t < ns ? (q == 0 ? st->I[t] : st->J[t]) : 0;
     __syncthreads();
-    gather_rows(a.Q0, a.ldq, idx, nI, kJ, Qs);
-    load_block(a.Uhat, pm, kJ, r, Us);
+    gather_rows(q == 0 ? a.Q0 : a.Q1, a.ldq, idx, ns, kc, Qs);
+    load_block(q == 0 ? a.Uhat : a.Vtil, a.pmax, kc, r, Us);
     __syncthreads();
-    lds_gemm(Qs, Us, E1, nI, r, !t1);
+    lds_gemm(Qs, Us, E, ns, r, !tall);
     __syncthreads();
-    gather_rows(a.Q1, a.ldq, idx + kPMax, nJ, kI, Qs);
-    load_block(a.Vtil, pm, kI, r, Us);
-    __syncthreads();
-    lds_gemm(Qs, Us, E2, nJ, r, !t2);
-    __syncthreads();
-    JacProb pp[2] = {{E1, t1 ? nI : r, t1 ? r : nI, nullptr}, {E2, t2 ? nJ : r, t2 ? r : nJ, nullptr}};
-    jacobi(pp, 2, flags);
-    if (t < 64) {  // smallest column norm of each
-      double v1 = INFINITY, v2 = INFINITY;
+    JacProb pp[1] = {{E, tall ? ns : r, tall ? r : ns, nullptr}};
+    jacobi(pp, 1, flags);
+    if (t < 64) {  // smallest column norm
+      double v = INFINITY;
       if (t < pp[0].k) {
         double s = 0.0;
-        for (int i = 0; i < pp[0].m; ++i) s = fma(E1[i + t * LDP], E1[i + t * LDP], s);
-        v1 = sqrt(s);
+        for (int i = 0; i < pp[0].m; ++i) s = fma(E[i + t * LDP], E[i + t * LDP], s);
+        v = sqrt(s);
       }
-      if (t < pp[1].k) {
-        double s = 0.0;
-        for (int i = 0; i < pp[1].m; ++i) s = fma(E2[i + t * LDP], E2[i + t * LDP], s);
-        v2 = sqrt(s);
-      }
-      for (int msk = 32; msk >= 1; msk >>= 1) {
-        v1 = fmin(v1, shfl_xor_d(v1, msk));
-        v2 = fmin(v2, shfl_xor_d(v2, msk));
-      }
-      if (t == 0) {
-        red[0] = v1;
-        red[1] = v2;
-      }
+      for (int msk = 32; msk >= 1; msk >>= 1) v = fmin(v, shfl_xor_d(v, msk));
+      if (t == 0) red[0] = v;
     }
     __syncthreads();
-    smin1 = red[0];
-    smin2 = red[1];
+    if (t == 0) st->smin[q] = red[0];
   }
+  // publish this workgroup's result, then count it; the second to arrive sees both
+  __threadfence();
+  __syncthreads();
+  if (t == 0) last = atomicAdd(&st->eta_count, 1) == (int)gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
   if (t == 0) {
+    const volatile double* sm = st->smin;
+    const double smin1 = need ? sm[0] : 0.0, smin2 = need ? sm[1] : 0.0;
+    st->eta_count = 0;
     const int kp = st->k;
     double ind = INFINITY;
     if (need) {
@@ -969,7 +957,7 @@ __global__ __launch_bounds__(kEtaThreads) void k_eta(Src in) {
 }
 
 int eta_launch(const EtaArgs& a, hipStream_t s) {
-  LRP_LAUNCH_G(K_ETA, k_eta<EtaArgs>, k_eta<GroupRef>, dim3(1), dim3(kEtaThreads), 0, s, a);
+  LRP_LAUNCH_G(K_ETA, k_eta<EtaArgs>, k_eta<GroupRef>, dim3(2), dim3(kEtaThreads), 0, s, a);
   return launch_status();
 }
 
@@ -1068,6 +1056,7 @@ __global__ void k_init_state(DevState* st, int rF, double eps, double tau, int r
   st->rho = INFINITY;
   st->eta1 = st->eta2 = INFINITY;
   st->eta_need = 0;
+  st->eta_count = 0;
   st->eps = eps;
   st->tau = tau;
   st->r[0] = st->r[1] = 0;

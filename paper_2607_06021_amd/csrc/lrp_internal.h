@@ -38,6 +38,8 @@ struct DevState {
   int replay_n;  // passes 0 .. replay_n-1 take their index sets from the replay buffers
   int guess_ok;  // 1: the initial guess was nonzero and replaced the start from the right-hand side
   double nrm, ind, rho, eta1, eta2;
+  double smin[2];  // sigma_min of U_k(I,:) and V_k(J,:) from the indicator's two workgroups
+  int eta_count;   // indicator workgroups done with the current pass (the second one decides)
   double eps;   // effective tolerance
   double tau;   // prune threshold
   int I[kPMax], J[kPMax];
