@@ -20,8 +20,9 @@
 // The warm start uses the same SVD on M = R_u R_v^T, the core of F^ = U^ V^^T.
 //
 // Jacobi: Hestenes' one-sided method; a pair is rotated unless
-// |a_p . a_q| <= sqrt(m) eps ||a_p|| ||a_q||, and the sweeps end when one makes no rotation (at
-// most 60). Every sweep visits each column pair once, in an order built for wavefronts (see
+// |a_p . a_q| <= sqrt(m) eps ||a_p|| ||a_q||, and the sweeps end after one whose rotations all
+// had |a_p . a_q| <= 1e-9 ||a_p|| ||a_q|| (at most 60): convergence is quadratic by then, so the
+// next sweep would find every pair below the rotation threshold and change nothing. Every sweep visits each column pair once, in an order built for wavefronts (see
 // jacobi_waves): each wave keeps 8 columns in registers for 4 rounds at a time.
 #include "lrp_kernels.h"
 
@@ -133,8 +134,11 @@ __device__ inline int jac_groups(int k) {
 // One Jacobi pair step on the 16 lanes of a pair slot: lane li holds rows li + 16u (u < 4)
 // of the two columns (a, b) and of their V columns; rows past m (or k for V) are zero, and so is
 // an empty column, which is never rotated (its dot products vanish).
+constexpr double kJacQuiet2 = 1e-18;  // (1e-9)^2: a rotation below this leaves the next sweep idle
+
 template <bool WV>
-__device__ inline bool jac_pair(double (&a)[4], double (&b)[4], double (&va)[4], double (&vb)[4], double tol2) {
+__device__ inline bool jac_pair(double (&a)[4], double (&b)[4], double (&va)[4], double (&vb)[4], double tol2,
+                                bool& loud) {
   double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
@@ -146,6 +150,7 @@ __device__ inline bool jac_pair(double (&a)[4], double (&b)[4], double (&va)[4],
   be = group_sum<16>(be);
   ga = group_sum<16>(ga);
   const bool rot = ga != 0.0 && ga * ga > tol2 * al * be;
+  loud |= rot && ga * ga > kJacQuiet2 * al * be;
   // Straight-line rotation for every slot (slots that do not rotate take c = 1, s = 0, which
   // leaves the values of their columns unchanged); the extreme-range formula is a rare branch.
   const double d = be - al, g2 = 2.0 * ga;
@@ -254,26 +259,26 @@ __device__ int jacobi_waves(JacProb* P, int nprob, int* flags) {
   const double tol = sqrt((double)max(pr.m, 1)) * kEps;
   const double tol2 = tol * tol;
   double a[4], b[4], va[4], vb[4];
-  bool active = true;
+  bool active = true;  // this problem's last sweep made a rotation above the quiet level
   int sweeps = 0;
   for (int sweep = 0; sweep < 60; ++sweep) {
     sweeps = sweep + 1;
     if (t < 2) flags[t] = 0;
     __syncthreads();
-    bool rot = false;
+    bool loud = false;
     for (int gr = 0; gr < ngmax - 1; ++gr) {
       if (active && mine && gr < ng - 1) {
         int g, h;
         rr_pair(ng, lw, gr, g, h);
         jac_load<WV>(pr, 4 * g + slot, li, a, va);
         jac_load<WV>(pr, 4 * h + slot, li, b, vb);
-        rot |= jac_pair<WV>(a, b, va, vb, tol2);  // s = 0
+        jac_pair<WV>(a, b, va, vb, tol2, loud);  // s = 0
         jac_move_b<WV>(b, vb, lane ^ 16);
-        rot |= jac_pair<WV>(a, b, va, vb, tol2);  // s = 1
+        jac_pair<WV>(a, b, va, vb, tol2, loud);  // s = 1
         jac_move_b<WV>(b, vb, lane ^ 32);
-        rot |= jac_pair<WV>(a, b, va, vb, tol2);  // s = 3
+        jac_pair<WV>(a, b, va, vb, tol2, loud);  // s = 3
         jac_move_b<WV>(b, vb, lane ^ 16);
-        rot |= jac_pair<WV>(a, b, va, vb, tol2);  // s = 2
+        jac_pair<WV>(a, b, va, vb, tol2, loud);  // s = 2
         jac_store<WV>(pr, 4 * g + slot, li, a, va);
         jac_store<WV>(pr, 4 * h + (slot ^ 2), li, b, vb);
       }
@@ -284,7 +289,7 @@ __device__ int jacobi_waves(JacProb* P, int nprob, int* flags) {
       const bool odd = slot & 1;
       jac_load<WV>(pr, c0 + (odd ? 2 : 0), li, a, va);
       jac_load<WV>(pr, c0 + (odd ? 3 : 1), li, b, vb);
-      rot |= jac_pair<WV>(a, b, va, vb, tol2);  // (0,1) (2,3)
+      jac_pair<WV>(a, b, va, vb, tol2, loud);  // (0,1) (2,3)
 #pragma unroll
       for (int u = 0; u < 4; ++u) {  // even slot: b <- partner's a; odd slot: a <- partner's b
         const double ta = lane_fetch(a[u], lane ^ 16), tb = lane_fetch(b[u], lane ^ 16);
@@ -300,13 +305,13 @@ __device__ int jacobi_waves(JacProb* P, int nprob, int* flags) {
             vb[u] = tva;
         }
       }
-      rot |= jac_pair<WV>(a, b, va, vb, tol2);  // (0,2) (1,3)
+      jac_pair<WV>(a, b, va, vb, tol2, loud);  // (0,2) (1,3)
       jac_move_b<WV>(b, vb, lane ^ 16);
-      rot |= jac_pair<WV>(a, b, va, vb, tol2);  // (0,3) (1,2)
+      jac_pair<WV>(a, b, va, vb, tol2, loud);  // (0,3) (1,2)
       jac_store<WV>(pr, c0 + (odd ? 1 : 0), li, a, va);
       jac_store<WV>(pr, c0 + (odd ? 2 : 3), li, b, vb);
     }
-    if (rot) flags[q] = 1;
+    if (loud) flags[q] = 1;
     __syncthreads();
     const bool any0 = flags[0] != 0, any1 = flags[1] != 0;
     active = q == 0 ? any0 : any1;
@@ -317,7 +322,7 @@ __device__ int jacobi_waves(JacProb* P, int nprob, int* flags) {
   return sweeps;
 }
 
-// Returns the number of sweeps made (the last one made no rotation).
+// Returns the number of sweeps made (the last one made no rotation above the quiet level).
 __device__ int jacobi(JacProb* P, int nprob, int* flags) {
   bool wv = false;
   for (int x = 0; x < nprob; ++x) wv |= P[x].V != nullptr;
