@@ -688,13 +688,20 @@ int enqueue_pass_polled(lrp_ctx* c, int k) {
 }
 
 // After pass k: copy the stop flag to pinned memory and mark the point with an event.
+// The stop flag into its pinned host slot. A one-thread kernel rather than a copy, so that the
+// pass boundary stays on the compute queue (a copy may go to a DMA engine, and the next pass
+// would wait for the hand-over between the two).
+__global__ void k_flag_copy(const int* src, int* dst) {
+  if (threadIdx.x == 0) {
+    *dst = *src;
+    __threadfence_system();
+  }
+}
+
 int enqueue_poll(lrp_ctx* c, int k) {
   const int slot = k & 1;
-  prof_begin(c->stream, K_COPY);
-  if (hipMemcpyAsync(&c->done_host[slot], &c->st->done, sizeof(int), hipMemcpyDeviceToHost, c->stream) !=
-      hipSuccess)
-    return LRP_EDEVICE;
-  prof_end(c->stream);
+  LRP_LAUNCH(K_COPY, k_flag_copy, dim3(1), dim3(64), 0, c->stream, &c->st->done, &c->done_host[slot]);
+  TRY(launch_status());
   return hipEventRecord(c->evit[slot], c->stream) == hipSuccess ? LRP_OK : LRP_EDEVICE;
 }
 
