@@ -103,14 +103,15 @@ def time_solves(sol, args_dev, steps, warmup):
     out = (empty_fortran(sol.n, sol.r_max, torch.float64, dev),
            torch.empty(sol.r_max, dtype=torch.float64, device=dev),
            empty_fortran(sol.n, sol.r_max, torch.float64, dev))
-    for _ in range(warmup):
-        sol.solve(*args_dev, out=out)
-    torch.cuda.synchronize()
-    # Python's cyclic garbage collector is paused over the timed loop (as timeit does): a full
-    # collection with torch loaded takes tens of milliseconds and otherwise lands on one solve.
+    # Python's cyclic garbage collector is paused over the warm-up and the timed loop (as timeit
+    # does): a full collection with torch loaded takes tens of milliseconds and otherwise lands on
+    # one solve. It runs before the warm-up, so the device is busy right up to the timed loop.
     gc.collect()
     gc.disable()
     try:
+        for _ in range(warmup):
+            sol.solve(*args_dev, out=out)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         infos = []
         marks = []
