@@ -522,7 +522,7 @@ def sketched_rel_err(n, U, S, V, gold):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU per process; --gpus must be 1"}))
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
