@@ -196,8 +196,8 @@ int lrp_get_index_sets(const lrp_ctx* ctx, int64_t* I, int32_t* nI, int64_t* J, 
  *               QR (a bound showed that the cutoff drops no singular value, so the pseudo-inverse
  *               is the left inverse), 1 through a Jacobi SVD with the cutoff;
  *   sweeps      host, count: one-sided Jacobi sweeps of the SVD of the pass's core (the last
- *               sweep rotates no pair by more than a cosine of 1e-9, so a further sweep would
- *               rotate none).
+ *               sweep rotates no pair by more than a cosine of 1e-8, after which a further sweep
+ *               would find the pairs orthogonal to rounding).
  *   count       host in/out: capacity in passes on input, passes recorded on output.
  * Any array pointer may be NULL. Returns LRP_OK or LRP_EINVAL.
  */

@@ -21,8 +21,9 @@
 //
 // Jacobi: Hestenes' one-sided method; a pair is rotated unless
 // |a_p . a_q| <= sqrt(m) eps ||a_p|| ||a_q||, and the sweeps end after one whose rotations all
-// had |a_p . a_q| <= 1e-9 ||a_p|| ||a_q|| (at most 60): convergence is quadratic by then, so the
-// next sweep would find every pair below the rotation threshold and change nothing. Every sweep visits each column pair once, in an order built for wavefronts (see
+// had |a_p . a_q| <= 1e-8 ||a_p|| ||a_q|| (at most 60): convergence is quadratic by then, so the
+// next sweep would find the pairs at about 1e-16, at the rotation threshold, and change nothing
+// beyond rounding. Every sweep visits each column pair once, in an order built for wavefronts (see
 // jacobi_waves): each wave keeps 8 columns in registers for 4 rounds at a time.
 #include "lrp_kernels.h"
 
@@ -134,7 +135,7 @@ __device__ inline int jac_groups(int k) {
 // One Jacobi pair step on the 16 lanes of a pair slot: lane li holds rows li + 16u (u < 4)
 // of the two columns (a, b) and of their V columns; rows past m (or k for V) are zero, and so is
 // an empty column, which is never rotated (its dot products vanish).
-constexpr double kJacQuiet2 = 1e-18;  // (1e-9)^2: a rotation below this leaves the next sweep idle
+constexpr double kJacQuiet2 = 1e-16;  // (1e-8)^2: a rotation below this leaves the next sweep idle
 
 template <bool WV>
 __device__ inline bool jac_pair(double (&a)[4], double (&b)[4], double (&va)[4], double (&vb)[4], double tol2,
